@@ -1,0 +1,21 @@
+"""Build the oracle shared library (plain C, gcc).  Test infrastructure."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libpivco_ref.so")
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(HERE, "pivco_ref.c")
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
+           src, "-o", LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

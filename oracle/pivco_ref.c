@@ -1,0 +1,819 @@
+/*
+ * pivco_ref.c -- TEST INFRASTRUCTURE ONLY: plain scalar CPU oracle for the
+ * PivCo-Huffman codec.  Nothing in the product path may call this file; it
+ * exists so that tests can check the GPU library against an implementation
+ * that can be read against the paper line by line.  See pivco_ref.h for the
+ * passage each function follows.
+ *
+ * Wire format v1 (all integers little-endian):
+ *
+ *   stream header, 48 bytes:
+ *     magic u32 = "PVC1" | version u16 = 1 | flags u16 = 0 | n_total u64
+ *     | block_size u32 | n_blocks u32 | max_len u8 | chunk_log2 u8
+ *     | reserved u16 = 0 | reserved u32 = 0 | ans_words u64 | reserved u64 = 0
+ *   block_off u64[n_blocks + 1]   byte offset of each block from the stream
+ *                                 start; the last entry is the stream size
+ *   ans_off   u64[n_blocks + 1]   running count of scratch words (u32) that
+ *                                 the rANS-coded nodes of earlier blocks
+ *                                 decode into: sum of ceil(n_v / 32)
+ *   blocks, each starting at a multiple of 4 bytes:
+ *     comp_size u32 | n u32 | mode u8 (0 coded, 1 constant) | const_sym u8
+ *     | cnt_width u8 (2 if n <= 65535 else 4) | pad u8 = 0
+ *     mode 0 only:
+ *       code_len u8[128]: symbol 2j in the low nibble of byte j, 2j+1 in the
+ *                         high nibble; 0 = absent (App. D)
+ *       kind u8[ceil(I/8)]: bit i (LSB first) = internal node i is rANS-coded
+ *       n_right u16|u32 [I]: number of 1 bits (symbols going right) of every
+ *                         internal node
+ *       raw bodies of nodes with kind 0, node order: ceil(n_v/8) bytes, bit j
+ *                         of the node in byte j>>3 at bit j&7, pad bits zero
+ *       rANS bodies of nodes with kind 1, node order, each at a multiple of 4
+ *                         bytes: p1q u16 | pad u16 | body_len u32 | chunks
+ *     comp_size counts the block's bytes from its first header byte to the
+ *     end of its last body.
+ *   Internal nodes are numbered breadth-first: by depth, then left to right.
+ *   Bit 0 = left child, bit 1 = right child (Listing 1).
+ */
+#include "pivco_ref.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXSYM 256
+#define MAXNODE 511   /* 255 internal + 256 leaves */
+
+/* ------------------------------------------------------------------ */
+/* little-endian helpers                                               */
+/* ------------------------------------------------------------------ */
+static void put16(uint8_t *p, uint32_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put32(uint8_t *p, uint32_t v) { for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static void put64(uint8_t *p, uint64_t v) { for (int i = 0; i < 8; i++) p[i] = (uint8_t)(v >> (8 * i)); }
+static uint32_t get16(const uint8_t *p) { return (uint32_t)p[0] | ((uint32_t)p[1] << 8); }
+static uint32_t get32(const uint8_t *p) {
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+static uint64_t get64(const uint8_t *p) { return (uint64_t)get32(p) | ((uint64_t)get32(p + 4) << 32); }
+
+static int getbit(const uint8_t *bm, uint64_t j) { return (bm[j >> 3] >> (j & 7)) & 1; }
+static void setbit(uint8_t *bm, uint64_t j) { bm[j >> 3] |= (uint8_t)(1u << (j & 7)); }
+
+/* ------------------------------------------------------------------ */
+/* Code lengths: package-merge (coin collector)                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint64_t w;     /* weight */
+    int kind;       /* 0 = leaf, 1 = package */
+    int sym;        /* leaf symbol */
+    int a, b;       /* package: indices of its two items in the deeper list */
+} pm_item;
+
+int pivco_ref_lengths(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]) {
+    if (!counts || !len || max_len < 1 || max_len > 15) return PVO_E_ARG;
+    int syms[MAXSYM], m = 0;
+    memset(len, 0, 256);
+    for (int s = 0; s < 256; s++)
+        if (counts[s]) syms[m++] = s;
+    if (m < 2 || ((uint32_t)1 << max_len) < (uint32_t)m) return PVO_E_ARG;
+    /* leaves sorted by (weight asc, symbol asc): insertion sort, stable */
+    for (int i = 1; i < m; i++) {
+        int s = syms[i], j = i - 1;
+        while (j >= 0 && counts[syms[j]] > counts[s]) { syms[j + 1] = syms[j]; j--; }
+        syms[j + 1] = s;
+    }
+    int L = (int)max_len;
+    pm_item *lists[16];
+    int nlist[16];
+    /* list[L] = leaves; list[l-1] = merge(leaves, packages of list[l]) */
+    for (int l = 0; l < 16; l++) lists[l] = NULL;
+    lists[L] = (pm_item *)malloc(sizeof(pm_item) * (size_t)m);
+    for (int i = 0; i < m; i++) {
+        lists[L][i].w = counts[syms[i]]; lists[L][i].kind = 0; lists[L][i].sym = syms[i];
+        lists[L][i].a = lists[L][i].b = -1;
+    }
+    nlist[L] = m;
+    for (int l = L; l >= 2; l--) {
+        int np = nlist[l] / 2;
+        pm_item *out = (pm_item *)malloc(sizeof(pm_item) * (size_t)(m + np));
+        int i = 0, p = 0, o = 0;
+        while (i < m || p < np) {
+            int take_leaf;
+            if (p >= np) take_leaf = 1;
+            else if (i >= m) take_leaf = 0;
+            else {
+                uint64_t pw = lists[l][2 * p].w + lists[l][2 * p + 1].w;
+                take_leaf = counts[syms[i]] <= pw; /* leaf first on equal weight */
+            }
+            if (take_leaf) {
+                out[o].w = counts[syms[i]]; out[o].kind = 0; out[o].sym = syms[i];
+                out[o].a = out[o].b = -1; i++;
+            } else {
+                out[o].w = lists[l][2 * p].w + lists[l][2 * p + 1].w; out[o].kind = 1;
+                out[o].sym = -1; out[o].a = 2 * p; out[o].b = 2 * p + 1; p++;
+            }
+            o++;
+        }
+        lists[l - 1] = out;
+        nlist[l - 1] = o;
+    }
+    /* select the first 2m-2 items of list[1]; expand packages downwards */
+    int cnt[256];
+    memset(cnt, 0, sizeof(cnt));
+    char *sel = (char *)calloc((size_t)(2 * m + 2), 1);
+    char *nsel = (char *)calloc((size_t)(2 * m + 2), 1);
+    for (int i = 0; i < 2 * m - 2 && i < nlist[1]; i++) sel[i] = 1;
+    for (int l = 1; l <= L; l++) {
+        memset(nsel, 0, (size_t)(2 * m + 2));
+        for (int i = 0; i < nlist[l]; i++) {
+            if (!sel[i]) continue;
+            if (lists[l][i].kind == 0) cnt[lists[l][i].sym]++;
+            else { nsel[lists[l][i].a] = 1; nsel[lists[l][i].b] = 1; }
+        }
+        char *t = sel; sel = nsel; nsel = t;
+    }
+    free(sel); free(nsel);
+    for (int l = 1; l <= L; l++) free(lists[l]);
+    /* deterministic assignment: ascending lengths to (count desc, sym asc) */
+    int hist[16];
+    memset(hist, 0, sizeof(hist));
+    for (int s = 0; s < 256; s++)
+        if (counts[s]) hist[cnt[s]]++;
+    int order[MAXSYM];
+    for (int i = 0; i < m; i++) order[i] = syms[i];
+    /* syms sorted by (w asc, sym asc); want (w desc, sym asc) */
+    for (int i = 1; i < m; i++) {
+        int s = order[i], j = i - 1;
+        while (j >= 0 && (counts[order[j]] < counts[s] ||
+                          (counts[order[j]] == counts[s] && order[j] > s))) {
+            order[j + 1] = order[j]; j--;
+        }
+        order[j + 1] = s;
+    }
+    int k = 0;
+    for (int l = 1; l <= L; l++)
+        for (int c = 0; c < hist[l]; c++) len[order[k++]] = (uint8_t)l;
+    return k == m ? PVO_OK : PVO_E_ARG;
+}
+
+int pivco_ref_codes(const uint8_t len[256], uint16_t code[256]) {
+    if (!len || !code) return PVO_E_ARG;
+    memset(code, 0, 256 * sizeof(uint16_t));
+    uint32_t c = 0;
+    int prevlen = 0, first = 1;
+    for (int l = 1; l <= 15; l++) {
+        for (int s = 0; s < 256; s++) {
+            if (len[s] != l) continue;
+            if (first) { c = 0; first = 0; }
+            else c = (c + 1) << (l - prevlen);
+            prevlen = l;
+            if (c >> l) return PVO_E_ARG; /* over-subscribed */
+            code[s] = (uint16_t)c;
+        }
+    }
+    return PVO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Explicit code tree (trie) built from the canonical codes            */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int leaf, sym, child[2], depth;
+    int id;              /* breadth-first index among internal nodes */
+    uint64_t n, n_right; /* symbols passing / symbols going right */
+} tnode;
+
+typedef struct {
+    tnode nd[MAXNODE];
+    int nn;
+    int bfs[255];        /* node index of internal node i (BFS order) */
+    int ni;              /* number of internal nodes */
+} tree_t;
+
+/* Returns 0 if the lengths form a complete prefix code (Kraft sum == 1) with
+ * at least two symbols, and builds the tree. */
+static int build_tree(const uint8_t len[256], tree_t *t) {
+    uint64_t kraft = 0;
+    int m = 0;
+    for (int s = 0; s < 256; s++) {
+        if (len[s] > 15) return PVO_E_CORRUPT;
+        if (len[s]) { kraft += (uint64_t)1 << (15 - len[s]); m++; }
+    }
+    if (m < 2 || kraft != ((uint64_t)1 << 15)) return PVO_E_CORRUPT;
+    uint16_t code[256];
+    if (pivco_ref_codes(len, code)) return PVO_E_CORRUPT;
+    memset(t, 0, sizeof(*t));
+    t->nn = 1;
+    t->nd[0].leaf = 0; t->nd[0].child[0] = t->nd[0].child[1] = -1; t->nd[0].depth = 0;
+    for (int s = 0; s < 256; s++) {
+        if (!len[s]) continue;
+        int cur = 0;
+        for (int d = 0; d < len[s]; d++) {
+            int b = (code[s] >> (len[s] - 1 - d)) & 1;
+            if (t->nd[cur].leaf) return PVO_E_CORRUPT;
+            int c = t->nd[cur].child[b];
+            if (d == len[s] - 1) {
+                if (c != -1) return PVO_E_CORRUPT;
+                c = t->nn++;
+                t->nd[c].leaf = 1; t->nd[c].sym = s; t->nd[c].depth = d + 1;
+                t->nd[c].child[0] = t->nd[c].child[1] = -1;
+                t->nd[cur].child[b] = c;
+            } else {
+                if (c == -1) {
+                    c = t->nn++;
+                    t->nd[c].leaf = 0; t->nd[c].depth = d + 1;
+                    t->nd[c].child[0] = t->nd[c].child[1] = -1;
+                    t->nd[cur].child[b] = c;
+                }
+                cur = c;
+            }
+        }
+    }
+    /* breadth-first numbering of internal nodes */
+    int queue[MAXNODE], qh = 0, qt = 0;
+    queue[qt++] = 0;
+    t->ni = 0;
+    while (qh < qt) {
+        int v = queue[qh++];
+        if (t->nd[v].leaf) continue;
+        if (t->nd[v].child[0] < 0 || t->nd[v].child[1] < 0) return PVO_E_CORRUPT;
+        t->nd[v].id = t->ni;
+        t->bfs[t->ni++] = v;
+        queue[qt++] = t->nd[v].child[0];
+        queue[qt++] = t->nd[v].child[1];
+    }
+    return (t->ni == m - 1) ? PVO_OK : PVO_E_CORRUPT;
+}
+
+/* ------------------------------------------------------------------ */
+/* rANS (binary alphabet, 12-bit probabilities, 32 interleaved lanes)   */
+/* ------------------------------------------------------------------ */
+#define RANS_M 4096u
+#define RANS_L 65536u
+
+uint32_t pivco_ref_p1q(uint64_t n_v, uint64_t n_right) {
+    if (n_v == 0) return 2048;
+    uint64_t q = (n_right * 4096u + n_v / 2) / n_v;
+    if (q < 1) q = 1;
+    if (q > 4095) q = 4095;
+    return (uint32_t)q;
+}
+
+int pivco_ref_select_ans(uint32_t mode, uint64_t n_v, uint64_t n_right) {
+    if (n_v == 0) return 0;
+    if (mode == 1) return (10 * n_right < n_v) || (10 * n_right > 9 * n_v);
+    if (mode == 2) return 1;
+    return 0;
+}
+
+int pivco_ref_rans_encode(const uint8_t *bits, uint64_t nbits, uint32_t p1q,
+                          uint32_t chunk_log2, uint8_t *out, uint64_t cap,
+                          uint64_t *out_len) {
+    if (p1q < 1 || p1q > 4095 || chunk_log2 < 5 || chunk_log2 > 24) return PVO_E_ARG;
+    uint64_t C = (uint64_t)1 << chunk_log2;
+    uint32_t f[2] = {RANS_M - p1q, p1q};
+    uint32_t c[2] = {0, RANS_M - p1q};
+    uint16_t *stack = (uint16_t *)malloc(sizeof(uint16_t) * (C + 1));
+    uint64_t o = 0;
+    for (uint64_t start = 0; start < nbits; start += C) {
+        uint64_t cl = nbits - start < C ? nbits - start : C;
+        uint64_t K = (cl + 31) / 32;
+        uint32_t x[32];
+        for (int l = 0; l < 32; l++) x[l] = RANS_L;
+        uint64_t nw = 0;
+        for (uint64_t k = K; k-- > 0;) {
+            for (int lane = 31; lane >= 0; lane--) {
+                uint64_t j = 32 * k + (uint64_t)lane;
+                if (j >= cl) continue;
+                int b = getbit(bits, start + j);
+                if (x[lane] >= (f[b] << 20)) { stack[nw++] = (uint16_t)(x[lane] & 0xFFFF); x[lane] >>= 16; }
+                x[lane] = (x[lane] / f[b]) * RANS_M + (x[lane] % f[b]) + c[b];
+            }
+        }
+        uint64_t need = 4 + 128 + 2 * nw;
+        need = (need + 3) & ~(uint64_t)3;
+        if (o + need > cap) { free(stack); return PVO_E_CAPACITY; }
+        put32(out + o, (uint32_t)nw);
+        for (int l = 0; l < 32; l++) put32(out + o + 4 + 4 * l, x[l]);
+        for (uint64_t i = 0; i < nw; i++) put16(out + o + 132 + 2 * i, stack[nw - 1 - i]);
+        for (uint64_t i = 132 + 2 * nw; i < need; i++) out[o + i] = 0;
+        o += need;
+    }
+    free(stack);
+    *out_len = o;
+    return PVO_OK;
+}
+
+int pivco_ref_rans_decode(const uint8_t *body, uint64_t body_len, uint64_t nbits,
+                          uint32_t p1q, uint32_t chunk_log2, uint8_t *bits_out) {
+    if (p1q < 1 || p1q > 4095 || chunk_log2 < 5 || chunk_log2 > 24) return PVO_E_ARG;
+    uint64_t C = (uint64_t)1 << chunk_log2;
+    uint32_t f0 = RANS_M - p1q, f[2] = {RANS_M - p1q, p1q}, c[2] = {0, RANS_M - p1q};
+    memset(bits_out, 0, (size_t)((nbits + 7) / 8));
+    uint64_t o = 0;
+    for (uint64_t start = 0; start < nbits; start += C) {
+        uint64_t cl = nbits - start < C ? nbits - start : C;
+        uint64_t K = (cl + 31) / 32;
+        if (o + 132 > body_len) return PVO_E_CORRUPT;
+        uint64_t nw = get32(body + o);
+        uint64_t size = (132 + 2 * nw + 3) & ~(uint64_t)3;
+        if (nw > C || o + size > body_len) return PVO_E_CORRUPT;
+        uint32_t x[32];
+        for (int l = 0; l < 32; l++) {
+            x[l] = get32(body + o + 4 + 4 * l);
+            if (x[l] < RANS_L) return PVO_E_CORRUPT;
+        }
+        const uint8_t *w = body + o + 132;
+        uint64_t pos = 0;
+        for (uint64_t k = 0; k < K; k++) {
+            for (int lane = 0; lane < 32; lane++) {
+                uint64_t j = 32 * k + (uint64_t)lane;
+                if (j >= cl) continue;
+                uint32_t slot = x[lane] & (RANS_M - 1);
+                int b = slot >= f0;
+                x[lane] = f[b] * (x[lane] >> 12) + slot - c[b];
+                if (x[lane] < RANS_L) {
+                    if (pos >= nw) return PVO_E_CORRUPT;
+                    x[lane] = (x[lane] << 16) | get16(w + 2 * pos);
+                    pos++;
+                }
+                if (b) setbit(bits_out, start + j);
+            }
+        }
+        if (pos != nw) return PVO_E_CORRUPT;
+        for (int l = 0; l < 32; l++)
+            if (x[l] != RANS_L) return PVO_E_CORRUPT;
+        for (uint64_t i = 132 + 2 * nw; i < size; i++)
+            if (body[o + i]) return PVO_E_CORRUPT;
+        o += size;
+    }
+    return o == body_len ? PVO_OK : PVO_E_CORRUPT;
+}
+
+/* ------------------------------------------------------------------ */
+/* Encoder                                                              */
+/* ------------------------------------------------------------------ */
+#define HDR 48
+
+uint64_t pivco_ref_encode_bound(uint64_t n, uint32_t block_size, uint32_t ans_mode) {
+    if (block_size == 0) return 0;
+    uint64_t nb = (n + block_size - 1) / block_size;
+    uint64_t b = HDR + 16 * (nb + 1);
+    /* per block: fixed header, length table, kind bits, counts, padding */
+    b += nb * (12 + 128 + 32 + 4 * 255 + 8);
+    /* bodies: every symbol contributes at most 15 bits; one byte of padding
+     * per node; rANS adds per-chunk headers and up to 2 bytes per bit */
+    if (ans_mode == 0) b += (15 * n) / 8 + nb * 255;
+    else b += 2 * 15 * n + nb * 255 * (12 + 136) + 136 * ((15 * n) >> 16);
+    return b;
+}
+
+static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_t ans_mode,
+                        uint32_t chunk_log2, const uint8_t *tree_len, uint8_t *out,
+                        uint64_t cap, uint64_t *out_len, uint64_t *ans_words) {
+    uint64_t counts[256];
+    memset(counts, 0, sizeof(counts));
+    for (uint64_t i = 0; i < n; i++) counts[in[i]]++;
+    int m = 0, last = 0;
+    for (int s = 0; s < 256; s++) if (counts[s]) { m++; last = s; }
+    *ans_words = 0;
+    if (cap < 12) return PVO_E_CAPACITY;
+    uint32_t cw = n <= 65535 ? 2 : 4;
+    put32(out + 4, (uint32_t)n);
+    out[10] = (uint8_t)cw; out[11] = 0;
+    if (!tree_len && m == 1) {           /* constant block */
+        put32(out, 12); out[8] = 1; out[9] = (uint8_t)last;
+        *out_len = 12;
+        return PVO_OK;
+    }
+    uint8_t len[256];
+    if (tree_len) {
+        memcpy(len, tree_len, 256);
+        for (int s = 0; s < 256; s++)
+            if (counts[s] && !len[s]) return PVO_E_ARG;
+        for (int s = 0; s < 256; s++) if (len[s] > max_len) return PVO_E_ARG;
+    } else {
+        int r = pivco_ref_lengths(counts, max_len, len);
+        if (r) return r;
+    }
+    tree_t *t = (tree_t *)malloc(sizeof(tree_t));
+    if (build_tree(len, t)) { free(t); return PVO_E_ARG; }
+    uint16_t code[256];
+    pivco_ref_codes(len, code);
+    /* n_v and n_right from the symbol counts */
+    for (int s = 0; s < 256; s++) {
+        if (!len[s] || !counts[s]) continue;
+        int cur = 0;
+        for (int d = 0; d < len[s]; d++) {
+            int b = (code[s] >> (len[s] - 1 - d)) & 1;
+            t->nd[cur].n += counts[s];
+            if (b) t->nd[cur].n_right += counts[s];
+            cur = t->nd[cur].child[b];
+        }
+    }
+    int I = t->ni;
+    uint8_t *bm[255];
+    uint64_t cur_pos[255];
+    for (int i = 0; i < I; i++) {
+        bm[i] = (uint8_t *)calloc((size_t)((t->nd[t->bfs[i]].n + 7) / 8 + 1), 1);
+        cur_pos[i] = 0;
+    }
+    /* bitmaps: each symbol appends one bit to every internal node on its path */
+    for (uint64_t i = 0; i < n; i++) {
+        int s = in[i], cur = 0;
+        for (int d = 0; d < len[s]; d++) {
+            int b = (code[s] >> (len[s] - 1 - d)) & 1;
+            int id = t->nd[cur].id;
+            if (b) setbit(bm[id], cur_pos[id]);
+            cur_pos[id]++;
+            cur = t->nd[cur].child[b];
+        }
+    }
+    int rc = PVO_OK;
+    uint64_t o = 12;
+    out[8] = 0; out[9] = 0;
+    if (o + 128 > cap) { rc = PVO_E_CAPACITY; goto done; }
+    for (int j = 0; j < 128; j++) out[o + j] = (uint8_t)(len[2 * j] | (len[2 * j + 1] << 4));
+    o += 128;
+    uint8_t kind[255];
+    for (int i = 0; i < I; i++) {
+        tnode *v = &t->nd[t->bfs[i]];
+        kind[i] = (uint8_t)pivco_ref_select_ans(ans_mode, v->n, v->n_right);
+    }
+    uint64_t kb = ((uint64_t)I + 7) / 8;
+    if (o + kb + (uint64_t)cw * I > cap) { rc = PVO_E_CAPACITY; goto done; }
+    memset(out + o, 0, (size_t)kb);
+    for (int i = 0; i < I; i++) if (kind[i]) out[o + i / 8] |= (uint8_t)(1u << (i % 8));
+    o += kb;
+    for (int i = 0; i < I; i++) {
+        uint64_t r = t->nd[t->bfs[i]].n_right;
+        if (cw == 2) put16(out + o, (uint32_t)r); else put32(out + o, (uint32_t)r);
+        o += cw;
+    }
+    for (int i = 0; i < I; i++) {
+        if (kind[i]) continue;
+        uint64_t nb = (t->nd[t->bfs[i]].n + 7) / 8;
+        if (o + nb > cap) { rc = PVO_E_CAPACITY; goto done; }
+        memcpy(out + o, bm[i], (size_t)nb);
+        o += nb;
+    }
+    for (int i = 0; i < I; i++) {
+        if (!kind[i]) continue;
+        tnode *v = &t->nd[t->bfs[i]];
+        while (o & 3) { if (o >= cap) { rc = PVO_E_CAPACITY; goto done; } out[o++] = 0; }
+        if (o + 8 > cap) { rc = PVO_E_CAPACITY; goto done; }
+        uint32_t p1q = pivco_ref_p1q(v->n, v->n_right);
+        uint64_t blen;
+        rc = pivco_ref_rans_encode(bm[i], v->n, p1q, chunk_log2, out + o + 8, cap - o - 8, &blen);
+        if (rc) goto done;
+        put16(out + o, p1q); put16(out + o + 2, 0); put32(out + o + 4, (uint32_t)blen);
+        o += 8 + blen;
+        *ans_words += (v->n + 31) / 32;
+    }
+    put32(out, (uint32_t)o);
+    *out_len = o;
+done:
+    for (int i = 0; i < I; i++) free(bm[i]);
+    free(t);
+    return rc;
+}
+
+int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
+                     uint32_t max_len, uint32_t ans_mode, uint32_t chunk_log2,
+                     const uint8_t *tree_len, uint8_t *out, uint64_t cap,
+                     uint64_t *out_len) {
+    if ((!in && n) || !out || !out_len || block_size == 0 || max_len < 1 || max_len > 15 ||
+        ans_mode > 2 || chunk_log2 < 5 || chunk_log2 > 24)
+        return PVO_E_ARG;
+    uint64_t nb64 = (n + block_size - 1) / block_size;
+    if (nb64 > 0xFFFFFFFFull) return PVO_E_ARG;
+    uint32_t nb = (uint32_t)nb64;
+    uint64_t o = HDR + 16 * ((uint64_t)nb + 1);
+    if (o > cap) return PVO_E_CAPACITY;
+    memset(out, 0, (size_t)o);
+    put32(out, 0x31435650u);  /* "PVC1" */
+    put16(out + 4, 1); put16(out + 6, 0);
+    put64(out + 8, n);
+    put32(out + 16, block_size); put32(out + 20, nb);
+    out[24] = (uint8_t)max_len; out[25] = (uint8_t)chunk_log2;
+    uint64_t ans_total = 0;
+    for (uint32_t b = 0; b < nb; b++) {
+        uint64_t start = (uint64_t)b * block_size;
+        uint64_t bn = n - start < block_size ? n - start : block_size;
+        put64(out + HDR + 8 * (uint64_t)b, o);
+        put64(out + HDR + 8 * ((uint64_t)nb + 1) + 8 * (uint64_t)b, ans_total);
+        uint64_t bl, aw;
+        int rc = encode_block(in + start, bn, max_len, ans_mode, chunk_log2, tree_len,
+                              out + o, cap - o, &bl, &aw);
+        if (rc) return rc;
+        o += bl;
+        while (o & 3) { if (o >= cap) return PVO_E_CAPACITY; out[o++] = 0; }
+        ans_total += aw;
+    }
+    put64(out + HDR + 8 * (uint64_t)nb, o);
+    put64(out + HDR + 8 * ((uint64_t)nb + 1) + 8 * (uint64_t)nb, ans_total);
+    put64(out + 32, ans_total);
+    *out_len = o;
+    return PVO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Stream parsing and validation (shared by both decoders)             */
+/* ------------------------------------------------------------------ */
+int pivco_ref_stream_info(const uint8_t *in, uint64_t in_len, uint64_t *n_total,
+                          uint32_t *n_blocks, uint32_t *block_size, uint64_t *ans_words) {
+    if (!in || in_len < HDR) return PVO_E_CORRUPT;
+    if (get32(in) != 0x31435650u) return PVO_E_CORRUPT;
+    if (n_total) *n_total = get64(in + 8);
+    if (block_size) *block_size = get32(in + 16);
+    if (n_blocks) *n_blocks = get32(in + 20);
+    if (ans_words) *ans_words = get64(in + 32);
+    return PVO_OK;
+}
+
+typedef struct {
+    uint32_t mode, cw, I;
+    uint8_t const_sym;
+    uint8_t len[256];
+    tree_t *t;
+    uint8_t kind[255];
+    uint8_t *bm[255];    /* raw bitmap of every internal node (decoded) */
+    uint64_t n;
+} block_t;
+
+static void free_block(block_t *bk) {
+    if (bk->t) {
+        for (uint32_t i = 0; i < bk->I; i++) free(bk->bm[i]);
+        free(bk->t);
+        bk->t = NULL;
+    }
+}
+
+/* Parse and fully validate block b; all node bitmaps decoded into bk->bm. */
+static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *bk) {
+    memset(bk, 0, sizeof(*bk));
+    if (in_len < HDR || get32(in) != 0x31435650u || get16(in + 4) != 1 || get16(in + 6) != 0)
+        return PVO_E_CORRUPT;
+    uint64_t n_total = get64(in + 8);
+    uint32_t bs = get32(in + 16), nb = get32(in + 20), max_len = in[24], cl2 = in[25];
+    if (bs == 0 || max_len < 1 || max_len > 15 || cl2 < 5 || cl2 > 24) return PVO_E_CORRUPT;
+    if ((n_total + bs - 1) / bs != nb || b >= nb) return PVO_E_CORRUPT;
+    uint64_t tab = HDR + 16 * ((uint64_t)nb + 1);
+    if (tab > in_len) return PVO_E_CORRUPT;
+    uint64_t off = get64(in + HDR + 8 * (uint64_t)b), end = get64(in + HDR + 8 * ((uint64_t)b + 1));
+    uint64_t a0 = get64(in + HDR + 8 * ((uint64_t)nb + 1) + 8 * (uint64_t)b);
+    uint64_t a1 = get64(in + HDR + 8 * ((uint64_t)nb + 1) + 8 * ((uint64_t)b + 1));
+    if (off < tab || end < off || end > in_len || (off & 3) || end - off < 12 || a1 < a0)
+        return PVO_E_CORRUPT;
+    const uint8_t *p = in + off;
+    uint64_t comp = get32(p);
+    if (comp > end - off || comp < 12) return PVO_E_CORRUPT;
+    uint64_t n = get32(p + 4);
+    uint64_t want = n_total - (uint64_t)b * bs < bs ? n_total - (uint64_t)b * bs : bs;
+    if (n != want) return PVO_E_CORRUPT;
+    bk->n = n;
+    bk->mode = p[8]; bk->const_sym = p[9]; bk->cw = p[10];
+    if (p[11] != 0 || bk->cw != (n <= 65535 ? 2u : 4u)) return PVO_E_CORRUPT;
+    if (bk->mode == 1) return (comp == 12 && a1 == a0 && n > 0) ? PVO_OK : PVO_E_CORRUPT;
+    if (bk->mode != 0 || bk->const_sym != 0) return PVO_E_CORRUPT;
+    if (comp < 12 + 128) return PVO_E_CORRUPT;
+    for (int j = 0; j < 128; j++) { bk->len[2 * j] = p[12 + j] & 15; bk->len[2 * j + 1] = p[12 + j] >> 4; }
+    for (int s = 0; s < 256; s++) if (bk->len[s] > max_len) return PVO_E_CORRUPT;
+    bk->t = (tree_t *)malloc(sizeof(tree_t));
+    if (build_tree(bk->len, bk->t)) { free(bk->t); bk->t = NULL; return PVO_E_CORRUPT; }
+    tree_t *t = bk->t;
+    uint32_t I = (uint32_t)t->ni;
+    uint64_t o = 140, kb = (I + 7) / 8;
+    if (o + kb + (uint64_t)bk->cw * I > comp) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
+    for (uint32_t i = 0; i < I; i++) bk->kind[i] = (p[o + i / 8] >> (i % 8)) & 1;
+    for (uint32_t i = I; i < kb * 8; i++)
+        if ((p[o + i / 8] >> (i % 8)) & 1) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
+    o += kb;
+    /* node sizes top-down: root sees n symbols; left child n_v - n_right */
+    t->nd[0].n = n;
+    for (uint32_t i = 0; i < I; i++) {
+        tnode *v = &t->nd[t->bfs[i]];
+        v->n_right = bk->cw == 2 ? get16(p + o) : get32(p + o);
+        o += bk->cw;
+        if (v->n_right > v->n) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
+        t->nd[v->child[0]].n = v->n - v->n_right;
+        t->nd[v->child[1]].n = v->n_right;
+    }
+    bk->I = I;
+    for (uint32_t i = 0; i < I; i++) bk->bm[i] = NULL;
+    int rc = PVO_OK;
+    uint64_t aw = 0;
+    for (uint32_t i = 0; i < I; i++) {
+        tnode *v = &t->nd[t->bfs[i]];
+        bk->bm[i] = (uint8_t *)calloc((size_t)((v->n + 7) / 8 + 1), 1);
+        if (bk->kind[i]) continue;
+        uint64_t nbytes = (v->n + 7) / 8;
+        if (o + nbytes > comp) { rc = PVO_E_CORRUPT; goto fail; }
+        memcpy(bk->bm[i], p + o, (size_t)nbytes);
+        if ((v->n & 7) && (p[o + nbytes - 1] >> (v->n & 7))) { rc = PVO_E_CORRUPT; goto fail; }
+        o += nbytes;
+    }
+    for (uint32_t i = 0; i < I; i++) {
+        if (!bk->kind[i]) continue;
+        tnode *v = &t->nd[t->bfs[i]];
+        while (o & 3) { if (o >= comp || p[o]) { rc = PVO_E_CORRUPT; goto fail; } o++; }
+        if (o + 8 > comp || v->n == 0) { rc = PVO_E_CORRUPT; goto fail; }
+        uint32_t p1q = get16(p + o), blen = get32(p + o + 4);
+        if (get16(p + o + 2) != 0 || o + 8 + blen > comp) { rc = PVO_E_CORRUPT; goto fail; }
+        if (pivco_ref_rans_decode(p + o + 8, blen, v->n, p1q, cl2, bk->bm[i])) { rc = PVO_E_CORRUPT; goto fail; }
+        o += 8 + blen;
+        aw += (v->n + 31) / 32;
+    }
+    if (o != comp || aw != a1 - a0) { rc = PVO_E_CORRUPT; goto fail; }
+    /* every node's bitmap must hold exactly n_right ones */
+    for (uint32_t i = 0; i < I; i++) {
+        tnode *v = &t->nd[t->bfs[i]];
+        uint64_t ones = 0;
+        for (uint64_t j = 0; j < v->n; j++) ones += (uint64_t)getbit(bk->bm[i], j);
+        if (ones != v->n_right) { rc = PVO_E_CORRUPT; goto fail; }
+    }
+    return PVO_OK;
+fail:
+    free_block(bk);
+    return rc;
+}
+
+static int check_stream(const uint8_t *in, uint64_t in_len, uint64_t *n_total, uint32_t *nb,
+                        uint32_t *bs) {
+    if (!in || in_len < HDR || get32(in) != 0x31435650u || get16(in + 4) != 1 || get16(in + 6) != 0)
+        return PVO_E_CORRUPT;
+    *n_total = get64(in + 8); *bs = get32(in + 16); *nb = get32(in + 20);
+    if (*bs == 0 || (*n_total + *bs - 1) / *bs != *nb) return PVO_E_CORRUPT;
+    uint64_t tab = HDR + 16 * ((uint64_t)*nb + 1);
+    if (tab > in_len) return PVO_E_CORRUPT;
+    if (get64(in + HDR + 8 * (uint64_t)*nb) > in_len) return PVO_E_CORRUPT;
+    if (get64(in + HDR + 8 * ((uint64_t)*nb + 1)) != 0) return PVO_E_CORRUPT;
+    if (get64(in + HDR + 8 * ((uint64_t)*nb + 1) + 8 * (uint64_t)*nb) != get64(in + 32)) return PVO_E_CORRUPT;
+    return PVO_OK;
+}
+
+/* Listing 1, one cursor per internal node */
+static void walk_block(const block_t *bk, uint8_t *out) {
+    if (bk->mode == 1) { memset(out, bk->const_sym, (size_t)bk->n); return; }
+    const tree_t *t = bk->t;
+    uint64_t cur[255];
+    memset(cur, 0, sizeof(cur));
+    for (uint64_t i = 0; i < bk->n; i++) {
+        int node = 0;
+        while (!t->nd[node].leaf) {
+            int id = t->nd[node].id;
+            int bit = getbit(bk->bm[id], cur[id]++);
+            node = bit ? t->nd[node].child[1] : t->nd[node].child[0];
+        }
+        out[i] = (uint8_t)t->nd[node].sym;
+    }
+}
+
+/* Sec. 3: bottom-up merge; deepest internal nodes first (reverse BFS) */
+static void merge_block(const block_t *bk, uint8_t *out) {
+    if (bk->mode == 1) { memset(out, bk->const_sym, (size_t)bk->n); return; }
+    const tree_t *t = bk->t;
+    uint8_t *seq[255];
+    for (int i = (int)bk->I - 1; i >= 0; i--) {
+        const tnode *v = &t->nd[t->bfs[i]];
+        uint8_t *o = (i == 0) ? out : (uint8_t *)malloc((size_t)v->n + 1);
+        const tnode *l = &t->nd[v->child[0]], *r = &t->nd[v->child[1]];
+        const uint8_t *ls = l->leaf ? NULL : seq[l->id];
+        const uint8_t *rs = r->leaf ? NULL : seq[r->id];
+        uint64_t nl = 0, nr = 0;
+        for (uint64_t j = 0; j < v->n; j++) {
+            if (getbit(bk->bm[i], j)) o[j] = r->leaf ? (uint8_t)r->sym : rs[nr++];
+            else o[j] = l->leaf ? (uint8_t)l->sym : ls[nl++];
+        }
+        seq[i] = o;
+        if (!l->leaf) free(seq[l->id]);
+        if (!r->leaf) free(seq[r->id]);
+    }
+}
+
+static int decode_range(const uint8_t *in, uint64_t in_len, uint32_t b0, uint32_t b1,
+                        uint8_t *out, uint64_t cap, uint64_t *n_out, int merge) {
+    uint64_t n_total; uint32_t nb, bs;
+    int rc = check_stream(in, in_len, &n_total, &nb, &bs);
+    if (rc) return rc;
+    if (b1 > nb) b1 = nb;
+    if (b0 > b1) return PVO_E_ARG;
+    uint64_t o = 0;
+    for (uint32_t b = b0; b < b1; b++) {
+        block_t bk;
+        rc = parse_block(in, in_len, b, &bk);
+        if (rc) return rc;
+        if (o + bk.n > cap) { free_block(&bk); return PVO_E_CAPACITY; }
+        if (merge) merge_block(&bk, out + o); else walk_block(&bk, out + o);
+        o += bk.n;
+        free_block(&bk);
+    }
+    if (n_out) *n_out = o;
+    return PVO_OK;
+}
+
+int pivco_ref_decode(const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t cap,
+                     uint64_t *n_out) {
+    return decode_range(in, in_len, 0, 0xFFFFFFFFu, out, cap, n_out, 0);
+}
+
+int pivco_ref_decode_merge(const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t cap,
+                           uint64_t *n_out) {
+    return decode_range(in, in_len, 0, 0xFFFFFFFFu, out, cap, n_out, 1);
+}
+
+int pivco_ref_decode_blocks(const uint8_t *in, uint64_t in_len, uint32_t b0, uint32_t b1,
+                            uint8_t *out, uint64_t cap, uint64_t *n_out) {
+    return decode_range(in, in_len, b0, b1, out, cap, n_out, 0);
+}
+
+int pivco_ref_block_info(const uint8_t *in, uint64_t in_len, uint32_t block, uint8_t len[256],
+                         uint32_t *mode, uint32_t *n_internal, uint8_t depth[255],
+                         uint64_t n_v[255], uint64_t n_right[255], uint8_t kind[255]) {
+    uint64_t n_total; uint32_t nb, bs;
+    int rc = check_stream(in, in_len, &n_total, &nb, &bs);
+    if (rc) return rc;
+    block_t bk;
+    rc = parse_block(in, in_len, block, &bk);
+    if (rc) return rc;
+    *mode = bk.mode;
+    *n_internal = bk.mode == 0 ? bk.I : 0;
+    memcpy(len, bk.len, 256);
+    for (uint32_t i = 0; i < *n_internal; i++) {
+        const tnode *v = &bk.t->nd[bk.t->bfs[i]];
+        depth[i] = (uint8_t)v->depth; n_v[i] = v->n; n_right[i] = v->n_right; kind[i] = bk.kind[i];
+    }
+    free_block(&bk);
+    return PVO_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Classical (code-after-code) streams, for the cross-checks            */
+/* ------------------------------------------------------------------ */
+int pivco_ref_classical_encode(const uint8_t *in, uint64_t n, const uint8_t len[256],
+                               uint8_t *out, uint64_t cap, uint64_t *nbits) {
+    uint16_t code[256];
+    if (pivco_ref_codes(len, code)) return PVO_E_ARG;
+    uint64_t nb = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        if (!len[in[i]]) return PVO_E_ARG;
+        nb += len[in[i]];
+    }
+    if ((nb + 7) / 8 > cap) return PVO_E_CAPACITY;
+    memset(out, 0, (size_t)((nb + 7) / 8));
+    uint64_t p = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        int s = in[i];
+        for (int d = 0; d < len[s]; d++, p++)
+            if ((code[s] >> (len[s] - 1 - d)) & 1) out[p >> 3] |= (uint8_t)(0x80u >> (p & 7));
+    }
+    *nbits = nb;
+    return PVO_OK;
+}
+
+int pivco_ref_classical_decode(const uint8_t *bits, uint64_t nbits, const uint8_t len[256],
+                               uint8_t *out, uint64_t n) {
+    tree_t *t = (tree_t *)malloc(sizeof(tree_t));
+    if (build_tree(len, t)) { free(t); return PVO_E_ARG; }
+    uint64_t p = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        int node = 0;
+        while (!t->nd[node].leaf) {                 /* Listing 1 */
+            if (p >= nbits) { free(t); return PVO_E_CORRUPT; }
+            int bit = (bits[p >> 3] >> (7 - (p & 7))) & 1;
+            p++;
+            node = bit ? t->nd[node].child[1] : t->nd[node].child[0];
+        }
+        out[i] = (uint8_t)t->nd[node].sym;
+    }
+    free(t);
+    return p == nbits ? PVO_OK : PVO_E_CORRUPT;
+}
+
+int pivco_ref_pivoted_to_classical(const uint8_t *in, uint64_t in_len, uint8_t *out,
+                                   uint64_t cap, uint64_t *nbits) {
+    uint64_t n_total; uint32_t nb, bs;
+    int rc = check_stream(in, in_len, &n_total, &nb, &bs);
+    if (rc) return rc;
+    if (nb < 1) return PVO_E_ARG;
+    block_t bk;
+    rc = parse_block(in, in_len, 0, &bk);
+    if (rc) return rc;
+    if (bk.mode != 0) { free_block(&bk); return PVO_E_UNSUPPORTED; }
+    const tree_t *t = bk.t;
+    uint64_t cur[255], p = 0;
+    memset(cur, 0, sizeof(cur));
+    memset(out, 0, (size_t)cap);
+    for (uint64_t i = 0; i < bk.n; i++) {
+        int node = 0;
+        while (!t->nd[node].leaf) {
+            int id = t->nd[node].id;
+            int bit = getbit(bk.bm[id], cur[id]++);
+            if ((p >> 3) >= cap) { free_block(&bk); return PVO_E_CAPACITY; }
+            if (bit) out[p >> 3] |= (uint8_t)(0x80u >> (p & 7));
+            p++;
+            node = t->nd[node].child[bit];
+        }
+    }
+    *nbits = p;
+    free_block(&bk);
+    return PVO_OK;
+}
