@@ -1,0 +1,173 @@
+/*
+ * pivco.h -- C ABI of the MI355X (gfx950) PivCo-Huffman codec.
+ *
+ * PivCo-Huffman (Zukowski, 2026) stores a Huffman-coded block "pivoted": every
+ * internal node of the (length-limited, canonical) code tree keeps one bitmap
+ * with one bit per symbol that passes through it, in stream order (Sec. 2,
+ * Fig. 2-3).  Decoding merges the children's dense symbol sequences bottom-up
+ * under control of each node's bitmap (Sec. 3); encoding splits the codes
+ * top-down and emits the bitmaps (Sec. 4, Table 11).  Skewed nodes may be
+ * entropy-coded instead of stored raw (Sec. 5); here with 32-lane interleaved
+ * binary rANS with 12-bit probabilities (method of ref. [4] of the paper).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HIP device memory, e.g. the
+ *     data_ptr() of a torch tensor); h_* are host pointers.  The caller owns
+ *     every buffer; the library never frees caller memory.
+ *   - Device inputs (d_in) must be 16-byte aligned.
+ *   - Work is enqueued on the given stream and is asynchronous unless the
+ *     comment says "synchronous".  Argument errors are returned at once;
+ *     errors found in the data (corrupt stream, too small output) are written
+ *     per job to d_status as a pivco_status value.
+ *   - Decoding never reads outside [d_in, d_in + in_len) and never writes
+ *     outside [d_out, d_out + out_cap), also on corrupt input.
+ *   - Functions are thread-safe; a plan object may be used by one thread at a
+ *     time.
+ *
+ * Stream format (v1, little-endian; layout written out in the library's
+ * format notes): a 48-byte stream header, a table of block offsets, a table
+ * of rANS scratch offsets, then blocks.  Each block holds its 4-bit code
+ * lengths (128 bytes, App. D), one kind bit and one count of 1 bits per
+ * internal node (breadth-first order), the raw bitmaps, then the rANS bodies.
+ */
+#ifndef PIVCO_H
+#define PIVCO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIVCO_OK = 0,
+  PIVCO_E_ARG = -1,          /* bad argument (returned synchronously) */
+  PIVCO_E_CAPACITY = -2,     /* output or workspace too small */
+  PIVCO_E_CORRUPT = -3,      /* stream fails validation */
+  PIVCO_E_UNSUPPORTED = -4,  /* valid stream outside this build's limits */
+  PIVCO_E_DEVICE = -5,       /* HIP runtime error */
+  PIVCO_E_BUDGET = -6        /* serving: request larger than the memory budget */
+} pivco_status;
+
+/* A code tree given by its 256 code lengths (0 = symbol absent).  Codes are
+ * canonical: ordered by (length, symbol), first code 0 (ref. [5]). */
+typedef struct {
+  uint8_t code_len[256];
+} pivco_tree;
+
+typedef struct {
+  uint32_t block_size;       /* symbols per block, >= 1 */
+  uint32_t max_len;          /* code length limit; 11 as in App. D (8..12) */
+  uint32_t ans_mode;         /* 0: raw bitmaps only; 1: rANS for nodes whose
+                                one-bit fraction is < 0.1 or > 0.9;
+                                2: rANS for every internal node (testing) */
+  uint32_t rans_chunk_log2;  /* bits per rANS chunk = 2^this; 16 */
+  const pivco_tree *tree;    /* NULL: one optimal tree per block from its
+                                histogram; else this tree for every block */
+} pivco_encode_opts;
+
+/* One decode job: a whole stream. */
+typedef struct {
+  const void *d_in;          /* stream, 16-byte aligned */
+  uint64_t in_len;           /* bytes readable at d_in */
+  void *d_out;               /* decoded bytes */
+  uint64_t out_cap;          /* bytes writable at d_out */
+} pivco_job;
+
+/* ---------------------------------------------------------------------- */
+/* Tree construction (host, synchronous)                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Optimal code lengths limited to max_len bits for the given symbol counts
+ * (App. D fixes the limit at 11 bits).  Package-merge, then the ascending
+ * lengths are assigned to symbols ordered by (count desc, symbol asc).
+ * E_ARG if fewer than two symbols have a nonzero count or max_len is out of
+ * [1, 15] or too small for the alphabet. */
+pivco_status pivco_build_tree(const uint64_t counts[256], uint32_t max_len, pivco_tree *out);
+
+/* ---------------------------------------------------------------------- */
+/* Encode (Sec. 4)                                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Upper bound on the stream size for n input bytes. */
+uint64_t pivco_encode_bound(uint64_t n, const pivco_encode_opts *o);
+
+/* Device workspace bytes pivco_encode needs for n input bytes. */
+uint64_t pivco_encode_workspace(uint64_t n, const pivco_encode_opts *o);
+
+/* Encode n bytes at d_in into a v1 stream at d_out.  Synchronous: it waits
+ * for the block histograms (the host builds the trees) and for the rANS
+ * body sizes, and returns the stream length in *h_out_len.  The stream is
+ * byte-identical to the one the format definition implies.  Errors:
+ * E_ARG (bad options or a supplied tree that misses a symbol present in the
+ * data), E_CAPACITY (out_cap or ws_bytes too small), E_DEVICE. */
+pivco_status pivco_encode(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                          uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
+                          uint64_t ws_bytes, hipStream_t s);
+
+/* ---------------------------------------------------------------------- */
+/* Decode (Sec. 3, bottom-up merge)                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Header fields of a stream from a host copy of its first 48 bytes. */
+pivco_status pivco_stream_info(const void *h_hdr, uint64_t hdr_len, uint64_t *n_total,
+                               uint32_t *n_blocks, uint32_t *block_size, uint64_t *ans_words);
+
+/* Device workspace bytes needed to decode these jobs.  Synchronous: reads
+ * the stream headers from device memory.  Returns 0 on an argument error. */
+uint64_t pivco_decode_workspace(const pivco_job *h_jobs, uint32_t count, hipStream_t s);
+
+/* Decode every job in one batched launch: a persistent kernel takes blocks
+ * from an atomic queue ordered by decreasing block size.  Synchronous up to
+ * the point where kernels are enqueued (it reads the stream headers); the
+ * decode itself runs asynchronously on s.  d_status[count] receives one
+ * pivco_status per job. */
+pivco_status pivco_decode_batch(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                void *d_ws, uint64_t ws_bytes, hipStream_t s);
+
+/* One job; same as pivco_decode_batch with count = 1. */
+pivco_status pivco_decode(const void *d_in, uint64_t in_len, void *d_out, uint64_t out_cap,
+                          int32_t *d_status, void *d_ws, uint64_t ws_bytes, hipStream_t s);
+
+/* Baseline for comparison: the same kernel launched once per block, one
+ * launch after the other on s (no persistent queue, no graph). */
+pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                void *d_ws, uint64_t ws_bytes, hipStream_t s);
+
+/* Launch configuration of the batched decode, chosen by pivco_autotune. */
+typedef struct {
+  uint32_t merge_variant;    /* index into the compiled merge kernels */
+  uint32_t merge_grid;       /* workgroups of the persistent merge kernel */
+  uint32_t rans_grid;        /* workgroups of the rANS decode kernel */
+  uint32_t reserved;
+} pivco_tune;
+
+/* Number of compiled merge-kernel variants and a short description of one. */
+uint32_t pivco_merge_variants(void);
+const char *pivco_merge_variant_name(uint32_t v);
+
+/* A prepared batch: job table and work queue uploaded once, the decode
+ * captured in a HIP graph; each launch replays the graph.  Creation is
+ * synchronous.  tune may be NULL (default configuration). */
+typedef struct pivco_batch_plan pivco_batch_plan;
+pivco_status pivco_batch_plan_create(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                     void *d_ws, uint64_t ws_bytes, const pivco_tune *tune,
+                                     hipStream_t s, pivco_batch_plan **out);
+pivco_status pivco_batch_plan_launch(pivco_batch_plan *p, hipStream_t s);
+/* Record hEvents around the merge kernel only (no graph) for timing. */
+pivco_status pivco_batch_plan_launch_timed(pivco_batch_plan *p, hipStream_t s,
+                                           hipEvent_t merge_begin, hipEvent_t merge_end);
+void pivco_batch_plan_destroy(pivco_batch_plan *p);
+
+/* Time every merge variant and a few grid sizes on these jobs and return the
+ * fastest configuration (synchronous; decodes the jobs several times). */
+pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                            void *d_ws, uint64_t ws_bytes, hipStream_t s, pivco_tune *out);
+
+const char *pivco_strerror(pivco_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,501 @@
+// api.cpp -- C ABI of the PivCo-Huffman library: argument checks, host-side
+// planning of batched decodes (stream headers -> job table and a work queue
+// ordered by decreasing block size), HIP-graph plans, the autotuner, and the
+// encode driver.
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "pivco_int.h"
+
+namespace pivco {
+// decode.hip
+uint32_t merge_variant_count();
+const char *merge_variant_name(uint32_t v);
+int merge_variant_occupancy(uint32_t v);
+hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
+                        const uint2 *items, uint32_t n_items, Counters *ctr,
+                        const uint32_t *scratch, uint64_t scratch_words, int32_t single);
+hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
+                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single);
+int rans_occupancy();
+hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
+                       uint32_t count);
+hipError_t launch_gather_headers(hipStream_t s, const pivco_job *jobs, uint32_t count, uint8_t *hdr);
+// tree.cpp
+pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]);
+// encode.hip
+pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                           uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
+                           uint64_t ws_bytes, hipStream_t s);
+uint64_t encode_bound(uint64_t n, const pivco_encode_opts *o);
+uint64_t encode_workspace(uint64_t n, const pivco_encode_opts *o);
+}  // namespace pivco
+
+using namespace pivco;
+
+namespace {
+
+inline uint64_t rd64(const uint8_t *p) {
+  uint64_t v;
+  std::memcpy(&v, p, 8);
+  return v;
+}
+inline uint32_t rd32(const uint8_t *p) {
+  uint32_t v;
+  std::memcpy(&v, p, 4);
+  return v;
+}
+inline uint16_t rd16(const uint8_t *p) {
+  uint16_t v;
+  std::memcpy(&v, p, 2);
+  return v;
+}
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+int device_cus() {
+  static int cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (cus <= 0) cus = 256;
+  });
+  return cus;
+}
+
+struct StreamHdr {
+  uint64_t n_total = 0, ans_words = 0;
+  uint32_t block_size = 0, n_blocks = 0, max_len = 0, chunk_log2 = 0;
+};
+
+// Parses the 48-byte stream header; returns PIVCO_OK or PIVCO_E_CORRUPT.
+pivco_status parse_stream_header(const uint8_t *h, uint64_t avail, StreamHdr *o) {
+  if (avail < kHeaderBytes) return PIVCO_E_CORRUPT;
+  if (rd32(h) != kMagic || rd16(h + 4) != 1 || rd16(h + 6) != 0) return PIVCO_E_CORRUPT;
+  o->n_total = rd64(h + 8);
+  o->block_size = rd32(h + 16);
+  o->n_blocks = rd32(h + 20);
+  o->max_len = h[24];
+  o->chunk_log2 = h[25];
+  o->ans_words = rd64(h + 32);
+  if (o->block_size == 0 || o->max_len < 1 || o->max_len > 15 || o->chunk_log2 < 5 ||
+      o->chunk_log2 > 24)
+    return PIVCO_E_CORRUPT;
+  if (div_up(o->n_total, o->block_size) != o->n_blocks) return PIVCO_E_CORRUPT;
+  return PIVCO_OK;
+}
+
+// Everything the device needs for one batched decode.
+struct HostPlan {
+  uint32_t count = 0;
+  std::vector<JobDev> jobs;
+  std::vector<uint2> items;    // (job, block), largest blocks first
+  std::vector<uint2> ritems;   // blocks of jobs that contain rANS nodes
+  std::vector<int32_t> status0;
+  uint64_t scratch_words = 0;
+  // workspace layout (byte offsets)
+  uint64_t off_ctr = 0, off_jobs = 0, off_items = 0, off_ritems = 0, off_status0 = 0,
+           off_scratch = 0, total = 0;
+};
+
+void layout(HostPlan &p) {
+  uint64_t o = 0;
+  p.off_ctr = o; o += 256;
+  p.off_jobs = o; o = align_up(o + sizeof(JobDev) * p.count, 256);
+  p.off_items = o; o = align_up(o + 8 * p.items.size(), 256);
+  p.off_ritems = o; o = align_up(o + 8 * p.ritems.size(), 256);
+  p.off_status0 = o; o = align_up(o + 4ull * p.count, 256);
+  p.off_scratch = o; o = align_up(o + 4 * p.scratch_words + 64, 256);
+  // header gathering reuses the start of the workspace before the upload
+  const uint64_t gather = align_up(sizeof(pivco_job) * p.count, 256) + kHeaderBytes * p.count;
+  p.total = std::max(o, gather);
+}
+
+pivco_status read_headers(const pivco_job *h_jobs, uint32_t count, void *d_ws, uint64_t ws_bytes,
+                          hipStream_t s, std::vector<uint8_t> &hdr) {
+  hdr.assign(static_cast<size_t>(count) * kHeaderBytes, 0);
+  if (count == 0) return PIVCO_OK;
+  const uint64_t jb = align_up(sizeof(pivco_job) * count, 256);
+  if (d_ws && ws_bytes >= jb + kHeaderBytes * count) {
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    if (hipMemcpyAsync(ws, h_jobs, sizeof(pivco_job) * count, hipMemcpyHostToDevice, s) != hipSuccess)
+      return PIVCO_E_DEVICE;
+    if (launch_gather_headers(s, reinterpret_cast<const pivco_job *>(ws), count, ws + jb) != hipSuccess)
+      return PIVCO_E_DEVICE;
+    if (hipMemcpyAsync(hdr.data(), ws + jb, kHeaderBytes * count, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return PIVCO_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return PIVCO_E_DEVICE;
+    return PIVCO_OK;
+  }
+  for (uint32_t j = 0; j < count; ++j) {
+    const uint64_t nbytes = std::min<uint64_t>(kHeaderBytes, h_jobs[j].in_len);
+    if (nbytes && h_jobs[j].d_in &&
+        hipMemcpy(&hdr[static_cast<size_t>(j) * kHeaderBytes], h_jobs[j].d_in, nbytes,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return PIVCO_E_DEVICE;
+  }
+  return PIVCO_OK;
+}
+
+pivco_status check_jobs(const pivco_job *h_jobs, uint32_t count) {
+  if (count && !h_jobs) return PIVCO_E_ARG;
+  for (uint32_t j = 0; j < count; ++j) {
+    if (h_jobs[j].in_len && (!h_jobs[j].d_in || (reinterpret_cast<uintptr_t>(h_jobs[j].d_in) & 15)))
+      return PIVCO_E_ARG;
+    if (h_jobs[j].out_cap && !h_jobs[j].d_out) return PIVCO_E_ARG;
+  }
+  return PIVCO_OK;
+}
+
+pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vector<uint8_t> &hdr,
+                        int32_t *d_status, HostPlan &p) {
+  p.count = count;
+  p.jobs.assign(count, JobDev{});
+  p.status0.assign(count, PIVCO_OK);
+  p.items.clear();
+  p.ritems.clear();
+  uint64_t sw = 0;
+  std::vector<std::pair<uint64_t, uint2>> sized;
+  for (uint32_t j = 0; j < count; ++j) {
+    const pivco_job &jb = h_jobs[j];
+    StreamHdr sh;
+    pivco_status st = parse_stream_header(&hdr[static_cast<size_t>(j) * kHeaderBytes],
+                                          std::min<uint64_t>(jb.in_len, kHeaderBytes), &sh);
+    if (st == PIVCO_OK && jb.in_len < kHeaderBytes + 16ull * (sh.n_blocks + 1ull)) st = PIVCO_E_CORRUPT;
+    if (st == PIVCO_OK && sh.n_total > jb.out_cap) st = PIVCO_E_CAPACITY;
+    JobDev &d = p.jobs[j];
+    d.in = static_cast<const uint8_t *>(jb.d_in);
+    d.in_len = jb.in_len;
+    d.out = static_cast<uint8_t *>(jb.d_out);
+    d.out_cap = jb.out_cap;
+    d.status = d_status + j;
+    p.status0[j] = st;
+    if (st != PIVCO_OK) continue;
+    d.n_total = sh.n_total;
+    d.n_blocks = sh.n_blocks;
+    d.block_size = sh.block_size;
+    d.max_len = sh.max_len;
+    d.chunk_log2 = sh.chunk_log2;
+    d.scratch_base = sw;
+    sw = align_up(sw + sh.ans_words, 4);
+    for (uint32_t b = 0; b < sh.n_blocks; ++b) {
+      const uint64_t start = static_cast<uint64_t>(b) * sh.block_size;
+      const uint64_t sz = std::min<uint64_t>(sh.block_size, sh.n_total - start);
+      sized.push_back({sz, make_uint2(j, b)});
+      if (sh.ans_words) p.ritems.push_back(make_uint2(j, b));
+    }
+  }
+  std::stable_sort(sized.begin(), sized.end(),
+                   [](const std::pair<uint64_t, uint2> &a, const std::pair<uint64_t, uint2> &b) {
+                     return a.first > b.first;
+                   });
+  p.items.reserve(sized.size());
+  for (auto &x : sized) p.items.push_back(x.second);
+  if (p.items.size() > 0xFFFFFFF0ull) return PIVCO_E_UNSUPPORTED;
+  p.scratch_words = sw;
+  layout(p);
+  return PIVCO_OK;
+}
+
+pivco_status upload_plan(const HostPlan &p, void *d_ws, hipStream_t s) {
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  auto cp = [&](uint64_t off, const void *src, uint64_t n) {
+    return n == 0 || hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  if (!cp(p.off_jobs, p.jobs.data(), sizeof(JobDev) * p.count) ||
+      !cp(p.off_items, p.items.data(), 8 * p.items.size()) ||
+      !cp(p.off_ritems, p.ritems.data(), 8 * p.ritems.size()) ||
+      !cp(p.off_status0, p.status0.data(), 4ull * p.count))
+    return PIVCO_E_DEVICE;
+  return PIVCO_OK;
+}
+
+struct Dev {
+  Counters *ctr;
+  const JobDev *jobs;
+  const uint2 *items, *ritems;
+  const int32_t *status0;
+  uint32_t *scratch;
+};
+
+Dev dev_ptrs(const HostPlan &p, void *d_ws) {
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  Dev d;
+  d.ctr = reinterpret_cast<Counters *>(ws + p.off_ctr);
+  d.jobs = reinterpret_cast<const JobDev *>(ws + p.off_jobs);
+  d.items = reinterpret_cast<const uint2 *>(ws + p.off_items);
+  d.ritems = reinterpret_cast<const uint2 *>(ws + p.off_ritems);
+  d.status0 = reinterpret_cast<const int32_t *>(ws + p.off_status0);
+  d.scratch = reinterpret_cast<uint32_t *>(ws + p.off_scratch);
+  return d;
+}
+
+pivco_tune default_tune(uint32_t n_items, uint32_t n_ritems) {
+  pivco_tune t{};
+  t.merge_variant = 0;
+  const uint32_t g = static_cast<uint32_t>(device_cus() * merge_variant_occupancy(0));
+  t.merge_grid = std::max<uint32_t>(1, std::min<uint32_t>(g, n_items ? n_items : 1));
+  const uint32_t rg = static_cast<uint32_t>(device_cus() * rans_occupancy());
+  t.rans_grid = std::max<uint32_t>(1, std::min<uint32_t>(rg, n_ritems ? n_ritems : 1));
+  return t;
+}
+
+// Enqueue one batched decode (kernels only; capturable).
+pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, const pivco_tune &t,
+                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  Dev d = dev_ptrs(p, d_ws);
+  if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
+  if (!p.ritems.empty() &&
+      launch_rans(t.rans_grid, s, d.jobs, d.ritems, static_cast<uint32_t>(p.ritems.size()), d.ctr,
+                  d.scratch, -1) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PIVCO_E_DEVICE;
+  if (!p.items.empty() &&
+      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.items,
+                   static_cast<uint32_t>(p.items.size()), d.ctr, d.scratch, p.scratch_words,
+                   -1) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return PIVCO_E_DEVICE;
+  return PIVCO_OK;
+}
+
+pivco_status prepare(const pivco_job *h_jobs, uint32_t count, int32_t *d_status, void *d_ws,
+                     uint64_t ws_bytes, hipStream_t s, HostPlan &p) {
+  pivco_status st = check_jobs(h_jobs, count);
+  if (st) return st;
+  if (count && (!d_status || !d_ws)) return PIVCO_E_ARG;
+  std::vector<uint8_t> hdr;
+  st = read_headers(h_jobs, count, d_ws, ws_bytes, s, hdr);
+  if (st) return st;
+  st = build_plan(h_jobs, count, hdr, d_status, p);
+  if (st) return st;
+  if (p.total > ws_bytes) return PIVCO_E_CAPACITY;
+  return upload_plan(p, d_ws, s);
+}
+
+}  // namespace
+
+struct pivco_batch_plan {
+  HostPlan plan;
+  void *ws = nullptr;
+  int32_t *status = nullptr;
+  pivco_tune tune{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+const char *pivco_strerror(pivco_status st) {
+  switch (st) {
+    case PIVCO_OK: return "ok";
+    case PIVCO_E_ARG: return "invalid argument";
+    case PIVCO_E_CAPACITY: return "output or workspace too small";
+    case PIVCO_E_CORRUPT: return "corrupt stream";
+    case PIVCO_E_UNSUPPORTED: return "stream outside this build's limits";
+    case PIVCO_E_DEVICE: return "HIP runtime error";
+    case PIVCO_E_BUDGET: return "request exceeds the memory budget";
+  }
+  return "unknown status";
+}
+
+pivco_status pivco_build_tree(const uint64_t counts[256], uint32_t max_len, pivco_tree *out) {
+  if (!counts || !out) return PIVCO_E_ARG;
+  return lengths_from_counts(counts, max_len, out->code_len);
+}
+
+pivco_status pivco_stream_info(const void *h_hdr, uint64_t hdr_len, uint64_t *n_total,
+                               uint32_t *n_blocks, uint32_t *block_size, uint64_t *ans_words) {
+  if (!h_hdr) return PIVCO_E_ARG;
+  StreamHdr sh;
+  const pivco_status st = parse_stream_header(static_cast<const uint8_t *>(h_hdr), hdr_len, &sh);
+  if (st) return st;
+  if (n_total) *n_total = sh.n_total;
+  if (n_blocks) *n_blocks = sh.n_blocks;
+  if (block_size) *block_size = sh.block_size;
+  if (ans_words) *ans_words = sh.ans_words;
+  return PIVCO_OK;
+}
+
+uint64_t pivco_decode_workspace(const pivco_job *h_jobs, uint32_t count, hipStream_t s) {
+  if (check_jobs(h_jobs, count)) return 0;
+  std::vector<uint8_t> hdr;
+  if (read_headers(h_jobs, count, nullptr, 0, s, hdr)) return 0;
+  HostPlan p;
+  if (build_plan(h_jobs, count, hdr, nullptr, p)) return 0;
+  return p.total;
+}
+
+pivco_status pivco_decode_batch(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                void *d_ws, uint64_t ws_bytes, hipStream_t s) {
+  HostPlan p;
+  pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
+  if (st) return st;
+  if (count == 0) return PIVCO_OK;
+  const pivco_tune t = default_tune(static_cast<uint32_t>(p.items.size()),
+                                    static_cast<uint32_t>(p.ritems.size()));
+  return enqueue_batch(p, d_ws, d_status, t, s, nullptr, nullptr);
+}
+
+pivco_status pivco_decode(const void *d_in, uint64_t in_len, void *d_out, uint64_t out_cap,
+                          int32_t *d_status, void *d_ws, uint64_t ws_bytes, hipStream_t s) {
+  pivco_job j{d_in, in_len, d_out, out_cap};
+  return pivco_decode_batch(&j, 1, d_status, d_ws, ws_bytes, s);
+}
+
+pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                void *d_ws, uint64_t ws_bytes, hipStream_t s) {
+  HostPlan p;
+  pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
+  if (st) return st;
+  if (count == 0) return PIVCO_OK;
+  Dev d = dev_ptrs(p, d_ws);
+  if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
+  // one launch per block, in stream order: rANS first when the job has any
+  std::vector<uint32_t> idx(p.items.size());
+  for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    return p.items[a].x != p.items[b].x ? p.items[a].x < p.items[b].x : p.items[a].y < p.items[b].y;
+  });
+  size_t r = 0;
+  for (uint32_t i : idx) {
+    const uint2 it = p.items[i];
+    while (r < p.ritems.size() &&
+           (p.ritems[r].x < it.x || (p.ritems[r].x == it.x && p.ritems[r].y < it.y)))
+      ++r;
+    if (r < p.ritems.size() && p.ritems[r].x == it.x && p.ritems[r].y == it.y) {
+      if (launch_rans(1, s, d.jobs, d.ritems, static_cast<uint32_t>(p.ritems.size()), d.ctr,
+                      d.scratch, static_cast<int32_t>(r)) != hipSuccess)
+        return PIVCO_E_DEVICE;
+    }
+    if (launch_merge(0, 1, s, d.jobs, d.items, static_cast<uint32_t>(p.items.size()), d.ctr,
+                     d.scratch, p.scratch_words, static_cast<int32_t>(i)) != hipSuccess)
+      return PIVCO_E_DEVICE;
+  }
+  return PIVCO_OK;
+}
+
+uint32_t pivco_merge_variants(void) { return merge_variant_count(); }
+const char *pivco_merge_variant_name(uint32_t v) { return merge_variant_name(v); }
+
+pivco_status pivco_batch_plan_create(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                     void *d_ws, uint64_t ws_bytes, const pivco_tune *tune,
+                                     hipStream_t s, pivco_batch_plan **out) {
+  if (!out) return PIVCO_E_ARG;
+  *out = nullptr;
+  pivco_batch_plan *bp = new pivco_batch_plan();
+  pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, bp->plan);
+  if (st) { delete bp; return st; }
+  bp->ws = d_ws;
+  bp->status = d_status;
+  bp->tune = tune ? *tune : default_tune(static_cast<uint32_t>(bp->plan.items.size()),
+                                         static_cast<uint32_t>(bp->plan.ritems.size()));
+  if (bp->tune.merge_variant >= merge_variant_count() || bp->tune.merge_grid == 0 ||
+      bp->tune.rans_grid == 0) {
+    delete bp;
+    return PIVCO_E_ARG;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) { delete bp; return PIVCO_E_DEVICE; }
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete bp; return PIVCO_E_DEVICE; }
+  st = PIVCO_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = PIVCO_E_DEVICE;
+  if (!st) {
+    const pivco_status e = enqueue_batch(bp->plan, d_ws, d_status, bp->tune, cs, nullptr, nullptr);
+    const hipError_t ce = hipStreamEndCapture(cs, &bp->graph);
+    if (e) st = e;
+    else if (ce != hipSuccess) st = PIVCO_E_DEVICE;
+  }
+  if (!st && hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = PIVCO_E_DEVICE;
+  (void)hipStreamDestroy(cs);
+  if (st) {
+    pivco_batch_plan_destroy(bp);
+    return st;
+  }
+  *out = bp;
+  return PIVCO_OK;
+}
+
+pivco_status pivco_batch_plan_launch(pivco_batch_plan *p, hipStream_t s) {
+  if (!p || !p->exec) return PIVCO_E_ARG;
+  return hipGraphLaunch(p->exec, s) == hipSuccess ? PIVCO_OK : PIVCO_E_DEVICE;
+}
+
+pivco_status pivco_batch_plan_launch_timed(pivco_batch_plan *p, hipStream_t s,
+                                           hipEvent_t merge_begin, hipEvent_t merge_end) {
+  if (!p) return PIVCO_E_ARG;
+  return enqueue_batch(p->plan, p->ws, p->status, p->tune, s, merge_begin, merge_end);
+}
+
+void pivco_batch_plan_destroy(pivco_batch_plan *p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  delete p;
+}
+
+pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                            void *d_ws, uint64_t ws_bytes, hipStream_t s, pivco_tune *out) {
+  if (!out) return PIVCO_E_ARG;
+  HostPlan p;
+  pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
+  if (st) return st;
+  pivco_tune best = default_tune(static_cast<uint32_t>(p.items.size()),
+                                 static_cast<uint32_t>(p.ritems.size()));
+  if (p.items.empty()) { *out = best; return PIVCO_OK; }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PIVCO_E_DEVICE;
+  float best_ms = 1e30f;
+  const int cus = device_cus();
+  for (uint32_t v = 0; v < merge_variant_count(); ++v) {
+    const uint32_t occ = static_cast<uint32_t>(merge_variant_occupancy(v));
+    for (uint32_t frac : {4u, 3u, 2u}) {
+      pivco_tune t = best;
+      t.merge_variant = v;
+      t.merge_grid = std::max<uint32_t>(1, std::min<uint32_t>(cus * occ * frac / 4,
+                                                              static_cast<uint32_t>(p.items.size())));
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        if (hipEventRecord(e0, s) != hipSuccess) return PIVCO_E_DEVICE;
+        st = enqueue_batch(p, d_ws, d_status, t, s, nullptr, nullptr);
+        if (st) return st;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+          return PIVCO_E_DEVICE;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms_min = std::min(ms_min, ms);
+      }
+      if (ms_min < best_ms) {
+        best_ms = ms_min;
+        best = t;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *out = best;
+  return PIVCO_OK;
+}
+
+uint64_t pivco_encode_bound(uint64_t n, const pivco_encode_opts *o) {
+  return o ? encode_bound(n, o) : 0;
+}
+
+uint64_t pivco_encode_workspace(uint64_t n, const pivco_encode_opts *o) {
+  return o ? encode_workspace(n, o) : 0;
+}
+
+pivco_status pivco_encode(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                          uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
+                          uint64_t ws_bytes, hipStream_t s) {
+  return encode_stream(d_in, n, d_out, out_cap, h_out_len, o, d_ws, ws_bytes, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,839 @@
+// decode.hip -- gfx950 kernels for PivCo-Huffman decoding.
+//
+// Decoding follows the bottom-up scheme of the paper (Sec. 3): every internal
+// node of the code tree produces the dense symbol sequence of its subtree by
+// merging its two children's sequences under control of its bitmap
+// (out[j] = bit_j ? right[#ones before j] : left[#zeros before j]); a leaf
+// child contributes a constant.  The root's sequence is the block's output.
+//
+// GPU mapping (one workgroup per block, persistent over a work queue):
+//   1. parse the block header: code lengths -> canonical code tree (the
+//      internal nodes of a canonical tree at depth d are exactly the prefixes
+//      [fc(d) + cnt(d), 2^d)), per-node symbol counts from the stored counts
+//      of 1 bits, body offsets;
+//   2. copy every node bitmap of the block into LDS with 16-byte loads
+//      (entropy-coded nodes come from the scratch the rANS kernel wrote);
+//   3. for each tile of T output symbols:
+//      count phase, top-down by level: each node's share of the tile is
+//        popcounted from its bitmap; the tile's bits are staged dword-aligned
+//        together with a running popcount per 32-bit word (a rank directory);
+//      merge phase, bottom-up by level: a lane makes 4 output bytes from 4
+//        bitmap bits, their rank (directory + popcount), two unaligned 4-byte
+//        LDS windows of the children's sequences and one v_perm_b32 whose
+//        selector comes from a 16-entry table indexed by the 4 bits; the
+//        root level stores straight to global memory.
+// A second kernel decodes the rANS-coded node bitmaps: 32 interleaved lanes
+// per chunk, renormalisation words addressed with ballot + mbcnt.
+#include <hip/hip_runtime.h>
+
+#include "pivco_int.h"
+
+namespace pivco {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void set_err(int32_t *status, int32_t e) {
+  atomicCAS(reinterpret_cast<int *>(status), 0, e);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// 32 bits starting at bit position `bit` of a dword array (bits LSB-first).
+__device__ __forceinline__ uint32_t bits32_lds(const uint32_t *w, uint32_t bit) {
+  const uint32_t q = bit >> 5;
+  return __builtin_amdgcn_alignbit(w[q + 1], w[q], bit & 31);
+}
+
+// Same from global memory with the dword index bounded by `lim`.
+__device__ __forceinline__ uint32_t bits32_glb(const uint32_t *w, uint64_t bit, uint64_t lim) {
+  const uint64_t q = bit >> 5;
+  const uint32_t lo = q < lim ? w[q] : 0u;
+  const uint32_t hi = q + 1 < lim ? w[q + 1] : 0u;
+  return __builtin_amdgcn_alignbit(hi, lo, static_cast<uint32_t>(bit & 31));
+}
+
+// Unaligned 4-byte window at byte address a of an LDS dword array.
+__device__ __forceinline__ uint32_t win4(const uint32_t *buf, uint32_t a) {
+  const uint32_t q = a >> 2;
+  return __builtin_amdgcn_alignbyte(buf[q + 1], buf[q], a);
+}
+
+__device__ __forceinline__ uint32_t load_u8(const uint8_t *p, uint64_t off, uint64_t len) {
+  return off < len ? p[off] : 0u;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, kWave);
+    if (static_cast<int>(lane_id()) >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint64_t t = __shfl_up(v, d, kWave);
+    if (static_cast<int>(lane_id()) >= d) v += t;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Block header state shared by the rANS and merge kernels
+// ---------------------------------------------------------------------------
+struct BlockHdr {
+  uint64_t blk;        // byte offset of the block in the stream
+  uint64_t out_off;    // first output byte of the block
+  uint64_t ans_word0;  // absolute scratch word of the block's first rANS node
+  uint32_t comp, n, mode, csym, cw, I, maxlen, kb;
+  uint32_t raw_base, raw_end, ans_words, n_ans;
+  int32_t err;
+  uint32_t kraft;
+  uint32_t cnt[17], fc[18], lbase[17], lvl[18];
+  uint64_t lvl_total[17];  // symbols passing each level (sum of n_v)
+};
+
+// Per-node tables (breadth-first node ids).
+struct NodeTab {
+  uint32_t nv[256];        // symbols passing the node
+  uint32_t nr[256];        // of which go right (1 bits)
+  uint32_t boff[256];      // raw: byte offset of the body in the block;
+                           // rANS: word offset in the block's scratch
+  uint16_t child[256][2];  // internal id, or 0x8000 | symbol for a leaf
+  uint8_t kind[256];       // 1 = rANS-coded
+  uint8_t depth[256];
+  uint8_t len[256];
+  uint8_t leafsym[256];    // symbols ordered by (length, symbol)
+  uint32_t wcnt[4][16];    // per-wave per-length counts
+  uint64_t scan_tot[16];
+};
+
+// Parse and validate the header of block b of job J; every thread of the
+// workgroup must call it.  On return h.err != 0 or h.mode == 1 means the
+// node tables are not filled.
+template <int NT>
+__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t) {
+  static_assert(NT >= 256, "header parse needs 256 threads");
+  const int tid = threadIdx.x;
+  const uint8_t *in = J.in;
+  if (tid == 0) {
+    int32_t err = 0;
+    const uint64_t nb = J.n_blocks;
+    const uint64_t *tab = reinterpret_cast<const uint64_t *>(in + kHeaderBytes);
+    const uint64_t tab_end = kHeaderBytes + 16 * (nb + 1);
+    const uint64_t off = tab[b], end = tab[b + 1];
+    const uint64_t a0 = tab[nb + 1 + b], a1 = tab[nb + 2 + b];
+    uint32_t comp = 0, n = 0, mode = 0, csym = 0, cw = 0;
+    if (off < tab_end || end < off || end > J.in_len || (off & 3) || end - off < kBlockFixed ||
+        a1 < a0 || a1 - a0 > 0xFFFFFFFFull) {
+      err = PIVCO_E_CORRUPT;
+    } else {
+      const uint32_t *bp = reinterpret_cast<const uint32_t *>(in + off);
+      comp = bp[0];
+      n = bp[1];
+      const uint32_t w2 = bp[2];
+      mode = w2 & 255;
+      csym = (w2 >> 8) & 255;
+      cw = (w2 >> 16) & 255;
+      const uint64_t start = static_cast<uint64_t>(b) * J.block_size;
+      const uint64_t want = J.n_total - start < J.block_size ? J.n_total - start : J.block_size;
+      if (comp > end - off || comp < kBlockFixed || n != want || (w2 >> 24) != 0 ||
+          cw != (n <= 65535 ? 2u : 4u))
+        err = PIVCO_E_CORRUPT;
+      else if (mode == 1) {
+        if (comp != kBlockFixed || a1 != a0 || n == 0) err = PIVCO_E_CORRUPT;
+      } else if (mode != 0 || csym != 0 || comp < kBlockFixed + kLenTable) {
+        err = PIVCO_E_CORRUPT;
+      }
+    }
+    h.blk = off;
+    h.out_off = static_cast<uint64_t>(b) * J.block_size;
+    h.ans_word0 = J.scratch_base + a0;
+    h.ans_words = static_cast<uint32_t>(a1 - a0);
+    h.comp = comp; h.n = n; h.mode = mode; h.csym = csym; h.cw = cw;
+    h.err = err;
+    h.kraft = 0;
+  }
+  if (tid < 17) h.cnt[tid] = 0;
+  __syncthreads();
+  if (h.err || h.mode == 1) return;
+  const uint64_t blk = h.blk;
+  if (tid < 128) {
+    const uint32_t v = in[blk + kBlockFixed + tid];
+    t.len[2 * tid] = v & 15;
+    t.len[2 * tid + 1] = v >> 4;
+  }
+  __syncthreads();
+  // lengths -> counts per length, ranks within a length (canonical order)
+  uint32_t myrank = 0, l = 0;
+  if (tid < 256) {
+    l = t.len[tid];
+    if (l > J.max_len) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+    if (l) atomicAdd(&h.kraft, 1u << (15 - l));
+    const int w = tid >> 6, lane = tid & 63;
+    for (uint32_t L = 1; L <= 15; ++L) {
+      const uint64_t m = __ballot(l == L);
+      if (l == L) myrank = __popcll(m & ((1ull << lane) - 1));
+      if (lane == static_cast<int>(L)) t.wcnt[w][L] = __popcll(m);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t m = 0, maxlen = 0;
+    for (uint32_t L = 1; L <= 15; ++L) {
+      h.cnt[L] = t.wcnt[0][L] + t.wcnt[1][L] + t.wcnt[2][L] + t.wcnt[3][L];
+      m += h.cnt[L];
+      if (h.cnt[L]) maxlen = L;
+    }
+    if (h.err == 0) {
+      if (m < 2 || h.kraft != (1u << 15)) h.err = PIVCO_E_CORRUPT;
+      else if (maxlen > kMaxLenGpu) h.err = PIVCO_E_UNSUPPORTED;
+    }
+    h.lbase[1] = 0;
+    for (uint32_t L = 1; L < 16; ++L) h.lbase[L + 1] = h.lbase[L] + h.cnt[L];
+    h.cnt[0] = 0;
+    h.fc[0] = 0;
+    h.lvl[0] = 0;
+    for (uint32_t d = 0; d <= 15; ++d) {
+      h.fc[d + 1] = 2 * (h.fc[d] + h.cnt[d]);
+      const uint32_t Id = d < maxlen ? (1u << d) - h.fc[d] - h.cnt[d] : 0u;
+      h.lvl[d + 1] = h.lvl[d] + Id;
+    }
+    const uint32_t I = m >= 2 ? m - 1 : 0;
+    if (!h.err && h.lvl[maxlen < 16 ? maxlen : 15] != I) h.err = PIVCO_E_CORRUPT;
+    h.I = I;
+    h.maxlen = maxlen;
+    h.kb = (I + 7) / 8;
+    const uint64_t need = kBlockFixed + kLenTable + h.kb + static_cast<uint64_t>(h.cw) * I;
+    if (need > h.comp && !h.err) h.err = PIVCO_E_CORRUPT;
+    h.raw_base = static_cast<uint32_t>(need);
+  }
+  __syncthreads();
+  if (h.err) return;
+  if (tid < 256 && l) {
+    const int w = tid >> 6;
+    uint32_t r = myrank;
+    for (int w2 = 0; w2 < w; ++w2) r += t.wcnt[w2][l];
+    t.leafsym[h.lbase[l] + r] = static_cast<uint8_t>(tid);
+  }
+  __syncthreads();
+  const uint32_t I = h.I;
+  const uint64_t kbase = blk + kBlockFixed + kLenTable;
+  if (tid < static_cast<int>(I)) {
+    const uint32_t i = tid;
+    uint32_t d = 0;
+    while (h.lvl[d + 1] <= i) ++d;
+    const uint32_t p = h.fc[d] + h.cnt[d] + (i - h.lvl[d]);
+    const uint32_t leafend = h.fc[d + 1] + h.cnt[d + 1];
+    for (int bb = 0; bb < 2; ++bb) {
+      const uint32_t q = 2 * p + bb;
+      t.child[i][bb] = q < leafend
+                           ? static_cast<uint16_t>(0x8000u | t.leafsym[h.lbase[d + 1] + q - h.fc[d + 1]])
+                           : static_cast<uint16_t>(h.lvl[d + 1] + (q - leafend));
+    }
+    t.depth[i] = static_cast<uint8_t>(d);
+    t.kind[i] = (in[kbase + (i >> 3)] >> (i & 7)) & 1;
+    const uint64_t co = kbase + h.kb + static_cast<uint64_t>(h.cw) * i;
+    uint32_t r = in[co] | (static_cast<uint32_t>(in[co + 1]) << 8);
+    if (h.cw == 4) r |= (static_cast<uint32_t>(in[co + 2]) << 16) | (static_cast<uint32_t>(in[co + 3]) << 24);
+    t.nr[i] = r;
+    if (i == 0) t.nv[0] = h.n;
+  }
+  if (tid == 0 && (I & 7)) {
+    if (in[kbase + (I >> 3)] >> (I & 7)) h.err = PIVCO_E_CORRUPT;   // unused kind bits
+  }
+  if (tid < 17) h.lvl_total[tid] = 0;
+  __syncthreads();
+  // symbol counts top-down, one level at a time
+  for (uint32_t d = 0; d < h.maxlen; ++d) {
+    const uint32_t lo = h.lvl[d], hi = h.lvl[d + 1];
+    for (uint32_t i = lo + tid; i < hi; i += NT) {
+      const uint32_t v = t.nv[i], r = t.nr[i];
+      atomicAdd(reinterpret_cast<unsigned long long *>(&h.lvl_total[d]), static_cast<unsigned long long>(v));
+      if (r > v) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+      const uint16_t c0 = t.child[i][0], c1 = t.child[i][1];
+      if (!(c0 & 0x8000)) t.nv[c0] = v - (r > v ? v : r);
+      if (!(c1 & 0x8000)) t.nv[c1] = r > v ? v : r;
+    }
+    __syncthreads();
+  }
+  // body offsets: exclusive scans of raw bytes and rANS scratch words
+  uint64_t x = 0;
+  if (tid < 256 && tid < static_cast<int>(I)) {
+    const uint64_t v = t.nv[tid];
+    x = t.kind[tid] ? (div_up(v, 32) << 32) : div_up(v, 8);
+  }
+  uint64_t inc = 0;
+  if (tid < 256) {
+    inc = wave_incl_scan64(x);
+    if ((tid & 63) == 63) t.scan_tot[tid >> 6] = inc;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint64_t base = 0;
+    for (int w = 0; w < (tid >> 6); ++w) base += t.scan_tot[w];
+    const uint64_t ex = base + inc - x;
+    if (tid < static_cast<int>(I))
+      t.boff[tid] = t.kind[tid] ? static_cast<uint32_t>(ex >> 32)
+                                : h.raw_base + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
+    if (tid == 255) {
+      const uint64_t tot = base + inc;
+      const uint64_t raw_end = h.raw_base + (tot & 0xFFFFFFFFu);
+      h.raw_end = raw_end > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(raw_end);
+      if (raw_end > h.comp) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+      if ((tot >> 32) != h.ans_words) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+      uint32_t na = 0;
+      for (uint32_t i = 0; i < I; ++i) na += t.kind[i];
+      h.n_ans = na;
+      if (na == 0 && raw_end != h.comp) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+    }
+  }
+  __syncthreads();
+  if (h.err) return;
+  // padding bits of raw bodies must be zero
+  if (tid < static_cast<int>(I) && !t.kind[tid] && (t.nv[tid] & 7)) {
+    const uint32_t last = in[blk + t.boff[tid] + (t.nv[tid] >> 3)];
+    if (last >> (t.nv[tid] & 7)) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernel: rANS decode of entropy-coded node bitmaps into scratch
+// ---------------------------------------------------------------------------
+constexpr int kRansNT = 256;
+constexpr int kRansWin = 2048;        // u16 words per wave window in LDS
+constexpr int kMaxChunks = 1024;
+
+struct RansChunk {
+  uint64_t src;        // byte offset of the chunk in the stream
+  uint64_t dst;        // scratch word of the chunk's first output word
+  uint32_t nbits;
+  uint32_t nw;
+  uint32_t p1q;
+  uint32_t pad;
+};
+
+struct RansSmem {
+  BlockHdr h;
+  NodeTab t;
+  RansChunk ch[kMaxChunks];
+  uint32_t nch;
+  uint16_t win[kRansNT / kWave][kRansWin];
+};
+
+__device__ void rans_chunk(const JobDev &J, const RansChunk &c, uint32_t *scratch,
+                           uint16_t *win, int32_t &werr) {
+  const uint32_t lane = lane_id();
+  const uint8_t *base = J.in + c.src;
+  const bool lane_ok = lane < kRansLanes;
+  uint32_t x = lane_ok ? reinterpret_cast<const uint32_t *>(base)[1 + lane] : kRansL;
+  if (__ballot(x < kRansL)) werr = PIVCO_E_CORRUPT;
+  const uint16_t *words = reinterpret_cast<const uint16_t *>(base + kChunkHdr);
+  const uint32_t f0 = kRansM - c.p1q, f1 = c.p1q;
+  const uint32_t K = (c.nbits + 31) / 32;
+  uint32_t pos = 0, wstart = 0, wend = 0;
+  uint32_t *dst = scratch + c.dst;
+  const uint64_t lanemask_lt = (1ull << lane) - 1;
+  for (uint32_t k = 0; k < K; ++k) {
+    const bool act = lane_ok && (32 * k + lane < c.nbits);
+    const uint32_t slot = x & (kRansM - 1);
+    const bool bit = slot >= f0;
+    if (act) x = (bit ? f1 : f0) * (x >> 12) + slot - (bit ? f0 : 0u);
+    const bool need = act && x < kRansL;
+    const uint64_t m = __ballot(need);
+    const uint32_t cnt = __popcll(m);
+    if (pos + cnt > wend) {       // refill the window (wave-uniform branch)
+      wstart = pos;
+      wend = pos + kRansWin < c.nw ? pos + kRansWin : c.nw;
+      for (uint32_t i = lane; i < wend - wstart; i += kWave) win[i] = words[wstart + i];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (pos + cnt > wend) werr = PIVCO_E_CORRUPT;
+    }
+    if (need) {
+      const uint32_t idx = pos + __popcll(m & lanemask_lt);
+      const uint32_t w = idx < wend ? win[idx - wstart] : 0u;
+      x = (x << 16) | w;
+    }
+    pos += cnt;
+    const uint64_t bm = __ballot(act && bit);
+    if (lane == 0) dst[k] = static_cast<uint32_t>(bm);
+  }
+  if (pos != c.nw) werr = PIVCO_E_CORRUPT;
+  if (__ballot(lane_ok && x != kRansL)) werr = PIVCO_E_CORRUPT;
+  // zero padding after the last word
+  const uint32_t used = kChunkHdr + 2 * c.nw, size = (used + 3) & ~3u;
+  if (lane < size - used && base[used + lane] != 0) werr = PIVCO_E_CORRUPT;
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const uint2 *items,
+                                                   uint32_t n_items, Counters *ctr,
+                                                   uint32_t *scratch, int32_t single) {
+  __shared__ RansSmem sm;
+  __shared__ uint32_t s_item;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  for (bool first = true;; first = false) {
+    if (single >= 0 && !first) break;
+    if (tid == 0) s_item = single >= 0 ? static_cast<uint32_t>(single) : atomicAdd(&ctr->rans_next, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const uint2 item = items[it];
+    const JobDev &J = jobs[item.x];
+    parse_block<kRansNT>(J, item.y, sm.h, sm.t);
+    if (sm.h.err) {
+      if (tid == 0) set_err(J.status, sm.h.err);
+      continue;
+    }
+    if (sm.h.mode == 1 || sm.h.n_ans == 0) continue;
+    // walk the rANS bodies: body headers and chunk headers (serial, thread 0)
+    if (tid == 0) {
+      int32_t err = 0;
+      uint32_t nch = 0;
+      const uint8_t *bp = J.in + sm.h.blk;
+      uint64_t o = sm.h.raw_end;
+      const uint64_t comp = sm.h.comp;
+      const uint64_t C = 1ull << J.chunk_log2;
+      for (uint32_t i = 0; i < sm.h.I && !err; ++i) {
+        if (!sm.t.kind[i]) continue;
+        while (o & 3) {
+          if (o >= comp || bp[o]) { err = PIVCO_E_CORRUPT; break; }
+          ++o;
+        }
+        if (err) break;
+        if (o + 8 > comp || sm.t.nv[i] == 0) { err = PIVCO_E_CORRUPT; break; }
+        const uint32_t p1q = bp[o] | (bp[o + 1] << 8);
+        const uint32_t pad = bp[o + 2] | (bp[o + 3] << 8);
+        const uint32_t blen = *reinterpret_cast<const uint32_t *>(bp + o + 4);
+        if (pad || p1q < 1 || p1q > 4095 || o + 8 + blen > comp) { err = PIVCO_E_CORRUPT; break; }
+        const uint64_t body = o + 8;
+        uint64_t co = 0;
+        const uint64_t nv = sm.t.nv[i];
+        for (uint64_t s = 0; s < nv; s += C) {
+          const uint64_t cl = nv - s < C ? nv - s : C;
+          if (co + kChunkHdr > blen) { err = PIVCO_E_CORRUPT; break; }
+          const uint32_t nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
+          const uint64_t size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
+          if (nw > C || co + size > blen) { err = PIVCO_E_CORRUPT; break; }
+          if (nch >= kMaxChunks) { err = PIVCO_E_UNSUPPORTED; break; }
+          RansChunk &c = sm.ch[nch++];
+          c.src = sm.h.blk + body + co;
+          c.dst = sm.h.ans_word0 + sm.t.boff[i] + s / 32;
+          c.nbits = static_cast<uint32_t>(cl);
+          c.nw = nw;
+          c.p1q = p1q;
+          co += size;
+        }
+        if (!err && co != blen) err = PIVCO_E_CORRUPT;
+        o = body + blen;
+      }
+      if (!err && o != comp) err = PIVCO_E_CORRUPT;
+      sm.nch = err ? 0 : nch;
+      if (err) set_err(J.status, err);
+    }
+    __syncthreads();
+    int32_t werr = 0;
+    for (uint32_t c = wave; c < sm.nch; c += kRansNT / kWave)
+      rans_chunk(J, sm.ch[c], scratch, sm.win[wave], werr);
+    if (werr && lane_id() == 0) set_err(J.status, werr);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel: bottom-up merge decode
+// ---------------------------------------------------------------------------
+template <int NT_, int T_, int BODY_>
+struct MergeCfg {
+  static constexpr int NT = NT_;
+  static constexpr int T = T_;                        // output symbols per tile
+  static constexpr int BODY = BODY_;                  // resident bitmap bytes
+  static constexpr int NW = NT / kWave;
+  static constexpr int STG = 6 * (T / 32) + 2 * 256;  // staged words per tile
+  static constexpr int LVL = T + 4 * 128 + 16;        // bytes per level buffer
+  static constexpr int ITEMS = T / 256 + 129;         // merge items per level
+  static constexpr int LEVELS = kMaxLenGpu;
+};
+
+template <class C>
+struct MergeSmem {
+  BlockHdr h;
+  NodeTab t;
+  uint32_t cur[256];       // bits of the node consumed by earlier tiles
+  uint32_t tv[256];        // node's share of the current tile
+  uint32_t stg[256];       // first staged word of the node
+  uint32_t obase[256];     // node's output offset in its level buffer
+  uint32_t src[256];       // resident: LDS byte offset of the node bitmap
+  uint32_t out_top[C::LEVELS + 1];
+  uint32_t item_cnt[C::LEVELS + 1];
+  uint32_t stage_top;
+  uint32_t tile;           // runtime tile size for this block
+  uint32_t resident;
+  uint32_t sel[16];
+  uint32_t item;
+  uint2 stage[C::STG];
+  uint32_t lvl[2][C::LVL / 4];
+  uint16_t items[C::LEVELS + 1][C::ITEMS];
+  uint32_t body[C::BODY / 4 + 8];
+};
+
+// Largest tile (multiple of 256, at most C::T) whose staged words fit.
+template <class C>
+__device__ uint32_t pick_tile(const BlockHdr &h) {
+  uint32_t T = C::T;
+  for (; T > 256; T -= 256) {
+    uint64_t need = h.I + h.maxlen + 1;
+    for (uint32_t d = 0; d < h.maxlen; ++d) {
+      const uint64_t ld = h.lvl_total[d] < T ? h.lvl_total[d] : T;
+      need += div_up(ld, 32) + (h.lvl[d + 1] - h.lvl[d]);
+    }
+    if (need <= static_cast<uint64_t>(C::STG)) break;
+  }
+  return T;
+}
+
+template <class C>
+__device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch,
+                            uint64_t scratch_words, MergeSmem<C> &sm) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  BlockHdr &h = sm.h;
+  NodeTab &t = sm.t;
+  parse_block<C::NT>(J, b, h, t);
+  if (h.err) {
+    if (tid == 0) set_err(J.status, h.err);
+    return;
+  }
+  uint8_t *out = J.out + h.out_off;
+  const uint32_t n = h.n;
+  if (h.mode == 1) {                 // constant block
+    const uint32_t c4 = h.csym * 0x01010101u;
+    const uint32_t head = static_cast<uint32_t>((4 - (reinterpret_cast<uintptr_t>(out) & 3)) & 3);
+    for (uint32_t i = tid; i < n && i < head; i += C::NT) out[i] = static_cast<uint8_t>(h.csym);
+    if (n > head) {
+      uint32_t *o4 = reinterpret_cast<uint32_t *>(out + head);
+      const uint32_t nd = (n - head) / 4;
+      for (uint32_t i = tid; i < nd; i += C::NT) o4[i] = c4;
+      for (uint32_t i = head + 4 * nd + tid; i < n; i += C::NT) out[i] = static_cast<uint8_t>(h.csym);
+    }
+    return;
+  }
+  const uint32_t I = h.I;
+  const uint64_t blk = h.blk;
+  // ---- decide residency and copy all node bitmaps into LDS ----------------
+  const uint64_t g0 = (blk + h.raw_base) & ~15ull;
+  const uint64_t g1 = (blk + h.raw_end + 15) & ~15ull;
+  const uint64_t raw_bytes = g1 - g0;
+  const uint64_t ans_bytes = 4ull * h.ans_words;
+  const bool resident = raw_bytes + ans_bytes + 16 <= static_cast<uint64_t>(C::BODY);
+  if (resident) {
+    const uint64_t in_dw = J.in_len >> 2;
+    const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
+    const uint32_t n16 = static_cast<uint32_t>(raw_bytes >> 4);
+    for (uint32_t i = tid; i < n16; i += C::NT) {
+      const uint64_t q = (g0 >> 2) + 4ull * i;
+      uint4 v;
+      if (q + 4 <= in_dw) {
+        v = *reinterpret_cast<const uint4 *>(gin + q);
+      } else {
+        v.x = q < in_dw ? gin[q] : 0u;
+        v.y = q + 1 < in_dw ? gin[q + 1] : 0u;
+        v.z = q + 2 < in_dw ? gin[q + 2] : 0u;
+        v.w = q + 3 < in_dw ? gin[q + 3] : 0u;
+      }
+      *reinterpret_cast<uint4 *>(&sm.body[4 * i]) = v;
+    }
+    const uint32_t abase = static_cast<uint32_t>(raw_bytes >> 2);
+    for (uint32_t i = tid; i < h.ans_words; i += C::NT) {
+      const uint64_t q = h.ans_word0 + i;
+      sm.body[abase + i] = q < scratch_words ? scratch[q] : 0u;
+    }
+    for (uint32_t i = tid; i < 8; i += C::NT) sm.body[abase + h.ans_words + i] = 0u;
+    for (uint32_t i = tid; i < I; i += C::NT)
+      sm.src[i] = t.kind[i] ? 4 * (abase + t.boff[i]) : static_cast<uint32_t>(blk + t.boff[i] - g0);
+  }
+  if (tid < 16) {
+    // selector for v_perm_b32(R, L, sel): output byte k takes the left
+    // sequence's next byte (values 0-3) or the right one's (values 4-7)
+    uint32_t s = 0, ones = 0;
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t bit = (tid >> k) & 1;
+      const uint32_t v = bit ? 4 + ones : k - ones;
+      s |= v << (8 * k);
+      ones += bit;
+    }
+    sm.sel[tid] = s;
+  }
+  for (uint32_t i = tid; i < I; i += C::NT) sm.cur[i] = 0;
+  if (tid == 0) sm.tile = pick_tile<C>(h);
+  __syncthreads();
+  const uint32_t T = sm.tile;
+  const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
+  const uint32_t *gin32 = reinterpret_cast<const uint32_t *>(J.in);
+  const uint64_t in_dw = J.in_len >> 2;
+  bool bad = false;
+
+  for (uint32_t t0 = 0; t0 < n; t0 += T) {
+    const uint32_t troot = n - t0 < T ? n - t0 : T;
+    if (tid <= static_cast<int>(C::LEVELS)) { sm.out_top[tid] = 0; sm.item_cnt[tid] = 0; }
+    if (tid == 0) {
+      sm.stage_top = 0;
+      sm.tv[0] = troot;
+      sm.item_cnt[0] = (troot + 255) / 256;
+    }
+    for (uint32_t j = tid; j < (troot + 255) / 256; j += C::NT) sm.items[0][j] = static_cast<uint16_t>(j);
+    __syncthreads();
+    // ---- count phase: top-down -------------------------------------------
+    for (uint32_t d = 0; d < maxd; ++d) {
+      for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += C::NW) {
+        const uint32_t tvv = sm.tv[v];
+        const uint32_t nwords = (tvv + 31) / 32;
+        uint32_t base = 0;
+        if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (base + nwords > static_cast<uint32_t>(C::STG)) {   // cannot happen: tile sized for it
+          if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
+          break;
+        }
+        const uint32_t s0 = sm.cur[v];
+        uint32_t carry = 0;
+        for (uint32_t q0 = 0; q0 < nwords; q0 += kWave) {
+          const uint32_t q = q0 + lane;
+          uint32_t w = 0;
+          if (q < nwords) {
+            const uint32_t p = s0 + 32 * q;
+            if (resident) {
+              w = bits32_lds(sm.body, 8 * sm.src[v] + p);
+            } else if (t.kind[v]) {
+              w = bits32_glb(scratch, 32 * (h.ans_word0 + t.boff[v]) + p, scratch_words);
+            } else {
+              w = bits32_glb(gin32, 8 * (blk + t.boff[v]) + p, in_dw);
+            }
+            const uint32_t rem = tvv - 32 * q;
+            if (rem < 32) w &= (1u << rem) - 1;
+          }
+          const uint32_t pc = __popc(w);
+          const uint32_t inc = wave_incl_scan(pc);
+          if (q < nwords) sm.stage[base + q] = make_uint2(w, carry + inc - pc);
+          carry += __shfl(inc, kWave - 1, kWave);
+        }
+        if (lane == 0) sm.stg[v] = base;
+        const uint32_t ones = carry;
+        for (int bb = 0; bb < 2; ++bb) {
+          const uint16_t c = t.child[v][bb];
+          if (c & 0x8000) continue;
+          uint32_t tc = bb ? ones : tvv - ones;
+          if (sm.cur[c] + tc > t.nv[c]) {      // more symbols than the node holds
+            if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+            tc = 0;
+          }
+          if (lane == 0) {
+            sm.tv[c] = tc;
+            sm.obase[c] = tc ? atomicAdd(&sm.out_top[d + 1], (tc + 3) & ~3u) : 0u;
+          }
+          const uint32_t nit = (tc + 255) / 256;
+          uint32_t ib = 0;
+          if (lane == 0 && nit) ib = atomicAdd(&sm.item_cnt[d + 1], nit);
+          ib = __builtin_amdgcn_readfirstlane(ib);
+          for (uint32_t j = lane; j < nit; j += kWave)
+            if (ib + j < static_cast<uint32_t>(C::ITEMS))
+              sm.items[d + 1][ib + j] = static_cast<uint16_t>((c << 8) | j);
+        }
+      }
+      __syncthreads();
+    }
+    if (h.err) { bad = true; break; }
+    // ---- merge phase: bottom-up ------------------------------------------
+    for (int d = static_cast<int>(maxd) - 1; d >= 0; --d) {
+      const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
+      uint32_t *obuf = sm.lvl[d & 1];
+      const uint32_t nit = sm.item_cnt[d] < static_cast<uint32_t>(C::ITEMS) ? sm.item_cnt[d] : C::ITEMS;
+      for (uint32_t ii = wave; ii < nit; ii += C::NW) {
+        const uint32_t itv = sm.items[d][ii];
+        const uint32_t v = itv >> 8, c = itv & 255;
+        const uint32_t tvv = sm.tv[v];
+        const uint32_t j = 256 * c + 4 * lane;
+        if (j >= tvv) continue;
+        const uint2 wr = sm.stage[sm.stg[v] + (j >> 5)];
+        const uint32_t sh = j & 31;
+        const uint32_t m = (wr.x >> sh) & 15;
+        const uint32_t r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
+        const uint32_t r0 = j - r1;
+        const uint16_t cl = t.child[v][0], cr = t.child[v][1];
+        const uint32_t L = (cl & 0x8000) ? (cl & 255) * 0x01010101u : win4(cbuf, sm.obase[cl] + r0);
+        const uint32_t R = (cr & 0x8000) ? (cr & 255) * 0x01010101u : win4(cbuf, sm.obase[cr] + r1);
+        const uint32_t o = __builtin_amdgcn_perm(R, L, sm.sel[m]);
+        if (d == 0) {
+          uint8_t *dst = out + t0 + j;
+          if (j + 4 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 3)) {
+            *reinterpret_cast<uint32_t *>(dst) = o;
+          } else {
+            const uint32_t k = tvv - j < 4 ? tvv - j : 4;
+            for (uint32_t e = 0; e < k; ++e) dst[e] = static_cast<uint8_t>(o >> (8 * e));
+          }
+        } else {
+          obuf[(sm.obase[v] + j) >> 2] = o;
+        }
+      }
+      __syncthreads();
+    }
+    for (uint32_t i = tid; i < I; i += C::NT) {
+      sm.cur[i] += sm.tv[i];
+      sm.tv[i] = 0;
+    }
+    __syncthreads();
+  }
+  if (!bad) {
+    for (uint32_t i = tid; i < I; i += C::NT)
+      if (sm.cur[i] != t.nv[i]) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+  }
+  __syncthreads();
+  if (tid == 0 && h.err) set_err(J.status, h.err);
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *items,
+                                                  uint32_t n_items, Counters *ctr,
+                                                  const uint32_t *scratch, uint64_t scratch_words,
+                                                  int32_t single) {
+  __shared__ MergeSmem<C> sm;
+  const int tid = threadIdx.x;
+  for (;;) {
+    uint32_t it;
+    if (single >= 0) {
+      it = static_cast<uint32_t>(single);
+    } else {
+      if (tid == 0) sm.item = atomicAdd(&ctr->merge_next, 1u);
+      __syncthreads();
+      it = sm.item;
+    }
+    __syncthreads();
+    if (it >= n_items) break;
+    const uint2 item = items[it];
+    merge_block<C>(jobs[item.x], item.y, scratch, scratch_words, sm);
+    __syncthreads();
+    if (single >= 0) break;
+  }
+}
+
+// Resets the queue heads and the per-job status words (graph-safe: a kernel,
+// not a memset node).
+__global__ void k_init(Counters *ctr, int32_t *status, const int32_t *status0, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) { ctr->merge_next = 0; ctr->rans_next = 0; }
+  if (i < count) status[i] = status0[i];
+}
+
+// Copies the 48-byte header of every job's stream into hdr (planning).
+__global__ void k_gather_headers(const pivco_job *jobs, uint32_t count, uint8_t *hdr) {
+  const uint32_t j = blockIdx.x;
+  if (j >= count) return;
+  const uint32_t i = threadIdx.x;
+  if (i < kHeaderBytes) {
+    const pivco_job jb = jobs[j];
+    hdr[static_cast<uint64_t>(j) * kHeaderBytes + i] =
+        i < jb.in_len ? static_cast<const uint8_t *>(jb.d_in)[i] : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch table
+// ---------------------------------------------------------------------------
+using Cfg0 = MergeCfg<1024, 16384, 65536>;
+using Cfg1 = MergeCfg<1024, 8192, 98304>;
+using Cfg2 = MergeCfg<512, 8192, 49152>;
+
+struct MergeVariant {
+  const char *name;
+  const void *fn;
+  int nt;
+};
+
+template <class C>
+static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
+                                 uint32_t n_items, Counters *ctr, const uint32_t *scratch,
+                                 uint64_t scratch_words, int32_t single) {
+  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, items, n_items, ctr, scratch,
+                     scratch_words, single);
+  return hipGetLastError();
+}
+
+template <class C>
+static int occupancy_t() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<C>, C::NT, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace pivco
+
+// ---- entry points used by the host library (C++ linkage, internal) -------
+namespace pivco {
+
+uint32_t merge_variant_count() { return 3; }
+
+const char *merge_variant_name(uint32_t v) {
+  switch (v) {
+    case 0: return "wg1024_tile16k_lds64k";
+    case 1: return "wg1024_tile8k_lds96k";
+    case 2: return "wg512_tile8k_lds48k";
+    default: return "?";
+  }
+}
+
+int merge_variant_occupancy(uint32_t v) {
+  switch (v) {
+    case 0: return occupancy_t<Cfg0>();
+    case 1: return occupancy_t<Cfg1>();
+    default: return occupancy_t<Cfg2>();
+  }
+}
+
+hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
+                        const uint2 *items, uint32_t n_items, Counters *ctr,
+                        const uint32_t *scratch, uint64_t scratch_words, int32_t single) {
+  switch (variant) {
+    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, items, n_items, ctr, scratch, scratch_words, single);
+    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, items, n_items, ctr, scratch, scratch_words, single);
+    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, n_items, ctr, scratch, scratch_words, single);
+  }
+}
+
+hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
+                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single) {
+  hipLaunchKernelGGL(k_rans, dim3(grid), dim3(kRansNT), 0, s, jobs, items, n_items, ctr, scratch,
+                     single);
+  return hipGetLastError();
+}
+
+int rans_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rans, kRansNT, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
+                       uint32_t count) {
+  const uint32_t n = count > 0 ? count : 1;
+  hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, ctr, status, status0, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_headers(hipStream_t s, const pivco_job *jobs, uint32_t count, uint8_t *hdr) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_headers, dim3(count), dim3(64), 0, s, jobs, count, hdr);
+  return hipGetLastError();
+}
+
+}  // namespace pivco
