@@ -474,6 +474,7 @@ struct MergeSmem {
   uint32_t stg[256];       // first staged word of the node
   uint32_t obase[256];     // node's output offset in its level buffer
   uint32_t src[256];       // resident: LDS byte offset of the node bitmap
+  uint32_t ones[256];      // 1 bits seen so far (must end equal to n_right)
   uint32_t out_top[C::LEVELS + 1];
   uint32_t item_cnt[C::LEVELS + 1];
   uint32_t stage_top;
@@ -575,7 +576,7 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     }
     sm.sel[tid] = s;
   }
-  for (uint32_t i = tid; i < I; i += C::NT) sm.cur[i] = 0;
+  for (uint32_t i = tid; i < I; i += C::NT) { sm.cur[i] = 0; sm.ones[i] = 0; }
   if (tid == 0) sm.tile = pick_tile<C>(h);
   __syncthreads();
   const uint32_t T = sm.tile;
@@ -628,8 +629,8 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
           if (q < nwords) sm.stage[base + q] = make_uint2(w, carry + inc - pc);
           carry += __shfl(inc, kWave - 1, kWave);
         }
-        if (lane == 0) sm.stg[v] = base;
         const uint32_t ones = carry;
+        if (lane == 0) { sm.stg[v] = base; sm.ones[v] += ones; }
         for (int bb = 0; bb < 2; ++bb) {
           const uint16_t c = t.child[v][bb];
           if (c & 0x8000) continue;
@@ -696,7 +697,8 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
   }
   if (!bad) {
     for (uint32_t i = tid; i < I; i += C::NT)
-      if (sm.cur[i] != t.nv[i]) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+      if (sm.cur[i] != t.nv[i] || sm.ones[i] != t.nr[i])
+        atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
   }
   __syncthreads();
   if (tid == 0 && h.err) set_err(J.status, h.err);
