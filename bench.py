@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the PivCo-Huffman hot path on one MI355X.
+
+Workload (N=1): 256 MiB of uint8 symbols drawn i.i.d. from Zipf(1.1) over 256
+ranks with a seeded permutation of symbol ids, coded in 64 KiB blocks, each
+block with its own length-limited (11-bit) canonical tree, no entropy-coded
+nodes.  The stream is produced by the GPU encoder and checked against the
+input; a "step" is one batched decode of the whole stream (one persistent,
+HIP-graph-captured launch).  The JSON line reports decoded GB/s (10^9 B/s),
+the HBM roofline fraction of the merge kernel, the same decode as one launch
+per block ("plain"), the encode rate, and the CPU oracle timed on a sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded GB/s per MI355X (% HBM roofline), batched vs plain; p99 latency"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2606_05765_amd", "csrc", "decode.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, variant):
+    """HBM bytes per merge launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_k_merge_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("decode_hip_sha256_16") != kernel_source_hash() or t.get("variant") != variant:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(stream_np, n_blocks, block_size, budget_s=12.0):
+    import oracle
+    t0 = time.perf_counter()
+    done = 0
+    step = 16
+    while done < n_blocks and time.perf_counter() - t0 < budget_s:
+        b1 = min(n_blocks, done + step)
+        oracle.decode_blocks(stream_np, done, b1)
+        done = b1
+    dt = time.perf_counter() - t0
+    nbytes = done * block_size
+    return {"value": round(nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {n_blocks} blocks ({nbytes / 2**20:.0f} MiB) of the same "
+                      f"stream, single-threaded C oracle (tree walk per symbol), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variant", type=int, default=None, help="fixed merge variant (skips autotune)")
+    ap.add_argument("--grid", type=int, default=None, help="fixed merge grid (with --variant)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter scale reference)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(blocks are independent, so N GPUs would each decode their own share)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2606_05765_amd import pivco as P
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    log("generating workload zipf256m ...")
+    w = W.zipf256m(seed=args.seed)
+    x = w.jobs[0]
+    n = x.size
+    bs = w.block_size
+    d_x = torch.from_numpy(x).to(dev)
+
+    # encode on the GPU (timed, reported as extra)
+    enc_times = []
+    stream = None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stream = P.pivco_encode(d_x, bs, max_len=11, ans_mode=w.ans_mode)
+        torch.cuda.synchronize()
+        enc_times.append(time.perf_counter() - t0)
+    comp = stream.numel()
+    info = P.pivco_stream_info(stream)
+    log(f"encoded {n} -> {comp} bytes ({comp / n:.4f}), {info['n_blocks']} blocks, "
+        f"best encode {min(enc_times) * 1e3:.1f} ms")
+
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    tune = None
+    if args.variant is not None:
+        tune = P.Tune()
+        tune.merge_variant = args.variant
+        tune.merge_grid = args.grid or 256
+        tune.rans_grid = 256
+    elif not args.no_autotune:
+        tune = P.pivco_autotune([stream], [out])
+        log("autotune:", tune.as_dict(), P.pivco_merge_variants()[tune.merge_variant])
+    plan = P.BatchPlan([stream], [out], tune=tune)
+    variant = P.pivco_merge_variants()[plan.tune.merge_variant] if plan.tune is not None else \
+        P.pivco_merge_variants()[0]
+
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = n / (dt / args.steps) / 1e9
+
+    st = plan.statuses()
+    assert (st == 0).all(), f"decode status {st}"
+    got = out.cpu().numpy()
+    assert np.array_equal(got, x), "decoded bytes differ from the input"
+    log(f"batched graph decode: {ms_per_step:.3f} ms/step, {value:.1f} GB/s, output verified")
+
+    # roofline of the dominant kernel: HIP events around the merge kernel on
+    # the stream it runs on, same number of launches as the timed region
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(); ev1.record()
+    torch.cuda.synchronize()
+    merge_ms = []
+    for _ in range(args.steps):
+        plan.launch_timed(ev0, ev1)
+        ev1.synchronize()
+        merge_ms.append(ev0.elapsed_time(ev1))
+    merge_avg = float(np.mean(merge_ms))
+    algo_bytes = comp + n             # stream read once + output written once
+    achieved = algo_bytes / (merge_avg * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, variant)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic, "kernel": f"k_merge<{variant}>",
+                "merge_ms_avg": round(merge_avg, 4),
+                "algorithmic_bytes_per_launch": algo_bytes}
+    log(f"merge kernel: {merge_avg:.3f} ms avg, {achieved:.1f} GB/s algorithmic "
+        f"({achieved / HBM_PEAK_GBPS * 100:.1f}% of HBM peak)")
+
+    plain = None
+    if not args.no_plain:
+        out2 = torch.empty(n, dtype=torch.uint8, device=dev)
+        ws = P.Workspace(P.pivco_decode_workspace([stream], [out2]))
+        best = 1e30
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, pst = P.pivco_decode_plain([stream], [out2], ws=ws)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+            assert (pst == 0).all()
+        assert torch.equal(out2, out)
+        plain = round(n / best / 1e9, 2)
+        log(f"plain per-block launches: {best * 1e3:.2f} ms, {plain} GB/s")
+
+    if args.copy_probe:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        cpu = cpu_baseline(stream.cpu().numpy(), info["n_blocks"], bs)
+        log("cpu baseline:", cpu)
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "zipf256m: 256 MiB uint8, Zipf(1.1) over 256 permuted ids, "
+                               "64 KiB blocks, one L=11 canonical tree per block, no ANS",
+                   "decode": "batched: one persistent HIP-graph launch over all blocks",
+                   "variant": variant,
+                   "tune": plan.tune.as_dict() if plan.tune is not None else None},
+        "pct_hbm_roofline": round(achieved / HBM_PEAK_GBPS * 100, 2),
+        "plain_per_block_GBps": plain,
+        "encode_GBps": round(n / min(enc_times) / 1e9, 2),
+        "compression_ratio": round(n / comp, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -24,16 +24,14 @@
 
 namespace pivco {
 
-namespace {
-
-struct Coin {
-  uint64_t weight;
-  bool single;                 // one symbol (true) or a package (false)
-  std::vector<uint8_t> mult;   // how often each of the m symbols occurs in it
-};
-
-}  // namespace
-
+// Rows are built from the deepest denomination (2^-L) up.  Every row is the
+// merge of the m single coins with the packages formed from consecutive pairs
+// of the row below, so a row only needs, per position, its weight and whether
+// it is a single coin.  Buying the first k items of a row buys a prefix of its
+// singles (they appear in sorted order) and a prefix of its packages (they
+// appear in creation order); p bought packages buy the first 2p items of the
+// row below.  A symbol's length is the number of rows whose bought singles
+// include it.
 pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]) {
   std::memset(len, 0, 256);
   std::vector<int> sym;
@@ -42,39 +40,42 @@ pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, u
   const size_t m = sym.size();
   if (m < 2 || max_len < 1 || max_len > 15 || (size_t(1) << max_len) < m) return PIVCO_E_ARG;
   std::stable_sort(sym.begin(), sym.end(), [&](int a, int b) { return counts[a] < counts[b]; });
-  std::vector<Coin> singles(m);
-  for (size_t i = 0; i < m; ++i) {
-    singles[i].weight = counts[sym[i]];
-    singles[i].single = true;
-    singles[i].mult.assign(m, 0);
-    singles[i].mult[i] = 1;
-  }
-  // deepest denomination first: the row holds only single coins
-  std::vector<Coin> row = singles;
-  for (uint32_t level = max_len; level > 1; --level) {
-    std::vector<Coin> packs;
-    packs.reserve(row.size() / 2);
-    for (size_t i = 0; i + 1 < row.size(); i += 2) {
-      Coin p;
-      p.weight = row[i].weight + row[i + 1].weight;
-      p.single = false;
-      p.mult.resize(m);
-      for (size_t k = 0; k < m; ++k) p.mult[k] = row[i].mult[k] + row[i + 1].mult[k];
-      packs.push_back(std::move(p));
+  std::vector<uint64_t> w(m);
+  for (size_t i = 0; i < m; ++i) w[i] = counts[sym[i]];
+  // rows[r]: weights and single-coin flags, r = 1 (2^-1) .. max_len (2^-L)
+  std::vector<std::vector<uint64_t>> weight(max_len + 1);
+  std::vector<std::vector<uint8_t>> single(max_len + 1);
+  weight[max_len] = w;
+  single[max_len].assign(m, 1);
+  for (uint32_t r = max_len; r > 1; --r) {
+    const std::vector<uint64_t> &below = weight[r];
+    std::vector<uint64_t> &wr = weight[r - 1];
+    std::vector<uint8_t> &sr = single[r - 1];
+    const size_t np = below.size() / 2;
+    wr.reserve(m + np);
+    sr.reserve(m + np);
+    size_t a = 0, p = 0;
+    while (a < m || p < np) {
+      const uint64_t pw = p < np ? below[2 * p] + below[2 * p + 1] : 0;
+      if (p >= np || (a < m && w[a] <= pw)) {
+        wr.push_back(w[a++]);
+        sr.push_back(1);
+      } else {
+        wr.push_back(pw);
+        sr.push_back(0);
+        ++p;
+      }
     }
-    std::vector<Coin> next;
-    next.reserve(m + packs.size());
-    size_t a = 0, b = 0;
-    while (a < m || b < packs.size()) {
-      const bool take_single =
-          b >= packs.size() || (a < m && singles[a].weight <= packs[b].weight);
-      next.push_back(take_single ? singles[a++] : std::move(packs[b++]));
-    }
-    row.swap(next);
   }
   std::vector<uint32_t> depth(m, 0);
-  for (size_t i = 0; i < 2 * m - 2 && i < row.size(); ++i)
-    for (size_t k = 0; k < m; ++k) depth[k] += row[i].mult[k];
+  size_t k = 2 * m - 2;                       // items bought in row 1
+  for (uint32_t r = 1; r <= max_len && k; ++r) {
+    if (k > weight[r].size()) return PIVCO_E_ARG;
+    size_t singles = 0, packs = 0;
+    for (size_t i = 0; i < k; ++i) (single[r][i] ? singles : packs)++;
+    for (size_t i = 0; i < singles; ++i) depth[i]++;
+    k = 2 * packs;
+  }
   std::vector<uint32_t> pool(depth.begin(), depth.end());
   std::sort(pool.begin(), pool.end());
   std::vector<int> order(sym.begin(), sym.end());
