@@ -165,6 +165,65 @@ void pivco_batch_plan_destroy(pivco_batch_plan *p);
 pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
                             void *d_ws, uint64_t ws_bytes, hipStream_t s, pivco_tune *out);
 
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of decode requests                        */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  uint64_t mem_budget;         /* device bytes for outputs of admitted requests */
+  uint32_t slots;              /* batches in flight at once (one HIP stream each), 1..16 */
+  uint32_t max_batch;          /* requests per batch */
+  uint32_t max_blocks;         /* blocks per batch (work-queue capacity) */
+  uint32_t merge_variant;      /* merge kernel variant (see pivco_merge_variants) */
+  uint64_t max_scratch_words;  /* rANS scratch words per batch */
+  uint32_t keep_outputs;       /* 1: never recycle output space (for checking results) */
+  uint32_t reserved;
+} pivco_server_opts;
+
+typedef struct {
+  double arrival_s;            /* arrival time, seconds after run() starts */
+  uint32_t id;                 /* registered stream */
+  uint32_t reserved;
+} pivco_request;
+
+typedef struct {
+  int32_t status;              /* pivco_status of this request */
+  uint32_t reserved;
+  void *d_out;                 /* where its bytes were decoded (inside the pool) */
+  uint64_t n_out;
+  double t_admit, t_done;      /* seconds after run() starts; latency = t_done - arrival */
+} pivco_request_result;
+
+typedef struct {
+  double wall_s;
+  uint64_t bytes_decoded;
+  uint64_t peak_pool_bytes;
+  uint64_t batches;
+  uint64_t max_batch;
+} pivco_server_stats;
+
+typedef struct pivco_server pivco_server;
+
+/* Creates the server: per slot a non-blocking stream, a device workspace and
+ * pinned staging (allocated here, never on the request path). */
+pivco_status pivco_server_create(const pivco_server_opts *o, pivco_server **out);
+void pivco_server_destroy(pivco_server *sv);
+/* Device bytes held by the slot workspaces. */
+uint64_t pivco_server_workspace_bytes(const pivco_server *sv);
+/* Registers a stream resident in device memory (16-byte aligned); reads its
+ * header once (synchronous).  *id names it in requests. */
+pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint64_t len,
+                                   uint32_t *id);
+/* Replays the request trace (sorted by arrival) in real time: arrivals are
+ * admitted FIFO while a slot is free and the output fits in the budget
+ * (outputs are placed in d_pool, at most min(pool_bytes, mem_budget) bytes);
+ * each admission round is one batched decode on a free slot, overlapping
+ * with batches on other slots.  A request larger than the budget gets
+ * PIVCO_E_BUDGET.  Returns when every request has completed. */
+pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint32_t n_req,
+                              void *d_pool, uint64_t pool_bytes, pivco_request_result *res,
+                              pivco_server_stats *stats);
+
 const char *pivco_strerror(pivco_status st);
 
 #ifdef __cplusplus

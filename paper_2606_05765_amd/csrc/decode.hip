@@ -462,7 +462,9 @@ struct MergeCfg {
   static constexpr int STG = 6 * (T / 32) + 2 * 256;  // staged words per tile
   static constexpr int LVL = T + 4 * 128 + 16;        // bytes per level buffer
   static constexpr int ITEMS = T / 256 + 129;         // merge items per level
+  static constexpr int SITEMS = 6 * (T / 2048) + 256 + 16;  // staging items per tile
   static constexpr int LEVELS = kMaxLenGpu;
+  static constexpr int SUP = BODY / 32 + 8;           // rank directory entries
 };
 
 template <class C>
@@ -473,19 +475,25 @@ struct MergeSmem {
   uint32_t tv[256];        // node's share of the current tile
   uint32_t stg[256];       // first staged word of the node
   uint32_t obase[256];     // node's output offset in its level buffer
-  uint32_t src[256];       // resident: LDS byte offset of the node bitmap
-  uint32_t ones[256];      // 1 bits seen so far (must end equal to n_right)
+  uint32_t abit[256];      // resident: LDS bit address of the node bitmap
+  uint32_t arank[256];     // resident: 1 bits of the body before the cursor
+  uint32_t anext[256];     // resident: same after this tile
+  uint32_t r0[256];        // resident: 1 bits of the body before the node
+  uint32_t ones[256];      // streaming: 1 bits seen so far
   uint32_t out_top[C::LEVELS + 1];
   uint32_t item_cnt[C::LEVELS + 1];
   uint32_t stage_top;
+  uint32_t sitem_cnt;
   uint32_t tile;           // runtime tile size for this block
-  uint32_t resident;
   uint32_t sel[16];
   uint32_t item;
+  uint32_t scan_tot[C::NW];
   uint2 stage[C::STG];
   uint32_t lvl[2][C::LVL / 4];
   uint16_t items[C::LEVELS + 1][C::ITEMS];
-  uint32_t body[C::BODY / 4 + 8];
+  uint32_t sitems[C::SITEMS];
+  uint32_t sup[C::SUP];    // resident: 1 bits of the body before each 256-bit superblock
+  uint32_t body[C::BODY / 4 + 16] __attribute__((aligned(16)));
 };
 
 // Largest tile (multiple of 256, at most C::T) whose staged words fit.
@@ -493,14 +501,260 @@ template <class C>
 __device__ uint32_t pick_tile(const BlockHdr &h) {
   uint32_t T = C::T;
   for (; T > 256; T -= 256) {
-    uint64_t need = h.I + h.maxlen + 1;
+    uint64_t need = h.I + h.maxlen + 1, sitems = 1;
     for (uint32_t d = 0; d < h.maxlen; ++d) {
       const uint64_t ld = h.lvl_total[d] < T ? h.lvl_total[d] : T;
-      need += div_up(ld, 32) + (h.lvl[d + 1] - h.lvl[d]);
+      const uint64_t nodes = h.lvl[d + 1] - h.lvl[d];
+      need += div_up(ld, 32) + nodes;
+      sitems += div_up(ld, 2048) + nodes;
     }
-    if (need <= static_cast<uint64_t>(C::STG)) break;
+    if (need <= static_cast<uint64_t>(C::STG) && sitems <= static_cast<uint64_t>(C::SITEMS)) break;
   }
   return T;
+}
+
+// Number of 1 bits in LDS bits [0, x) of the resident body: superblock count
+// plus the popcounts of the superblock's dwords before x.
+__device__ __forceinline__ uint32_t rank_at(const uint32_t *body, const uint32_t *sup, uint32_t x) {
+  const uint32_t k = x >> 8;
+  const uint32_t q = (x >> 5) & 7;
+  const uint4 a = *reinterpret_cast<const uint4 *>(&body[8 * k]);
+  const uint4 c = *reinterpret_cast<const uint4 *>(&body[8 * k + 4]);
+  const uint32_t part = (1u << (x & 31)) - 1;
+  const uint32_t w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+  uint32_t r = sup[k];
+#pragma unroll
+  for (uint32_t i = 0; i < 8; ++i) {
+    const uint32_t m = i < q ? 0xFFFFFFFFu : (i == q ? part : 0u);
+    r += __popc(w[i] & m);
+  }
+  return r;
+}
+
+// Exclusive prefix over the 64 lanes of a wave, and the wave total.
+__device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total) {
+  const uint64_t inc = wave_incl_scan64(v);
+  total = __shfl(inc, kWave - 1, kWave);
+  return inc - v;
+}
+
+// Count phase on the resident body, run by wave 0 alone (no workgroup
+// barriers): level by level, every node's share of the tile gives its right
+// child's share as one rank difference, and the node's staging words, its
+// children's output space and the merge/staging work items are allocated
+// with wave-wide prefix sums.
+template <class C>
+__device__ void count_resident(MergeSmem<C> &sm, uint32_t maxd) {
+  const uint32_t lane = lane_id();
+  BlockHdr &h = sm.h;
+  NodeTab &t = sm.t;
+  uint32_t stage_top = 0, sitem_top = 0;
+  for (uint32_t d = 0; d < maxd; ++d) {
+    uint32_t out_top = 0, item_top = 0;
+    for (uint32_t v0 = h.lvl[d]; v0 < h.lvl[d + 1]; v0 += kWave) {
+      const uint32_t v = v0 + lane;
+      const bool valid = v < h.lvl[d + 1];
+      uint32_t tvv = 0, ones = 0, tc[2] = {0, 0};
+      uint16_t ch[2] = {0x8000, 0x8000};
+      if (valid) {
+        tvv = sm.tv[v];
+        const uint32_t a = sm.arank[v];
+        const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.abit[v] + sm.cur[v] + tvv) : a;
+        sm.anext[v] = e;
+        ones = e - a;
+        ch[0] = t.child[v][0];
+        ch[1] = t.child[v][1];
+        tc[0] = tvv - ones;
+        tc[1] = ones;
+        for (int bb = 0; bb < 2; ++bb) {
+          if (ch[bb] & 0x8000) { tc[bb] = 0; continue; }
+          if (sm.cur[ch[bb]] + tc[bb] > t.nv[ch[bb]]) {     // more symbols than the node holds
+            atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+            tc[bb] = 0;
+          }
+        }
+      }
+      const uint32_t nwords = (tvv + 31) / 32, nsit = (tvv + 2047) / 2048;
+      const uint32_t o0 = (tc[0] + 3) & ~3u, o1 = (tc[1] + 3) & ~3u;
+      const uint32_t m0 = (tc[0] + 255) / 256, m1 = (tc[1] + 255) / 256;
+      // packed prefix sums: staged words | staging items | output bytes | merge items
+      const uint64_t pk = static_cast<uint64_t>(nwords) | (static_cast<uint64_t>(nsit) << 16) |
+                          (static_cast<uint64_t>(o0 + o1) << 24) | (static_cast<uint64_t>(m0 + m1) << 48);
+      uint64_t tot;
+      const uint64_t ex = wave_excl_scan64(pk, tot);
+      if (valid) {
+        const uint32_t stg = stage_top + static_cast<uint32_t>(ex & 0xFFFF);
+        const uint32_t sit = sitem_top + static_cast<uint32_t>((ex >> 16) & 0xFF);
+        const uint32_t ob = out_top + static_cast<uint32_t>((ex >> 24) & 0xFFFFFF);
+        const uint32_t mi = item_top + static_cast<uint32_t>(ex >> 48);
+        sm.stg[v] = stg;
+        for (uint32_t j = 0; j < nsit; ++j)
+          if (sit + j < static_cast<uint32_t>(C::SITEMS)) sm.sitems[sit + j] = (v << 16) | j;
+        uint32_t ob2 = ob, mi2 = mi;
+        for (int bb = 0; bb < 2; ++bb) {
+          if (ch[bb] & 0x8000) continue;
+          const uint16_t c = ch[bb];
+          sm.tv[c] = tc[bb];
+          sm.obase[c] = ob2;
+          const uint32_t nm = (tc[bb] + 255) / 256;
+          for (uint32_t j = 0; j < nm; ++j)
+            if (mi2 + j < static_cast<uint32_t>(C::ITEMS))
+              sm.items[d + 1][mi2 + j] = static_cast<uint16_t>((c << 8) | j);
+          ob2 += (tc[bb] + 3) & ~3u;
+          mi2 += nm;
+        }
+      }
+      stage_top += static_cast<uint32_t>(tot & 0xFFFF);
+      sitem_top += static_cast<uint32_t>((tot >> 16) & 0xFF);
+      out_top += static_cast<uint32_t>((tot >> 24) & 0xFFFFFF);
+      item_top += static_cast<uint32_t>(tot >> 48);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (lane == 0) sm.item_cnt[d + 1] = item_top;
+  }
+  if (lane == 0) {
+    sm.stage_top = stage_top;
+    sm.sitem_cnt = sitem_top;
+    if (stage_top > static_cast<uint32_t>(C::STG) || sitem_top > static_cast<uint32_t>(C::SITEMS))
+      atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));   // tile sized to fit
+  }
+}
+
+// Staging pass on the resident body, all waves, all levels at once: each
+// item is 64 words of one node; the words are copied dword-aligned with
+// their rank (1 bits of the node's tile share before the word).
+template <class C>
+__device__ void stage_resident(MergeSmem<C> &sm) {
+  const int wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const uint32_t nit = sm.sitem_cnt;
+  for (uint32_t it = wave; it < nit; it += C::NW) {
+    const uint32_t e = sm.sitems[it];
+    const uint32_t v = e >> 16, c = e & 0xFFFF;
+    const uint32_t tvv = sm.tv[v];
+    const uint32_t nwords = (tvv + 31) / 32;
+    const uint32_t x0 = sm.abit[v] + sm.cur[v];
+    const uint32_t wq = 64 * c + lane;
+    uint32_t w = 0;
+    if (wq < nwords) {
+      w = bits32_lds(sm.body, x0 + 32 * wq);
+      const uint32_t rem = tvv - 32 * wq;
+      if (rem < 32) w &= (1u << rem) - 1;
+    }
+    const uint32_t pc = __popc(w);
+    const uint32_t inc = wave_incl_scan(pc);
+    const uint32_t base = c ? rank_at(sm.body, sm.sup, x0 + 2048 * c) - sm.arank[v] : 0u;
+    if (wq < nwords) sm.stage[sm.stg[v] + wq] = make_uint2(w, base + inc - pc);
+  }
+}
+
+// Count phase when the block does not fit in LDS: per level, one wave per
+// node popcounts the node's share straight from global memory and stages it.
+template <class C>
+__device__ void count_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_t maxd,
+                                const uint32_t *scratch, uint64_t scratch_words) {
+  const int wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  BlockHdr &h = sm.h;
+  NodeTab &t = sm.t;
+  const uint32_t *gin32 = reinterpret_cast<const uint32_t *>(J.in);
+  const uint64_t in_dw = J.in_len >> 2;
+  for (uint32_t d = 0; d < maxd; ++d) {
+    for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += C::NW) {
+      const uint32_t tvv = sm.tv[v];
+      const uint32_t nwords = (tvv + 31) / 32;
+      uint32_t base = 0;
+      if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
+      base = __builtin_amdgcn_readfirstlane(base);
+      if (base + nwords > static_cast<uint32_t>(C::STG)) {   // cannot happen: tile sized for it
+        if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
+        break;
+      }
+      const uint32_t s0 = sm.cur[v];
+      uint32_t carry = 0;
+      for (uint32_t q0 = 0; q0 < nwords; q0 += kWave) {
+        const uint32_t q = q0 + lane;
+        uint32_t w = 0;
+        if (q < nwords) {
+          const uint32_t p = s0 + 32 * q;
+          if (t.kind[v]) w = bits32_glb(scratch, 32 * (h.ans_word0 + t.boff[v]) + p, scratch_words);
+          else w = bits32_glb(gin32, 8 * (h.blk + t.boff[v]) + p, in_dw);
+          const uint32_t rem = tvv - 32 * q;
+          if (rem < 32) w &= (1u << rem) - 1;
+        }
+        const uint32_t pc = __popc(w);
+        const uint32_t inc = wave_incl_scan(pc);
+        if (q < nwords) sm.stage[base + q] = make_uint2(w, carry + inc - pc);
+        carry += __shfl(inc, kWave - 1, kWave);
+      }
+      const uint32_t ones = carry;
+      if (lane == 0) { sm.stg[v] = base; sm.ones[v] += ones; }
+      for (int bb = 0; bb < 2; ++bb) {
+        const uint16_t c = t.child[v][bb];
+        if (c & 0x8000) continue;
+        uint32_t tc = bb ? ones : tvv - ones;
+        if (sm.cur[c] + tc > t.nv[c]) {
+          if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+          tc = 0;
+        }
+        if (lane == 0) {
+          sm.tv[c] = tc;
+          sm.obase[c] = tc ? atomicAdd(&sm.out_top[d + 1], (tc + 3) & ~3u) : 0u;
+        }
+        const uint32_t nit = (tc + 255) / 256;
+        uint32_t ib = 0;
+        if (lane == 0 && nit) ib = atomicAdd(&sm.item_cnt[d + 1], nit);
+        ib = __builtin_amdgcn_readfirstlane(ib);
+        for (uint32_t j = lane; j < nit; j += kWave)
+          if (ib + j < static_cast<uint32_t>(C::ITEMS))
+            sm.items[d + 1][ib + j] = static_cast<uint16_t>((c << 8) | j);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Merge phase: bottom-up by level, one wave per item of 256 outputs.
+template <class C>
+__device__ void merge_levels(MergeSmem<C> &sm, uint32_t maxd, uint8_t *out) {
+  const int wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  NodeTab &t = sm.t;
+  for (int d = static_cast<int>(maxd) - 1; d >= 0; --d) {
+    const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
+    uint32_t *obuf = sm.lvl[d & 1];
+    const uint32_t nit = sm.item_cnt[d] < static_cast<uint32_t>(C::ITEMS) ? sm.item_cnt[d] : C::ITEMS;
+    for (uint32_t ii = wave; ii < nit; ii += C::NW) {
+      const uint32_t itv = sm.items[d][ii];
+      const uint32_t v = itv >> 8, c = itv & 255;
+      const uint32_t tvv = sm.tv[v];
+      const uint32_t j = 256 * c + 4 * lane;
+      if (j >= tvv) continue;
+      const uint2 wr = sm.stage[sm.stg[v] + (j >> 5)];
+      const uint32_t sh = j & 31;
+      const uint32_t m = (wr.x >> sh) & 15;
+      const uint32_t r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
+      const uint32_t r0 = j - r1;
+      const uint16_t cl = t.child[v][0], cr = t.child[v][1];
+      const uint32_t L = (cl & 0x8000) ? (cl & 255) * 0x01010101u : win4(cbuf, sm.obase[cl] + r0);
+      const uint32_t R = (cr & 0x8000) ? (cr & 255) * 0x01010101u : win4(cbuf, sm.obase[cr] + r1);
+      const uint32_t o = __builtin_amdgcn_perm(R, L, sm.sel[m]);
+      if (d == 0) {
+        uint8_t *dst = out + j;
+        if (j + 4 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 3)) {
+          *reinterpret_cast<uint32_t *>(dst) = o;
+        } else {
+          const uint32_t k = tvv - j < 4 ? tvv - j : 4;
+          for (uint32_t e = 0; e < k; ++e) dst[e] = static_cast<uint8_t>(o >> (8 * e));
+        }
+      } else {
+        obuf[(sm.obase[v] + j) >> 2] = o;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 template <class C>
@@ -532,12 +786,13 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
   }
   const uint32_t I = h.I;
   const uint64_t blk = h.blk;
-  // ---- decide residency and copy all node bitmaps into LDS ----------------
+  // ---- residency: all node bitmaps of the block in LDS --------------------
   const uint64_t g0 = (blk + h.raw_base) & ~15ull;
   const uint64_t g1 = (blk + h.raw_end + 15) & ~15ull;
   const uint64_t raw_bytes = g1 - g0;
   const uint64_t ans_bytes = 4ull * h.ans_words;
-  const bool resident = raw_bytes + ans_bytes + 16 <= static_cast<uint64_t>(C::BODY);
+  const bool resident = raw_bytes + ans_bytes + 64 <= static_cast<uint64_t>(C::BODY);
+  uint32_t body_dw = 0;
   if (resident) {
     const uint64_t in_dw = J.in_len >> 2;
     const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
@@ -560,9 +815,11 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
       const uint64_t q = h.ans_word0 + i;
       sm.body[abase + i] = q < scratch_words ? scratch[q] : 0u;
     }
-    for (uint32_t i = tid; i < 8; i += C::NT) sm.body[abase + h.ans_words + i] = 0u;
+    body_dw = abase + h.ans_words;
+    // zero tail up to the next superblock plus one
+    for (uint32_t i = body_dw + tid; i < ((body_dw + 7) & ~7u) + 8; i += C::NT) sm.body[i] = 0u;
     for (uint32_t i = tid; i < I; i += C::NT)
-      sm.src[i] = t.kind[i] ? 4 * (abase + t.boff[i]) : static_cast<uint32_t>(blk + t.boff[i] - g0);
+      sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : static_cast<uint32_t>(blk + t.boff[i] - g0));
   }
   if (tid < 16) {
     // selector for v_perm_b32(R, L, sel): output byte k takes the left
@@ -579,10 +836,38 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
   for (uint32_t i = tid; i < I; i += C::NT) { sm.cur[i] = 0; sm.ones[i] = 0; }
   if (tid == 0) sm.tile = pick_tile<C>(h);
   __syncthreads();
+  if (resident) {
+    // rank directory: exclusive prefix of popcounts over 256-bit superblocks
+    const uint32_t nsb = (body_dw + 7) / 8 + 1;
+    const uint32_t per = (nsb + C::NT - 1) / C::NT;
+    const uint32_t s0 = tid * per;
+    uint32_t loc = 0;
+    for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
+      uint32_t c = 0;
+      for (int i = 0; i < 8; ++i) c += __popc(sm.body[8 * k + i]);
+      sm.sup[k] = c;
+      loc += c;
+    }
+    const uint32_t inc = wave_incl_scan(loc);
+    if (lane == kWave - 1) sm.scan_tot[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - loc;
+    for (int w = 0; w < wave; ++w) run += sm.scan_tot[w];
+    for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
+      const uint32_t c = sm.sup[k];
+      sm.sup[k] = run;
+      run += c;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < I; i += C::NT) {
+      const uint32_t r = rank_at(sm.body, sm.sup, sm.abit[i]);
+      sm.r0[i] = r;
+      sm.arank[i] = r;
+    }
+    __syncthreads();
+  }
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
-  const uint32_t *gin32 = reinterpret_cast<const uint32_t *>(J.in);
-  const uint64_t in_dw = J.in_len >> 2;
   bool bad = false;
 
   for (uint32_t t0 = 0; t0 < n; t0 += T) {
@@ -595,110 +880,30 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     }
     for (uint32_t j = tid; j < (troot + 255) / 256; j += C::NT) sm.items[0][j] = static_cast<uint16_t>(j);
     __syncthreads();
-    // ---- count phase: top-down -------------------------------------------
-    for (uint32_t d = 0; d < maxd; ++d) {
-      for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += C::NW) {
-        const uint32_t tvv = sm.tv[v];
-        const uint32_t nwords = (tvv + 31) / 32;
-        uint32_t base = 0;
-        if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
-        base = __builtin_amdgcn_readfirstlane(base);
-        if (base + nwords > static_cast<uint32_t>(C::STG)) {   // cannot happen: tile sized for it
-          if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
-          break;
-        }
-        const uint32_t s0 = sm.cur[v];
-        uint32_t carry = 0;
-        for (uint32_t q0 = 0; q0 < nwords; q0 += kWave) {
-          const uint32_t q = q0 + lane;
-          uint32_t w = 0;
-          if (q < nwords) {
-            const uint32_t p = s0 + 32 * q;
-            if (resident) {
-              w = bits32_lds(sm.body, 8 * sm.src[v] + p);
-            } else if (t.kind[v]) {
-              w = bits32_glb(scratch, 32 * (h.ans_word0 + t.boff[v]) + p, scratch_words);
-            } else {
-              w = bits32_glb(gin32, 8 * (blk + t.boff[v]) + p, in_dw);
-            }
-            const uint32_t rem = tvv - 32 * q;
-            if (rem < 32) w &= (1u << rem) - 1;
-          }
-          const uint32_t pc = __popc(w);
-          const uint32_t inc = wave_incl_scan(pc);
-          if (q < nwords) sm.stage[base + q] = make_uint2(w, carry + inc - pc);
-          carry += __shfl(inc, kWave - 1, kWave);
-        }
-        const uint32_t ones = carry;
-        if (lane == 0) { sm.stg[v] = base; sm.ones[v] += ones; }
-        for (int bb = 0; bb < 2; ++bb) {
-          const uint16_t c = t.child[v][bb];
-          if (c & 0x8000) continue;
-          uint32_t tc = bb ? ones : tvv - ones;
-          if (sm.cur[c] + tc > t.nv[c]) {      // more symbols than the node holds
-            if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-            tc = 0;
-          }
-          if (lane == 0) {
-            sm.tv[c] = tc;
-            sm.obase[c] = tc ? atomicAdd(&sm.out_top[d + 1], (tc + 3) & ~3u) : 0u;
-          }
-          const uint32_t nit = (tc + 255) / 256;
-          uint32_t ib = 0;
-          if (lane == 0 && nit) ib = atomicAdd(&sm.item_cnt[d + 1], nit);
-          ib = __builtin_amdgcn_readfirstlane(ib);
-          for (uint32_t j = lane; j < nit; j += kWave)
-            if (ib + j < static_cast<uint32_t>(C::ITEMS))
-              sm.items[d + 1][ib + j] = static_cast<uint16_t>((c << 8) | j);
-        }
-      }
+    if (resident) {
+      if (wave == 0) count_resident<C>(sm, maxd);
       __syncthreads();
-    }
-    if (h.err) { bad = true; break; }
-    // ---- merge phase: bottom-up ------------------------------------------
-    for (int d = static_cast<int>(maxd) - 1; d >= 0; --d) {
-      const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
-      uint32_t *obuf = sm.lvl[d & 1];
-      const uint32_t nit = sm.item_cnt[d] < static_cast<uint32_t>(C::ITEMS) ? sm.item_cnt[d] : C::ITEMS;
-      for (uint32_t ii = wave; ii < nit; ii += C::NW) {
-        const uint32_t itv = sm.items[d][ii];
-        const uint32_t v = itv >> 8, c = itv & 255;
-        const uint32_t tvv = sm.tv[v];
-        const uint32_t j = 256 * c + 4 * lane;
-        if (j >= tvv) continue;
-        const uint2 wr = sm.stage[sm.stg[v] + (j >> 5)];
-        const uint32_t sh = j & 31;
-        const uint32_t m = (wr.x >> sh) & 15;
-        const uint32_t r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
-        const uint32_t r0 = j - r1;
-        const uint16_t cl = t.child[v][0], cr = t.child[v][1];
-        const uint32_t L = (cl & 0x8000) ? (cl & 255) * 0x01010101u : win4(cbuf, sm.obase[cl] + r0);
-        const uint32_t R = (cr & 0x8000) ? (cr & 255) * 0x01010101u : win4(cbuf, sm.obase[cr] + r1);
-        const uint32_t o = __builtin_amdgcn_perm(R, L, sm.sel[m]);
-        if (d == 0) {
-          uint8_t *dst = out + t0 + j;
-          if (j + 4 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 3)) {
-            *reinterpret_cast<uint32_t *>(dst) = o;
-          } else {
-            const uint32_t k = tvv - j < 4 ? tvv - j : 4;
-            for (uint32_t e = 0; e < k; ++e) dst[e] = static_cast<uint8_t>(o >> (8 * e));
-          }
-        } else {
-          obuf[(sm.obase[v] + j) >> 2] = o;
-        }
-      }
+      if (h.err) { bad = true; break; }
+      stage_resident<C>(sm);
       __syncthreads();
+    } else {
+      count_streaming<C>(J, sm, maxd, scratch, scratch_words);
+      if (h.err) { bad = true; break; }
     }
+    merge_levels<C>(sm, maxd, out + t0);
     for (uint32_t i = tid; i < I; i += C::NT) {
       sm.cur[i] += sm.tv[i];
+      if (resident) sm.arank[i] = sm.anext[i];
       sm.tv[i] = 0;
     }
     __syncthreads();
   }
   if (!bad) {
-    for (uint32_t i = tid; i < I; i += C::NT)
-      if (sm.cur[i] != t.nv[i] || sm.ones[i] != t.nr[i])
+    for (uint32_t i = tid; i < I; i += C::NT) {
+      const uint32_t ones = resident ? sm.arank[i] - sm.r0[i] : sm.ones[i];
+      if (sm.cur[i] != t.nv[i] || ones != t.nr[i])
         atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+    }
   }
   __syncthreads();
   if (tid == 0 && h.err) set_err(J.status, h.err);
@@ -753,8 +958,8 @@ __global__ void k_gather_headers(const pivco_job *jobs, uint32_t count, uint8_t 
 // host-side launch table
 // ---------------------------------------------------------------------------
 using Cfg0 = MergeCfg<1024, 16384, 65536>;
-using Cfg1 = MergeCfg<1024, 8192, 98304>;
-using Cfg2 = MergeCfg<512, 8192, 49152>;
+using Cfg1 = MergeCfg<1024, 8192, 90112>;
+using Cfg2 = MergeCfg<512, 4096, 40960>;
 
 struct MergeVariant {
   const char *name;
@@ -788,8 +993,8 @@ uint32_t merge_variant_count() { return 3; }
 const char *merge_variant_name(uint32_t v) {
   switch (v) {
     case 0: return "wg1024_tile16k_lds64k";
-    case 1: return "wg1024_tile8k_lds96k";
-    case 2: return "wg512_tile8k_lds48k";
+    case 1: return "wg1024_tile8k_lds88k";
+    case 2: return "wg512_tile4k_lds40k";
     default: return "?";
   }
 }

@@ -1,0 +1,377 @@
+// serve.cpp -- continuous-batching decode server.
+//
+// Streams (already encoded, resident in device memory) are registered once;
+// their headers are read at registration, so planning a batch later needs no
+// device round trip.  run() replays a trace of (arrival time, request) pairs
+// in real time on the host clock:
+//   * arrivals join a FIFO;
+//   * a request is admitted when an execution slot is free and its output
+//     buffer fits in the device-memory budget (a first-fit allocator over a
+//     caller-provided pool); a request larger than the whole budget fails
+//     with PIVCO_E_BUDGET;
+//   * each admission round packs the admitted requests into one batch:
+//     job table + LPT work queue uploaded from pinned memory, then the same
+//     init / rANS / merge kernels as pivco_decode_batch, on the slot's own
+//     stream, so batches on different slots overlap on the device;
+//   * completion is polled with hipEventQuery; latency = completion time on
+//     the host clock minus arrival time; the output space is released.
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "pivco_int.h"
+
+namespace pivco {
+uint32_t merge_variant_count();
+int merge_variant_occupancy(uint32_t v);
+hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
+                        const uint2 *items, uint32_t n_items, Counters *ctr,
+                        const uint32_t *scratch, uint64_t scratch_words, int32_t single);
+hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
+                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single);
+int rans_occupancy();
+hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
+                       uint32_t count);
+}  // namespace pivco
+
+using namespace pivco;
+
+namespace {
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+struct Registered {
+  const uint8_t *d_in;
+  uint64_t in_len;
+  uint64_t n_total, ans_words;
+  uint32_t n_blocks, block_size, max_len, chunk_log2;
+};
+
+// First-fit allocator over [0, size) with coalescing on free.
+class PoolAlloc {
+ public:
+  void reset(uint64_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(uint64_t n, uint64_t *off) {
+    n = align_up(std::max<uint64_t>(n, 1), 256);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const uint64_t rest = it->second - n, start = it->first + n;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += n;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t n) {
+    n = align_up(std::max<uint64_t>(n, 1), 256);
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t used() const { return used_; }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;
+  uint64_t used_ = 0;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  uint8_t *ws = nullptr;          // device workspace of this slot
+  uint8_t *pinned = nullptr;      // host staging of job table + queue
+  bool busy = false;
+  std::vector<uint32_t> reqs;     // trace indices in this batch
+};
+
+}  // namespace
+
+struct pivco_server {
+  pivco_server_opts opts{};
+  std::vector<Registered> reg;
+  std::vector<Slot> slots;
+  uint64_t ws_bytes_per_slot = 0, pinned_bytes = 0;
+  // workspace layout inside a slot
+  uint64_t off_ctr = 0, off_jobs = 0, off_items = 0, off_ritems = 0, off_status0 = 0,
+           off_status = 0, off_scratch = 0;
+  uint64_t off_pstatus = 0;
+  uint32_t max_items = 0;
+  uint64_t max_scratch_words = 0;
+};
+
+extern "C" {
+
+pivco_status pivco_server_create(const pivco_server_opts *o, pivco_server **out) {
+  if (!o || !out || o->slots == 0 || o->slots > 16 || o->max_batch == 0 || o->max_blocks == 0)
+    return PIVCO_E_ARG;
+  pivco_server *sv = new pivco_server();
+  sv->opts = *o;
+  sv->max_items = o->max_blocks;
+  sv->max_scratch_words = o->max_scratch_words;
+  uint64_t x = 0;
+  sv->off_ctr = x; x += 256;
+  sv->off_jobs = x; x = align_up(x + sizeof(JobDev) * o->max_batch, 256);
+  sv->off_items = x; x = align_up(x + 8ull * o->max_blocks, 256);
+  sv->off_ritems = x; x = align_up(x + 8ull * o->max_blocks, 256);
+  sv->off_status0 = x; x = align_up(x + 4ull * o->max_batch, 256);
+  const uint64_t pinned = x;          // job table .. status0 staged from pinned memory
+  sv->off_status = x; x = align_up(x + 4ull * o->max_batch, 256);
+  sv->off_pstatus = pinned;           // statuses copied back into pinned memory
+  sv->off_scratch = x; x = align_up(x + 4ull * o->max_scratch_words + 64, 256);
+  sv->ws_bytes_per_slot = x;
+  sv->pinned_bytes = pinned;
+  sv->slots.resize(o->slots);
+  for (auto &s : sv->slots) {
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s.ws, sv->ws_bytes_per_slot) != hipSuccess ||
+        hipHostMalloc(&s.pinned, pinned + 4ull * o->max_batch, hipHostMallocDefault) != hipSuccess) {
+      pivco_server_destroy(sv);
+      return PIVCO_E_DEVICE;
+    }
+  }
+  *out = sv;
+  return PIVCO_OK;
+}
+
+void pivco_server_destroy(pivco_server *sv) {
+  if (!sv) return;
+  for (auto &s : sv->slots) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.ws) (void)hipFree(s.ws);
+    if (s.pinned) (void)hipHostFree(s.pinned);
+  }
+  delete sv;
+}
+
+uint64_t pivco_server_workspace_bytes(const pivco_server *sv) {
+  return sv ? sv->ws_bytes_per_slot * sv->slots.size() : 0;
+}
+
+pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint64_t len,
+                                   uint32_t *id) {
+  if (!sv || !d_stream || !id || (reinterpret_cast<uintptr_t>(d_stream) & 15) || len < kHeaderBytes)
+    return PIVCO_E_ARG;
+  uint8_t h[kHeaderBytes];
+  if (hipMemcpy(h, d_stream, kHeaderBytes, hipMemcpyDeviceToHost) != hipSuccess) return PIVCO_E_DEVICE;
+  uint64_t n_total, ans;
+  uint32_t nb, bs;
+  pivco_status st = pivco_stream_info(h, kHeaderBytes, &n_total, &nb, &bs, &ans);
+  if (st) return st;
+  if (len < kHeaderBytes + 16ull * (nb + 1ull)) return PIVCO_E_CORRUPT;
+  if (nb > sv->max_items || ans > sv->max_scratch_words) return PIVCO_E_UNSUPPORTED;
+  Registered r;
+  r.d_in = static_cast<const uint8_t *>(d_stream);
+  r.in_len = len;
+  r.n_total = n_total;
+  r.ans_words = ans;
+  r.n_blocks = nb;
+  r.block_size = bs;
+  r.max_len = h[24];
+  r.chunk_log2 = h[25];
+  *id = static_cast<uint32_t>(sv->reg.size());
+  sv->reg.push_back(r);
+  return PIVCO_OK;
+}
+
+pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint32_t n_req,
+                              void *d_pool, uint64_t pool_bytes, pivco_request_result *res,
+                              pivco_server_stats *stats) {
+  if (!sv || (n_req && (!reqs || !res)) || (pool_bytes && !d_pool)) return PIVCO_E_ARG;
+  for (uint32_t i = 0; i < n_req; ++i)
+    if (reqs[i].id >= sv->reg.size()) return PIVCO_E_ARG;
+  if (pool_bytes > sv->opts.mem_budget) pool_bytes = sv->opts.mem_budget;
+  PoolAlloc pool;
+  pool.reset(pool_bytes);
+  uint8_t *pool_base = static_cast<uint8_t *>(d_pool);
+  const int cus = [] {
+    int dev = 0, c = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      c = 256;
+    return c > 0 ? c : 256;
+  }();
+  const uint32_t variant = sv->opts.merge_variant < merge_variant_count() ? sv->opts.merge_variant : 0;
+  const uint32_t mgrid_full = static_cast<uint32_t>(cus * merge_variant_occupancy(variant));
+  const uint32_t rgrid_full = static_cast<uint32_t>(cus * rans_occupancy());
+  std::vector<uint64_t> out_off(n_req, 0);
+  std::deque<uint32_t> pending;
+  uint32_t next = 0, done = 0;
+  uint64_t peak = 0, bytes_done = 0, batches = 0, max_batch_seen = 0;
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto now_s = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  for (uint32_t i = 0; i < n_req; ++i) {
+    res[i].status = PIVCO_OK;
+    res[i].d_out = nullptr;
+    res[i].n_out = sv->reg[reqs[i].id].n_total;
+    res[i].t_admit = res[i].t_done = -1.0;
+  }
+  while (done < n_req) {
+    const double now = now_s();
+    while (next < n_req && reqs[next].arrival_s <= now) pending.push_back(next++);
+    bool progressed = false;
+    // completions
+    for (auto &s : sv->slots) {
+      if (!s.busy) continue;
+      const hipError_t q = hipEventQuery(s.done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return PIVCO_E_DEVICE;
+      const double t = now_s();
+      const int32_t *st = reinterpret_cast<const int32_t *>(s.pinned + sv->off_pstatus);
+      for (size_t k = 0; k < s.reqs.size(); ++k) {
+        const uint32_t r = s.reqs[k];
+        res[r].t_done = t;
+        res[r].status = st[k];
+        bytes_done += res[r].n_out;
+        if (!sv->opts.keep_outputs) pool.release(out_off[r], res[r].n_out);
+        ++done;
+      }
+      s.reqs.clear();
+      s.busy = false;
+      progressed = true;
+    }
+    // admissions: one batch per free slot
+    for (auto &s : sv->slots) {
+      if (s.busy || pending.empty()) continue;
+      std::vector<uint32_t> batch;
+      uint64_t items = 0, scratch = 0;
+      while (!pending.empty() && batch.size() < sv->opts.max_batch) {
+        const uint32_t r = pending.front();
+        const Registered &g = sv->reg[reqs[r].id];
+        const uint64_t need = g.n_total;
+        if (align_up(std::max<uint64_t>(need, 1), 256) > pool_bytes) {   // can never fit
+          res[r].status = PIVCO_E_BUDGET;
+          res[r].t_admit = res[r].t_done = now_s();
+          pending.pop_front();
+          ++done;
+          progressed = true;
+          continue;
+        }
+        if (items + g.n_blocks > sv->max_items ||
+            align_up(scratch + g.ans_words, 4) > sv->max_scratch_words)
+          break;
+        uint64_t off = 0;
+        if (!pool.alloc(need, &off)) break;          // wait for memory to free up
+        out_off[r] = off;
+        res[r].d_out = pool_base + off;
+        res[r].t_admit = now_s();
+        items += g.n_blocks;
+        scratch = align_up(scratch + g.ans_words, 4);
+        batch.push_back(r);
+        pending.pop_front();
+      }
+      if (batch.empty()) continue;
+      peak = std::max(peak, pool.used());
+      // plan the batch in pinned memory, then upload and launch
+      JobDev *jobs = reinterpret_cast<JobDev *>(s.pinned + sv->off_jobs);
+      uint2 *it = reinterpret_cast<uint2 *>(s.pinned + sv->off_items);
+      uint2 *rit = reinterpret_cast<uint2 *>(s.pinned + sv->off_ritems);
+      int32_t *st0 = reinterpret_cast<int32_t *>(s.pinned + sv->off_status0);
+      std::vector<std::pair<uint64_t, uint2>> sized;
+      uint32_t nr = 0;
+      uint64_t sw = 0;
+      for (uint32_t k = 0; k < batch.size(); ++k) {
+        const Registered &g = sv->reg[reqs[batch[k]].id];
+        JobDev d{};
+        d.in = g.d_in;
+        d.in_len = g.in_len;
+        d.out = static_cast<uint8_t *>(res[batch[k]].d_out);
+        d.out_cap = g.n_total;
+        d.n_total = g.n_total;
+        d.scratch_base = sw;
+        d.n_blocks = g.n_blocks;
+        d.block_size = g.block_size;
+        d.max_len = g.max_len;
+        d.chunk_log2 = g.chunk_log2;
+        d.status = reinterpret_cast<int32_t *>(s.ws + sv->off_status) + k;
+        jobs[k] = d;
+        st0[k] = PIVCO_OK;
+        sw = align_up(sw + g.ans_words, 4);
+        for (uint32_t b = 0; b < g.n_blocks; ++b) {
+          const uint64_t start = static_cast<uint64_t>(b) * g.block_size;
+          sized.push_back({std::min<uint64_t>(g.block_size, g.n_total - start), make_uint2(k, b)});
+          if (g.ans_words) rit[nr++] = make_uint2(k, b);
+        }
+      }
+      std::stable_sort(sized.begin(), sized.end(),
+                       [](const std::pair<uint64_t, uint2> &a, const std::pair<uint64_t, uint2> &b) {
+                         return a.first > b.first;
+                       });
+      for (size_t i = 0; i < sized.size(); ++i) it[i] = sized[i].second;
+      const uint32_t ni = static_cast<uint32_t>(sized.size());
+      if (hipMemcpyAsync(s.ws, s.pinned, sv->pinned_bytes, hipMemcpyHostToDevice, s.stream) != hipSuccess)
+        return PIVCO_E_DEVICE;
+      Counters *ctr = reinterpret_cast<Counters *>(s.ws + sv->off_ctr);
+      const JobDev *dj = reinterpret_cast<const JobDev *>(s.ws + sv->off_jobs);
+      uint32_t *scr = reinterpret_cast<uint32_t *>(s.ws + sv->off_scratch);
+      if (launch_init(s.stream, ctr, reinterpret_cast<int32_t *>(s.ws + sv->off_status),
+                      reinterpret_cast<const int32_t *>(s.ws + sv->off_status0),
+                      static_cast<uint32_t>(batch.size())) != hipSuccess)
+        return PIVCO_E_DEVICE;
+      if (nr && launch_rans(std::max<uint32_t>(1, std::min(rgrid_full, nr)), s.stream, dj,
+                            reinterpret_cast<const uint2 *>(s.ws + sv->off_ritems), nr, ctr, scr,
+                            -1) != hipSuccess)
+        return PIVCO_E_DEVICE;
+      if (ni && launch_merge(variant, std::max<uint32_t>(1, std::min(mgrid_full, ni)), s.stream, dj,
+                             reinterpret_cast<const uint2 *>(s.ws + sv->off_items), ni, ctr, scr,
+                             sw, -1) != hipSuccess)
+        return PIVCO_E_DEVICE;
+      if (hipMemcpyAsync(s.pinned + sv->off_pstatus, s.ws + sv->off_status, 4 * batch.size(),
+                         hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+        return PIVCO_E_DEVICE;
+      if (hipEventRecord(s.done, s.stream) != hipSuccess) return PIVCO_E_DEVICE;
+      s.reqs = batch;
+      s.busy = true;
+      ++batches;
+      max_batch_seen = std::max<uint64_t>(max_batch_seen, batch.size());
+      progressed = true;
+    }
+    if (!progressed) {
+      // nothing to do right now: wait for the next arrival or a completion
+      const bool any_busy = std::any_of(sv->slots.begin(), sv->slots.end(), [](const Slot &s) { return s.busy; });
+      if (!any_busy && next < n_req && pending.empty()) {
+        const double wait = reqs[next].arrival_s - now_s();
+        if (wait > 200e-6) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 100e-6));
+      } else {
+        std::this_thread::yield();
+      }
+    }
+  }
+  if (stats) {
+    stats->wall_s = now_s();
+    stats->bytes_decoded = bytes_done;
+    stats->peak_pool_bytes = peak;
+    stats->batches = batches;
+    stats->max_batch = max_batch_seen;
+  }
+  return PIVCO_OK;
+}
+
+}  // extern "C"

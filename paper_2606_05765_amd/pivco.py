@@ -51,6 +51,27 @@ class Tune(C.Structure):
                 "rans_grid": self.rans_grid}
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("mem_budget", C.c_uint64), ("slots", C.c_uint32), ("max_batch", C.c_uint32),
+                ("max_blocks", C.c_uint32), ("merge_variant", C.c_uint32),
+                ("max_scratch_words", C.c_uint64), ("keep_outputs", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("id", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_uint32), ("d_out", C.c_void_p),
+                ("n_out", C.c_uint64), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("wall_s", C.c_double), ("bytes_decoded", C.c_uint64),
+                ("peak_pool_bytes", C.c_uint64), ("batches", C.c_uint64), ("max_batch", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -84,6 +105,12 @@ def lib():
             "pivco_batch_plan_destroy": (None, [vp]),
             "pivco_autotune": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp, C.POINTER(Tune)]),
             "pivco_strerror": (C.c_char_p, [i32]),
+            "pivco_server_create": (i32, [C.POINTER(ServerOpts), C.POINTER(vp)]),
+            "pivco_server_destroy": (None, [vp]),
+            "pivco_server_workspace_bytes": (u64, [vp]),
+            "pivco_server_register": (i32, [vp, vp, u64, u32p]),
+            "pivco_server_run": (i32, [vp, C.POINTER(Request), u32, vp, u64,
+                                       C.POINTER(RequestResult), C.POINTER(ServerStats)]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -298,3 +325,61 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """pivco_server_*: continuous-batching decode of resident streams."""
+
+    def __init__(self, mem_budget, slots=4, max_batch=64, max_blocks=1 << 16,
+                 max_scratch_words=1 << 24, merge_variant=0, keep_outputs=False):
+        o = ServerOpts(int(mem_budget), slots, max_batch, max_blocks, merge_variant,
+                       max_scratch_words, 1 if keep_outputs else 0, 0)
+        self.handle = C.c_void_p()
+        _check(lib().pivco_server_create(C.byref(o), C.byref(self.handle)), "pivco_server_create")
+        self.streams = []
+
+    def register(self, stream):
+        stream = _dev_u8(stream)
+        rid = C.c_uint32(0)
+        _check(lib().pivco_server_register(self.handle, C.c_void_p(stream.data_ptr()),
+                                           stream.numel(), C.byref(rid)), "pivco_server_register")
+        self.streams.append(stream)
+        return rid.value
+
+    def workspace_bytes(self):
+        return int(lib().pivco_server_workspace_bytes(self.handle))
+
+    def run(self, arrivals, ids, pool):
+        """Replay (arrival_s, id) pairs; returns (results list of dicts, stats dict)."""
+        n = len(ids)
+        reqs = (Request * max(n, 1))()
+        for i, (a, r) in enumerate(zip(arrivals, ids)):
+            reqs[i].arrival_s = float(a)
+            reqs[i].id = int(r)
+        res = (RequestResult * max(n, 1))()
+        st = ServerStats()
+        _check(lib().pivco_server_run(self.handle, reqs, n, C.c_void_p(pool.data_ptr()), pool.numel(),
+                                      res, C.byref(st)), "pivco_server_run")
+        out = [{"status": res[i].status, "d_out": res[i].d_out, "n_out": res[i].n_out,
+                "t_admit": res[i].t_admit, "t_done": res[i].t_done, "arrival": float(arrivals[i])}
+               for i in range(n)]
+        return out, {"wall_s": st.wall_s, "bytes_decoded": st.bytes_decoded,
+                     "peak_pool_bytes": st.peak_pool_bytes, "batches": st.batches,
+                     "max_batch": st.max_batch}
+
+    def close(self):
+        if self.handle:
+            lib().pivco_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def view_output(pool, d_out, n):
+    """The decoded bytes of one served request as a tensor view into pool."""
+    off = int(d_out) - pool.data_ptr()
+    return pool[off:off + n]

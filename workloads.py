@@ -34,18 +34,31 @@ _CHUNK = 1 << 24  # symbols drawn per step, bounds temporary memory
 
 
 def draw(rng: np.random.Generator, p: np.ndarray, n: int) -> np.ndarray:
-    """n i.i.d. symbols from the distribution p over 256 ids (inverse CDF on
-    32-bit integers)."""
+    """n i.i.d. symbols from the distribution p over 256 ids: inverse CDF on
+    32-bit integers (symbol = number of CDF edges <= u).  A 65536-entry table
+    answers every u whose upper 16 bits select a bucket without an edge inside;
+    the few remaining values use a binary search, so the result equals the
+    plain search exactly."""
     p = np.asarray(p, dtype=np.float64)
     p = p / p.sum()
     cdf = np.minimum(np.floor(np.cumsum(p) * 2.0 ** 32), 2.0 ** 32).astype(np.uint64)
     cdf[-1] = 1 << 32
     edges = cdf[:-1]
+    lo = np.arange(1 << 16, dtype=np.uint64) << np.uint64(16)
+    base = np.searchsorted(edges, lo, side="right")
+    top = np.searchsorted(edges, lo + np.uint64(0xFFFF), side="right")
+    table = base.astype(np.uint8)
+    pure = base == top
     out = np.empty(n, dtype=np.uint8)
     for s in range(0, n, _CHUNK):
         k = min(_CHUNK, n - s)
         u = rng.integers(0, 1 << 32, size=k, dtype=np.uint64)
-        out[s:s + k] = np.searchsorted(edges, u, side="right").astype(np.uint8)
+        hi = (u >> np.uint64(16)).astype(np.int64)
+        sym = table[hi]
+        mixed = np.flatnonzero(~pure[hi])
+        if mixed.size:
+            sym[mixed] = np.searchsorted(edges, u[mixed], side="right").astype(np.uint8)
+        out[s:s + k] = sym
     return out
 
 
