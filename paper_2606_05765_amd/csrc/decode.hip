@@ -459,12 +459,12 @@ struct MergeCfg {
   static constexpr int T = T_;                        // output symbols per tile
   static constexpr int BODY = BODY_;                  // resident bitmap bytes
   static constexpr int NW = NT / kWave;
-  static constexpr int STG = 6 * (T / 32) + 2 * 256;  // staged words per tile
-  static constexpr int LVL = T + 4 * 128 + 16;        // bytes per level buffer
-  static constexpr int ITEMS = T / 256 + 129;         // merge items per level
-  static constexpr int SITEMS = 6 * (T / 2048) + 256 + 16;  // staging items per tile
+  static constexpr int CH = 1024;                     // outputs per merge item (16 per lane)
+  static constexpr int LVL = T + 16 * 128 + 64;       // bytes per level buffer
   static constexpr int LEVELS = kMaxLenGpu;
-  static constexpr int SUP = BODY / 32 + 8;           // rank directory entries
+  static constexpr int STG = BODY / 8;                // streaming: staged (word, rank) pairs
+  static constexpr int SUP = BODY / 32 + 8;           // rank directory, per 256 bits
+  static constexpr int REL = BODY / 8 + 32;           // rank directory, per 64 bits
 };
 
 template <class C>
@@ -473,61 +473,51 @@ struct MergeSmem {
   NodeTab t;
   uint32_t cur[256];       // bits of the node consumed by earlier tiles
   uint32_t tv[256];        // node's share of the current tile
-  uint32_t stg[256];       // first staged word of the node
-  uint32_t obase[256];     // node's output offset in its level buffer
+  uint32_t tone[256];      // 1 bits in that share
+  uint32_t obase[256];     // node's output offset in its level buffer (16-byte aligned)
   uint32_t abit[256];      // resident: LDS bit address of the node bitmap
   uint32_t arank[256];     // resident: 1 bits of the body before the cursor
   uint32_t anext[256];     // resident: same after this tile
   uint32_t r0[256];        // resident: 1 bits of the body before the node
   uint32_t ones[256];      // streaming: 1 bits seen so far
-  uint32_t out_top[C::LEVELS + 1];
-  uint32_t item_cnt[C::LEVELS + 1];
+  uint32_t stg[256];       // streaming: first staged word of the node
+  uint16_t pref[C::LEVELS + 1][132];  // merge items before each node of a level; [N] = total
   uint32_t stage_top;
-  uint32_t sitem_cnt;
   uint32_t tile;           // runtime tile size for this block
   uint32_t sel[16];
   uint32_t item;
   uint32_t scan_tot[C::NW];
-  uint2 stage[C::STG];
-  uint32_t lvl[2][C::LVL / 4];
-  uint16_t items[C::LEVELS + 1][C::ITEMS];
-  uint32_t sitems[C::SITEMS];
+  uint32_t lvl[2][C::LVL / 4] __attribute__((aligned(16)));
   uint32_t sup[C::SUP];    // resident: 1 bits of the body before each 256-bit superblock
+  uint8_t rel[C::REL];     // resident: 1 bits of the superblock before each 64-bit word
   uint32_t body[C::BODY / 4 + 16] __attribute__((aligned(16)));
 };
 
-// Largest tile (multiple of 256, at most C::T) whose staged words fit.
+// Streaming tile: largest multiple of 1024 (at most C::T) whose staged words fit.
 template <class C>
-__device__ uint32_t pick_tile(const BlockHdr &h) {
+__device__ uint32_t pick_tile_streaming(const BlockHdr &h) {
   uint32_t T = C::T;
-  for (; T > 256; T -= 256) {
-    uint64_t need = h.I + h.maxlen + 1, sitems = 1;
+  for (; T > 1024; T -= 1024) {
+    uint64_t need = h.I + h.maxlen + 1;
     for (uint32_t d = 0; d < h.maxlen; ++d) {
       const uint64_t ld = h.lvl_total[d] < T ? h.lvl_total[d] : T;
-      const uint64_t nodes = h.lvl[d + 1] - h.lvl[d];
-      need += div_up(ld, 32) + nodes;
-      sitems += div_up(ld, 2048) + nodes;
+      need += div_up(ld, 32) + (h.lvl[d + 1] - h.lvl[d]);
     }
-    if (need <= static_cast<uint64_t>(C::STG) && sitems <= static_cast<uint64_t>(C::SITEMS)) break;
+    if (need <= static_cast<uint64_t>(C::STG)) break;
   }
   return T;
 }
 
-// Number of 1 bits in LDS bits [0, x) of the resident body: superblock count
-// plus the popcounts of the superblock's dwords before x.
-__device__ __forceinline__ uint32_t rank_at(const uint32_t *body, const uint32_t *sup, uint32_t x) {
-  const uint32_t k = x >> 8;
-  const uint32_t q = (x >> 5) & 7;
-  const uint4 a = *reinterpret_cast<const uint4 *>(&body[8 * k]);
-  const uint4 c = *reinterpret_cast<const uint4 *>(&body[8 * k + 4]);
-  const uint32_t part = (1u << (x & 31)) - 1;
-  const uint32_t w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
-  uint32_t r = sup[k];
-#pragma unroll
-  for (uint32_t i = 0; i < 8; ++i) {
-    const uint32_t m = i < q ? 0xFFFFFFFFu : (i == q ? part : 0u);
-    r += __popc(w[i] & m);
-  }
+// Number of 1 bits in LDS bits [0, x) of the resident body: 256-bit
+// superblock count + 64-bit word count within it + popcount of the rest.
+__device__ __forceinline__ uint32_t rank_at(const uint32_t *body, const uint32_t *sup,
+                                            const uint8_t *rel, uint32_t x) {
+  const uint32_t q = x >> 6;
+  const uint32_t d0 = body[2 * q], d1 = body[2 * q + 1];
+  const uint32_t b = x & 63;
+  uint32_t r = sup[x >> 8] + rel[q];
+  if (b >= 32) r += __popc(d0) + __popc(d1 & ((1u << (b - 32)) - 1));
+  else r += __popc(d0 & ((1u << b) - 1));
   return r;
 }
 
@@ -538,222 +528,186 @@ __device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total
   return inc - v;
 }
 
-// Count phase on the resident body, run by wave 0 alone (no workgroup
-// barriers): level by level, every node's share of the tile gives its right
-// child's share as one rank difference, and the node's staging words, its
-// children's output space and the merge/staging work items are allocated
-// with wave-wide prefix sums.
-template <class C>
-__device__ void count_resident(MergeSmem<C> &sm, uint32_t maxd) {
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Allocation for the children of level d, run by one wave: every node's
+// share (sm.tv) and its 1 bits (sm.tone) give the children's shares; their
+// output space in the level buffer and their merge items (a prefix array in
+// breadth-first order) come from wave-wide prefix sums.  In resident mode
+// the 1 bits are computed here from the rank directory.
+template <class C, bool RESIDENT>
+__device__ void count_level(MergeSmem<C> &sm, uint32_t d) {
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.h;
   NodeTab &t = sm.t;
-  uint32_t stage_top = 0, sitem_top = 0;
-  for (uint32_t d = 0; d < maxd; ++d) {
-    uint32_t out_top = 0, item_top = 0;
-    for (uint32_t v0 = h.lvl[d]; v0 < h.lvl[d + 1]; v0 += kWave) {
-      const uint32_t v = v0 + lane;
-      const bool valid = v < h.lvl[d + 1];
-      uint32_t tvv = 0, ones = 0, tc[2] = {0, 0};
-      uint16_t ch[2] = {0x8000, 0x8000};
-      if (valid) {
-        tvv = sm.tv[v];
+  uint32_t out_top = 0, item_top = 0;
+  for (uint32_t v0 = h.lvl[d]; v0 < h.lvl[d + 1]; v0 += kWave) {
+    const uint32_t v = v0 + lane;
+    const bool valid = v < h.lvl[d + 1];
+    uint32_t tvv = 0, ones = 0, tc[2] = {0, 0};
+    uint16_t ch[2] = {0x8000, 0x8000};
+    if (valid) {
+      tvv = sm.tv[v];
+      if (RESIDENT) {
         const uint32_t a = sm.arank[v];
-        const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.abit[v] + sm.cur[v] + tvv) : a;
+        const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.rel, sm.abit[v] + sm.cur[v] + tvv) : a;
         sm.anext[v] = e;
         ones = e - a;
-        ch[0] = t.child[v][0];
-        ch[1] = t.child[v][1];
-        tc[0] = tvv - ones;
-        tc[1] = ones;
-        for (int bb = 0; bb < 2; ++bb) {
-          if (ch[bb] & 0x8000) { tc[bb] = 0; continue; }
-          if (sm.cur[ch[bb]] + tc[bb] > t.nv[ch[bb]]) {     // more symbols than the node holds
-            atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-            tc[bb] = 0;
-          }
+      } else {
+        ones = sm.tone[v];
+      }
+      ch[0] = t.child[v][0];
+      ch[1] = t.child[v][1];
+      tc[0] = tvv - ones;
+      tc[1] = ones;
+      for (int bb = 0; bb < 2; ++bb) {
+        if (ch[bb] & 0x8000) { tc[bb] = 0; continue; }
+        if (sm.cur[ch[bb]] + tc[bb] > t.nv[ch[bb]]) {     // more symbols than the node holds
+          atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+          tc[bb] = 0;
         }
       }
-      const uint32_t nwords = (tvv + 31) / 32, nsit = (tvv + 2047) / 2048;
-      const uint32_t o0 = (tc[0] + 3) & ~3u, o1 = (tc[1] + 3) & ~3u;
-      const uint32_t m0 = (tc[0] + 255) / 256, m1 = (tc[1] + 255) / 256;
-      // packed prefix sums: staged words | staging items | output bytes | merge items
-      const uint64_t pk = static_cast<uint64_t>(nwords) | (static_cast<uint64_t>(nsit) << 16) |
-                          (static_cast<uint64_t>(o0 + o1) << 24) | (static_cast<uint64_t>(m0 + m1) << 48);
-      uint64_t tot;
-      const uint64_t ex = wave_excl_scan64(pk, tot);
-      if (valid) {
-        const uint32_t stg = stage_top + static_cast<uint32_t>(ex & 0xFFFF);
-        const uint32_t sit = sitem_top + static_cast<uint32_t>((ex >> 16) & 0xFF);
-        const uint32_t ob = out_top + static_cast<uint32_t>((ex >> 24) & 0xFFFFFF);
-        const uint32_t mi = item_top + static_cast<uint32_t>(ex >> 48);
-        sm.stg[v] = stg;
-        for (uint32_t j = 0; j < nsit; ++j)
-          if (sit + j < static_cast<uint32_t>(C::SITEMS)) sm.sitems[sit + j] = (v << 16) | j;
-        uint32_t ob2 = ob, mi2 = mi;
-        for (int bb = 0; bb < 2; ++bb) {
-          if (ch[bb] & 0x8000) continue;
-          const uint16_t c = ch[bb];
-          sm.tv[c] = tc[bb];
-          sm.obase[c] = ob2;
-          const uint32_t nm = (tc[bb] + 255) / 256;
-          for (uint32_t j = 0; j < nm; ++j)
-            if (mi2 + j < static_cast<uint32_t>(C::ITEMS))
-              sm.items[d + 1][mi2 + j] = static_cast<uint16_t>((c << 8) | j);
-          ob2 += (tc[bb] + 3) & ~3u;
-          mi2 += nm;
-        }
+    }
+    const uint32_t o0 = (tc[0] + 15) & ~15u, o1 = (tc[1] + 15) & ~15u;
+    const uint32_t i0 = (tc[0] + C::CH - 1) / C::CH, i1 = (tc[1] + C::CH - 1) / C::CH;
+    const uint64_t pk = static_cast<uint64_t>(o0 + o1) | (static_cast<uint64_t>(i0 + i1) << 32);
+    uint64_t tot;
+    const uint64_t ex = wave_excl_scan64(pk, tot);
+    if (valid) {
+      uint32_t ob = out_top + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
+      uint32_t ib = item_top + static_cast<uint32_t>(ex >> 32);
+      for (int bb = 0; bb < 2; ++bb) {
+        if (ch[bb] & 0x8000) continue;
+        const uint16_t c = ch[bb];
+        sm.tv[c] = tc[bb];
+        sm.obase[c] = ob;
+        sm.pref[d + 1][c - h.lvl[d + 1]] = static_cast<uint16_t>(ib);
+        ob += bb ? o1 : o0;
+        ib += bb ? i1 : i0;
       }
-      stage_top += static_cast<uint32_t>(tot & 0xFFFF);
-      sitem_top += static_cast<uint32_t>((tot >> 16) & 0xFF);
-      out_top += static_cast<uint32_t>((tot >> 24) & 0xFFFFFF);
-      item_top += static_cast<uint32_t>(tot >> 48);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (lane == 0) sm.item_cnt[d + 1] = item_top;
+    out_top += static_cast<uint32_t>(tot & 0xFFFFFFFFu);
+    item_top += static_cast<uint32_t>(tot >> 32);
+    wave_sync_lds();
   }
-  if (lane == 0) {
-    sm.stage_top = stage_top;
-    sm.sitem_cnt = sitem_top;
-    if (stage_top > static_cast<uint32_t>(C::STG) || sitem_top > static_cast<uint32_t>(C::SITEMS))
-      atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));   // tile sized to fit
-  }
+  if (lane == 0) sm.pref[d + 1][h.lvl[d + 2] - h.lvl[d + 1]] = static_cast<uint16_t>(item_top);
+  wave_sync_lds();
 }
 
-// Staging pass on the resident body, all waves, all levels at once: each
-// item is 64 words of one node; the words are copied dword-aligned with
-// their rank (1 bits of the node's tile share before the word).
+// Streaming count for level d: one wave per node popcounts the node's share
+// straight from global memory and stages it as (word, rank) pairs.
 template <class C>
-__device__ void stage_resident(MergeSmem<C> &sm) {
-  const int wave = threadIdx.x >> 6;
-  const uint32_t lane = lane_id();
-  const uint32_t nit = sm.sitem_cnt;
-  for (uint32_t it = wave; it < nit; it += C::NW) {
-    const uint32_t e = sm.sitems[it];
-    const uint32_t v = e >> 16, c = e & 0xFFFF;
-    const uint32_t tvv = sm.tv[v];
-    const uint32_t nwords = (tvv + 31) / 32;
-    const uint32_t x0 = sm.abit[v] + sm.cur[v];
-    const uint32_t wq = 64 * c + lane;
-    uint32_t w = 0;
-    if (wq < nwords) {
-      w = bits32_lds(sm.body, x0 + 32 * wq);
-      const uint32_t rem = tvv - 32 * wq;
-      if (rem < 32) w &= (1u << rem) - 1;
-    }
-    const uint32_t pc = __popc(w);
-    const uint32_t inc = wave_incl_scan(pc);
-    const uint32_t base = c ? rank_at(sm.body, sm.sup, x0 + 2048 * c) - sm.arank[v] : 0u;
-    if (wq < nwords) sm.stage[sm.stg[v] + wq] = make_uint2(w, base + inc - pc);
-  }
-}
-
-// Count phase when the block does not fit in LDS: per level, one wave per
-// node popcounts the node's share straight from global memory and stages it.
-template <class C>
-__device__ void count_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_t maxd,
-                                const uint32_t *scratch, uint64_t scratch_words) {
+__device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_t d,
+                                      const uint32_t *scratch, uint64_t scratch_words) {
   const int wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.h;
   NodeTab &t = sm.t;
+  uint2 *stage = reinterpret_cast<uint2 *>(sm.body);
   const uint32_t *gin32 = reinterpret_cast<const uint32_t *>(J.in);
   const uint64_t in_dw = J.in_len >> 2;
-  for (uint32_t d = 0; d < maxd; ++d) {
-    for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += C::NW) {
-      const uint32_t tvv = sm.tv[v];
-      const uint32_t nwords = (tvv + 31) / 32;
-      uint32_t base = 0;
-      if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
-      base = __builtin_amdgcn_readfirstlane(base);
-      if (base + nwords > static_cast<uint32_t>(C::STG)) {   // cannot happen: tile sized for it
-        if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
-        break;
-      }
-      const uint32_t s0 = sm.cur[v];
-      uint32_t carry = 0;
-      for (uint32_t q0 = 0; q0 < nwords; q0 += kWave) {
-        const uint32_t q = q0 + lane;
-        uint32_t w = 0;
-        if (q < nwords) {
-          const uint32_t p = s0 + 32 * q;
-          if (t.kind[v]) w = bits32_glb(scratch, 32 * (h.ans_word0 + t.boff[v]) + p, scratch_words);
-          else w = bits32_glb(gin32, 8 * (h.blk + t.boff[v]) + p, in_dw);
-          const uint32_t rem = tvv - 32 * q;
-          if (rem < 32) w &= (1u << rem) - 1;
-        }
-        const uint32_t pc = __popc(w);
-        const uint32_t inc = wave_incl_scan(pc);
-        if (q < nwords) sm.stage[base + q] = make_uint2(w, carry + inc - pc);
-        carry += __shfl(inc, kWave - 1, kWave);
-      }
-      const uint32_t ones = carry;
-      if (lane == 0) { sm.stg[v] = base; sm.ones[v] += ones; }
-      for (int bb = 0; bb < 2; ++bb) {
-        const uint16_t c = t.child[v][bb];
-        if (c & 0x8000) continue;
-        uint32_t tc = bb ? ones : tvv - ones;
-        if (sm.cur[c] + tc > t.nv[c]) {
-          if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-          tc = 0;
-        }
-        if (lane == 0) {
-          sm.tv[c] = tc;
-          sm.obase[c] = tc ? atomicAdd(&sm.out_top[d + 1], (tc + 3) & ~3u) : 0u;
-        }
-        const uint32_t nit = (tc + 255) / 256;
-        uint32_t ib = 0;
-        if (lane == 0 && nit) ib = atomicAdd(&sm.item_cnt[d + 1], nit);
-        ib = __builtin_amdgcn_readfirstlane(ib);
-        for (uint32_t j = lane; j < nit; j += kWave)
-          if (ib + j < static_cast<uint32_t>(C::ITEMS))
-            sm.items[d + 1][ib + j] = static_cast<uint16_t>((c << 8) | j);
-      }
+  for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += C::NW) {
+    const uint32_t tvv = sm.tv[v];
+    const uint32_t nwords = (tvv + 31) / 32;
+    uint32_t base = 0;
+    if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (base + nwords > static_cast<uint32_t>(C::STG)) {   // cannot happen: tile sized for it
+      if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
+      if (lane == 0) sm.tone[v] = 0;
+      continue;
     }
-    __syncthreads();
+    const uint32_t s0 = sm.cur[v];
+    uint32_t carry = 0;
+    for (uint32_t q0 = 0; q0 < nwords; q0 += kWave) {
+      const uint32_t q = q0 + lane;
+      uint32_t w = 0;
+      if (q < nwords) {
+        const uint32_t p = s0 + 32 * q;
+        if (t.kind[v]) w = bits32_glb(scratch, 32 * (h.ans_word0 + t.boff[v]) + p, scratch_words);
+        else w = bits32_glb(gin32, 8 * (h.blk + t.boff[v]) + p, in_dw);
+        const uint32_t rem = tvv - 32 * q;
+        if (rem < 32) w &= (1u << rem) - 1;
+      }
+      const uint32_t pc = __popc(w);
+      const uint32_t inc = wave_incl_scan(pc);
+      if (q < nwords) stage[base + q] = make_uint2(w, carry + inc - pc);
+      carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) { sm.stg[v] = base; sm.tone[v] = carry; sm.ones[v] += carry; }
   }
 }
 
-// Merge phase: bottom-up by level, one wave per item of 256 outputs.
-template <class C>
-__device__ void merge_levels(MergeSmem<C> &sm, uint32_t maxd, uint8_t *out) {
+// Merge of level d: item i of the level is chunk (i - pref[k]) of its k-th
+// node, found with a ballot over the prefix array.  A lane makes 16
+// consecutive outputs: 16 bitmap bits and their rank, then 4 groups of 4
+// bytes, each one v_perm_b32 over unaligned 4-byte windows of the children's
+// sequences; one 16-byte store (LDS, or HBM at the root).
+template <class C, bool RESIDENT>
+__device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   const int wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   NodeTab &t = sm.t;
-  for (int d = static_cast<int>(maxd) - 1; d >= 0; --d) {
-    const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
-    uint32_t *obuf = sm.lvl[d & 1];
-    const uint32_t nit = sm.item_cnt[d] < static_cast<uint32_t>(C::ITEMS) ? sm.item_cnt[d] : C::ITEMS;
-    for (uint32_t ii = wave; ii < nit; ii += C::NW) {
-      const uint32_t itv = sm.items[d][ii];
-      const uint32_t v = itv >> 8, c = itv & 255;
-      const uint32_t tvv = sm.tv[v];
-      const uint32_t j = 256 * c + 4 * lane;
-      if (j >= tvv) continue;
-      const uint2 wr = sm.stage[sm.stg[v] + (j >> 5)];
-      const uint32_t sh = j & 31;
-      const uint32_t m = (wr.x >> sh) & 15;
-      const uint32_t r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
-      const uint32_t r0 = j - r1;
-      const uint16_t cl = t.child[v][0], cr = t.child[v][1];
-      const uint32_t L = (cl & 0x8000) ? (cl & 255) * 0x01010101u : win4(cbuf, sm.obase[cl] + r0);
-      const uint32_t R = (cr & 0x8000) ? (cr & 255) * 0x01010101u : win4(cbuf, sm.obase[cr] + r1);
-      const uint32_t o = __builtin_amdgcn_perm(R, L, sm.sel[m]);
-      if (d == 0) {
-        uint8_t *dst = out + j;
-        if (j + 4 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 3)) {
-          *reinterpret_cast<uint32_t *>(dst) = o;
-        } else {
-          const uint32_t k = tvv - j < 4 ? tvv - j : 4;
-          for (uint32_t e = 0; e < k; ++e) dst[e] = static_cast<uint8_t>(o >> (8 * e));
-        }
-      } else {
-        obuf[(sm.obase[v] + j) >> 2] = o;
-      }
+  const BlockHdr &h = sm.h;
+  const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
+  uint32_t *obuf = sm.lvl[d & 1];
+  const uint32_t N = h.lvl[d + 1] - h.lvl[d];
+  const uint32_t total = sm.pref[d][N];
+  const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
+  for (uint32_t i = wave; i < total; i += C::NW) {
+    uint32_t k = 0;
+    for (uint32_t b0 = 0; b0 < N; b0 += kWave) {
+      const uint32_t p = b0 + lane < N ? sm.pref[d][b0 + lane] : 0xFFFFFFFFu;
+      k += __popcll(__ballot(p <= i));
     }
-    __syncthreads();
+    k -= 1;
+    const uint32_t v = h.lvl[d] + k;
+    const uint32_t c = i - sm.pref[d][k];
+    const uint32_t tvv = sm.tv[v];
+    const uint32_t j0 = C::CH * c + 16 * lane;
+    if (j0 >= tvv) continue;
+    uint32_t bits, r1;
+    if (RESIDENT) {
+      const uint32_t x = sm.abit[v] + sm.cur[v] + j0;
+      bits = bits32_lds(sm.body, x);
+      r1 = rank_at(sm.body, sm.sup, sm.rel, x) - sm.arank[v];
+    } else {
+      const uint2 wr = stage[sm.stg[v] + (j0 >> 5)];
+      const uint32_t sh = j0 & 31;
+      bits = wr.x >> sh;
+      r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
+    }
+    uint32_t r0 = j0 - r1;
+    const uint16_t cl = t.child[v][0], cr = t.child[v][1];
+    const bool leafL = cl & 0x8000, leafR = cr & 0x8000;
+    const uint32_t bl = leafL ? 0u : sm.obase[cl], br = leafR ? 0u : sm.obase[cr];
+    const uint32_t cL = (cl & 255) * 0x01010101u, cR = (cr & 255) * 0x01010101u;
+    uint32_t o[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const uint32_t m = (bits >> (4 * g)) & 15;
+      const uint32_t L = leafL ? cL : win4(cbuf, bl + r0);
+      const uint32_t R = leafR ? cR : win4(cbuf, br + r1);
+      o[g] = __builtin_amdgcn_perm(R, L, sm.sel[m]);
+      const uint32_t pc = __popc(m);
+      r1 += pc;
+      r0 += 4 - pc;
+    }
+    if (d == 0) {
+      uint8_t *dst = out + j0;
+      if (j0 + 16 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 15)) {
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(o[0], o[1], o[2], o[3]);
+      } else {
+        const uint32_t kk = tvv - j0 < 16 ? tvv - j0 : 16;
+        for (uint32_t e = 0; e < kk; ++e) dst[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
+      }
+    } else {
+      *reinterpret_cast<uint4 *>(&obuf[(sm.obase[v] + j0) >> 2]) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
   }
 }
 
@@ -816,7 +770,7 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
       sm.body[abase + i] = q < scratch_words ? scratch[q] : 0u;
     }
     body_dw = abase + h.ans_words;
-    // zero tail up to the next superblock plus one
+    // zero tail: up to the next superblock plus one
     for (uint32_t i = body_dw + tid; i < ((body_dw + 7) & ~7u) + 8; i += C::NT) sm.body[i] = 0u;
     for (uint32_t i = tid; i < I; i += C::NT)
       sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : static_cast<uint32_t>(blk + t.boff[i] - g0));
@@ -834,19 +788,27 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     sm.sel[tid] = s;
   }
   for (uint32_t i = tid; i < I; i += C::NT) { sm.cur[i] = 0; sm.ones[i] = 0; }
-  if (tid == 0) sm.tile = pick_tile<C>(h);
+  if (tid == 0) sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
   __syncthreads();
   if (resident) {
-    // rank directory: exclusive prefix of popcounts over 256-bit superblocks
+    // rank directory: per 256-bit superblock the 1 bits before it, per
+    // 64-bit word the 1 bits of its superblock before it
     const uint32_t nsb = (body_dw + 7) / 8 + 1;
     const uint32_t per = (nsb + C::NT - 1) / C::NT;
     const uint32_t s0 = tid * per;
     uint32_t loc = 0;
     for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
-      uint32_t c = 0;
-      for (int i = 0; i < 8; ++i) c += __popc(sm.body[8 * k + i]);
-      sm.sup[k] = c;
-      loc += c;
+      const uint4 a = *reinterpret_cast<const uint4 *>(&sm.body[8 * k]);
+      const uint4 c = *reinterpret_cast<const uint4 *>(&sm.body[8 * k + 4]);
+      const uint32_t w0 = __popc(a.x) + __popc(a.y), w1 = __popc(a.z) + __popc(a.w);
+      const uint32_t w2 = __popc(c.x) + __popc(c.y), w3 = __popc(c.z) + __popc(c.w);
+      sm.rel[4 * k] = 0;
+      sm.rel[4 * k + 1] = static_cast<uint8_t>(w0);
+      sm.rel[4 * k + 2] = static_cast<uint8_t>(w0 + w1);
+      sm.rel[4 * k + 3] = static_cast<uint8_t>(w0 + w1 + w2);
+      const uint32_t cnt = w0 + w1 + w2 + w3;
+      sm.sup[k] = cnt;
+      loc += cnt;
     }
     const uint32_t inc = wave_incl_scan(loc);
     if (lane == kWave - 1) sm.scan_tot[wave] = inc;
@@ -860,37 +822,43 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     }
     __syncthreads();
     for (uint32_t i = tid; i < I; i += C::NT) {
-      const uint32_t r = rank_at(sm.body, sm.sup, sm.abit[i]);
+      const uint32_t r = rank_at(sm.body, sm.sup, sm.rel, sm.abit[i]);
       sm.r0[i] = r;
       sm.arank[i] = r;
     }
-    __syncthreads();
   }
+  __syncthreads();
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
   bool bad = false;
 
   for (uint32_t t0 = 0; t0 < n; t0 += T) {
     const uint32_t troot = n - t0 < T ? n - t0 : T;
-    if (tid <= static_cast<int>(C::LEVELS)) { sm.out_top[tid] = 0; sm.item_cnt[tid] = 0; }
     if (tid == 0) {
       sm.stage_top = 0;
       sm.tv[0] = troot;
-      sm.item_cnt[0] = (troot + 255) / 256;
+      sm.pref[0][0] = 0;
+      sm.pref[0][1] = static_cast<uint16_t>((troot + C::CH - 1) / C::CH);
     }
-    for (uint32_t j = tid; j < (troot + 255) / 256; j += C::NT) sm.items[0][j] = static_cast<uint16_t>(j);
     __syncthreads();
     if (resident) {
-      if (wave == 0) count_resident<C>(sm, maxd);
-      __syncthreads();
-      if (h.err) { bad = true; break; }
-      stage_resident<C>(sm);
+      if (wave == 0)
+        for (uint32_t d = 0; d < maxd; ++d) count_level<C, true>(sm, d);
       __syncthreads();
     } else {
-      count_streaming<C>(J, sm, maxd, scratch, scratch_words);
-      if (h.err) { bad = true; break; }
+      for (uint32_t d = 0; d < maxd; ++d) {
+        stage_level_streaming<C>(J, sm, d, scratch, scratch_words);
+        __syncthreads();
+        if (wave == 0) count_level<C, false>(sm, d);
+        __syncthreads();
+      }
     }
-    merge_levels<C>(sm, maxd, out + t0);
+    if (h.err) { bad = true; break; }
+    for (int d = static_cast<int>(maxd) - 1; d >= 0; --d) {
+      if (resident) merge_level<C, true>(sm, d, out + t0);
+      else merge_level<C, false>(sm, d, out + t0);
+      __syncthreads();
+    }
     for (uint32_t i = tid; i < I; i += C::NT) {
       sm.cur[i] += sm.tv[i];
       if (resident) sm.arank[i] = sm.anext[i];
@@ -957,9 +925,9 @@ __global__ void k_gather_headers(const pivco_job *jobs, uint32_t count, uint8_t 
 // ---------------------------------------------------------------------------
 // host-side launch table
 // ---------------------------------------------------------------------------
-using Cfg0 = MergeCfg<1024, 16384, 65536>;
-using Cfg1 = MergeCfg<1024, 8192, 90112>;
-using Cfg2 = MergeCfg<512, 4096, 40960>;
+using Cfg0 = MergeCfg<1024, 32768, 57344>;
+using Cfg1 = MergeCfg<1024, 16384, 81920>;
+using Cfg2 = MergeCfg<512, 8192, 49152>;
 
 struct MergeVariant {
   const char *name;
@@ -992,9 +960,9 @@ uint32_t merge_variant_count() { return 3; }
 
 const char *merge_variant_name(uint32_t v) {
   switch (v) {
-    case 0: return "wg1024_tile16k_lds64k";
-    case 1: return "wg1024_tile8k_lds88k";
-    case 2: return "wg512_tile4k_lds40k";
+    case 0: return "wg1024_tile32k_body56k";
+    case 1: return "wg1024_tile16k_body80k";
+    case 2: return "wg512_tile8k_body48k";
     default: return "?";
   }
 }
