@@ -89,6 +89,7 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
 // ---------------------------------------------------------------------------
 struct BlockHdr {
   uint64_t blk;        // byte offset of the block in the stream
+  uint64_t end;        // byte offset of the next block
   uint64_t out_off;    // first output byte of the block
   uint64_t ans_word0;  // absolute scratch word of the block's first rANS node
   uint32_t comp, n, mode, csym, cw, I, maxlen, kb;
@@ -114,58 +115,68 @@ struct NodeTab {
   uint64_t scan_tot[16];
 };
 
-// Parse and validate the header of block b of job J; every thread of the
-// workgroup must call it.  On return h.err != 0 or h.mode == 1 means the
-// node tables are not filled.
-template <int NT>
-__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t) {
+// Byte readers for block-relative offsets: the block in global memory, or
+// a copy of it in LDS.
+struct GlbBytes {
+  const uint8_t *p;
+  __device__ uint32_t u8(uint32_t o) const { return p[o]; }
+  __device__ uint32_t u32(uint32_t o) const { return *reinterpret_cast<const uint32_t *>(p + o); }
+};
+struct LdsBytes {
+  const uint8_t *p;
+  __device__ uint32_t u8(uint32_t o) const { return p[o]; }
+  __device__ uint32_t u32(uint32_t o) const { return *reinterpret_cast<const uint32_t *>(p + o); }
+};
+
+// Offsets of block b from the stream's tables (thread 0 only).
+__device__ void parse_offsets(const JobDev &J, uint32_t b, BlockHdr &h) {
+  const uint64_t nb = J.n_blocks;
+  const uint64_t *tab = reinterpret_cast<const uint64_t *>(J.in + kHeaderBytes);
+  const uint64_t tab_end = kHeaderBytes + 16 * (nb + 1);
+  const uint64_t off = tab[b], end = tab[b + 1];
+  const uint64_t a0 = tab[nb + 1 + b], a1 = tab[nb + 2 + b];
+  int32_t err = 0;
+  if (off < tab_end || end < off || end > J.in_len || (off & 3) || end - off < kBlockFixed ||
+      end - off > 0xFFFFFFF0ull || a1 < a0 || a1 - a0 > 0xFFFFFFFFull)
+    err = PIVCO_E_CORRUPT;
+  h.blk = off;
+  h.end = err ? off : end;
+  h.out_off = static_cast<uint64_t>(b) * J.block_size;
+  h.ans_word0 = J.scratch_base + a0;
+  h.ans_words = err ? 0u : static_cast<uint32_t>(a1 - a0);
+  h.err = err;
+  h.kraft = 0;
+}
+
+// Parse and validate the rest of the header of block b (offsets already in
+// h); every thread of the workgroup must call it.  On return h.err != 0 or
+// h.mode == 1 means the node tables are not filled.
+template <int NT, class Rd>
+__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
   static_assert(NT >= 256, "header parse needs 256 threads");
   const int tid = threadIdx.x;
-  const uint8_t *in = J.in;
-  if (tid == 0) {
+  if (tid == 0 && !h.err) {
     int32_t err = 0;
-    const uint64_t nb = J.n_blocks;
-    const uint64_t *tab = reinterpret_cast<const uint64_t *>(in + kHeaderBytes);
-    const uint64_t tab_end = kHeaderBytes + 16 * (nb + 1);
-    const uint64_t off = tab[b], end = tab[b + 1];
-    const uint64_t a0 = tab[nb + 1 + b], a1 = tab[nb + 2 + b];
-    uint32_t comp = 0, n = 0, mode = 0, csym = 0, cw = 0;
-    if (off < tab_end || end < off || end > J.in_len || (off & 3) || end - off < kBlockFixed ||
-        a1 < a0 || a1 - a0 > 0xFFFFFFFFull) {
+    const uint32_t comp = rd.u32(0), n = rd.u32(4), w2 = rd.u32(8);
+    const uint32_t mode = w2 & 255, csym = (w2 >> 8) & 255, cw = (w2 >> 16) & 255;
+    const uint64_t start = static_cast<uint64_t>(b) * J.block_size;
+    const uint64_t want = J.n_total - start < J.block_size ? J.n_total - start : J.block_size;
+    if (comp > h.end - h.blk || comp < kBlockFixed || n != want || (w2 >> 24) != 0 ||
+        cw != (n <= 65535 ? 2u : 4u))
       err = PIVCO_E_CORRUPT;
-    } else {
-      const uint32_t *bp = reinterpret_cast<const uint32_t *>(in + off);
-      comp = bp[0];
-      n = bp[1];
-      const uint32_t w2 = bp[2];
-      mode = w2 & 255;
-      csym = (w2 >> 8) & 255;
-      cw = (w2 >> 16) & 255;
-      const uint64_t start = static_cast<uint64_t>(b) * J.block_size;
-      const uint64_t want = J.n_total - start < J.block_size ? J.n_total - start : J.block_size;
-      if (comp > end - off || comp < kBlockFixed || n != want || (w2 >> 24) != 0 ||
-          cw != (n <= 65535 ? 2u : 4u))
-        err = PIVCO_E_CORRUPT;
-      else if (mode == 1) {
-        if (comp != kBlockFixed || a1 != a0 || n == 0) err = PIVCO_E_CORRUPT;
-      } else if (mode != 0 || csym != 0 || comp < kBlockFixed + kLenTable) {
-        err = PIVCO_E_CORRUPT;
-      }
+    else if (mode == 1) {
+      if (comp != kBlockFixed || h.ans_words != 0 || n == 0) err = PIVCO_E_CORRUPT;
+    } else if (mode != 0 || csym != 0 || comp < kBlockFixed + kLenTable) {
+      err = PIVCO_E_CORRUPT;
     }
-    h.blk = off;
-    h.out_off = static_cast<uint64_t>(b) * J.block_size;
-    h.ans_word0 = J.scratch_base + a0;
-    h.ans_words = static_cast<uint32_t>(a1 - a0);
     h.comp = comp; h.n = n; h.mode = mode; h.csym = csym; h.cw = cw;
     h.err = err;
-    h.kraft = 0;
   }
   if (tid < 17) h.cnt[tid] = 0;
   __syncthreads();
   if (h.err || h.mode == 1) return;
-  const uint64_t blk = h.blk;
   if (tid < 128) {
-    const uint32_t v = in[blk + kBlockFixed + tid];
+    const uint32_t v = rd.u8(kBlockFixed + tid);
     t.len[2 * tid] = v & 15;
     t.len[2 * tid + 1] = v >> 4;
   }
@@ -224,7 +235,7 @@ __device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t
   }
   __syncthreads();
   const uint32_t I = h.I;
-  const uint64_t kbase = blk + kBlockFixed + kLenTable;
+  const uint32_t kbase = kBlockFixed + kLenTable;
   if (tid < static_cast<int>(I)) {
     const uint32_t i = tid;
     uint32_t d = 0;
@@ -238,15 +249,15 @@ __device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t
                            : static_cast<uint16_t>(h.lvl[d + 1] + (q - leafend));
     }
     t.depth[i] = static_cast<uint8_t>(d);
-    t.kind[i] = (in[kbase + (i >> 3)] >> (i & 7)) & 1;
-    const uint64_t co = kbase + h.kb + static_cast<uint64_t>(h.cw) * i;
-    uint32_t r = in[co] | (static_cast<uint32_t>(in[co + 1]) << 8);
-    if (h.cw == 4) r |= (static_cast<uint32_t>(in[co + 2]) << 16) | (static_cast<uint32_t>(in[co + 3]) << 24);
+    t.kind[i] = (rd.u8(kbase + (i >> 3)) >> (i & 7)) & 1;
+    const uint32_t co = kbase + h.kb + h.cw * i;
+    uint32_t r = rd.u8(co) | (rd.u8(co + 1) << 8);
+    if (h.cw == 4) r |= (rd.u8(co + 2) << 16) | (rd.u8(co + 3) << 24);
     t.nr[i] = r;
     if (i == 0) t.nv[0] = h.n;
   }
   if (tid == 0 && (I & 7)) {
-    if (in[kbase + (I >> 3)] >> (I & 7)) h.err = PIVCO_E_CORRUPT;   // unused kind bits
+    if (rd.u8(kbase + (I >> 3)) >> (I & 7)) h.err = PIVCO_E_CORRUPT;   // unused kind bits
   }
   if (tid < 17) h.lvl_total[tid] = 0;
   __syncthreads();
@@ -298,7 +309,7 @@ __device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t
   if (h.err) return;
   // padding bits of raw bodies must be zero
   if (tid < static_cast<int>(I) && !t.kind[tid] && (t.nv[tid] & 7)) {
-    const uint32_t last = in[blk + t.boff[tid] + (t.nv[tid] >> 3)];
+    const uint32_t last = rd.u8(t.boff[tid] + (t.nv[tid] >> 3));
     if (last >> (t.nv[tid] & 7)) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
   }
   __syncthreads();
@@ -390,7 +401,9 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const uint
     if (it >= n_items) break;
     const uint2 item = items[it];
     const JobDev &J = jobs[item.x];
-    parse_block<kRansNT>(J, item.y, sm.h, sm.t);
+    if (tid == 0) parse_offsets(J, item.y, sm.h);
+    __syncthreads();
+    parse_block<kRansNT>(J, item.y, sm.h, sm.t, GlbBytes{J.in + sm.h.blk});
     if (sm.h.err) {
       if (tid == 0) set_err(J.status, sm.h.err);
       continue;
@@ -457,14 +470,24 @@ template <int NT_, int T_, int BODY_>
 struct MergeCfg {
   static constexpr int NT = NT_;
   static constexpr int T = T_;                        // output symbols per tile
-  static constexpr int BODY = BODY_;                  // resident bitmap bytes
+  static constexpr int BODY = BODY_;                  // resident block bytes
   static constexpr int NW = NT / kWave;
-  static constexpr int CH = 1024;                     // outputs per merge item (16 per lane)
   static constexpr int LVL = T + 16 * 128 + 64;       // bytes per level buffer
   static constexpr int LEVELS = kMaxLenGpu;
   static constexpr int STG = BODY / 8;                // streaming: staged (word, rank) pairs
   static constexpr int SUP = BODY / 32 + 8;           // rank directory, per 256 bits
   static constexpr int REL = BODY / 8 + 32;           // rank directory, per 64 bits
+};
+
+// What a merge lane needs about a node for the current tile (16 bytes):
+// where its bits start (resident: LDS bit address; streaming: first staged
+// word), the 1 bits before that point, its output offset, and per child
+// either the child's output offset / 16 or 0x8000 | leaf symbol.
+struct NodeRec {
+  uint32_t x0;
+  uint32_t arank;
+  uint32_t obase;
+  uint32_t kids;
 };
 
 template <class C>
@@ -473,19 +496,28 @@ struct MergeSmem {
   NodeTab t;
   uint32_t cur[256];       // bits of the node consumed by earlier tiles
   uint32_t tv[256];        // node's share of the current tile
-  uint32_t tone[256];      // 1 bits in that share
   uint32_t obase[256];     // node's output offset in its level buffer (16-byte aligned)
-  uint32_t abit[256];      // resident: LDS bit address of the node bitmap
-  uint32_t arank[256];     // resident: 1 bits of the body before the cursor
-  uint32_t anext[256];     // resident: same after this tile
-  uint32_t r0[256];        // resident: 1 bits of the body before the node
-  uint32_t ones[256];      // streaming: 1 bits seen so far
-  uint32_t stg[256];       // streaming: first staged word of the node
-  uint16_t pref[C::LEVELS + 1][132];  // merge items before each node of a level; [N] = total
+  union {
+    struct {
+      uint32_t abit[256];  // resident: LDS bit address of the node bitmap
+      uint32_t arank[256]; // resident: 1 bits of the body before the cursor
+      uint32_t r0[256];    // resident: 1 bits of the body before the node
+    };
+    struct {
+      uint32_t tone[256];  // streaming: 1 bits in the tile share
+      uint32_t ones[256];  // streaming: 1 bits seen so far
+      uint32_t stg[256];   // streaming: first staged word of the node
+    };
+  };
+  NodeRec rec[256];
+  uint8_t act[C::LEVELS + 1][132];    // nodes of a level with a nonzero share
+  uint16_t tpref[C::LEVELS + 1][132]; // 16-output tasks before each of them; [nact] = total
+  uint32_t nact[C::LEVELS + 1];
   uint32_t stage_top;
   uint32_t tile;           // runtime tile size for this block
   uint32_t sel[16];
   uint32_t item;
+  uint32_t lds_base;       // resident: LDS byte offset of the block's first byte
   uint32_t scan_tot[C::NW];
   uint32_t lvl[2][C::LVL / 4] __attribute__((aligned(16)));
   uint32_t sup[C::SUP];    // resident: 1 bits of the body before each 256-bit superblock
@@ -534,30 +566,34 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Allocation for the children of level d, run by one wave: every node's
-// share (sm.tv) and its 1 bits (sm.tone) give the children's shares; their
-// output space in the level buffer and their merge items (a prefix array in
-// breadth-first order) come from wave-wide prefix sums.  In resident mode
-// the 1 bits are computed here from the rank directory.
+// Count for level d, run by one wave: every node's share (sm.tv) and its 1
+// bits give the children's shares; the node's merge record, the children's
+// output space in the next level buffer, and the compacted list of the
+// level's nodes with work (with a prefix of their 16-output tasks) come from
+// wave-wide prefix sums.  Resident mode takes the 1 bits from the rank
+// directory; streaming mode from the staging pass.  Cursors advance here.
 template <class C, bool RESIDENT>
 __device__ void count_level(MergeSmem<C> &sm, uint32_t d) {
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.h;
   NodeTab &t = sm.t;
-  uint32_t out_top = 0, item_top = 0;
+  uint32_t out_top = 0, task_top = 0, act_top = 0;
   for (uint32_t v0 = h.lvl[d]; v0 < h.lvl[d + 1]; v0 += kWave) {
     const uint32_t v = v0 + lane;
     const bool valid = v < h.lvl[d + 1];
     uint32_t tvv = 0, ones = 0, tc[2] = {0, 0};
     uint16_t ch[2] = {0x8000, 0x8000};
+    uint32_t x0 = 0, ar = 0;
     if (valid) {
       tvv = sm.tv[v];
       if (RESIDENT) {
-        const uint32_t a = sm.arank[v];
-        const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.rel, sm.abit[v] + sm.cur[v] + tvv) : a;
-        sm.anext[v] = e;
-        ones = e - a;
+        x0 = sm.abit[v] + sm.cur[v];
+        ar = sm.arank[v];
+        const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.rel, x0 + tvv) : ar;
+        ones = e - ar;
+        sm.arank[v] = e;
       } else {
+        x0 = sm.stg[v];
         ones = sm.tone[v];
       }
       ch[0] = t.child[v][0];
@@ -573,28 +609,49 @@ __device__ void count_level(MergeSmem<C> &sm, uint32_t d) {
       }
     }
     const uint32_t o0 = (tc[0] + 15) & ~15u, o1 = (tc[1] + 15) & ~15u;
-    const uint32_t i0 = (tc[0] + C::CH - 1) / C::CH, i1 = (tc[1] + C::CH - 1) / C::CH;
-    const uint64_t pk = static_cast<uint64_t>(o0 + o1) | (static_cast<uint64_t>(i0 + i1) << 32);
+    const uint32_t tasks = (tvv + 15) / 16;
+    const uint32_t isact = tvv ? 1u : 0u;
+    const uint64_t pk = static_cast<uint64_t>(o0 + o1) | (static_cast<uint64_t>(tasks) << 32) |
+                        (static_cast<uint64_t>(isact) << 48);
     uint64_t tot;
     const uint64_t ex = wave_excl_scan64(pk, tot);
     if (valid) {
-      uint32_t ob = out_top + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
-      uint32_t ib = item_top + static_cast<uint32_t>(ex >> 32);
+      const uint32_t ob = out_top + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
+      uint32_t kids = 0;
       for (int bb = 0; bb < 2; ++bb) {
-        if (ch[bb] & 0x8000) continue;
-        const uint16_t c = ch[bb];
-        sm.tv[c] = tc[bb];
-        sm.obase[c] = ob;
-        sm.pref[d + 1][c - h.lvl[d + 1]] = static_cast<uint16_t>(ib);
-        ob += bb ? o1 : o0;
-        ib += bb ? i1 : i0;
+        uint32_t code;
+        if (ch[bb] & 0x8000) {
+          code = ch[bb];
+        } else {
+          const uint32_t cob = ob + (bb ? o0 : 0u);
+          sm.tv[ch[bb]] = tc[bb];
+          sm.obase[ch[bb]] = cob;
+          code = cob >> 4;
+        }
+        kids |= code << (16 * bb);
       }
+      NodeRec r;
+      r.x0 = x0;
+      r.arank = ar;
+      r.obase = sm.obase[v];
+      r.kids = kids;
+      sm.rec[v] = r;
+      if (isact) {
+        const uint32_t ai = act_top + static_cast<uint32_t>(ex >> 48);
+        sm.act[d][ai] = static_cast<uint8_t>(v);
+        sm.tpref[d][ai] = static_cast<uint16_t>(task_top + ((ex >> 32) & 0xFFFF));
+      }
+      sm.cur[v] += tvv;
     }
     out_top += static_cast<uint32_t>(tot & 0xFFFFFFFFu);
-    item_top += static_cast<uint32_t>(tot >> 32);
+    task_top += static_cast<uint32_t>((tot >> 32) & 0xFFFF);
+    act_top += static_cast<uint32_t>(tot >> 48);
     wave_sync_lds();
   }
-  if (lane == 0) sm.pref[d + 1][h.lvl[d + 2] - h.lvl[d + 1]] = static_cast<uint16_t>(item_top);
+  if (lane == 0) {
+    sm.tpref[d][act_top] = static_cast<uint16_t>(task_top);
+    sm.nact[d] = act_top;
+  }
   wave_sync_lds();
 }
 
@@ -617,8 +674,11 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
     if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
     base = __builtin_amdgcn_readfirstlane(base);
     if (base + nwords > static_cast<uint32_t>(C::STG)) {   // cannot happen: tile sized for it
-      if (lane == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
-      if (lane == 0) sm.tone[v] = 0;
+      if (lane == 0) {
+        atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
+        sm.tone[v] = 0;
+        sm.stg[v] = 0;
+      }
       continue;
     }
     const uint32_t s0 = sm.cur[v];
@@ -642,50 +702,51 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
   }
 }
 
-// Merge of level d: item i of the level is chunk (i - pref[k]) of its k-th
-// node, found with a ballot over the prefix array.  A lane makes 16
-// consecutive outputs: 16 bitmap bits and their rank, then 4 groups of 4
-// bytes, each one v_perm_b32 over unaligned 4-byte windows of the children's
-// sequences; one 16-byte store (LDS, or HBM at the root).
+// Merge of level d.  The level's work is a list of 16-output tasks over its
+// nodes with a nonzero share; a lane takes one task (its node by a binary
+// search of the task prefix), reads 16 bitmap bits and their rank, then makes
+// 4 groups of 4 bytes, each one v_perm_b32 over unaligned 4-byte windows of
+// the children's sequences (a leaf child is a constant), and stores the 16
+// bytes at once (LDS, or HBM at the root).
 template <class C, bool RESIDENT>
 __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   const int wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
-  NodeTab &t = sm.t;
-  const BlockHdr &h = sm.h;
   const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
   uint32_t *obuf = sm.lvl[d & 1];
-  const uint32_t N = h.lvl[d + 1] - h.lvl[d];
-  const uint32_t total = sm.pref[d][N];
+  const uint32_t na = sm.nact[d];
+  const uint32_t total = sm.tpref[d][na];
+  const uint16_t *tp = sm.tpref[d];
   const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
-  for (uint32_t i = wave; i < total; i += C::NW) {
-    uint32_t k = 0;
-    for (uint32_t b0 = 0; b0 < N; b0 += kWave) {
-      const uint32_t p = b0 + lane < N ? sm.pref[d][b0 + lane] : 0xFFFFFFFFu;
-      k += __popcll(__ballot(p <= i));
+  for (uint32_t base = kWave * wave; base < total; base += kWave * C::NW) {
+    const uint32_t task = base + lane;
+    if (task >= total) continue;
+    // largest k with tp[k] <= task
+    uint32_t lo = 0, hi = na;            // tp[lo] <= task < tp[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tp[mid] <= task) lo = mid; else hi = mid;
     }
-    k -= 1;
-    const uint32_t v = h.lvl[d] + k;
-    const uint32_t c = i - sm.pref[d][k];
+    const uint32_t v = sm.act[d][lo];
+    const uint32_t j0 = 16 * (task - tp[lo]);
+    const NodeRec r = sm.rec[v];
     const uint32_t tvv = sm.tv[v];
-    const uint32_t j0 = C::CH * c + 16 * lane;
-    if (j0 >= tvv) continue;
     uint32_t bits, r1;
     if (RESIDENT) {
-      const uint32_t x = sm.abit[v] + sm.cur[v] + j0;
+      const uint32_t x = r.x0 + j0;
       bits = bits32_lds(sm.body, x);
-      r1 = rank_at(sm.body, sm.sup, sm.rel, x) - sm.arank[v];
+      r1 = rank_at(sm.body, sm.sup, sm.rel, x) - r.arank;
     } else {
-      const uint2 wr = stage[sm.stg[v] + (j0 >> 5)];
+      const uint2 wr = stage[r.x0 + (j0 >> 5)];
       const uint32_t sh = j0 & 31;
       bits = wr.x >> sh;
       r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
     }
     uint32_t r0 = j0 - r1;
-    const uint16_t cl = t.child[v][0], cr = t.child[v][1];
-    const bool leafL = cl & 0x8000, leafR = cr & 0x8000;
-    const uint32_t bl = leafL ? 0u : sm.obase[cl], br = leafR ? 0u : sm.obase[cr];
-    const uint32_t cL = (cl & 255) * 0x01010101u, cR = (cr & 255) * 0x01010101u;
+    const uint32_t kl = r.kids & 0xFFFF, kr = r.kids >> 16;
+    const bool leafL = kl & 0x8000, leafR = kr & 0x8000;
+    const uint32_t bl = kl << 4, br = kr << 4;
+    const uint32_t cL = (kl & 255) * 0x01010101u, cR = (kr & 255) * 0x01010101u;
     uint32_t o[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -706,7 +767,7 @@ __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
         for (uint32_t e = 0; e < kk; ++e) dst[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
       }
     } else {
-      *reinterpret_cast<uint4 *>(&obuf[(sm.obase[v] + j0) >> 2]) = make_uint4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<uint4 *>(&obuf[(r.obase + j0) >> 2]) = make_uint4(o[0], o[1], o[2], o[3]);
     }
   }
 }
@@ -719,7 +780,44 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.h;
   NodeTab &t = sm.t;
-  parse_block<C::NT>(J, b, h, t);
+  if (tid == 0) parse_offsets(J, b, h);
+  __syncthreads();
+  // ---- residency: the whole block (header and bodies) and the decoded
+  // rANS bitmaps in LDS, loaded with 16-byte reads ----------------------------
+  const uint64_t g0 = h.blk & ~15ull;
+  const uint64_t g1 = (h.end + 15) & ~15ull;
+  const uint64_t span = g1 - g0;
+  const bool resident = !h.err && span + 4ull * h.ans_words + 64 <= static_cast<uint64_t>(C::BODY);
+  if (resident) {
+    const uint64_t in_dw = J.in_len >> 2;
+    const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
+    const uint32_t n16 = static_cast<uint32_t>(span >> 4);
+    for (uint32_t i = tid; i < n16; i += C::NT) {
+      const uint64_t q = (g0 >> 2) + 4ull * i;
+      uint4 v;
+      if (q + 4 <= in_dw) {
+        v = *reinterpret_cast<const uint4 *>(gin + q);
+      } else {
+        v.x = q < in_dw ? gin[q] : 0u;
+        v.y = q + 1 < in_dw ? gin[q + 1] : 0u;
+        v.z = q + 2 < in_dw ? gin[q + 2] : 0u;
+        v.w = q + 3 < in_dw ? gin[q + 3] : 0u;
+      }
+      *reinterpret_cast<uint4 *>(&sm.body[4 * i]) = v;
+    }
+    const uint32_t abase = static_cast<uint32_t>(span >> 2);
+    for (uint32_t i = tid; i < h.ans_words; i += C::NT) {
+      const uint64_t q = h.ans_word0 + i;
+      sm.body[abase + i] = q < scratch_words ? scratch[q] : 0u;
+    }
+    const uint32_t body_dw = abase + h.ans_words;
+    for (uint32_t i = body_dw + tid; i < ((body_dw + 7) & ~7u) + 8; i += C::NT) sm.body[i] = 0u;
+    if (tid == 0) sm.lds_base = static_cast<uint32_t>(h.blk - g0);
+    __syncthreads();
+    parse_block<C::NT>(J, b, h, t, LdsBytes{reinterpret_cast<const uint8_t *>(sm.body) + (h.blk - g0)});
+  } else {
+    parse_block<C::NT>(J, b, h, t, GlbBytes{J.in + h.blk});
+  }
   if (h.err) {
     if (tid == 0) set_err(J.status, h.err);
     return;
@@ -739,41 +837,11 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     return;
   }
   const uint32_t I = h.I;
-  const uint64_t blk = h.blk;
-  // ---- residency: all node bitmaps of the block in LDS --------------------
-  const uint64_t g0 = (blk + h.raw_base) & ~15ull;
-  const uint64_t g1 = (blk + h.raw_end + 15) & ~15ull;
-  const uint64_t raw_bytes = g1 - g0;
-  const uint64_t ans_bytes = 4ull * h.ans_words;
-  const bool resident = raw_bytes + ans_bytes + 64 <= static_cast<uint64_t>(C::BODY);
-  uint32_t body_dw = 0;
   if (resident) {
-    const uint64_t in_dw = J.in_len >> 2;
-    const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
-    const uint32_t n16 = static_cast<uint32_t>(raw_bytes >> 4);
-    for (uint32_t i = tid; i < n16; i += C::NT) {
-      const uint64_t q = (g0 >> 2) + 4ull * i;
-      uint4 v;
-      if (q + 4 <= in_dw) {
-        v = *reinterpret_cast<const uint4 *>(gin + q);
-      } else {
-        v.x = q < in_dw ? gin[q] : 0u;
-        v.y = q + 1 < in_dw ? gin[q + 1] : 0u;
-        v.z = q + 2 < in_dw ? gin[q + 2] : 0u;
-        v.w = q + 3 < in_dw ? gin[q + 3] : 0u;
-      }
-      *reinterpret_cast<uint4 *>(&sm.body[4 * i]) = v;
-    }
-    const uint32_t abase = static_cast<uint32_t>(raw_bytes >> 2);
-    for (uint32_t i = tid; i < h.ans_words; i += C::NT) {
-      const uint64_t q = h.ans_word0 + i;
-      sm.body[abase + i] = q < scratch_words ? scratch[q] : 0u;
-    }
-    body_dw = abase + h.ans_words;
-    // zero tail: up to the next superblock plus one
-    for (uint32_t i = body_dw + tid; i < ((body_dw + 7) & ~7u) + 8; i += C::NT) sm.body[i] = 0u;
+    const uint32_t lb = static_cast<uint32_t>(h.blk - g0);
+    const uint32_t abase = static_cast<uint32_t>(span >> 2);
     for (uint32_t i = tid; i < I; i += C::NT)
-      sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : static_cast<uint32_t>(blk + t.boff[i] - g0));
+      sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : lb + t.boff[i]);
   }
   if (tid < 16) {
     // selector for v_perm_b32(R, L, sel): output byte k takes the left
@@ -787,12 +855,20 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     }
     sm.sel[tid] = s;
   }
-  for (uint32_t i = tid; i < I; i += C::NT) { sm.cur[i] = 0; sm.ones[i] = 0; }
-  if (tid == 0) sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
+  for (uint32_t i = tid; i < I; i += C::NT) {
+    sm.cur[i] = 0;
+    sm.tv[i] = 0;
+    if (!resident) sm.ones[i] = 0;
+  }
+  if (tid == 0) {
+    sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
+    sm.obase[0] = 0;
+  }
   __syncthreads();
   if (resident) {
     // rank directory: per 256-bit superblock the 1 bits before it, per
     // 64-bit word the 1 bits of its superblock before it
+    const uint32_t body_dw = static_cast<uint32_t>(span >> 2) + h.ans_words;
     const uint32_t nsb = (body_dw + 7) / 8 + 1;
     const uint32_t per = (nsb + C::NT - 1) / C::NT;
     const uint32_t s0 = tid * per;
@@ -837,8 +913,6 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     if (tid == 0) {
       sm.stage_top = 0;
       sm.tv[0] = troot;
-      sm.pref[0][0] = 0;
-      sm.pref[0][1] = static_cast<uint16_t>((troot + C::CH - 1) / C::CH);
     }
     __syncthreads();
     if (resident) {
@@ -859,11 +933,7 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
       else merge_level<C, false>(sm, d, out + t0);
       __syncthreads();
     }
-    for (uint32_t i = tid; i < I; i += C::NT) {
-      sm.cur[i] += sm.tv[i];
-      if (resident) sm.arank[i] = sm.anext[i];
-      sm.tv[i] = 0;
-    }
+    for (uint32_t i = tid; i < I; i += C::NT) sm.tv[i] = 0;
     __syncthreads();
   }
   if (!bad) {
