@@ -65,23 +65,35 @@ __device__ __forceinline__ uint32_t load_u8(const uint8_t *p, uint64_t off, uint
   return off < len ? p[off] : 0u;
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t t = __shfl_up(v, d, kWave);
-    if (static_cast<int>(lane_id()) >= d) v += t;
-  }
+// Wave-wide inclusive scans with DPP (wave64): Hillis-Steele inside each
+// 16-lane row (row_shr 1, 2, 4, 8), then row_bcast:15 and row_bcast:31
+// carry the row totals to the following rows.  Lanes without a source get
+// the identity (0).
+template <class Op>
+__device__ __forceinline__ uint32_t wave_incl_scan_op(uint32_t v, Op op) {
+  v = op(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, false)));
+  v = op(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, false)));
+  v = op(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, false)));
+  v = op(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, false)));
+  v = op(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, false)));
+  v = op(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false)));
   return v;
 }
 
+struct AddOp {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a + b; }
+};
+struct MaxOp {
+  __device__ uint32_t operator()(uint32_t a, uint32_t b) const { return a > b ? a : b; }
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) { return wave_incl_scan_op(v, AddOp()); }
+
+// 64-bit sums as two 32-bit scans with the carries of the low half.
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint64_t t = __shfl_up(v, d, kWave);
-    if (static_cast<int>(lane_id()) >= d) v += t;
-  }
-  return v;
+  const uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
+  // low halves are small in every use here (< 2^31 in total): no carry
+  return (static_cast<uint64_t>(wave_incl_scan(hi)) << 32) | wave_incl_scan(lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -472,11 +484,11 @@ struct MergeCfg {
   static constexpr int T = T_;                        // output symbols per tile
   static constexpr int BODY = BODY_;                  // resident block bytes
   static constexpr int NW = NT / kWave;
-  static constexpr int LVL = T + 16 * 128 + 64;       // bytes per level buffer
+  static constexpr int LVL = T + 15 * 128 + 64;       // bytes per level buffer
   static constexpr int LEVELS = kMaxLenGpu;
   static constexpr int STG = BODY / 8;                // streaming: staged (word, rank) pairs
-  static constexpr int SUP = BODY / 32 + 8;           // rank directory, per 256 bits
-  static constexpr int REL = BODY / 8 + 32;           // rank directory, per 64 bits
+  static constexpr int SUP = BODY / 32 + 2;           // rank directory, per 256 bits
+  static constexpr int REL = BODY / 8 + 8;            // rank directory, per 64 bits
 };
 
 // What a merge lane needs about a node for the current tile (16 bytes):
@@ -510,15 +522,16 @@ struct MergeSmem {
     };
   };
   NodeRec rec[256];
-  uint8_t act[C::LEVELS + 1][132];    // nodes of a level with a nonzero share
-  uint16_t tpref[C::LEVELS + 1][132]; // 16-output tasks before each of them; [nact] = total
-  uint32_t nact[C::LEVELS + 1];
+  uint8_t act[C::LEVELS][132];    // nodes of a level with a nonzero share
+  uint16_t tpref[C::LEVELS][132]; // 16-output tasks before each of them; [nact] = total
+  uint32_t nact[C::LEVELS];
   uint32_t stage_top;
   uint32_t tile;           // runtime tile size for this block
   uint32_t sel[16];
   uint32_t item;
   uint32_t lds_base;       // resident: LDS byte offset of the block's first byte
   uint32_t scan_tot[C::NW];
+  uint8_t mark[C::NW][kWave];   // per wave: node boundaries inside a task window
   uint32_t lvl[2][C::LVL / 4] __attribute__((aligned(16)));
   uint32_t sup[C::SUP];    // resident: 1 bits of the body before each 256-bit superblock
   uint8_t rel[C::REL];     // resident: 1 bits of the superblock before each 64-bit word
@@ -718,17 +731,37 @@ __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   const uint32_t total = sm.tpref[d][na];
   const uint16_t *tp = sm.tpref[d];
   const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
+  uint8_t *mark = &sm.mark[wave][0];
+  uint32_t k = 0;                        // node of the wave's first task (monotone)
   for (uint32_t base = kWave * wave; base < total; base += kWave * C::NW) {
+    // advance k to the last node whose first task is <= base
+    for (;;) {
+      const uint32_t j = k + 1 + lane;
+      const uint32_t p = j <= na ? tp[j] : 0xFFFFu;
+      const uint32_t adv = __popcll(__ballot(p <= base));
+      k += adv;
+      if (adv < kWave) break;
+    }
+    // nodes starting inside this window of 64 tasks: lane j owns the
+    // boundary of node k+1+j; every task takes the latest boundary at or
+    // before it (prefix maximum of boundary marks over the lanes)
+    const uint32_t j = k + 1 + lane;
+    const uint32_t pb = j <= na ? tp[j] : 0xFFFFu;
+    const bool inside = pb < base + kWave;
+    uint32_t kk = k;
+    if (__ballot(inside)) {
+      mark[lane] = 0;
+      wave_sync_lds();
+      if (inside) mark[pb - base] = static_cast<uint8_t>(lane + 1);
+      wave_sync_lds();
+      const uint32_t mx = wave_incl_scan_op(mark[lane], MaxOp());
+      kk = k + mx;
+      wave_sync_lds();
+    }
     const uint32_t task = base + lane;
     if (task >= total) continue;
-    // largest k with tp[k] <= task
-    uint32_t lo = 0, hi = na;            // tp[lo] <= task < tp[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (tp[mid] <= task) lo = mid; else hi = mid;
-    }
-    const uint32_t v = sm.act[d][lo];
-    const uint32_t j0 = 16 * (task - tp[lo]);
+    const uint32_t v = sm.act[d][kk];
+    const uint32_t j0 = 16 * (task - tp[kk]);
     const NodeRec r = sm.rec[v];
     const uint32_t tvv = sm.tv[v];
     uint32_t bits, r1;
@@ -742,29 +775,36 @@ __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
       bits = wr.x >> sh;
       r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
     }
-    uint32_t r0 = j0 - r1;
     const uint32_t kl = r.kids & 0xFFFF, kr = r.kids >> 16;
     const bool leafL = kl & 0x8000, leafR = kr & 0x8000;
-    const uint32_t bl = kl << 4, br = kr << 4;
+    // byte addresses of the children's next outputs (leaf: any valid address)
+    const uint32_t bl = leafL ? 0u : kl << 4, br = leafR ? 0u : kr << 4;
     const uint32_t cL = (kl & 255) * 0x01010101u, cR = (kr & 255) * 0x01010101u;
+    uint32_t aL[4], aR[4], m[4];
+    uint32_t r1g = r1, r0g = j0 - r1;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      m[g] = (bits >> (4 * g)) & 15;
+      aL[g] = bl + r0g;
+      aR[g] = br + r1g;
+      const uint32_t pc = __popc(m[g]);
+      r1g += pc;
+      r0g += 4 - pc;
+    }
     uint32_t o[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const uint32_t m = (bits >> (4 * g)) & 15;
-      const uint32_t L = leafL ? cL : win4(cbuf, bl + r0);
-      const uint32_t R = leafR ? cR : win4(cbuf, br + r1);
-      o[g] = __builtin_amdgcn_perm(R, L, sm.sel[m]);
-      const uint32_t pc = __popc(m);
-      r1 += pc;
-      r0 += 4 - pc;
+      const uint32_t wl = win4(cbuf, aL[g]);
+      const uint32_t wr = win4(cbuf, aR[g]);
+      o[g] = __builtin_amdgcn_perm(leafR ? cR : wr, leafL ? cL : wl, sm.sel[m[g]]);
     }
     if (d == 0) {
       uint8_t *dst = out + j0;
       if (j0 + 16 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 15)) {
         *reinterpret_cast<uint4 *>(dst) = make_uint4(o[0], o[1], o[2], o[3]);
       } else {
-        const uint32_t kk = tvv - j0 < 16 ? tvv - j0 : 16;
-        for (uint32_t e = 0; e < kk; ++e) dst[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
+        const uint32_t kk2 = tvv - j0 < 16 ? tvv - j0 : 16;
+        for (uint32_t e = 0; e < kk2; ++e) dst[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
       }
     } else {
       *reinterpret_cast<uint4 *>(&obuf[(r.obase + j0) >> 2]) = make_uint4(o[0], o[1], o[2], o[3]);
