@@ -160,17 +160,32 @@ __device__ void parse_offsets(const JobDev &J, uint32_t b, BlockHdr &h) {
   h.kraft = 0;
 }
 
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Parse and validate the rest of the header of block b (offsets already in
-// h); every thread of the workgroup must call it.  On return h.err != 0 or
+// h), run by ONE wave (wave-synchronous, no workgroup barrier); the caller
+// synchronises the workgroup afterwards.  On return h.err != 0 or
 // h.mode == 1 means the node tables are not filled.
-template <int NT, class Rd>
-__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
-  static_assert(NT >= 256, "header parse needs 256 threads");
-  const int tid = threadIdx.x;
-  if (tid == 0 && !h.err) {
-    int32_t err = 0;
-    const uint32_t comp = rd.u32(0), n = rd.u32(4), w2 = rd.u32(8);
-    const uint32_t mode = w2 & 255, csym = (w2 >> 8) & 255, cw = (w2 >> 16) & 255;
+//
+// The canonical code is never materialised: with cnt(L) codes of length L
+// and fc(L) the first of them, fc(L+1) = 2 (fc(L) + cnt(L)), the internal
+// nodes at depth d are the prefixes [fc(d) + cnt(d), 2^d), numbered
+// breadth-first; child q of such a node is a leaf iff q < fc(d+1) + cnt(d+1),
+// and then it is the (q - fc(d+1))-th symbol of length d+1 by id.
+template <class Rd>
+__device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
+  const uint32_t lane = lane_id();
+  int32_t err = h.err;
+  uint32_t mode = 0, csym = 0, cw = 0, comp = 0, n = 0;
+  if (!err) {
+    comp = rd.u32(0);
+    n = rd.u32(4);
+    const uint32_t w2 = rd.u32(8);
+    mode = w2 & 255; csym = (w2 >> 8) & 255; cw = (w2 >> 16) & 255;
     const uint64_t start = static_cast<uint64_t>(b) * J.block_size;
     const uint64_t want = J.n_total - start < J.block_size ? J.n_total - start : J.block_size;
     if (comp > h.end - h.blk || comp < kBlockFixed || n != want || (w2 >> 24) != 0 ||
@@ -181,149 +196,172 @@ __device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t
     } else if (mode != 0 || csym != 0 || comp < kBlockFixed + kLenTable) {
       err = PIVCO_E_CORRUPT;
     }
-    h.comp = comp; h.n = n; h.mode = mode; h.csym = csym; h.cw = cw;
-    h.err = err;
   }
-  if (tid < 17) h.cnt[tid] = 0;
-  __syncthreads();
-  if (h.err || h.mode == 1) return;
-  if (tid < 128) {
-    const uint32_t v = rd.u8(kBlockFixed + tid);
-    t.len[2 * tid] = v & 15;
-    t.len[2 * tid + 1] = v >> 4;
+  if (lane == 0) { h.comp = comp; h.n = n; h.mode = mode; h.csym = csym; h.cw = cw; h.err = err; }
+  if (err || mode == 1) { wave_sync_lds(); return; }
+  // code lengths: lane owns symbols 4*lane .. 4*lane+3 (two table bytes)
+  const uint32_t lb = rd.u8(kBlockFixed + 2 * lane) | (rd.u8(kBlockFixed + 2 * lane + 1) << 8);
+  uint32_t l[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) l[k] = (lb >> (4 * k)) & 15;
+  const uint64_t below = (1ull << lane) - 1;
+  uint32_t rank[4] = {0, 0, 0, 0};
+  uint32_t cnt[17];
+  cnt[0] = 0;
+  uint32_t kraft = 0, m = 0, maxlen = 0;
+  for (uint32_t L = 1; L <= 15; ++L) {
+    uint64_t mk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mk[k] = __ballot(l[k] == L);
+    const uint32_t c = __popcll(mk[0]) + __popcll(mk[1]) + __popcll(mk[2]) + __popcll(mk[3]);
+    const uint32_t before = __popcll(mk[0] & below) + __popcll(mk[1] & below) +
+                            __popcll(mk[2] & below) + __popcll(mk[3] & below);
+    uint32_t own = 0;   // same-length symbols of this lane with a smaller id
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (l[k] == L) { rank[k] = before + own; ++own; }
+    cnt[L] = c;
+    m += c;
+    kraft += c << (15 - L);
+    if (c) maxlen = L;
   }
-  __syncthreads();
-  // lengths -> counts per length, ranks within a length (canonical order)
-  uint32_t myrank = 0, l = 0;
-  if (tid < 256) {
-    l = t.len[tid];
-    if (l > J.max_len) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-    if (l) atomicAdd(&h.kraft, 1u << (15 - l));
-    const int w = tid >> 6, lane = tid & 63;
-    for (uint32_t L = 1; L <= 15; ++L) {
-      const uint64_t m = __ballot(l == L);
-      if (l == L) myrank = __popcll(m & ((1ull << lane) - 1));
-      if (lane == static_cast<int>(L)) t.wcnt[w][L] = __popcll(m);
-    }
+  for (uint32_t L = 16; L < 17; ++L) cnt[L] = 0;
+  if (maxlen > J.max_len) err = PIVCO_E_CORRUPT;
+  else if (m < 2 || kraft != (1u << 15)) err = PIVCO_E_CORRUPT;
+  else if (maxlen > kMaxLenGpu) err = PIVCO_E_UNSUPPORTED;
+  // canonical structure (every lane computes the same values)
+  uint32_t lbase[17], fc[18], lvl[18];
+  lbase[0] = 0;
+  lbase[1] = 0;
+  for (uint32_t L = 1; L < 16; ++L) lbase[L + 1] = lbase[L] + cnt[L];
+  fc[0] = 0;
+  lvl[0] = 0;
+  for (uint32_t d = 0; d <= 16; ++d) {
+    const uint32_t cd = d < 17 ? cnt[d] : 0;
+    fc[d + 1] = 2 * (fc[d] + cd);
+    const uint32_t Id = d < maxlen ? (1u << d) - fc[d] - cd : 0u;
+    lvl[d + 1] = lvl[d] + Id;
   }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t m = 0, maxlen = 0;
-    for (uint32_t L = 1; L <= 15; ++L) {
-      h.cnt[L] = t.wcnt[0][L] + t.wcnt[1][L] + t.wcnt[2][L] + t.wcnt[3][L];
-      m += h.cnt[L];
-      if (h.cnt[L]) maxlen = L;
-    }
-    if (h.err == 0) {
-      if (m < 2 || h.kraft != (1u << 15)) h.err = PIVCO_E_CORRUPT;
-      else if (maxlen > kMaxLenGpu) h.err = PIVCO_E_UNSUPPORTED;
-    }
-    h.lbase[1] = 0;
-    for (uint32_t L = 1; L < 16; ++L) h.lbase[L + 1] = h.lbase[L] + h.cnt[L];
-    h.cnt[0] = 0;
-    h.fc[0] = 0;
-    h.lvl[0] = 0;
-    for (uint32_t d = 0; d <= 15; ++d) {
-      h.fc[d + 1] = 2 * (h.fc[d] + h.cnt[d]);
-      const uint32_t Id = d < maxlen ? (1u << d) - h.fc[d] - h.cnt[d] : 0u;
-      h.lvl[d + 1] = h.lvl[d] + Id;
-    }
-    const uint32_t I = m >= 2 ? m - 1 : 0;
-    if (!h.err && h.lvl[maxlen < 16 ? maxlen : 15] != I) h.err = PIVCO_E_CORRUPT;
-    h.I = I;
-    h.maxlen = maxlen;
-    h.kb = (I + 7) / 8;
-    const uint64_t need = kBlockFixed + kLenTable + h.kb + static_cast<uint64_t>(h.cw) * I;
-    if (need > h.comp && !h.err) h.err = PIVCO_E_CORRUPT;
-    h.raw_base = static_cast<uint32_t>(need);
+  const uint32_t I = m >= 2 ? m - 1 : 0;
+  if (!err && lvl[maxlen] != I) err = PIVCO_E_CORRUPT;
+  const uint32_t kb = (I + 7) / 8;
+  const uint32_t raw_base = kBlockFixed + kLenTable + kb + cw * I;
+  if (!err && raw_base > comp) err = PIVCO_E_CORRUPT;
+  if (lane < 17) { h.cnt[lane] = cnt[lane]; h.lbase[lane] = lbase[lane]; }
+  if (lane < 18) { h.fc[lane] = fc[lane]; h.lvl[lane] = lvl[lane]; }
+  if (lane == 0) {
+    h.I = I; h.maxlen = maxlen; h.kb = kb; h.raw_base = raw_base; h.err = err; h.kraft = kraft;
   }
-  __syncthreads();
-  if (h.err) return;
-  if (tid < 256 && l) {
-    const int w = tid >> 6;
-    uint32_t r = myrank;
-    for (int w2 = 0; w2 < w; ++w2) r += t.wcnt[w2][l];
-    t.leafsym[h.lbase[l] + r] = static_cast<uint8_t>(tid);
-  }
-  __syncthreads();
-  const uint32_t I = h.I;
+  if (err) { wave_sync_lds(); return; }
+  // symbols in canonical order
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (l[k]) t.leafsym[lbase[l[k]] + rank[k]] = static_cast<uint8_t>(4 * lane + k);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t.len[4 * lane + k] = static_cast<uint8_t>(l[k]);
+  wave_sync_lds();
+  // node table: lane owns nodes 4*lane .. 4*lane+3
   const uint32_t kbase = kBlockFixed + kLenTable;
-  if (tid < static_cast<int>(I)) {
-    const uint32_t i = tid;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    if (i >= I) continue;
     uint32_t d = 0;
-    while (h.lvl[d + 1] <= i) ++d;
-    const uint32_t p = h.fc[d] + h.cnt[d] + (i - h.lvl[d]);
-    const uint32_t leafend = h.fc[d + 1] + h.cnt[d + 1];
+    while (lvl[d + 1] <= i) ++d;
+    const uint32_t p = fc[d] + cnt[d] + (i - lvl[d]);
+    const uint32_t leafend = fc[d + 1] + cnt[d + 1];
     for (int bb = 0; bb < 2; ++bb) {
       const uint32_t q = 2 * p + bb;
       t.child[i][bb] = q < leafend
-                           ? static_cast<uint16_t>(0x8000u | t.leafsym[h.lbase[d + 1] + q - h.fc[d + 1]])
-                           : static_cast<uint16_t>(h.lvl[d + 1] + (q - leafend));
+                           ? static_cast<uint16_t>(0x8000u | t.leafsym[lbase[d + 1] + q - fc[d + 1]])
+                           : static_cast<uint16_t>(lvl[d + 1] + (q - leafend));
     }
     t.depth[i] = static_cast<uint8_t>(d);
     t.kind[i] = (rd.u8(kbase + (i >> 3)) >> (i & 7)) & 1;
-    const uint32_t co = kbase + h.kb + h.cw * i;
+    const uint32_t co = kbase + kb + cw * i;
     uint32_t r = rd.u8(co) | (rd.u8(co + 1) << 8);
-    if (h.cw == 4) r |= (rd.u8(co + 2) << 16) | (rd.u8(co + 3) << 24);
+    if (cw == 4) r |= (rd.u8(co + 2) << 16) | (rd.u8(co + 3) << 24);
     t.nr[i] = r;
-    if (i == 0) t.nv[0] = h.n;
   }
-  if (tid == 0 && (I & 7)) {
-    if (rd.u8(kbase + (I >> 3)) >> (I & 7)) h.err = PIVCO_E_CORRUPT;   // unused kind bits
-  }
-  if (tid < 17) h.lvl_total[tid] = 0;
-  __syncthreads();
-  // symbol counts top-down, one level at a time
-  for (uint32_t d = 0; d < h.maxlen; ++d) {
-    const uint32_t lo = h.lvl[d], hi = h.lvl[d + 1];
-    for (uint32_t i = lo + tid; i < hi; i += NT) {
+  if ((I & 7) && (rd.u8(kbase + (I >> 3)) >> (I & 7))) err = PIVCO_E_CORRUPT;  // unused kind bits
+  if (lane == 0) t.nv[0] = n;
+  wave_sync_lds();
+  // symbol counts top-down, one level at a time (the wave stays in step)
+  uint64_t ltot = 0;                   // lane d: symbols passing level d
+  for (uint32_t d = 0; d < maxlen; ++d) {
+    uint64_t lsum = 0;
+    for (uint32_t i = lvl[d] + lane; i < lvl[d + 1]; i += kWave) {
       const uint32_t v = t.nv[i], r = t.nr[i];
-      atomicAdd(reinterpret_cast<unsigned long long *>(&h.lvl_total[d]), static_cast<unsigned long long>(v));
-      if (r > v) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+      lsum += v;
+      if (r > v) err = PIVCO_E_CORRUPT;
+      const uint32_t rr = r > v ? v : r;
       const uint16_t c0 = t.child[i][0], c1 = t.child[i][1];
-      if (!(c0 & 0x8000)) t.nv[c0] = v - (r > v ? v : r);
-      if (!(c1 & 0x8000)) t.nv[c1] = r > v ? v : r;
+      if (!(c0 & 0x8000)) t.nv[c0] = v - rr;
+      if (!(c1 & 0x8000)) t.nv[c1] = rr;
     }
-    __syncthreads();
+    const uint32_t lo = wave_incl_scan(static_cast<uint32_t>(lsum));   // per level <= 4 GiB of
+    const uint32_t tot = __shfl(lo, kWave - 1, kWave);                  // symbols (fits: n < 2^32)
+    if (lane == d) ltot = tot;
+    wave_sync_lds();
   }
-  // body offsets: exclusive scans of raw bytes and rANS scratch words
-  uint64_t x = 0;
-  if (tid < 256 && tid < static_cast<int>(I)) {
-    const uint64_t v = t.nv[tid];
-    x = t.kind[tid] ? (div_up(v, 32) << 32) : div_up(v, 8);
-  }
-  uint64_t inc = 0;
-  if (tid < 256) {
-    inc = wave_incl_scan64(x);
-    if ((tid & 63) == 63) t.scan_tot[tid >> 6] = inc;
-  }
-  __syncthreads();
-  if (tid < 256) {
-    uint64_t base = 0;
-    for (int w = 0; w < (tid >> 6); ++w) base += t.scan_tot[w];
-    const uint64_t ex = base + inc - x;
-    if (tid < static_cast<int>(I))
-      t.boff[tid] = t.kind[tid] ? static_cast<uint32_t>(ex >> 32)
-                                : h.raw_base + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
-    if (tid == 255) {
-      const uint64_t tot = base + inc;
-      const uint64_t raw_end = h.raw_base + (tot & 0xFFFFFFFFu);
-      h.raw_end = raw_end > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(raw_end);
-      if (raw_end > h.comp) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-      if ((tot >> 32) != h.ans_words) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-      uint32_t na = 0;
-      for (uint32_t i = 0; i < I; ++i) na += t.kind[i];
-      h.n_ans = na;
-      if (na == 0 && raw_end != h.comp) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+  if (lane < 17) h.lvl_total[lane] = lane < maxlen ? ltot : 0;
+  // body offsets: lane owns nodes 4*lane .. 4*lane+3 (contiguous for the scan)
+  uint32_t rawb[4], answ[4], lraw = 0, lans = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    uint32_t rb = 0, aw = 0;
+    if (i < I) {
+      const uint32_t v = t.nv[i];
+      if (t.kind[i]) aw = (v + 31) / 32; else rb = (v + 7) / 8;
     }
+    rawb[k] = lraw; answ[k] = lans;
+    lraw += rb; lans += aw;
   }
-  __syncthreads();
-  if (h.err) return;
+  const uint32_t iraw = wave_incl_scan(lraw), ians = wave_incl_scan(lans);
+  const uint32_t xraw = iraw - lraw, xans = ians - lans;
+  uint32_t na = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    if (i >= I) continue;
+    t.boff[i] = t.kind[i] ? xans + answ[k] : raw_base + xraw + rawb[k];
+    na += t.kind[i];
+  }
+  const uint32_t raw_total = __shfl(iraw, kWave - 1, kWave);
+  const uint32_t ans_total = __shfl(ians, kWave - 1, kWave);
+  const uint32_t n_ans = __shfl(wave_incl_scan(na), kWave - 1, kWave);
+  const uint64_t raw_end = static_cast<uint64_t>(raw_base) + raw_total;
+  if (raw_end > comp || ans_total != h.ans_words || (n_ans == 0 && raw_end != comp)) err = PIVCO_E_CORRUPT;
+  wave_sync_lds();
   // padding bits of raw bodies must be zero
-  if (tid < static_cast<int>(I) && !t.kind[tid] && (t.nv[tid] & 7)) {
-    const uint32_t last = rd.u8(t.boff[tid] + (t.nv[tid] >> 3));
-    if (last >> (t.nv[tid] & 7)) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+  if (!err) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4 * lane + k;
+      if (i < I && !t.kind[i] && (t.nv[i] & 7)) {
+        const uint32_t last = rd.u8(t.boff[i] + (t.nv[i] >> 3));
+        if (last >> (t.nv[i] & 7)) err = PIVCO_E_CORRUPT;
+      }
+    }
   }
+  const bool any = __ballot(err != 0) != 0;
+  if (any) {
+    const uint64_t bad = __ballot(err != 0);
+    const int src = __ffsll(static_cast<long long>(bad)) - 1;
+    err = __shfl(err, src, kWave);
+  }
+  if (lane == 0) {
+    h.raw_end = raw_end > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(raw_end);
+    h.n_ans = n_ans;
+    h.err = err;
+  }
+  wave_sync_lds();
+}
+
+template <int NT, class Rd>
+__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
+  if ((threadIdx.x >> 6) == 0) parse_block_wave(J, b, h, t, rd);
   __syncthreads();
 }
 
@@ -573,11 +611,6 @@ __device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total
   return inc - v;
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Count for level d, run by one wave: every node's share (sm.tv) and its 1
 // bits give the children's shares; the node's merge record, the children's
@@ -830,20 +863,27 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
   const bool resident = !h.err && span + 4ull * h.ans_words + 64 <= static_cast<uint64_t>(C::BODY);
   if (resident) {
     const uint64_t in_dw = J.in_len >> 2;
+    const uint64_t in16 = J.in_len >> 4;
     const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
     const uint32_t n16 = static_cast<uint32_t>(span >> 4);
-    for (uint32_t i = tid; i < n16; i += C::NT) {
-      const uint64_t q = (g0 >> 2) + 4ull * i;
-      uint4 v;
-      if (q + 4 <= in_dw) {
-        v = *reinterpret_cast<const uint4 *>(gin + q);
+    // 16-byte chunks straight into LDS (global_load_lds_dwordx4: lane i of a
+    // wave fills LDS bytes [16 i, 16 i + 16) after the wave's base); wave
+    // iterations that touch the end of the stream use guarded loads instead
+    for (uint32_t base = kWave * wave; base < n16; base += kWave * C::NW) {
+      if (base + kWave <= n16 && (g0 >> 4) + base + kWave <= in16) {
+        __builtin_amdgcn_global_load_lds(J.in + g0 + 16ull * (base + lane), &sm.body[4 * base], 16, 0, 0);
       } else {
-        v.x = q < in_dw ? gin[q] : 0u;
-        v.y = q + 1 < in_dw ? gin[q + 1] : 0u;
-        v.z = q + 2 < in_dw ? gin[q + 2] : 0u;
-        v.w = q + 3 < in_dw ? gin[q + 3] : 0u;
+        const uint32_t i = base + lane;
+        if (i < n16) {
+          const uint64_t q = (g0 >> 2) + 4ull * i;
+          uint4 v;
+          v.x = q < in_dw ? gin[q] : 0u;
+          v.y = q + 1 < in_dw ? gin[q + 1] : 0u;
+          v.z = q + 2 < in_dw ? gin[q + 2] : 0u;
+          v.w = q + 3 < in_dw ? gin[q + 3] : 0u;
+          *reinterpret_cast<uint4 *>(&sm.body[4 * i]) = v;
+        }
       }
-      *reinterpret_cast<uint4 *>(&sm.body[4 * i]) = v;
     }
     const uint32_t abase = static_cast<uint32_t>(span >> 2);
     for (uint32_t i = tid; i < h.ans_words; i += C::NT) {
@@ -853,6 +893,7 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     const uint32_t body_dw = abase + h.ans_words;
     for (uint32_t i = body_dw + tid; i < ((body_dw + 7) & ~7u) + 8; i += C::NT) sm.body[i] = 0u;
     if (tid == 0) sm.lds_base = static_cast<uint32_t>(h.blk - g0);
+    __builtin_amdgcn_s_waitcnt(0);     // direct-to-LDS loads of this wave have landed
     __syncthreads();
     parse_block<C::NT>(J, b, h, t, LdsBytes{reinterpret_cast<const uint8_t *>(sm.body) + (h.blk - g0)});
   } else {
