@@ -206,9 +206,11 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
   for (int k = 0; k < 4; ++k) l[k] = (lb >> (4 * k)) & 15;
   const uint64_t below = (1ull << lane) - 1;
   uint32_t rank[4] = {0, 0, 0, 0};
-  uint32_t cnt[17];
-  cnt[0] = 0;
+  // Per-length values are held lane-distributed (lane L holds the value for
+  // length or depth L) and copied to h; dynamic lookups read h from LDS.
+  uint32_t cnt_l = 0;
   uint32_t kraft = 0, m = 0, maxlen = 0;
+#pragma unroll
   for (uint32_t L = 1; L <= 15; ++L) {
     uint64_t mk[4];
 #pragma unroll
@@ -220,38 +222,39 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if (l[k] == L) { rank[k] = before + own; ++own; }
-    cnt[L] = c;
+    if (lane == L) cnt_l = c;
     m += c;
     kraft += c << (15 - L);
     if (c) maxlen = L;
   }
-  for (uint32_t L = 16; L < 17; ++L) cnt[L] = 0;
   if (maxlen > J.max_len) err = PIVCO_E_CORRUPT;
   else if (m < 2 || kraft != (1u << 15)) err = PIVCO_E_CORRUPT;
   else if (maxlen > kMaxLenGpu) err = PIVCO_E_UNSUPPORTED;
-  // canonical structure (every lane computes the same values)
-  uint32_t lbase[17], fc[18], lvl[18];
-  lbase[0] = 0;
-  lbase[1] = 0;
-  for (uint32_t L = 1; L < 16; ++L) lbase[L + 1] = lbase[L] + cnt[L];
-  fc[0] = 0;
-  lvl[0] = 0;
+  // canonical structure: lbase(L) = codes shorter than L; fc(d+1) =
+  // 2 (fc(d) + cnt(d)); lvl(d) = internal nodes above depth d
+  const uint32_t lbase_l = wave_incl_scan(lane <= 16 ? cnt_l : 0u) - cnt_l;
+  uint32_t fc_l = 0, lvl_l = 0, fcd = 0, lvd = 0, lvl_max = 0;
+#pragma unroll
   for (uint32_t d = 0; d <= 16; ++d) {
-    const uint32_t cd = d < 17 ? cnt[d] : 0;
-    fc[d + 1] = 2 * (fc[d] + cd);
-    const uint32_t Id = d < maxlen ? (1u << d) - fc[d] - cd : 0u;
-    lvl[d + 1] = lvl[d] + Id;
+    const uint32_t cd = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(cnt_l), d));
+    const uint32_t Id = d < maxlen ? (1u << d) - fcd - cd : 0u;
+    fcd = 2 * (fcd + cd);
+    lvd += Id;
+    if (lane == d + 1) { fc_l = fcd; lvl_l = lvd; }
+    if (d + 1 == maxlen) lvl_max = lvd;
   }
   const uint32_t I = m >= 2 ? m - 1 : 0;
-  if (!err && lvl[maxlen] != I) err = PIVCO_E_CORRUPT;
+  if (!err && lvl_max != I) err = PIVCO_E_CORRUPT;
   const uint32_t kb = (I + 7) / 8;
   const uint32_t raw_base = kBlockFixed + kLenTable + kb + cw * I;
   if (!err && raw_base > comp) err = PIVCO_E_CORRUPT;
-  if (lane < 17) { h.cnt[lane] = cnt[lane]; h.lbase[lane] = lbase[lane]; }
-  if (lane < 18) { h.fc[lane] = fc[lane]; h.lvl[lane] = lvl[lane]; }
+  if (lane < 17) { h.cnt[lane] = cnt_l; h.lbase[lane] = lbase_l; }
+  if (lane < 18) { h.fc[lane] = fc_l; h.lvl[lane] = lvl_l; }
   if (lane == 0) {
     h.I = I; h.maxlen = maxlen; h.kb = kb; h.raw_base = raw_base; h.err = err; h.kraft = kraft;
   }
+  wave_sync_lds();
+  const uint32_t *cnt = h.cnt, *lbase = h.lbase, *fc = h.fc, *lvl = h.lvl;
   if (err) { wave_sync_lds(); return; }
   // symbols in canonical order
 #pragma unroll
