@@ -123,8 +123,6 @@ struct NodeTab {
   uint8_t depth[256];
   uint8_t len[256];
   uint8_t leafsym[256];    // symbols ordered by (length, symbol)
-  uint32_t wcnt[4][16];    // per-wave per-length counts
-  uint64_t scan_tot[16];
 };
 
 // Byte readers for block-relative offsets: the block in global memory, or
@@ -177,7 +175,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // breadth-first; child q of such a node is a leaf iff q < fc(d+1) + cnt(d+1),
 // and then it is the (q - fc(d+1))-th symbol of length d+1 by id.
 template <class Rd>
-__device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
+__device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd,
+                                 bool totals) {
   const uint32_t lane = lane_id();
   int32_t err = h.err;
   uint32_t mode = 0, csym = 0, cw = 0, comp = 0, n = 0;
@@ -253,32 +252,47 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
   if (lane == 0) {
     h.I = I; h.maxlen = maxlen; h.kb = kb; h.raw_base = raw_base; h.err = err; h.kraft = kraft;
   }
-  wave_sync_lds();
-  const uint32_t *cnt = h.cnt, *lbase = h.lbase, *fc = h.fc, *lvl = h.lvl;
   if (err) { wave_sync_lds(); return; }
   // symbols in canonical order
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (l[k]) t.leafsym[lbase[l[k]] + rank[k]] = static_cast<uint8_t>(4 * lane + k);
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t lb_k = __shfl(lbase_l, l[k], kWave);     // every lane takes part
+    if (l[k]) t.leafsym[lb_k + rank[k]] = static_cast<uint8_t>(4 * lane + k);
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) t.len[4 * lane + k] = static_cast<uint8_t>(l[k]);
-  wave_sync_lds();
-  // node table: lane owns nodes 4*lane .. 4*lane+3
+  // node table: lane owns nodes 4*lane .. 4*lane+3.  A node's depth is the
+  // number of levels that start at or before it; the per-depth values come
+  // from the lanes holding them (fc | cnt << 16 and lvl | lbase << 16, all
+  // below 2^14 for depths up to the length limit + 1).
+  const uint32_t pa = fc_l | (cnt_l << 16), pb = lvl_l | (lbase_l << 16);
+  uint32_t dd[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 1; j <= kMaxLenGpu; ++j) {
+    const uint32_t lj = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(lvl_l), j));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dd[k] += (4 * lane + k >= lj) ? 1u : 0u;
+  }
+  wave_sync_lds();                       // leaf symbols written
   const uint32_t kbase = kBlockFixed + kLenTable;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = 4 * lane + k;
+    const uint32_t d = dd[k];
+    const uint32_t a0 = __shfl(pa, d, kWave), b0 = __shfl(pb, d, kWave);
+    const uint32_t a1 = __shfl(pa, d + 1, kWave), b1 = __shfl(pb, d + 1, kWave);
     if (i >= I) continue;
-    uint32_t d = 0;
-    while (lvl[d + 1] <= i) ++d;
-    const uint32_t p = fc[d] + cnt[d] + (i - lvl[d]);
-    const uint32_t leafend = fc[d + 1] + cnt[d + 1];
+    const uint32_t fcd = a0 & 0xFFFF, cntd = a0 >> 16, lvd = b0 & 0xFFFF;
+    const uint32_t fcd1 = a1 & 0xFFFF, cntd1 = a1 >> 16, lvd1 = b1 & 0xFFFF, lbd1 = b1 >> 16;
+    const uint32_t p = fcd + cntd + (i - lvd);
+    const uint32_t leafend = fcd1 + cntd1;
+    uint32_t cc = 0;
     for (int bb = 0; bb < 2; ++bb) {
       const uint32_t q = 2 * p + bb;
-      t.child[i][bb] = q < leafend
-                           ? static_cast<uint16_t>(0x8000u | t.leafsym[lbase[d + 1] + q - fc[d + 1]])
-                           : static_cast<uint16_t>(lvl[d + 1] + (q - leafend));
+      const uint32_t c = q < leafend ? 0x8000u | t.leafsym[lbd1 + q - fcd1] : lvd1 + (q - leafend);
+      cc |= c << (16 * bb);
     }
+    *reinterpret_cast<uint32_t *>(t.child[i]) = cc;
     t.depth[i] = static_cast<uint8_t>(d);
     t.kind[i] = (rd.u8(kbase + (i >> 3)) >> (i & 7)) & 1;
     const uint32_t co = kbase + kb + cw * i;
@@ -290,24 +304,33 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
   if (lane == 0) t.nv[0] = n;
   wave_sync_lds();
   // symbol counts top-down, one level at a time (the wave stays in step)
-  uint64_t ltot = 0;                   // lane d: symbols passing level d
   for (uint32_t d = 0; d < maxlen; ++d) {
-    uint64_t lsum = 0;
-    for (uint32_t i = lvl[d] + lane; i < lvl[d + 1]; i += kWave) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(lvl_l), d));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(lvl_l), d + 1));
+    for (uint32_t i = lo + lane; i < hi; i += kWave) {
       const uint32_t v = t.nv[i], r = t.nr[i];
-      lsum += v;
+      const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[i]);
       if (r > v) err = PIVCO_E_CORRUPT;
       const uint32_t rr = r > v ? v : r;
-      const uint16_t c0 = t.child[i][0], c1 = t.child[i][1];
+      const uint32_t c0 = cc & 0xFFFF, c1 = cc >> 16;
       if (!(c0 & 0x8000)) t.nv[c0] = v - rr;
       if (!(c1 & 0x8000)) t.nv[c1] = rr;
     }
-    const uint32_t lo = wave_incl_scan(static_cast<uint32_t>(lsum));   // per level <= 4 GiB of
-    const uint32_t tot = __shfl(lo, kWave - 1, kWave);                  // symbols (fits: n < 2^32)
-    if (lane == d) ltot = tot;
     wave_sync_lds();
   }
-  if (lane < 17) h.lvl_total[lane] = lane < maxlen ? ltot : 0;
+  if (totals) {
+    // symbols passing each level (only the streaming tile choice needs them)
+    uint64_t ltot = 0;                 // lane d: level d
+    for (uint32_t d = 0; d < maxlen; ++d) {
+      uint32_t s = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4 * lane + k < I && dd[k] == d) s += t.nv[4 * lane + k];
+      const uint32_t tot = __shfl(wave_incl_scan(s), kWave - 1, kWave);  // < 2^32: n < 2^32
+      if (lane == d) ltot = tot;
+    }
+    if (lane < 17) h.lvl_total[lane] = lane < maxlen ? ltot : 0;
+  }
   // body offsets: lane owns nodes 4*lane .. 4*lane+3 (contiguous for the scan)
   uint32_t rawb[4], answ[4], lraw = 0, lans = 0;
 #pragma unroll
@@ -363,8 +386,9 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
 }
 
 template <int NT, class Rd>
-__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
-  if ((threadIdx.x >> 6) == 0) parse_block_wave(J, b, h, t, rd);
+__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd,
+                            bool totals = false) {
+  if ((threadIdx.x >> 6) == 0) parse_block_wave(J, b, h, t, rd, totals);
   __syncthreads();
 }
 
@@ -527,19 +551,21 @@ struct MergeCfg {
   static constexpr int NW = NT / kWave;
   static constexpr int LVL = T + 15 * 128 + 64;       // bytes per level buffer
   static constexpr int LEVELS = kMaxLenGpu;
+  static constexpr int WIN = (T / 16 + 128 + 63) / 64 + 1;   // 64-task windows per level
   static constexpr int STG = BODY / 8;                // streaming: staged (word, rank) pairs
   static constexpr int SUP = BODY / 32 + 2;           // rank directory, per 256 bits
   static constexpr int REL = BODY / 8 + 8;            // rank directory, per 64 bits
 };
 
-// What a merge lane needs about a node for the current tile (16 bytes):
-// where its bits start (resident: LDS bit address; streaming: first staged
-// word), the 1 bits before that point, its output offset, and per child
-// either the child's output offset / 16 or 0x8000 | leaf symbol.
+// What a merge lane needs about a node with work in the current tile (16
+// bytes): where its bits start (resident: LDS bit address; streaming: first
+// staged word), the 1 bits before that point, its output offset in its level
+// buffer | its first task in the level << 16, and per child either the
+// child's output offset / 16 or 0x8000 | leaf symbol.
 struct NodeRec {
   uint32_t x0;
   uint32_t arank;
-  uint32_t obase;
+  uint32_t ot;
   uint32_t kids;
 };
 
@@ -549,30 +575,33 @@ struct MergeSmem {
   NodeTab t;
   uint32_t cur[256];       // bits of the node consumed by earlier tiles
   uint32_t tv[256];        // node's share of the current tile
-  uint32_t obase[256];     // node's output offset in its level buffer (16-byte aligned)
   union {
     struct {
       uint32_t abit[256];  // resident: LDS bit address of the node bitmap
       uint32_t arank[256]; // resident: 1 bits of the body before the cursor
       uint32_t r0[256];    // resident: 1 bits of the body before the node
+      uint32_t aend[256];  // resident: 1 bits of the body before the share's end
     };
     struct {
       uint32_t tone[256];  // streaming: 1 bits in the tile share
       uint32_t ones[256];  // streaming: 1 bits seen so far
       uint32_t stg[256];   // streaming: first staged word of the node
+      uint32_t obase[256]; // streaming: output offset in the level buffer (16-byte aligned)
     };
   };
-  NodeRec rec[256];
-  uint8_t act[C::LEVELS][132];    // nodes of a level with a nonzero share
-  uint16_t tpref[C::LEVELS][132]; // 16-output tasks before each of them; [nact] = total
-  uint32_t nact[C::LEVELS];
+  NodeRec rec[256];        // nodes with work, level by level (slot order)
+  uint64_t smask[C::LEVELS][C::WIN];  // bit i of window w: a node's first task is 64 w + i
+  uint8_t wstart[C::LEVELS][C::WIN];  // level slot of the node holding task 64 w
+  uint32_t ntask[C::LEVELS];          // 16-output tasks of the level
+  uint32_t actbase[C::LEVELS];        // slots of the levels above
+  uint32_t act_run;
   uint32_t stage_top;
   uint32_t tile;           // runtime tile size for this block
   uint32_t sel[16];
   uint32_t item;
   uint32_t lds_base;       // resident: LDS byte offset of the block's first byte
   uint32_t scan_tot[C::NW];
-  uint8_t mark[C::NW][kWave];   // per wave: node boundaries inside a task window
+  uint32_t leafrow[256];   // four copies of byte s: the "sequence" of a leaf child s
   uint32_t lvl[2][C::LVL / 4] __attribute__((aligned(16)));
   uint32_t sup[C::SUP];    // resident: 1 bits of the body before each 256-bit superblock
   uint8_t rel[C::REL];     // resident: 1 bits of the superblock before each 64-bit word
@@ -598,13 +627,26 @@ __device__ uint32_t pick_tile_streaming(const BlockHdr &h) {
 // superblock count + 64-bit word count within it + popcount of the rest.
 __device__ __forceinline__ uint32_t rank_at(const uint32_t *body, const uint32_t *sup,
                                             const uint8_t *rel, uint32_t x) {
-  const uint32_t q = x >> 6;
-  const uint32_t d0 = body[2 * q], d1 = body[2 * q + 1];
-  const uint32_t b = x & 63;
-  uint32_t r = sup[x >> 8] + rel[q];
-  if (b >= 32) r += __popc(d0) + __popc(d1 & ((1u << (b - 32)) - 1));
-  else r += __popc(d0 & ((1u << b) - 1));
-  return r;
+  const uint64_t w = reinterpret_cast<const uint64_t *>(body)[x >> 6];
+  return sup[x >> 8] + rel[x >> 6] + static_cast<uint32_t>(__popcll(w & ((1ull << (x & 63)) - 1)));
+}
+
+// The 4 bytes at LDS byte address a (relative to lds): two aligned dword
+// reads and a byte funnel shift (unaligned DS reads are much slower).
+__device__ __forceinline__ uint32_t lds_win(const uint8_t *lds, uint32_t a) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(lds + (a & ~3u));
+  return __builtin_amdgcn_alignbyte(p[1], p[0], a);
+}
+
+// Enters a node with work into its level's task windows: its record goes to
+// its slot, its first task sets a bit of the window start mask, and the
+// windows whose first task falls inside it point at its level slot.
+template <class C>
+__device__ __forceinline__ void list_node(MergeSmem<C> &sm, uint32_t d, uint32_t ai, uint32_t gslot,
+                                          uint32_t tp, uint32_t nt, const NodeRec &r) {
+  sm.rec[gslot] = r;
+  atomicOr(reinterpret_cast<unsigned long long *>(&sm.smask[d][tp >> 6]), 1ull << (tp & 63));
+  for (uint32_t w = (tp + 63) >> 6; kWave * w < tp + nt; ++w) sm.wstart[d][w] = static_cast<uint8_t>(ai);
 }
 
 // Exclusive prefix over the 64 lanes of a wave, and the wave total.
@@ -615,36 +657,31 @@ __device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total
 }
 
 
-// Count for level d, run by one wave: every node's share (sm.tv) and its 1
-// bits give the children's shares; the node's merge record, the children's
-// output space in the next level buffer, and the compacted list of the
-// level's nodes with work (with a prefix of their 16-output tasks) come from
-// wave-wide prefix sums.  Resident mode takes the 1 bits from the rank
-// directory; streaming mode from the staging pass.  Cursors advance here.
-template <class C, bool RESIDENT>
-__device__ void count_level(MergeSmem<C> &sm, uint32_t d) {
+// Streaming count for level d, run by one wave: every node's share (sm.tv)
+// and its 1 bits (from the staging pass) give the children's shares; the
+// node's merge record, the children's output space in the next level buffer,
+// and the compacted list of the level's nodes with work (with a prefix of
+// their 16-output tasks) come from wave-wide prefix sums.  Cursors advance
+// here.
+template <class C>
+__device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.h;
   NodeTab &t = sm.t;
   uint32_t out_top = 0, task_top = 0, act_top = 0;
+  if (lane < static_cast<uint32_t>(C::WIN)) sm.smask[d][lane] = 0;
+  const uint32_t act_base = sm.act_run;
+  wave_sync_lds();
   for (uint32_t v0 = h.lvl[d]; v0 < h.lvl[d + 1]; v0 += kWave) {
     const uint32_t v = v0 + lane;
     const bool valid = v < h.lvl[d + 1];
     uint32_t tvv = 0, ones = 0, tc[2] = {0, 0};
     uint16_t ch[2] = {0x8000, 0x8000};
-    uint32_t x0 = 0, ar = 0;
+    uint32_t x0 = 0;
     if (valid) {
       tvv = sm.tv[v];
-      if (RESIDENT) {
-        x0 = sm.abit[v] + sm.cur[v];
-        ar = sm.arank[v];
-        const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.rel, x0 + tvv) : ar;
-        ones = e - ar;
-        sm.arank[v] = e;
-      } else {
-        x0 = sm.stg[v];
-        ones = sm.tone[v];
-      }
+      x0 = sm.stg[v];
+      ones = sm.tone[v];
       ch[0] = t.child[v][0];
       ch[1] = t.child[v][1];
       tc[0] = tvv - ones;
@@ -679,16 +716,15 @@ __device__ void count_level(MergeSmem<C> &sm, uint32_t d) {
         }
         kids |= code << (16 * bb);
       }
-      NodeRec r;
-      r.x0 = x0;
-      r.arank = ar;
-      r.obase = sm.obase[v];
-      r.kids = kids;
-      sm.rec[v] = r;
       if (isact) {
         const uint32_t ai = act_top + static_cast<uint32_t>(ex >> 48);
-        sm.act[d][ai] = static_cast<uint8_t>(v);
-        sm.tpref[d][ai] = static_cast<uint16_t>(task_top + ((ex >> 32) & 0xFFFF));
+        const uint32_t tp = task_top + static_cast<uint32_t>((ex >> 32) & 0xFFFF);
+        NodeRec r;
+        r.x0 = x0;
+        r.arank = 0;
+        r.ot = sm.obase[v] | (tp << 16);
+        r.kids = kids;
+        list_node<C>(sm, d, ai, act_base + ai, tp, tasks, r);
       }
       sm.cur[v] += tvv;
     }
@@ -698,10 +734,127 @@ __device__ void count_level(MergeSmem<C> &sm, uint32_t d) {
     wave_sync_lds();
   }
   if (lane == 0) {
-    sm.tpref[d][act_top] = static_cast<uint16_t>(task_top);
-    sm.nact[d] = act_top;
+    sm.ntask[d] = task_top;
+    sm.actbase[d] = act_base;
+    sm.act_run = act_base + act_top;
   }
   wave_sync_lds();
+}
+
+// Resident count for a tile that ends inside the block, run by one wave:
+// top-down, a node's share and the 1 bits in it (rank directory at the
+// share's end) give the children's shares.  A child that would receive more
+// symbols than it has left marks the block corrupt and gets none.
+template <class C>
+__device__ void count_chain(MergeSmem<C> &sm) {
+  const uint32_t lane = lane_id();
+  BlockHdr &h = sm.h;
+  NodeTab &t = sm.t;
+  const uint32_t maxd = h.maxlen;
+  for (uint32_t d = 0; d < maxd; ++d) {
+    const uint32_t hi = h.lvl[d + 1];
+    for (uint32_t v = h.lvl[d] + lane; v < hi; v += kWave) {
+      const uint32_t tvv = sm.tv[v], ar = sm.arank[v];
+      const uint32_t x0 = sm.abit[v] + sm.cur[v];
+      const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
+      const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.rel, x0 + tvv) : ar;
+      sm.aend[v] = e;
+      const uint32_t ones = e - ar;
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        const uint32_t c = (cc >> (16 * bb)) & 0xFFFF;
+        if (c & 0x8000) continue;
+        uint32_t tc = bb ? ones : tvv - ones;
+        if (sm.cur[c] + tc > t.nv[c]) {
+          atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+          tc = 0;
+        }
+        sm.tv[c] = tc;
+      }
+    }
+    wave_sync_lds();
+  }
+}
+
+// Resident count for the block's last tile (all threads): every node's
+// share is what is left of it, and the rank at the node's end closes it.
+template <class C>
+__device__ void count_last(MergeSmem<C> &sm) {
+  const NodeTab &t = sm.t;
+  for (uint32_t v = threadIdx.x; v < sm.h.I; v += C::NT) {
+    const uint32_t nv = t.nv[v];
+    const uint32_t rest = nv - sm.cur[v];
+    sm.tv[v] = rest;
+    sm.aend[v] = rest ? rank_at(sm.body, sm.sup, sm.rel, sm.abit[v] + nv) : sm.arank[v];
+  }
+}
+
+// Resident tile bookkeeping (all threads), from the shares in sm.tv: one
+// exclusive scan over the nodes in breadth-first order, where every level is
+// a contiguous range, of (share rounded up to 16 bytes | 16-output tasks <<
+// 32 | has-work << 48).  Differences of the scan within a level give each
+// node's output offset in its level buffer, its slot in the level's list of
+// nodes with work and the tasks before it; the merge records follow, and
+// the cursors advance.
+template <class C>
+__device__ void tile_lists(MergeSmem<C> &sm) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  BlockHdr &h = sm.h;
+  NodeTab &t = sm.t;
+  const uint32_t I = h.I;
+  uint64_t *pfx = reinterpret_cast<uint64_t *>(sm.lvl[0]);   // level buffers are idle here
+  uint64_t *wtot = pfx + 260;
+  uint64_t pk = 0, inc = 0;
+  for (int i = tid; i < C::LEVELS * C::WIN; i += C::NT) (&sm.smask[0][0])[i] = 0;
+  if (tid < 256) {
+    const uint32_t tvv = static_cast<uint32_t>(tid) < I ? sm.tv[tid] : 0u;
+    pk = ((tvv + 15) & ~15u) | (static_cast<uint64_t>((tvv + 15) >> 4) << 32) |
+         (static_cast<uint64_t>(tvv ? 1u : 0u) << 48);
+    inc = wave_incl_scan64(pk);
+    if (lane == kWave - 1) wtot[wave] = inc;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint64_t ex = inc - pk;
+    for (int w = 0; w < wave; ++w) ex += wtot[w];
+    pfx[tid] = ex;                       // pfx[I] is the total (I <= 255)
+  }
+  __syncthreads();
+  if (static_cast<uint32_t>(tid) < I) {
+    const uint32_t v = tid;
+    const uint32_t d = t.depth[v];
+    const uint64_t base1 = pfx[h.lvl[d + 1]];
+    const uint64_t rel = pfx[v] - pfx[h.lvl[d]];
+    const uint32_t tvv = sm.tv[v];
+    const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
+    uint32_t kids = 0;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const uint32_t c = (cc >> (16 * bb)) & 0xFFFF;
+      const uint32_t code = (c & 0x8000) ? c : static_cast<uint32_t>(pfx[c] - base1) >> 4;
+      kids |= code << (16 * bb);
+    }
+    if (tvv) {
+      const uint32_t tp = static_cast<uint32_t>(rel >> 32) & 0xFFFF;
+      NodeRec r;
+      r.x0 = sm.abit[v] + sm.cur[v];
+      r.arank = sm.arank[v];
+      r.ot = static_cast<uint32_t>(rel) | (tp << 16);
+      r.kids = kids;
+      list_node<C>(sm, d, static_cast<uint32_t>(rel >> 48), static_cast<uint32_t>(pfx[v] >> 48), tp,
+                   (tvv + 15) >> 4, r);
+    }
+    sm.cur[v] += tvv;
+    sm.arank[v] = sm.aend[v];
+  }
+  if (static_cast<uint32_t>(tid) < h.maxlen) {
+    const uint64_t tot = pfx[h.lvl[tid + 1]] - pfx[h.lvl[tid]];
+    sm.ntask[tid] = static_cast<uint32_t>(tot >> 32) & 0xFFFF;
+    sm.actbase[tid] = static_cast<uint32_t>(pfx[h.lvl[tid]] >> 48);
+  }
+  __syncthreads();
 }
 
 // Streaming count for level d: one wave per node popcounts the node's share
@@ -752,54 +905,36 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
 }
 
 // Merge of level d.  The level's work is a list of 16-output tasks over its
-// nodes with a nonzero share; a lane takes one task (its node by a binary
-// search of the task prefix), reads 16 bitmap bits and their rank, then makes
-// 4 groups of 4 bytes, each one v_perm_b32 over unaligned 4-byte windows of
-// the children's sequences (a leaf child is a constant), and stores the 16
-// bytes at once (LDS, or HBM at the root).
+// nodes with work; a wave takes 64 consecutive tasks (a window), and a lane
+// finds its node as the window's first node plus the node starts inside the
+// window up to its task (popcount of the window's start mask).  The lane
+// reads 16 bitmap bits and their rank, then makes 4 groups of 4 bytes, each
+// one v_perm_b32 over unaligned 4-byte windows of the children's sequences (a
+// leaf child reads its constant row: the offset is multiplied by 0), and
+// stores the 16 bytes at once (LDS, or HBM at the root).
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) U32x4 GlobalU4;
+typedef __attribute__((address_space(1))) uint8_t GlobalU8;
+
 template <class C, bool RESIDENT>
 __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   const int wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
-  const uint32_t *cbuf = sm.lvl[(d + 1) & 1];
-  uint32_t *obuf = sm.lvl[d & 1];
-  const uint32_t na = sm.nact[d];
-  const uint32_t total = sm.tpref[d][na];
-  const uint16_t *tp = sm.tpref[d];
+  const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
+  const uint32_t cbase = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[(d + 1) & 1]) - lds);
+  const uint32_t lrow = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.leafrow) - lds);
+  uint8_t *obuf = reinterpret_cast<uint8_t *>(sm.lvl[d & 1]);
+  const uint32_t ntask = sm.ntask[d];
+  const uint32_t abase = sm.actbase[d];
+  const uint64_t upto = ((2ull << lane) - 1) & ~1ull;   // window bits 1 .. lane
   const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
-  uint8_t *mark = &sm.mark[wave][0];
-  uint32_t k = 0;                        // node of the wave's first task (monotone)
-  for (uint32_t base = kWave * wave; base < total; base += kWave * C::NW) {
-    // advance k to the last node whose first task is <= base
-    for (;;) {
-      const uint32_t j = k + 1 + lane;
-      const uint32_t p = j <= na ? tp[j] : 0xFFFFu;
-      const uint32_t adv = __popcll(__ballot(p <= base));
-      k += adv;
-      if (adv < kWave) break;
-    }
-    // nodes starting inside this window of 64 tasks: lane j owns the
-    // boundary of node k+1+j; every task takes the latest boundary at or
-    // before it (prefix maximum of boundary marks over the lanes)
-    const uint32_t j = k + 1 + lane;
-    const uint32_t pb = j <= na ? tp[j] : 0xFFFFu;
-    const bool inside = pb < base + kWave;
-    uint32_t kk = k;
-    if (__ballot(inside)) {
-      mark[lane] = 0;
-      wave_sync_lds();
-      if (inside) mark[pb - base] = static_cast<uint8_t>(lane + 1);
-      wave_sync_lds();
-      const uint32_t mx = wave_incl_scan_op(mark[lane], MaxOp());
-      kk = k + mx;
-      wave_sync_lds();
-    }
-    const uint32_t task = base + lane;
-    if (task >= total) continue;
-    const uint32_t v = sm.act[d][kk];
-    const uint32_t j0 = 16 * (task - tp[kk]);
-    const NodeRec r = sm.rec[v];
-    const uint32_t tvv = sm.tv[v];
+  for (uint32_t w = wave; kWave * w < ntask; w += C::NW) {
+    const uint64_t B = sm.smask[d][w];
+    const uint32_t slot = sm.wstart[d][w] + static_cast<uint32_t>(__popcll(B & upto));
+    const uint32_t task = kWave * w + lane;
+    if (task >= ntask) continue;
+    const NodeRec r = sm.rec[abase + slot];
+    const uint32_t j0 = 16 * (task - (r.ot >> 16));
     uint32_t bits, r1;
     if (RESIDENT) {
       const uint32_t x = r.x0 + j0;
@@ -807,43 +942,38 @@ __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
       r1 = rank_at(sm.body, sm.sup, sm.rel, x) - r.arank;
     } else {
       const uint2 wr = stage[r.x0 + (j0 >> 5)];
-      const uint32_t sh = j0 & 31;
+      const uint32_t sh = j0 & 31;      // 0 or 16: staged words start at the node's cursor
       bits = wr.x >> sh;
       r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
     }
     const uint32_t kl = r.kids & 0xFFFF, kr = r.kids >> 16;
-    const bool leafL = kl & 0x8000, leafR = kr & 0x8000;
-    // byte addresses of the children's next outputs (leaf: any valid address)
-    const uint32_t bl = leafL ? 0u : kl << 4, br = leafR ? 0u : kr << 4;
-    const uint32_t cL = (kl & 255) * 0x01010101u, cR = (kr & 255) * 0x01010101u;
-    uint32_t aL[4], aR[4], m[4];
+    const uint32_t mL = (kl & 0x8000) ? 0u : 1u, mR = (kr & 0x8000) ? 0u : 1u;
+    const uint32_t bL = mL ? cbase + (kl << 4) : lrow + 4 * (kl & 255);
+    const uint32_t bR = mR ? cbase + (kr << 4) : lrow + 4 * (kr & 255);
     uint32_t r1g = r1, r0g = j0 - r1;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      m[g] = (bits >> (4 * g)) & 15;
-      aL[g] = bl + r0g;
-      aR[g] = br + r1g;
-      const uint32_t pc = __popc(m[g]);
-      r1g += pc;
-      r0g += 4 - pc;
-    }
     uint32_t o[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const uint32_t wl = win4(cbuf, aL[g]);
-      const uint32_t wr = win4(cbuf, aR[g]);
-      o[g] = __builtin_amdgcn_perm(leafR ? cR : wr, leafL ? cL : wl, sm.sel[m[g]]);
+      const uint32_t m = (bits >> (4 * g)) & 15;
+      const uint32_t wl = lds_win(lds, bL + __umul24(mL, r0g));
+      const uint32_t wr = lds_win(lds, bR + __umul24(mR, r1g));
+      o[g] = __builtin_amdgcn_perm(wr, wl, sm.sel[m]);
+      const uint32_t pc = __popc(m);
+      r1g += pc;
+      r0g += 4 - pc;
     }
     if (d == 0) {
+      const uint32_t tvv = sm.tv[0];
       uint8_t *dst = out + j0;
       if (j0 + 16 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 15)) {
-        *reinterpret_cast<uint4 *>(dst) = make_uint4(o[0], o[1], o[2], o[3]);
+        *(GlobalU4 *)(dst) = U32x4{o[0], o[1], o[2], o[3]};   // C cast: generic to global
       } else {
         const uint32_t kk2 = tvv - j0 < 16 ? tvv - j0 : 16;
-        for (uint32_t e = 0; e < kk2; ++e) dst[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
+        GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
+        for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
       }
     } else {
-      *reinterpret_cast<uint4 *>(&obuf[(r.obase + j0) >> 2]) = make_uint4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<uint4 *>(obuf + (r.ot & 0xFFFF) + j0) = make_uint4(o[0], o[1], o[2], o[3]);
     }
   }
 }
@@ -900,7 +1030,7 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     __syncthreads();
     parse_block<C::NT>(J, b, h, t, LdsBytes{reinterpret_cast<const uint8_t *>(sm.body) + (h.blk - g0)});
   } else {
-    parse_block<C::NT>(J, b, h, t, GlbBytes{J.in + h.blk});
+    parse_block<C::NT>(J, b, h, t, GlbBytes{J.in + h.blk}, true);
   }
   if (h.err) {
     if (tid == 0) set_err(J.status, h.err);
@@ -946,7 +1076,7 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
   }
   if (tid == 0) {
     sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
-    sm.obase[0] = 0;
+    if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
   }
   __syncthreads();
   if (resident) {
@@ -996,18 +1126,23 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
     const uint32_t troot = n - t0 < T ? n - t0 : T;
     if (tid == 0) {
       sm.stage_top = 0;
+      sm.act_run = 0;
       sm.tv[0] = troot;
     }
     __syncthreads();
     if (resident) {
-      if (wave == 0)
-        for (uint32_t d = 0; d < maxd; ++d) count_level<C, true>(sm, d);
+      if (t0 + troot < n) {
+        if (wave == 0) count_chain<C>(sm);
+      } else {
+        count_last<C>(sm);
+      }
       __syncthreads();
+      tile_lists<C>(sm);
     } else {
       for (uint32_t d = 0; d < maxd; ++d) {
         stage_level_streaming<C>(J, sm, d, scratch, scratch_words);
         __syncthreads();
-        if (wave == 0) count_level<C, false>(sm, d);
+        if (wave == 0) count_level_streaming<C>(sm, d);
         __syncthreads();
       }
     }
@@ -1017,8 +1152,10 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
       else merge_level<C, false>(sm, d, out + t0);
       __syncthreads();
     }
-    for (uint32_t i = tid; i < I; i += C::NT) sm.tv[i] = 0;
-    __syncthreads();
+    if (!resident) {
+      for (uint32_t i = tid; i < I; i += C::NT) sm.tv[i] = 0;
+      __syncthreads();
+    }
   }
   if (!bad) {
     for (uint32_t i = tid; i < I; i += C::NT) {
@@ -1038,6 +1175,7 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
                                                   int32_t single) {
   __shared__ MergeSmem<C> sm;
   const int tid = threadIdx.x;
+  for (int i = tid; i < 256; i += C::NT) sm.leafrow[i] = static_cast<uint32_t>(i) * 0x01010101u;
   for (;;) {
     uint32_t it;
     if (single >= 0) {
