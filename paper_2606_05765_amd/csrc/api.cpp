@@ -12,19 +12,6 @@
 #include "pivco_int.h"
 
 namespace pivco {
-// decode.hip
-uint32_t merge_variant_count();
-const char *merge_variant_name(uint32_t v);
-int merge_variant_occupancy(uint32_t v);
-hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *items, uint32_t n_items, Counters *ctr,
-                        const uint32_t *scratch, uint64_t scratch_words, int32_t single);
-hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
-                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single);
-int rans_occupancy();
-hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
-                       uint32_t count);
-hipError_t launch_gather_headers(hipStream_t s, const pivco_job *jobs, uint32_t count, uint8_t *hdr);
 // tree.cpp
 pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]);
 // encode.hip
@@ -101,7 +88,7 @@ struct HostPlan {
   uint64_t scratch_words = 0;
   // workspace layout (byte offsets)
   uint64_t off_ctr = 0, off_jobs = 0, off_items = 0, off_ritems = 0, off_status0 = 0,
-           off_scratch = 0, total = 0;
+           off_recs = 0, off_scratch = 0, total = 0;
 };
 
 void layout(HostPlan &p) {
@@ -111,6 +98,7 @@ void layout(HostPlan &p) {
   p.off_items = o; o = align_up(o + 8 * p.items.size(), 256);
   p.off_ritems = o; o = align_up(o + 8 * p.ritems.size(), 256);
   p.off_status0 = o; o = align_up(o + 4ull * p.count, 256);
+  p.off_recs = o; o = align_up(o + static_cast<uint64_t>(kParsedBlockBytes) * p.items.size(), 256);
   p.off_scratch = o; o = align_up(o + 4 * p.scratch_words + 64, 256);
   // header gathering reuses the start of the workspace before the upload
   const uint64_t gather = align_up(sizeof(pivco_job) * p.count, 256) + kHeaderBytes * p.count;
@@ -221,6 +209,7 @@ struct Dev {
   const JobDev *jobs;
   const uint2 *items, *ritems;
   const int32_t *status0;
+  void *recs;
   uint32_t *scratch;
 };
 
@@ -232,6 +221,7 @@ Dev dev_ptrs(const HostPlan &p, void *d_ws) {
   d.items = reinterpret_cast<const uint2 *>(ws + p.off_items);
   d.ritems = reinterpret_cast<const uint2 *>(ws + p.off_ritems);
   d.status0 = reinterpret_cast<const int32_t *>(ws + p.off_status0);
+  d.recs = ws + p.off_recs;
   d.scratch = reinterpret_cast<uint32_t *>(ws + p.off_scratch);
   return d;
 }
@@ -251,13 +241,15 @@ pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, con
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   Dev d = dev_ptrs(p, d_ws);
   if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
+  if (launch_plan(s, d.jobs, d.items, static_cast<uint32_t>(p.items.size()), d.recs) != hipSuccess)
+    return PIVCO_E_DEVICE;
   if (!p.ritems.empty() &&
       launch_rans(t.rans_grid, s, d.jobs, d.ritems, static_cast<uint32_t>(p.ritems.size()), d.ctr,
                   d.scratch, -1) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PIVCO_E_DEVICE;
   if (!p.items.empty() &&
-      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.items,
+      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.items, d.recs,
                    static_cast<uint32_t>(p.items.size()), d.ctr, d.scratch, p.scratch_words,
                    -1) != hipSuccess)
     return PIVCO_E_DEVICE;
@@ -357,6 +349,8 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
   if (count == 0) return PIVCO_OK;
   Dev d = dev_ptrs(p, d_ws);
   if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
+  if (launch_plan(s, d.jobs, d.items, static_cast<uint32_t>(p.items.size()), d.recs) != hipSuccess)
+    return PIVCO_E_DEVICE;
   // one launch per block, in stream order: rANS first when the job has any
   std::vector<uint32_t> idx(p.items.size());
   for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
@@ -374,7 +368,7 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
                       d.scratch, static_cast<int32_t>(r)) != hipSuccess)
         return PIVCO_E_DEVICE;
     }
-    if (launch_merge(0, 1, s, d.jobs, d.items, static_cast<uint32_t>(p.items.size()), d.ctr,
+    if (launch_merge(0, 1, s, d.jobs, d.items, d.recs, static_cast<uint32_t>(p.items.size()), d.ctr,
                      d.scratch, p.scratch_words, static_cast<int32_t>(i)) != hipSuccess)
       return PIVCO_E_DEVICE;
   }

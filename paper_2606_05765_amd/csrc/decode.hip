@@ -99,18 +99,30 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
 // ---------------------------------------------------------------------------
 // Block header state shared by the rANS and merge kernels
 // ---------------------------------------------------------------------------
-struct BlockHdr {
+// The block's extent: the first 32 bytes of its header state, all the
+// merge kernel needs before it loads the rest.
+struct BlockExt {
   uint64_t blk;        // byte offset of the block in the stream
   uint64_t end;        // byte offset of the next block
-  uint64_t out_off;    // first output byte of the block
   uint64_t ans_word0;  // absolute scratch word of the block's first rANS node
-  uint32_t comp, n, mode, csym, cw, I, maxlen, kb;
-  uint32_t raw_base, raw_end, ans_words, n_ans;
+  uint32_t ans_words;  // scratch words of its rANS nodes
   int32_t err;
+};
+
+struct BlockHdr {
+  uint64_t blk;        // (these five as in BlockExt)
+  uint64_t end;
+  uint64_t ans_word0;
+  uint32_t ans_words;
+  int32_t err;
+  uint64_t out_off;    // first output byte of the block
+  uint32_t comp, n, mode, csym, cw, I, maxlen, kb;
+  uint32_t raw_base, raw_end, n_ans;
   uint32_t kraft;
   uint32_t cnt[17], fc[18], lbase[17], lvl[18];
   uint64_t lvl_total[17];  // symbols passing each level (sum of n_v)
 };
+static_assert(offsetof(BlockHdr, err) == offsetof(BlockExt, err) && sizeof(BlockExt) == 32, "BlockExt prefix");
 
 // Per-node tables (breadth-first node ids).
 struct NodeTab {
@@ -125,6 +137,14 @@ struct NodeTab {
   uint8_t leafsym[256];    // symbols ordered by (length, symbol)
 };
 
+// A block's parsed and validated header, written by the plan kernel and
+// copied as is into the merge kernel's LDS.
+struct alignas(16) ParsedBlock {
+  BlockHdr h;
+  NodeTab t;
+};
+static_assert(sizeof(ParsedBlock) == kParsedBlockBytes, "ParsedBlock layout");
+
 // Byte readers for block-relative offsets: the block in global memory, or
 // a copy of it in LDS.
 struct GlbBytes {
@@ -132,10 +152,16 @@ struct GlbBytes {
   __device__ uint32_t u8(uint32_t o) const { return p[o]; }
   __device__ uint32_t u32(uint32_t o) const { return *reinterpret_cast<const uint32_t *>(p + o); }
 };
-struct LdsBytes {
-  const uint8_t *p;
-  __device__ uint32_t u8(uint32_t o) const { return p[o]; }
-  __device__ uint32_t u32(uint32_t o) const { return *reinterpret_cast<const uint32_t *>(p + o); }
+// The block's first hn bytes copied into LDS, the rest read from global memory.
+struct SplitBytes {
+  const uint8_t *l;
+  uint32_t hn;
+  const uint8_t *g;
+  __device__ uint32_t u8(uint32_t o) const { return o < hn ? l[o] : g[o]; }
+  __device__ uint32_t u32(uint32_t o) const {
+    return o + 4 <= hn ? *reinterpret_cast<const uint32_t *>(l + o)
+                       : u8(o) | (u8(o + 1) << 8) | (u8(o + 2) << 16) | (u8(o + 3) << 24);
+  }
 };
 
 // Offsets of block b from the stream's tables (thread 0 only).
@@ -571,8 +597,9 @@ struct NodeRec {
 
 template <class C>
 struct MergeSmem {
-  BlockHdr h;
-  NodeTab t;
+  ParsedBlock pb;          // h and t of the current block
+  BlockExt nxt;            // extent of the next block (looked ahead)
+  uint2 nxt_item;
   uint32_t cur[256];       // bits of the node consumed by earlier tiles
   uint32_t tv[256];        // node's share of the current tile
   union {
@@ -599,7 +626,6 @@ struct MergeSmem {
   uint32_t tile;           // runtime tile size for this block
   uint32_t sel[16];
   uint32_t item;
-  uint32_t lds_base;       // resident: LDS byte offset of the block's first byte
   uint32_t scan_tot[C::NW];
   uint32_t leafrow[256];   // four copies of byte s: the "sequence" of a leaf child s
   uint32_t lvl[2][C::LVL / 4] __attribute__((aligned(16)));
@@ -666,8 +692,8 @@ __device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total
 template <class C>
 __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
   const uint32_t lane = lane_id();
-  BlockHdr &h = sm.h;
-  NodeTab &t = sm.t;
+  BlockHdr &h = sm.pb.h;
+  NodeTab &t = sm.pb.t;
   uint32_t out_top = 0, task_top = 0, act_top = 0;
   if (lane < static_cast<uint32_t>(C::WIN)) sm.smask[d][lane] = 0;
   const uint32_t act_base = sm.act_run;
@@ -748,8 +774,8 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
 template <class C>
 __device__ void count_chain(MergeSmem<C> &sm) {
   const uint32_t lane = lane_id();
-  BlockHdr &h = sm.h;
-  NodeTab &t = sm.t;
+  BlockHdr &h = sm.pb.h;
+  NodeTab &t = sm.pb.t;
   const uint32_t maxd = h.maxlen;
   for (uint32_t d = 0; d < maxd; ++d) {
     const uint32_t hi = h.lvl[d + 1];
@@ -780,8 +806,8 @@ __device__ void count_chain(MergeSmem<C> &sm) {
 // share is what is left of it, and the rank at the node's end closes it.
 template <class C>
 __device__ void count_last(MergeSmem<C> &sm) {
-  const NodeTab &t = sm.t;
-  for (uint32_t v = threadIdx.x; v < sm.h.I; v += C::NT) {
+  const NodeTab &t = sm.pb.t;
+  for (uint32_t v = threadIdx.x; v < sm.pb.h.I; v += C::NT) {
     const uint32_t nv = t.nv[v];
     const uint32_t rest = nv - sm.cur[v];
     sm.tv[v] = rest;
@@ -801,8 +827,8 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
-  BlockHdr &h = sm.h;
-  NodeTab &t = sm.t;
+  BlockHdr &h = sm.pb.h;
+  NodeTab &t = sm.pb.t;
   const uint32_t I = h.I;
   uint64_t *pfx = reinterpret_cast<uint64_t *>(sm.lvl[0]);   // level buffers are idle here
   uint64_t *wtot = pfx + 260;
@@ -864,8 +890,8 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
                                       const uint32_t *scratch, uint64_t scratch_words) {
   const int wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
-  BlockHdr &h = sm.h;
-  NodeTab &t = sm.t;
+  BlockHdr &h = sm.pb.h;
+  NodeTab &t = sm.pb.t;
   uint2 *stage = reinterpret_cast<uint2 *>(sm.body);
   const uint32_t *gin32 = reinterpret_cast<const uint32_t *>(J.in);
   const uint64_t in_dw = J.in_len >> 2;
@@ -978,30 +1004,51 @@ __device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   }
 }
 
+// The block's extent from the first 32 bytes of its record.
+__device__ __forceinline__ BlockExt load_ext(const ParsedBlock *rec) {
+  const uint4 *p = reinterpret_cast<const uint4 *>(rec);
+  const uint4 a = p[0], c = p[1];
+  BlockExt e;
+  e.blk = (static_cast<uint64_t>(a.y) << 32) | a.x;
+  e.end = (static_cast<uint64_t>(a.w) << 32) | a.z;
+  e.ans_word0 = (static_cast<uint64_t>(c.y) << 32) | c.x;
+  e.ans_words = c.z;
+  e.err = static_cast<int32_t>(c.w);
+  return e;
+}
+
+// Whether block ext is decoded from LDS: the whole block (header and raw
+// bodies, 16-byte aligned) plus its decoded rANS bitmaps fit.
 template <class C>
-__device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch,
-                            uint64_t scratch_words, MergeSmem<C> &sm) {
+__device__ __forceinline__ bool block_resident(const BlockExt &ext) {
+  const uint64_t span = ((ext.end + 15) & ~15ull) - (ext.blk & ~15ull);
+  return !ext.err && span + 4ull * ext.ans_words + 64 <= static_cast<uint64_t>(C::BODY);
+}
+
+// Loads the block's parsed header (its record) and, when resident, the block
+// itself and its decoded rANS bitmaps into LDS with 16-byte direct-to-LDS
+// reads (global_load_lds_dwordx4: lane i of a wave fills LDS bytes
+// [16 i, 16 i + 16) after the wave's base); wave iterations that touch the
+// end of the stream use guarded loads instead.  Ends with a barrier.
+template <class C>
+__device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockExt &ext,
+                           const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
-  BlockHdr &h = sm.h;
-  NodeTab &t = sm.t;
-  if (tid == 0) parse_offsets(J, b, h);
-  __syncthreads();
-  // ---- residency: the whole block (header and bodies) and the decoded
-  // rANS bitmaps in LDS, loaded with 16-byte reads ----------------------------
-  const uint64_t g0 = h.blk & ~15ull;
-  const uint64_t g1 = (h.end + 15) & ~15ull;
-  const uint64_t span = g1 - g0;
-  const bool resident = !h.err && span + 4ull * h.ans_words + 64 <= static_cast<uint64_t>(C::BODY);
-  if (resident) {
+  constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
+  const uint8_t *rb = reinterpret_cast<const uint8_t *>(rec);
+  uint32_t *pbw = reinterpret_cast<uint32_t *>(&sm.pb);
+  for (uint32_t base = kWave * wave; base < kRec16; base += kWave * C::NW)
+    if (base + lane < kRec16)
+      __builtin_amdgcn_global_load_lds(rb + 16ull * (base + lane), &pbw[4 * base], 16, 0, 0);
+  if (block_resident<C>(ext)) {
+    const uint64_t g0 = ext.blk & ~15ull;
+    const uint64_t span = ((ext.end + 15) & ~15ull) - g0;
     const uint64_t in_dw = J.in_len >> 2;
     const uint64_t in16 = J.in_len >> 4;
     const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
     const uint32_t n16 = static_cast<uint32_t>(span >> 4);
-    // 16-byte chunks straight into LDS (global_load_lds_dwordx4: lane i of a
-    // wave fills LDS bytes [16 i, 16 i + 16) after the wave's base); wave
-    // iterations that touch the end of the stream use guarded loads instead
     for (uint32_t base = kWave * wave; base < n16; base += kWave * C::NW) {
       if (base + kWave <= n16 && (g0 >> 4) + base + kWave <= in16) {
         __builtin_amdgcn_global_load_lds(J.in + g0 + 16ull * (base + lane), &sm.body[4 * base], 16, 0, 0);
@@ -1019,19 +1066,30 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
       }
     }
     const uint32_t abase = static_cast<uint32_t>(span >> 2);
-    for (uint32_t i = tid; i < h.ans_words; i += C::NT) {
-      const uint64_t q = h.ans_word0 + i;
+    for (uint32_t i = tid; i < ext.ans_words; i += C::NT) {
+      const uint64_t q = ext.ans_word0 + i;
       sm.body[abase + i] = q < scratch_words ? scratch[q] : 0u;
     }
-    const uint32_t body_dw = abase + h.ans_words;
+    const uint32_t body_dw = abase + ext.ans_words;
     for (uint32_t i = body_dw + tid; i < ((body_dw + 7) & ~7u) + 8; i += C::NT) sm.body[i] = 0u;
-    if (tid == 0) sm.lds_base = static_cast<uint32_t>(h.blk - g0);
-    __builtin_amdgcn_s_waitcnt(0);     // direct-to-LDS loads of this wave have landed
-    __syncthreads();
-    parse_block<C::NT>(J, b, h, t, LdsBytes{reinterpret_cast<const uint8_t *>(sm.body) + (h.blk - g0)});
-  } else {
-    parse_block<C::NT>(J, b, h, t, GlbBytes{J.in + h.blk}, true);
   }
+  __builtin_amdgcn_s_waitcnt(0);     // direct-to-LDS loads of this wave have landed
+  __syncthreads();
+}
+
+// Decodes the block whose record (and, when resident, body) load_block put
+// into LDS, with the whole workgroup.
+template <class C>
+__device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_t *scratch,
+                             uint64_t scratch_words, MergeSmem<C> &sm) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  BlockHdr &h = sm.pb.h;
+  NodeTab &t = sm.pb.t;
+  const bool resident = block_resident<C>(ext);
+  const uint64_t g0 = ext.blk & ~15ull;
+  const uint64_t span = ((ext.end + 15) & ~15ull) - g0;
   if (h.err) {
     if (tid == 0) set_err(J.status, h.err);
     return;
@@ -1170,28 +1228,88 @@ __device__ void merge_block(const JobDev &J, uint32_t b, const uint32_t *scratch
 
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *items,
-                                                  uint32_t n_items, Counters *ctr,
-                                                  const uint32_t *scratch, uint64_t scratch_words,
-                                                  int32_t single) {
+                                                  const ParsedBlock *recs, uint32_t n_items,
+                                                  Counters *ctr, const uint32_t *scratch,
+                                                  uint64_t scratch_words, int32_t single) {
   __shared__ MergeSmem<C> sm;
   const int tid = threadIdx.x;
   for (int i = tid; i < 256; i += C::NT) sm.leafrow[i] = static_cast<uint32_t>(i) * 0x01010101u;
+  if (tid == 0) {
+    const uint32_t it = single >= 0 ? static_cast<uint32_t>(single) : atomicAdd(&ctr->merge_next, 1u);
+    sm.item = it;
+    if (it < n_items) {
+      sm.nxt_item = items[it];
+      sm.nxt = load_ext(recs + it);
+    }
+  }
+  __syncthreads();
   for (;;) {
-    uint32_t it;
-    if (single >= 0) {
-      it = static_cast<uint32_t>(single);
-    } else {
-      if (tid == 0) sm.item = atomicAdd(&ctr->merge_next, 1u);
-      __syncthreads();
-      it = sm.item;
+    const uint32_t it = sm.item;
+    if (it >= n_items) break;
+    const uint2 item = sm.nxt_item;
+    const BlockExt ext = sm.nxt;
+    __syncthreads();                   // the look-ahead slots are rewritten below
+    // look ahead: take the next item now; its extent is read while this
+    // block is decoded (no other global loads wait behind it when resident)
+    uint32_t nit = n_items;
+    if (tid == 0 && single < 0) nit = atomicAdd(&ctr->merge_next, 1u);
+    const JobDev &J = jobs[item.x];
+    load_block<C>(J, recs + it, ext, scratch, scratch_words, sm);
+    uint2 nitem = make_uint2(0, 0);
+    BlockExt next{};
+    if (tid == 0 && nit < n_items) {
+      nitem = items[nit];
+      next = load_ext(recs + nit);
+    }
+    decode_block<C>(J, ext, scratch, scratch_words, sm);
+    if (tid == 0) {
+      sm.item = nit;
+      sm.nxt_item = nitem;
+      sm.nxt = next;
     }
     __syncthreads();
-    if (it >= n_items) break;
-    const uint2 item = items[it];
-    merge_block<C>(jobs[item.x], item.y, scratch, scratch_words, sm);
-    __syncthreads();
-    if (single >= 0) break;
   }
+}
+
+// Plan: one wave per work item parses and validates the block's header from
+// a copy of its first bytes in LDS (offsets, code lengths, canonical tree,
+// node table, symbol counts, body offsets, padding) and writes the result as
+// the item's record.
+constexpr int kPlanWaves = 4;
+constexpr uint32_t kHdrMax = kBlockFixed + kLenTable + 32 + 4 * kMaxInternal;   // largest header
+
+__global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs, const uint2 *items,
+                                                             uint32_t n_items, ParsedBlock *recs) {
+  __shared__ ParsedBlock pb[kPlanWaves];
+  __shared__ uint32_t hdr[kPlanWaves][kHdrMax / 4 + 1];
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const uint32_t it = blockIdx.x * kPlanWaves + wave;
+  if (it >= n_items) return;
+  const uint2 item = items[it];
+  const JobDev &J = jobs[item.x];
+  BlockHdr &h = pb[wave].h;
+  NodeTab &t = pb[wave].t;
+  if (lane == 0) parse_offsets(J, item.y, h);
+  wave_sync_lds();
+  const uint64_t len = h.end - h.blk;
+  const uint32_t hn = h.err ? 0u : static_cast<uint32_t>(len < kHdrMax ? len : kHdrMax);
+  const uint8_t *g = J.in + h.blk;
+  for (uint32_t i = lane; 4 * i < hn; i += kWave) {
+    uint32_t w;
+    if (4 * i + 4 <= hn) {
+      w = *reinterpret_cast<const uint32_t *>(g + 4 * i);      // the block is 4-byte aligned
+    } else {
+      w = 0;
+      for (uint32_t k = 0; 4 * i + k < hn; ++k) w |= static_cast<uint32_t>(g[4 * i + k]) << (8 * k);
+    }
+    hdr[wave][i] = w;
+  }
+  wave_sync_lds();
+  parse_block_wave(J, item.y, h, t, SplitBytes{reinterpret_cast<const uint8_t *>(hdr[wave]), hn, g}, true);
+  const uint4 *src = reinterpret_cast<const uint4 *>(&pb[wave]);
+  uint4 *dst = reinterpret_cast<uint4 *>(recs + it);
+  for (uint32_t i = lane; i < sizeof(ParsedBlock) / 16; i += kWave) dst[i] = src[i];
 }
 
 // Resets the queue heads and the per-job status words (graph-safe: a kernel,
@@ -1229,9 +1347,9 @@ struct MergeVariant {
 
 template <class C>
 static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
-                                 uint32_t n_items, Counters *ctr, const uint32_t *scratch,
-                                 uint64_t scratch_words, int32_t single) {
-  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, items, n_items, ctr, scratch,
+                                 const ParsedBlock *recs, uint32_t n_items, Counters *ctr,
+                                 const uint32_t *scratch, uint64_t scratch_words, int32_t single) {
+  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, items, recs, n_items, ctr, scratch,
                      scratch_words, single);
   return hipGetLastError();
 }
@@ -1268,13 +1386,22 @@ int merge_variant_occupancy(uint32_t v) {
 }
 
 hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *items, uint32_t n_items, Counters *ctr,
+                        const uint2 *items, const void *recs, uint32_t n_items, Counters *ctr,
                         const uint32_t *scratch, uint64_t scratch_words, int32_t single) {
+  const ParsedBlock *r = static_cast<const ParsedBlock *>(recs);
   switch (variant) {
-    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, items, n_items, ctr, scratch, scratch_words, single);
-    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, items, n_items, ctr, scratch, scratch_words, single);
-    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, n_items, ctr, scratch, scratch_words, single);
+    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, items, r, n_items, ctr, scratch, scratch_words, single);
+    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, items, r, n_items, ctr, scratch, scratch_words, single);
+    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, r, n_items, ctr, scratch, scratch_words, single);
   }
+}
+
+hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *items, uint32_t n_items,
+                       void *recs) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan, dim3((n_items + kPlanWaves - 1) / kPlanWaves), dim3(kWave * kPlanWaves), 0,
+                     s, jobs, items, n_items, static_cast<ParsedBlock *>(recs));
+  return hipGetLastError();
 }
 
 hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,

@@ -27,19 +27,6 @@
 
 #include "pivco_int.h"
 
-namespace pivco {
-uint32_t merge_variant_count();
-int merge_variant_occupancy(uint32_t v);
-hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *items, uint32_t n_items, Counters *ctr,
-                        const uint32_t *scratch, uint64_t scratch_words, int32_t single);
-hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
-                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single);
-int rans_occupancy();
-hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
-                       uint32_t count);
-}  // namespace pivco
-
 using namespace pivco;
 
 namespace {
@@ -117,7 +104,7 @@ struct pivco_server {
   uint64_t ws_bytes_per_slot = 0, pinned_bytes = 0;
   // workspace layout inside a slot
   uint64_t off_ctr = 0, off_jobs = 0, off_items = 0, off_ritems = 0, off_status0 = 0,
-           off_status = 0, off_scratch = 0;
+           off_status = 0, off_recs = 0, off_scratch = 0;
   uint64_t off_pstatus = 0;
   uint32_t max_items = 0;
   uint64_t max_scratch_words = 0;
@@ -141,6 +128,7 @@ pivco_status pivco_server_create(const pivco_server_opts *o, pivco_server **out)
   const uint64_t pinned = x;          // job table .. status0 staged from pinned memory
   sv->off_status = x; x = align_up(x + 4ull * o->max_batch, 256);
   sv->off_pstatus = pinned;           // statuses copied back into pinned memory
+  sv->off_recs = x; x = align_up(x + static_cast<uint64_t>(kParsedBlockBytes) * o->max_blocks, 256);
   sv->off_scratch = x; x = align_up(x + 4ull * o->max_scratch_words + 64, 256);
   sv->ws_bytes_per_slot = x;
   sv->pinned_bytes = pinned;
@@ -335,13 +323,17 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
                       reinterpret_cast<const int32_t *>(s.ws + sv->off_status0),
                       static_cast<uint32_t>(batch.size())) != hipSuccess)
         return PIVCO_E_DEVICE;
+      void *recs = s.ws + sv->off_recs;
+      if (launch_plan(s.stream, dj, reinterpret_cast<const uint2 *>(s.ws + sv->off_items), ni, recs) !=
+          hipSuccess)
+        return PIVCO_E_DEVICE;
       if (nr && launch_rans(std::max<uint32_t>(1, std::min(rgrid_full, nr)), s.stream, dj,
                             reinterpret_cast<const uint2 *>(s.ws + sv->off_ritems), nr, ctr, scr,
                             -1) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (ni && launch_merge(variant, std::max<uint32_t>(1, std::min(mgrid_full, ni)), s.stream, dj,
-                             reinterpret_cast<const uint2 *>(s.ws + sv->off_items), ni, ctr, scr,
-                             sw, -1) != hipSuccess)
+                             reinterpret_cast<const uint2 *>(s.ws + sv->off_items), recs, ni, ctr,
+                             scr, sw, -1) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (hipMemcpyAsync(s.pinned + sv->off_pstatus, s.ws + sv->off_status, 4 * batch.size(),
                          hipMemcpyDeviceToHost, s.stream) != hipSuccess)
