@@ -184,6 +184,15 @@ __device__ void parse_offsets(const JobDev &J, uint32_t b, BlockHdr &h) {
   h.kraft = 0;
 }
 
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for the wave's global loads and stores in flight (the merge
+// kernel's waves exchange data through LDS alone).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -569,15 +578,18 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const uint
 // ---------------------------------------------------------------------------
 // Kernel: bottom-up merge decode
 // ---------------------------------------------------------------------------
-template <int NT_, int T_, int BODY_>
+template <int NT_, int T_, int BODY_, int K_>
 struct MergeCfg {
   static constexpr int NT = NT_;
   static constexpr int T = T_;                        // output symbols per tile
   static constexpr int BODY = BODY_;                  // resident block bytes
+  static constexpr int K = K_;                        // outputs per merge task (8, 16 or 32)
+  static constexpr int CS = K < 16 ? 3 : 4;           // child output offsets are stored >> CS
   static constexpr int NW = NT / kWave;
-  static constexpr int LVL = T + 15 * 128 + 64;       // bytes per level buffer
+  static constexpr int LVL = T + (K - 1) * 128 + 64;  // bytes per level buffer (shares rounded to K)
   static constexpr int LEVELS = kMaxLenGpu;
-  static constexpr int WIN = (T / 16 + 128 + 63) / 64 + 1;   // 64-task windows per level
+  static constexpr int WIN = (T / K + 128 + 63) / 64 + 1;    // 64-task windows per level
+  static_assert(K == 8 || K == 16 || K == 32, "task width");
   static constexpr int STG = BODY / 8;                // streaming: staged (word, rank) pairs
   static constexpr int SUP = BODY / 32 + 2;           // rank directory, per 256 bits
   static constexpr int REL = BODY / 8 + 8;            // rank directory, per 64 bits
@@ -695,7 +707,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
   uint32_t out_top = 0, task_top = 0, act_top = 0;
-  if (lane < static_cast<uint32_t>(C::WIN)) sm.smask[d][lane] = 0;
+  for (uint32_t i = lane; i < static_cast<uint32_t>(C::WIN); i += kWave) sm.smask[d][i] = 0;
   const uint32_t act_base = sm.act_run;
   wave_sync_lds();
   for (uint32_t v0 = h.lvl[d]; v0 < h.lvl[d + 1]; v0 += kWave) {
@@ -720,8 +732,8 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
         }
       }
     }
-    const uint32_t o0 = (tc[0] + 15) & ~15u, o1 = (tc[1] + 15) & ~15u;
-    const uint32_t tasks = (tvv + 15) / 16;
+    const uint32_t o0 = (tc[0] + C::K - 1) & ~(C::K - 1u), o1 = (tc[1] + C::K - 1) & ~(C::K - 1u);
+    const uint32_t tasks = (tvv + C::K - 1) / C::K;
     const uint32_t isact = tvv ? 1u : 0u;
     const uint64_t pk = static_cast<uint64_t>(o0 + o1) | (static_cast<uint64_t>(tasks) << 32) |
                         (static_cast<uint64_t>(isact) << 48);
@@ -738,7 +750,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
           const uint32_t cob = ob + (bb ? o0 : 0u);
           sm.tv[ch[bb]] = tc[bb];
           sm.obase[ch[bb]] = cob;
-          code = cob >> 4;
+          code = cob >> C::CS;
         }
         kids |= code << (16 * bb);
       }
@@ -836,18 +848,18 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
   for (int i = tid; i < C::LEVELS * C::WIN; i += C::NT) (&sm.smask[0][0])[i] = 0;
   if (tid < 256) {
     const uint32_t tvv = static_cast<uint32_t>(tid) < I ? sm.tv[tid] : 0u;
-    pk = ((tvv + 15) & ~15u) | (static_cast<uint64_t>((tvv + 15) >> 4) << 32) |
+    pk = ((tvv + C::K - 1) & ~(C::K - 1u)) | (static_cast<uint64_t>((tvv + C::K - 1) / C::K) << 32) |
          (static_cast<uint64_t>(tvv ? 1u : 0u) << 48);
     inc = wave_incl_scan64(pk);
     if (lane == kWave - 1) wtot[wave] = inc;
   }
-  __syncthreads();
+  lds_barrier();
   if (tid < 256) {
     uint64_t ex = inc - pk;
     for (int w = 0; w < wave; ++w) ex += wtot[w];
     pfx[tid] = ex;                       // pfx[I] is the total (I <= 255)
   }
-  __syncthreads();
+  lds_barrier();
   if (static_cast<uint32_t>(tid) < I) {
     const uint32_t v = tid;
     const uint32_t d = t.depth[v];
@@ -859,7 +871,7 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       const uint32_t c = (cc >> (16 * bb)) & 0xFFFF;
-      const uint32_t code = (c & 0x8000) ? c : static_cast<uint32_t>(pfx[c] - base1) >> 4;
+      const uint32_t code = (c & 0x8000) ? c : static_cast<uint32_t>(pfx[c] - base1) >> C::CS;
       kids |= code << (16 * bb);
     }
     if (tvv) {
@@ -870,7 +882,7 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
       r.ot = static_cast<uint32_t>(rel) | (tp << 16);
       r.kids = kids;
       list_node<C>(sm, d, static_cast<uint32_t>(rel >> 48), static_cast<uint32_t>(pfx[v] >> 48), tp,
-                   (tvv + 15) >> 4, r);
+                   (tvv + C::K - 1) / C::K, r);
     }
     sm.cur[v] += tvv;
     sm.arank[v] = sm.aend[v];
@@ -880,7 +892,7 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
     sm.ntask[tid] = static_cast<uint32_t>(tot >> 32) & 0xFFFF;
     sm.actbase[tid] = static_cast<uint32_t>(pfx[h.lvl[tid]] >> 48);
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Streaming count for level d: one wave per node popcounts the node's share
@@ -930,77 +942,122 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
   }
 }
 
-// Merge of level d.  The level's work is a list of 16-output tasks over its
-// nodes with work; a wave takes 64 consecutive tasks (a window), and a lane
-// finds its node as the window's first node plus the node starts inside the
-// window up to its task (popcount of the window's start mask).  The lane
-// reads 16 bitmap bits and their rank, then makes 4 groups of 4 bytes, each
-// one v_perm_b32 over unaligned 4-byte windows of the children's sequences (a
-// leaf child reads its constant row: the offset is multiplied by 0), and
-// stores the 16 bytes at once (LDS, or HBM at the root).
+// Merge, bottom-up by level.  A level's work is a list of K-output tasks
+// over its nodes with work; a wave takes 64 consecutive tasks (a window), and
+// a lane finds its node as the window's first node plus the node starts
+// inside the window up to its task (popcount of the window's start mask).
+// merge_prep gathers what a task needs besides its children's bytes (node
+// record, K bitmap bits, their rank, the children's addresses); merge_finish
+// reads 4-byte windows of the children's sequences (a leaf child reads its
+// constant row: the offset is multiplied by 0), makes groups of 4 bytes with
+// one v_perm_b32 each, and stores 16 bytes at a time (LDS, or HBM at the
+// root).
 typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) U32x4 GlobalU4;
+typedef uint32_t U32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) U32x2 GlobalU2;
 typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 
+struct MergePrep {
+  uint32_t bL, bR;   // LDS byte addresses of the children's sequences at the task (leaf: its row)
+  uint32_t r0, r1;   // 0 and 1 bits of the node before the task
+  uint32_t bits;     // the task's K bitmap bits (K <= 32)
+  uint32_t flags;    // 1: task, 2: left is a node, 4: right is a node
+  uint32_t j0;       // first output of the task within its node
+  uint32_t dst;      // below the root: LDS byte address of the task's outputs
+};
+
 template <class C, bool RESIDENT>
-__device__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
-  const int wave = threadIdx.x >> 6;
+__device__ __forceinline__ MergePrep merge_prep(MergeSmem<C> &sm, int d, uint32_t w) {
   const uint32_t lane = lane_id();
+  MergePrep p;
+  p.flags = 0;
+  p.bL = p.bR = p.r0 = p.r1 = p.bits = p.j0 = p.dst = 0;
+  const uint32_t ntask = sm.ntask[d];
+  const uint32_t task = kWave * w + lane;
   const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
+  const uint64_t B = sm.smask[d][w];
+  const uint64_t upto = ((2ull << lane) - 1) & ~1ull;   // window bits 1 .. lane
+  const uint32_t slot = sm.wstart[d][w] + static_cast<uint32_t>(__popcll(B & upto));
+  if (task >= ntask) return p;
+  const NodeRec r = sm.rec[sm.actbase[d] + slot];
+  const uint32_t j0 = C::K * (task - (r.ot >> 16));
+  uint32_t bits, r1;
+  if (RESIDENT) {
+    const uint32_t x = r.x0 + j0;
+    bits = bits32_lds(sm.body, x);
+    r1 = rank_at(sm.body, sm.sup, sm.rel, x) - r.arank;
+  } else {
+    const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
+    const uint2 wr = stage[r.x0 + (j0 >> 5)];
+    const uint32_t sh = j0 & 31;      // 0, or 16 with K = 16: staged words start at the node's cursor
+    bits = wr.x >> sh;
+    r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
+  }
   const uint32_t cbase = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[(d + 1) & 1]) - lds);
   const uint32_t lrow = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.leafrow) - lds);
-  uint8_t *obuf = reinterpret_cast<uint8_t *>(sm.lvl[d & 1]);
-  const uint32_t ntask = sm.ntask[d];
-  const uint32_t abase = sm.actbase[d];
-  const uint64_t upto = ((2ull << lane) - 1) & ~1ull;   // window bits 1 .. lane
-  const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
-  for (uint32_t w = wave; kWave * w < ntask; w += C::NW) {
-    const uint64_t B = sm.smask[d][w];
-    const uint32_t slot = sm.wstart[d][w] + static_cast<uint32_t>(__popcll(B & upto));
-    const uint32_t task = kWave * w + lane;
-    if (task >= ntask) continue;
-    const NodeRec r = sm.rec[abase + slot];
-    const uint32_t j0 = 16 * (task - (r.ot >> 16));
-    uint32_t bits, r1;
-    if (RESIDENT) {
-      const uint32_t x = r.x0 + j0;
-      bits = bits32_lds(sm.body, x);
-      r1 = rank_at(sm.body, sm.sup, sm.rel, x) - r.arank;
-    } else {
-      const uint2 wr = stage[r.x0 + (j0 >> 5)];
-      const uint32_t sh = j0 & 31;      // 0 or 16: staged words start at the node's cursor
-      bits = wr.x >> sh;
-      r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
-    }
-    const uint32_t kl = r.kids & 0xFFFF, kr = r.kids >> 16;
-    const uint32_t mL = (kl & 0x8000) ? 0u : 1u, mR = (kr & 0x8000) ? 0u : 1u;
-    const uint32_t bL = mL ? cbase + (kl << 4) : lrow + 4 * (kl & 255);
-    const uint32_t bR = mR ? cbase + (kr << 4) : lrow + 4 * (kr & 255);
-    uint32_t r1g = r1, r0g = j0 - r1;
-    uint32_t o[4];
+  const uint32_t kl = r.kids & 0xFFFF, kr = r.kids >> 16;
+  const bool nl = !(kl & 0x8000), nr = !(kr & 0x8000);
+  p.bL = nl ? cbase + (kl << C::CS) : lrow + 4 * (kl & 255);
+  p.bR = nr ? cbase + (kr << C::CS) : lrow + 4 * (kr & 255);
+  p.r1 = r1;
+  p.r0 = j0 - r1;
+  p.bits = C::K == 32 ? bits : (bits & ((1u << C::K) - 1));
+  p.flags = 1u | (nl ? 2u : 0u) | (nr ? 4u : 0u);
+  p.j0 = j0;
+  p.dst = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[d & 1]) - lds) + (r.ot & 0xFFFF) + j0;
+  return p;
+}
+
+template <class C>
+__device__ __forceinline__ void merge_finish(MergeSmem<C> &sm, int d, const MergePrep &p, uint8_t *out) {
+  if (!(p.flags & 1)) return;
+  uint8_t *lds = reinterpret_cast<uint8_t *>(&sm);
+  const uint32_t mL = (p.flags >> 1) & 1, mR = (p.flags >> 2) & 1;
+  uint32_t r1g = p.r1, r0g = p.r0;
+  const uint32_t tvv = d == 0 ? sm.tv[0] : 0u;
+  constexpr int CB = C::K < 16 ? C::K : 16;   // bytes per store
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const uint32_t m = (bits >> (4 * g)) & 15;
-      const uint32_t wl = lds_win(lds, bL + __umul24(mL, r0g));
-      const uint32_t wr = lds_win(lds, bR + __umul24(mR, r1g));
+  for (int c = 0; c < C::K / CB; ++c) {
+    uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int g = 0; g < CB / 4; ++g) {
+      const uint32_t m = (p.bits >> (16 * c + 4 * g)) & 15;
+      const uint32_t wl = lds_win(lds, p.bL + __umul24(mL, r0g));
+      const uint32_t wr = lds_win(lds, p.bR + __umul24(mR, r1g));
       o[g] = __builtin_amdgcn_perm(wr, wl, sm.sel[m]);
       const uint32_t pc = __popc(m);
       r1g += pc;
       r0g += 4 - pc;
     }
     if (d == 0) {
-      const uint32_t tvv = sm.tv[0];
-      uint8_t *dst = out + j0;
-      if (j0 + 16 <= tvv && !(reinterpret_cast<uintptr_t>(dst) & 15)) {
-        *(GlobalU4 *)(dst) = U32x4{o[0], o[1], o[2], o[3]};   // C cast: generic to global
-      } else {
-        const uint32_t kk2 = tvv - j0 < 16 ? tvv - j0 : 16;
+      const uint32_t j = p.j0 + CB * c;
+      uint8_t *dst = out + j;
+      if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
+        if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[0], o[1], o[2], o[3]};   // C cast: generic to global
+        else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
+      } else if (j < tvv) {
+        const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
         GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
         for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
       }
+    } else if (CB == 16) {
+      *reinterpret_cast<uint4 *>(lds + p.dst + 16 * c) = make_uint4(o[0], o[1], o[2], o[3]);
     } else {
-      *reinterpret_cast<uint4 *>(obuf + (r.ot & 0xFFFF) + j0) = make_uint4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<uint2 *>(lds + p.dst + CB * c) = make_uint2(o[0], o[1]);
     }
+  }
+}
+
+// All levels of the tile, deepest first; one barrier per level.
+template <class C, bool RESIDENT>
+__device__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
+  const uint32_t wave = threadIdx.x >> 6;
+  for (int d = maxd - 1; d >= 0; --d) {
+    const uint32_t ntask = sm.ntask[d];
+    for (uint32_t w = wave; kWave * w < ntask; w += C::NW)
+      merge_finish<C>(sm, d, merge_prep<C, RESIDENT>(sm, d, w), out);
+    lds_barrier();
   }
 }
 
@@ -1136,7 +1193,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
     if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
   }
-  __syncthreads();
+  lds_barrier();
   if (resident) {
     // rank directory: per 256-bit superblock the 1 bits before it, per
     // 64-bit word the 1 bits of its superblock before it
@@ -1160,7 +1217,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     }
     const uint32_t inc = wave_incl_scan(loc);
     if (lane == kWave - 1) sm.scan_tot[wave] = inc;
-    __syncthreads();
+    lds_barrier();
     uint32_t run = inc - loc;
     for (int w = 0; w < wave; ++w) run += sm.scan_tot[w];
     for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
@@ -1168,14 +1225,14 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
       sm.sup[k] = run;
       run += c;
     }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t i = tid; i < I; i += C::NT) {
       const uint32_t r = rank_at(sm.body, sm.sup, sm.rel, sm.abit[i]);
       sm.r0[i] = r;
       sm.arank[i] = r;
     }
   }
-  __syncthreads();
+  lds_barrier();
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
   bool bad = false;
@@ -1187,32 +1244,29 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
       sm.act_run = 0;
       sm.tv[0] = troot;
     }
-    __syncthreads();
+    lds_barrier();
     if (resident) {
       if (t0 + troot < n) {
         if (wave == 0) count_chain<C>(sm);
       } else {
         count_last<C>(sm);
       }
-      __syncthreads();
+      lds_barrier();
       tile_lists<C>(sm);
     } else {
       for (uint32_t d = 0; d < maxd; ++d) {
         stage_level_streaming<C>(J, sm, d, scratch, scratch_words);
-        __syncthreads();
+        lds_barrier();
         if (wave == 0) count_level_streaming<C>(sm, d);
-        __syncthreads();
+        lds_barrier();
       }
     }
     if (h.err) { bad = true; break; }
-    for (int d = static_cast<int>(maxd) - 1; d >= 0; --d) {
-      if (resident) merge_level<C, true>(sm, d, out + t0);
-      else merge_level<C, false>(sm, d, out + t0);
-      __syncthreads();
-    }
+    if (resident) merge_tile<C, true>(sm, static_cast<int>(maxd), out + t0);
+    else merge_tile<C, false>(sm, static_cast<int>(maxd), out + t0);
     if (!resident) {
       for (uint32_t i = tid; i < I; i += C::NT) sm.tv[i] = 0;
-      __syncthreads();
+      lds_barrier();
     }
   }
   if (!bad) {
@@ -1222,7 +1276,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
         atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (tid == 0 && h.err) set_err(J.status, h.err);
 }
 
@@ -1242,13 +1296,13 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
       sm.nxt = load_ext(recs + it);
     }
   }
-  __syncthreads();
+  lds_barrier();
   for (;;) {
     const uint32_t it = sm.item;
     if (it >= n_items) break;
     const uint2 item = sm.nxt_item;
     const BlockExt ext = sm.nxt;
-    __syncthreads();                   // the look-ahead slots are rewritten below
+    lds_barrier();                   // the look-ahead slots are rewritten below
     // look ahead: take the next item now; its extent is read while this
     // block is decoded (no other global loads wait behind it when resident)
     uint32_t nit = n_items;
@@ -1267,7 +1321,7 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
       sm.nxt_item = nitem;
       sm.nxt = next;
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -1335,9 +1389,9 @@ __global__ void k_gather_headers(const pivco_job *jobs, uint32_t count, uint8_t 
 // ---------------------------------------------------------------------------
 // host-side launch table
 // ---------------------------------------------------------------------------
-using Cfg0 = MergeCfg<1024, 32768, 57344>;
-using Cfg1 = MergeCfg<1024, 16384, 81920>;
-using Cfg2 = MergeCfg<512, 8192, 49152>;
+using Cfg0 = MergeCfg<1024, 32768, 57344, 16>;
+using Cfg1 = MergeCfg<1024, 32768, 57344, 8>;
+using Cfg2 = MergeCfg<1024, 32768, 55296, 32>;
 
 struct MergeVariant {
   const char *name;
@@ -1370,9 +1424,9 @@ uint32_t merge_variant_count() { return 3; }
 
 const char *merge_variant_name(uint32_t v) {
   switch (v) {
-    case 0: return "wg1024_tile32k_body56k";
-    case 1: return "wg1024_tile16k_body80k";
-    case 2: return "wg512_tile8k_body48k";
+    case 0: return "wg1024_tile32k_body56k_k16";
+    case 1: return "wg1024_tile32k_body56k_k8";
+    case 2: return "wg1024_tile32k_body54k_k32";
     default: return "?";
   }
 }

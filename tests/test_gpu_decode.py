@@ -84,6 +84,9 @@ def test_every_merge_variant():
         t.merge_grid = 64
         t.rans_grid = 32
         plan = P.BatchPlan(streams, outs, tune=t)
+        for o in outs:
+            o.fill_(0xAB)                       # a byte left unwritten cannot match by chance
+        torch.cuda.synchronize()
         plan.launch()
         torch.cuda.synchronize()
         assert (plan.statuses() == 0).all()
