@@ -1012,39 +1012,59 @@ __device__ __forceinline__ MergePrep merge_prep(MergeSmem<C> &sm, int d, uint32_
 template <class C>
 __device__ __forceinline__ void merge_finish(MergeSmem<C> &sm, int d, const MergePrep &p, uint8_t *out) {
   if (!(p.flags & 1)) return;
-  uint8_t *lds = reinterpret_cast<uint8_t *>(&sm);
+  const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
+  constexpr int G = C::K / 4;                  // groups of 4 outputs
+  constexpr int CB = C::K < 16 ? C::K : 16;    // bytes per store
   const uint32_t mL = (p.flags >> 1) & 1, mR = (p.flags >> 2) & 1;
+  // every window address first (they depend on the bits only), then all
+  // reads at once, then the byte funnels and permutes: one LDS round trip
+  uint32_t aL[G], aR[G], m[G];
   uint32_t r1g = p.r1, r0g = p.r0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    m[g] = (p.bits >> (4 * g)) & 15;
+    aL[g] = p.bL + __umul24(mL, r0g);
+    aR[g] = p.bR + __umul24(mR, r1g);
+    const uint32_t pc = __popc(m[g]);
+    r1g += pc;
+    r0g += 4 - pc;
+  }
+  uint2 wl[G], wr[G];
+  uint32_t sel[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const uint32_t *ql = reinterpret_cast<const uint32_t *>(lds + (aL[g] & ~3u));   // 4-byte aligned:
+    const uint32_t *qr = reinterpret_cast<const uint32_t *>(lds + (aR[g] & ~3u));   // two dword reads
+    wl[g] = make_uint2(ql[0], ql[1]);
+    wr[g] = make_uint2(qr[0], qr[1]);
+    sel[g] = sm.sel[m[g]];
+  }
+  uint32_t o[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const uint32_t l4 = __builtin_amdgcn_alignbyte(wl[g].y, wl[g].x, aL[g]);
+    const uint32_t r4 = __builtin_amdgcn_alignbyte(wr[g].y, wr[g].x, aR[g]);
+    o[g] = __builtin_amdgcn_perm(r4, l4, sel[g]);
+  }
+  uint8_t *ldsw = reinterpret_cast<uint8_t *>(&sm);
   const uint32_t tvv = d == 0 ? sm.tv[0] : 0u;
-  constexpr int CB = C::K < 16 ? C::K : 16;   // bytes per store
 #pragma unroll
   for (int c = 0; c < C::K / CB; ++c) {
-    uint32_t o[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int g = 0; g < CB / 4; ++g) {
-      const uint32_t m = (p.bits >> (16 * c + 4 * g)) & 15;
-      const uint32_t wl = lds_win(lds, p.bL + __umul24(mL, r0g));
-      const uint32_t wr = lds_win(lds, p.bR + __umul24(mR, r1g));
-      o[g] = __builtin_amdgcn_perm(wr, wl, sm.sel[m]);
-      const uint32_t pc = __popc(m);
-      r1g += pc;
-      r0g += 4 - pc;
-    }
     if (d == 0) {
       const uint32_t j = p.j0 + CB * c;
       uint8_t *dst = out + j;
       if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
-        if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[0], o[1], o[2], o[3]};   // C cast: generic to global
+        if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};   // C cast: generic to global
         else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
       } else if (j < tvv) {
         const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
         GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
-        for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[e >> 2] >> (8 * (e & 3)));
+        for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[(CB * c + e) >> 2] >> (8 * (e & 3)));
       }
     } else if (CB == 16) {
-      *reinterpret_cast<uint4 *>(lds + p.dst + 16 * c) = make_uint4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<uint4 *>(ldsw + p.dst + 16 * c) = make_uint4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
     } else {
-      *reinterpret_cast<uint2 *>(lds + p.dst + CB * c) = make_uint2(o[0], o[1]);
+      *reinterpret_cast<uint2 *>(ldsw + p.dst) = make_uint2(o[0], o[1]);
     }
   }
 }
