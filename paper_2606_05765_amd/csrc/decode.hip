@@ -585,6 +585,7 @@ struct MergeCfg {
   static constexpr int BODY = BODY_;                  // resident block bytes
   static constexpr int K = K_;                        // outputs per merge task (8, 16 or 32)
   static constexpr int CS = K < 16 ? 3 : 4;           // child output offsets are stored >> CS
+  static constexpr int PAIR = K <= 16;                // merge two windows at once (registers allow)
   static constexpr int NW = NT / kWave;
   static constexpr int LVL = T + (K - 1) * 128 + 64;  // bytes per level buffer (shares rounded to K)
   static constexpr int LEVELS = kMaxLenGpu;
@@ -946,137 +947,138 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
 // over its nodes with work; a wave takes 64 consecutive tasks (a window), and
 // a lane finds its node as the window's first node plus the node starts
 // inside the window up to its task (popcount of the window's start mask).
-// merge_prep gathers what a task needs besides its children's bytes (node
-// record, K bitmap bits, their rank, the children's addresses); merge_finish
-// reads 4-byte windows of the children's sequences (a leaf child reads its
+// A task reads its node record, K bitmap bits and their rank, then 4-byte
+// windows of the children's sequences at the ranks (a leaf child reads its
 // constant row: the offset is multiplied by 0), makes groups of 4 bytes with
 // one v_perm_b32 each, and stores 16 bytes at a time (LDS, or HBM at the
-// root).
+// root).  All window addresses are computed before any window is read.
 typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) U32x4 GlobalU4;
 typedef uint32_t U32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) U32x2 GlobalU2;
 typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 
-struct MergePrep {
-  uint32_t bL, bR;   // LDS byte addresses of the children's sequences at the task (leaf: its row)
-  uint32_t r0, r1;   // 0 and 1 bits of the node before the task
-  uint32_t bits;     // the task's K bitmap bits (K <= 32)
-  uint32_t flags;    // 1: task, 2: left is a node, 4: right is a node
-  uint32_t j0;       // first output of the task within its node
-  uint32_t dst;      // below the root: LDS byte address of the task's outputs
-};
-
-template <class C, bool RESIDENT>
-__device__ __forceinline__ MergePrep merge_prep(MergeSmem<C> &sm, int d, uint32_t w) {
+// N windows of one level at once, stage by stage (records, bits and ranks,
+// child windows, permutes), so that each stage's LDS reads of all N windows
+// are in flight together.  Lanes without a task read from clamped addresses
+// and store nothing.
+template <class C, bool RESIDENT, int N>
+__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t (&w)[N],
+                                              uint32_t ntask, uint32_t abase, uint8_t *out) {
   const uint32_t lane = lane_id();
-  MergePrep p;
-  p.flags = 0;
-  p.bL = p.bR = p.r0 = p.r1 = p.bits = p.j0 = p.dst = 0;
-  const uint32_t ntask = sm.ntask[d];
-  const uint32_t task = kWave * w + lane;
+  constexpr int G = C::K / 4;                  // groups of 4 outputs
+  constexpr int CB = C::K < 16 ? C::K : 16;    // bytes per store
   const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
-  const uint64_t B = sm.smask[d][w];
   const uint64_t upto = ((2ull << lane) - 1) & ~1ull;   // window bits 1 .. lane
-  const uint32_t slot = sm.wstart[d][w] + static_cast<uint32_t>(__popcll(B & upto));
-  if (task >= ntask) return p;
-  const NodeRec r = sm.rec[sm.actbase[d] + slot];
-  const uint32_t j0 = C::K * (task - (r.ot >> 16));
-  uint32_t bits, r1;
-  if (RESIDENT) {
-    const uint32_t x = r.x0 + j0;
-    bits = bits32_lds(sm.body, x);
-    r1 = rank_at(sm.body, sm.sup, sm.rel, x) - r.arank;
-  } else {
-    const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
-    const uint2 wr = stage[r.x0 + (j0 >> 5)];
-    const uint32_t sh = j0 & 31;      // 0, or 16 with K = 16: staged words start at the node's cursor
-    bits = wr.x >> sh;
-    r1 = wr.y + __popc(wr.x & ((1u << sh) - 1));
+  bool valid[N];
+  NodeRec r[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const uint64_t B = sm.smask[d][w[i]];
+    const uint32_t slot = sm.wstart[d][w[i]] + static_cast<uint32_t>(__popcll(B & upto));
+    valid[i] = kWave * w[i] + lane < ntask;
+    r[i] = sm.rec[valid[i] ? abase + slot : 0u];
+  }
+  uint32_t j0[N], bits[N], r1[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    j0[i] = valid[i] ? C::K * (kWave * w[i] + lane - (r[i].ot >> 16)) : 0u;
+    if (RESIDENT) {
+      const uint32_t x = valid[i] ? r[i].x0 + j0[i] : 0u;
+      bits[i] = bits32_lds(sm.body, x);
+      r1[i] = rank_at(sm.body, sm.sup, sm.rel, x) - r[i].arank;
+    } else {
+      const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
+      const uint2 wr = stage[valid[i] ? r[i].x0 + (j0[i] >> 5) : 0u];
+      const uint32_t sh = j0[i] & 31;   // 0, or a multiple of K: staged words start at the node's cursor
+      bits[i] = wr.x >> sh;
+      r1[i] = wr.y + __popc(wr.x & ((1u << sh) - 1));
+    }
   }
   const uint32_t cbase = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[(d + 1) & 1]) - lds);
   const uint32_t lrow = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.leafrow) - lds);
-  const uint32_t kl = r.kids & 0xFFFF, kr = r.kids >> 16;
-  const bool nl = !(kl & 0x8000), nr = !(kr & 0x8000);
-  p.bL = nl ? cbase + (kl << C::CS) : lrow + 4 * (kl & 255);
-  p.bR = nr ? cbase + (kr << C::CS) : lrow + 4 * (kr & 255);
-  p.r1 = r1;
-  p.r0 = j0 - r1;
-  p.bits = C::K == 32 ? bits : (bits & ((1u << C::K) - 1));
-  p.flags = 1u | (nl ? 2u : 0u) | (nr ? 4u : 0u);
-  p.j0 = j0;
-  p.dst = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[d & 1]) - lds) + (r.ot & 0xFFFF) + j0;
-  return p;
-}
-
-template <class C>
-__device__ __forceinline__ void merge_finish(MergeSmem<C> &sm, int d, const MergePrep &p, uint8_t *out) {
-  if (!(p.flags & 1)) return;
-  const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
-  constexpr int G = C::K / 4;                  // groups of 4 outputs
-  constexpr int CB = C::K < 16 ? C::K : 16;    // bytes per store
-  const uint32_t mL = (p.flags >> 1) & 1, mR = (p.flags >> 2) & 1;
-  // every window address first (they depend on the bits only), then all
-  // reads at once, then the byte funnels and permutes: one LDS round trip
-  uint32_t aL[G], aR[G], m[G];
-  uint32_t r1g = p.r1, r0g = p.r0;
+  uint32_t aL[N][G], aR[N][G], sel[N][G];
+  uint2 wl[N][G], wr[N][G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    m[g] = (p.bits >> (4 * g)) & 15;
-    aL[g] = p.bL + __umul24(mL, r0g);
-    aR[g] = p.bR + __umul24(mR, r1g);
-    const uint32_t pc = __popc(m[g]);
-    r1g += pc;
-    r0g += 4 - pc;
+  for (int i = 0; i < N; ++i) {
+    const uint32_t kl = r[i].kids & 0xFFFF, kr = r[i].kids >> 16;
+    const uint32_t mL = (kl & 0x8000) ? 0u : 1u, mR = (kr & 0x8000) ? 0u : 1u;
+    const uint32_t bL = !valid[i] ? 0u : mL ? cbase + (kl << C::CS) : lrow + 4 * (kl & 255);
+    const uint32_t bR = !valid[i] ? 0u : mR ? cbase + (kr << C::CS) : lrow + 4 * (kr & 255);
+    uint32_t r1g = valid[i] ? r1[i] : 0u, r0g = valid[i] ? j0[i] - r1[i] : 0u;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint32_t m = (bits[i] >> (4 * g)) & 15;
+      aL[i][g] = bL + __umul24(mL, r0g);
+      aR[i][g] = bR + __umul24(mR, r1g);
+      sel[i][g] = m;
+      const uint32_t pc = __popc(m);
+      r1g += pc;
+      r0g += 4 - pc;
+    }
   }
-  uint2 wl[G], wr[G];
-  uint32_t sel[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const uint32_t *ql = reinterpret_cast<const uint32_t *>(lds + (aL[g] & ~3u));   // 4-byte aligned:
-    const uint32_t *qr = reinterpret_cast<const uint32_t *>(lds + (aR[g] & ~3u));   // two dword reads
-    wl[g] = make_uint2(ql[0], ql[1]);
-    wr[g] = make_uint2(qr[0], qr[1]);
-    sel[g] = sm.sel[m[g]];
-  }
-  uint32_t o[G];
+  for (int i = 0; i < N; ++i) {
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const uint32_t l4 = __builtin_amdgcn_alignbyte(wl[g].y, wl[g].x, aL[g]);
-    const uint32_t r4 = __builtin_amdgcn_alignbyte(wr[g].y, wr[g].x, aR[g]);
-    o[g] = __builtin_amdgcn_perm(r4, l4, sel[g]);
+    for (int g = 0; g < G; ++g) {
+      const uint32_t *ql = reinterpret_cast<const uint32_t *>(lds + (aL[i][g] & ~3u));   // 4-byte aligned:
+      const uint32_t *qr = reinterpret_cast<const uint32_t *>(lds + (aR[i][g] & ~3u));   // two dword reads
+      wl[i][g] = make_uint2(ql[0], ql[1]);
+      wr[i][g] = make_uint2(qr[0], qr[1]);
+      sel[i][g] = sm.sel[sel[i][g]];
+    }
   }
   uint8_t *ldsw = reinterpret_cast<uint8_t *>(&sm);
   const uint32_t tvv = d == 0 ? sm.tv[0] : 0u;
 #pragma unroll
-  for (int c = 0; c < C::K / CB; ++c) {
-    if (d == 0) {
-      const uint32_t j = p.j0 + CB * c;
-      uint8_t *dst = out + j;
-      if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
-        if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};   // C cast: generic to global
-        else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
-      } else if (j < tvv) {
-        const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
-        GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
-        for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[(CB * c + e) >> 2] >> (8 * (e & 3)));
+  for (int i = 0; i < N; ++i) {
+    uint32_t o[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint32_t l4 = __builtin_amdgcn_alignbyte(wl[i][g].y, wl[i][g].x, aL[i][g]);
+      const uint32_t r4 = __builtin_amdgcn_alignbyte(wr[i][g].y, wr[i][g].x, aR[i][g]);
+      o[g] = __builtin_amdgcn_perm(r4, l4, sel[i][g]);
+    }
+    if (!valid[i]) continue;
+#pragma unroll
+    for (int c = 0; c < C::K / CB; ++c) {
+      if (d == 0) {
+        const uint32_t j = j0[i] + CB * c;
+        uint8_t *dst = out + j;
+        if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
+          if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};   // C cast: generic to global
+          else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
+        } else if (j < tvv) {
+          const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
+          GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
+          for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[(CB * c + e) >> 2] >> (8 * (e & 3)));
+        }
+      } else {
+        const uint32_t dst = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[d & 1]) - lds) +
+                             (r[i].ot & 0xFFFF) + j0[i] + CB * c;
+        if (CB == 16) *reinterpret_cast<uint4 *>(ldsw + dst) = make_uint4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
+        else *reinterpret_cast<uint2 *>(ldsw + dst) = make_uint2(o[0], o[1]);
       }
-    } else if (CB == 16) {
-      *reinterpret_cast<uint4 *>(ldsw + p.dst + 16 * c) = make_uint4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
-    } else {
-      *reinterpret_cast<uint2 *>(ldsw + p.dst) = make_uint2(o[0], o[1]);
     }
   }
 }
 
-// All levels of the tile, deepest first; one barrier per level.
+// All levels of the tile, deepest first; one barrier per level.  A wave
+// takes its windows of a level two at a time (one at a time for K = 32).
 template <class C, bool RESIDENT>
 __device__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
   const uint32_t wave = threadIdx.x >> 6;
   for (int d = maxd - 1; d >= 0; --d) {
-    const uint32_t ntask = sm.ntask[d];
-    for (uint32_t w = wave; kWave * w < ntask; w += C::NW)
-      merge_finish<C>(sm, d, merge_prep<C, RESIDENT>(sm, d, w), out);
+    const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
+    for (uint32_t w = wave; kWave * w < ntask; w += (C::PAIR ? 2 : 1) * C::NW) {
+      if (C::PAIR && kWave * (w + C::NW) < ntask) {
+        const uint32_t ww[2] = {w, w + C::NW};
+        merge_windows<C, RESIDENT, 2>(sm, d, ww, ntask, abase, out);
+      } else {
+        const uint32_t ww[1] = {w};
+        merge_windows<C, RESIDENT, 1>(sm, d, ww, ntask, abase, out);
+      }
+    }
     lds_barrier();
   }
 }
