@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decoded GB/s per MI355X (% HBM roofline), batched vs plain; p99 latency"
 HBM_PEAK_GBPS = 8000.0
+# one element merge (a byte chosen by a bitmap bit) needs at least one VALU
+# lane operation: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_OPS_PEAK_G = 256 * 4 * 16 * 2.4
 
 
 def log(*a):
@@ -68,6 +71,57 @@ def cpu_baseline(stream_np, n_blocks, block_size, budget_s=12.0):
                       f"stream, single-threaded C oracle (tree walk per symbol), {dt:.1f} s"}
 
 
+def element_merges(x, block_size):
+    """Sum over blocks of the symbols passing every internal node (n * mean
+    code length): the element merges a decode performs.  Per-block trees
+    from the library's own tree builder (the encoder's default)."""
+    from paper_2606_05765_amd import pivco as P
+    total = 0
+    for b0 in range(0, x.size, block_size):
+        blk = x[b0:b0 + block_size]
+        counts = np.bincount(blk, minlength=256).astype(np.uint64)
+        if np.count_nonzero(counts) < 2:
+            continue
+        lens = P.pivco_build_tree(counts, 11)
+        total += int(np.dot(counts, np.asarray(lens, dtype=np.uint64)))
+    return total
+
+
+def serving_leg(torch, dev, seconds=1.0, rate_hz=2000.0, n_pool=48, seed=11,
+                budget=32 * 10**9):
+    """Poisson request trace against the continuous-batching server: decode
+    requests of resident streams (sizes log-uniform 16 KiB - 64 MiB, mixed
+    families, 1 MiB blocks), output space recycled under the byte budget."""
+    import workloads as W
+    from paper_2606_05765_amd import pivco as P
+    w = W.serve_requests(seed=seed, n_req=n_pool)
+    streams = [P.pivco_encode(torch.from_numpy(x).to(dev), w.block_size, ans_mode=w.ans_mode)
+               for x in w.jobs]
+    torch.cuda.synchronize()
+    pool = torch.empty(budget, dtype=torch.uint8, device=dev)
+    sv = P.Server(mem_budget=budget, slots=4, max_batch=64, keep_outputs=False)
+    ids = [sv.register(st) for st in streams]
+    n = int(rate_hz * seconds)
+    rng = np.random.default_rng(seed)
+    order = rng.integers(0, n_pool, size=n)
+    arrivals = W.poisson_arrivals(seed, rate_hz, n)
+    res, stats = sv.run(arrivals, [ids[k] for k in order], pool)
+    torch.cuda.synchronize()
+    sv.close()
+    bad = [r["status"] for r in res if r["status"] != 0]
+    assert not bad, f"serving statuses {bad[:5]}"
+    lat = np.array([r["t_done"] - r["arrival"] for r in res]) * 1e3
+    sizes = np.array([w.jobs[k].size for k in order], dtype=np.float64)
+    return {"requests": n, "rate_hz": rate_hz, "resident_requests": n_pool,
+            "mean_request_MB": round(float(sizes.mean()) / 1e6, 2),
+            "offered_GBps": round(float(sizes.sum()) / float(arrivals[-1]) / 1e9, 2),
+            "sustained_GBps": round(stats["bytes_decoded"] / stats["wall_s"] / 1e9, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "batches": stats["batches"], "max_batch": stats["max_batch"],
+            "budget_GB": round(budget / 1e9, 1), "slots": 4}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +133,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--variant", type=int, default=None, help="fixed merge variant (skips autotune)")
     ap.add_argument("--grid", type=int, default=None, help="fixed merge grid (with --variant)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -169,6 +224,13 @@ def main():
                 "algorithmic_bytes_per_launch": algo_bytes}
     log(f"merge kernel: {merge_avg:.3f} ms avg, {achieved:.1f} GB/s algorithmic "
         f"({achieved / HBM_PEAK_GBPS * 100:.1f}% of HBM peak)")
+    merges = element_merges(x, bs)
+    alu_view = {"unit": "G element merges/s", "element_merges_per_launch": merges,
+                "mean_code_len": round(merges / n, 4),
+                "achieved": round(merges / (merge_avg * 1e-3) / 1e9, 1),
+                "peak": round(VALU_LANE_OPS_PEAK_G, 1),
+                "frac": round(merges / (merge_avg * 1e-3) / 1e9 / VALU_LANE_OPS_PEAK_G, 4)}
+    log("element merges:", alu_view)
 
     plain = None
     if not args.no_plain:
@@ -193,6 +255,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    serving = None
+    if not args.no_serve:
+        log("serving leg (Poisson trace) ...")
+        serving = serving_leg(torch, dev)
+        log("serving:", serving)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
@@ -214,6 +282,8 @@ def main():
         "encode_GBps": round(n / min(enc_times) / 1e9, 2),
         "compression_ratio": round(n / comp, 4),
         "roofline": roofline,
+        "alu_view": alu_view,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     plan.close()
