@@ -578,14 +578,15 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const uint
 // ---------------------------------------------------------------------------
 // Kernel: bottom-up merge decode
 // ---------------------------------------------------------------------------
-template <int NT_, int T_, int BODY_, int K_>
+template <int NT_, int T_, int BODY_, int K_, int LOCK_>
 struct MergeCfg {
   static constexpr int NT = NT_;
   static constexpr int T = T_;                        // output symbols per tile
   static constexpr int BODY = BODY_;                  // resident block bytes
   static constexpr int K = K_;                        // outputs per merge task (8, 16 or 32)
   static constexpr int CS = K < 16 ? 3 : 4;           // child output offsets are stored >> CS
-  static constexpr int PAIR = K <= 16;                // merge two windows at once (registers allow)
+  static constexpr int LOCK = LOCK_;                  // windows a wave merges at once (1, 2 or 4)
+  static_assert(LOCK == 1 || LOCK == 2 || LOCK == 4, "windows per wave step");
   static constexpr int NW = NT / kWave;
   static constexpr int LVL = T + (K - 1) * 128 + 64;  // bytes per level buffer (shares rounded to K)
   static constexpr int LEVELS = kMaxLenGpu;
@@ -963,7 +964,7 @@ typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 // are in flight together.  Lanes without a task read from clamped addresses
 // and store nothing.
 template <class C, bool RESIDENT, int N>
-__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t (&w)[N],
+__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t *w,
                                               uint32_t ntask, uint32_t abase, uint8_t *out) {
   const uint32_t lane = lane_id();
   constexpr int G = C::K / 4;                  // groups of 4 outputs
@@ -1064,20 +1065,20 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
 }
 
 // All levels of the tile, deepest first; one barrier per level.  A wave
-// takes its windows of a level two at a time (one at a time for K = 32).
+// takes up to C::LOCK of its windows of a level at once.
 template <class C, bool RESIDENT>
 __device__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
   const uint32_t wave = threadIdx.x >> 6;
   for (int d = maxd - 1; d >= 0; --d) {
     const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
-    for (uint32_t w = wave; kWave * w < ntask; w += (C::PAIR ? 2 : 1) * C::NW) {
-      if (C::PAIR && kWave * (w + C::NW) < ntask) {
-        const uint32_t ww[2] = {w, w + C::NW};
-        merge_windows<C, RESIDENT, 2>(sm, d, ww, ntask, abase, out);
-      } else {
-        const uint32_t ww[1] = {w};
-        merge_windows<C, RESIDENT, 1>(sm, d, ww, ntask, abase, out);
-      }
+    const uint32_t nwin = (ntask + kWave - 1) / kWave;
+    for (uint32_t w = wave; w < nwin; w += C::LOCK * C::NW) {
+      const uint32_t left = (nwin - w + C::NW - 1) / C::NW;   // windows of this wave from w on
+      const uint32_t ww[4] = {w, w + C::NW, w + 2 * C::NW, w + 3 * C::NW};
+      if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1)>(sm, d, ww, ntask, abase, out);
+      else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1)>(sm, d, ww, ntask, abase, out);
+      else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1)>(sm, d, ww, ntask, abase, out);
+      else merge_windows<C, RESIDENT, 1>(sm, d, ww, ntask, abase, out);
     }
     lds_barrier();
   }
@@ -1411,9 +1412,9 @@ __global__ void k_gather_headers(const pivco_job *jobs, uint32_t count, uint8_t 
 // ---------------------------------------------------------------------------
 // host-side launch table
 // ---------------------------------------------------------------------------
-using Cfg0 = MergeCfg<1024, 32768, 57344, 16>;
-using Cfg1 = MergeCfg<1024, 32768, 57344, 8>;
-using Cfg2 = MergeCfg<1024, 32768, 55296, 32>;
+using Cfg0 = MergeCfg<1024, 32768, 57344, 16, 2>;
+using Cfg1 = MergeCfg<1024, 32768, 57344, 8, 2>;
+using Cfg2 = MergeCfg<1024, 32768, 55296, 32, 1>;
 
 struct MergeVariant {
   const char *name;
@@ -1446,9 +1447,9 @@ uint32_t merge_variant_count() { return 3; }
 
 const char *merge_variant_name(uint32_t v) {
   switch (v) {
-    case 0: return "wg1024_tile32k_body56k_k16";
-    case 1: return "wg1024_tile32k_body56k_k8";
-    case 2: return "wg1024_tile32k_body54k_k32";
+    case 0: return "wg1024_tile32k_body56k_k16_x2";
+    case 1: return "wg1024_tile32k_body56k_k8_x2";
+    case 2: return "wg1024_tile32k_body54k_k32_x1";
     default: return "?";
   }
 }
