@@ -636,6 +636,8 @@ struct MergeSmem {
   uint32_t ntask[C::LEVELS];          // 16-output tasks of the level
   uint32_t actbase[C::LEVELS];        // slots of the levels above
   uint32_t act_run;
+  uint32_t warm_sink;
+  const uint8_t *warm_in, *warm_rec;
   uint32_t stage_top;
   uint32_t tile;           // runtime tile size for this block
   uint32_t sel[16];
@@ -1157,11 +1159,53 @@ __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockE
   __syncthreads();
 }
 
+// The look-ahead of the persistent loop: the next item, its extent, and
+// where its bytes and record are (for warming the cache).  Held by one
+// thread (64) from the start of a block until publish_next puts it in LDS.
+struct Lookahead {
+  uint32_t item;             // next work item (n_items: none)
+  uint2 job_block;
+  BlockExt ext;
+  const uint8_t *in;         // its stream (null: nothing to warm)
+  const uint8_t *rec;        // its record
+};
+
+template <class C>
+__device__ __forceinline__ void publish_next(MergeSmem<C> &sm, const Lookahead &la) {
+  if (threadIdx.x != kWave) return;
+  sm.item = la.item;
+  sm.nxt_item = la.job_block;
+  sm.nxt = la.ext;
+  sm.warm_in = la.in;
+  sm.warm_rec = la.rec;
+}
+
+// Wave 1 reads a word of every 128-byte line of the next block (if it would
+// be resident) and of its record, and waits for them, so that the next
+// load_block finds them in the cache.  Runs while wave 0 computes the first
+// tile's shares and the other waves are idle.
+template <class C>
+__device__ void warm_next(MergeSmem<C> &sm) {
+  const uint32_t lane = lane_id();
+  const uint8_t *in = sm.warm_in;
+  if (!in) return;
+  const uint8_t *rec = sm.warm_rec;
+  const uint64_t blk = sm.nxt.blk, end = sm.nxt.end;
+  uint32_t acc = 0;
+  if (end > blk && end - blk <= static_cast<uint64_t>(C::BODY)) {
+    for (uint64_t a = (blk & ~127ull) + 128ull * lane; a < end; a += 128ull * kWave)
+      acc ^= *reinterpret_cast<const uint32_t *>(in + a);
+  }
+  for (uint32_t a = 128 * lane; a < sizeof(ParsedBlock); a += 128 * kWave)
+    acc ^= *reinterpret_cast<const uint32_t *>(rec + a);
+  if (acc == 0x9E3779B9u) sm.warm_sink = acc;   // keeps the reads; the value is irrelevant
+}
+
 // Decodes the block whose record (and, when resident, body) load_block put
 // into LDS, with the whole workgroup.
 template <class C>
 __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_t *scratch,
-                             uint64_t scratch_words, MergeSmem<C> &sm) {
+                             uint64_t scratch_words, MergeSmem<C> &sm, const Lookahead &la) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
@@ -1171,12 +1215,14 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
   const uint64_t g0 = ext.blk & ~15ull;
   const uint64_t span = ((ext.end + 15) & ~15ull) - g0;
   if (h.err) {
+    publish_next<C>(sm, la);
     if (tid == 0) set_err(J.status, h.err);
     return;
   }
   uint8_t *out = J.out + h.out_off;
   const uint32_t n = h.n;
   if (h.mode == 1) {                 // constant block
+    publish_next<C>(sm, la);
     const uint32_t c4 = h.csym * 0x01010101u;
     const uint32_t head = static_cast<uint32_t>((4 - (reinterpret_cast<uintptr_t>(out) & 3)) & 3);
     for (uint32_t i = tid; i < n && i < head; i += C::NT) out[i] = static_cast<uint8_t>(h.csym);
@@ -1260,6 +1306,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
   bool bad = false;
 
+  publish_next<C>(sm, la);            // visible after the next barrier
   for (uint32_t t0 = 0; t0 < n; t0 += T) {
     const uint32_t troot = n - t0 < T ? n - t0 : T;
     if (tid == 0) {
@@ -1271,6 +1318,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     if (resident) {
       if (t0 + troot < n) {
         if (wave == 0) count_chain<C>(sm);
+        else if (wave == 1 && t0 == 0) warm_next<C>(sm);
       } else {
         count_last<C>(sm);
       }
@@ -1326,24 +1374,21 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
     const uint2 item = sm.nxt_item;
     const BlockExt ext = sm.nxt;
     lds_barrier();                   // the look-ahead slots are rewritten below
-    // look ahead: take the next item now; its extent is read while this
-    // block is decoded (no other global loads wait behind it when resident)
-    uint32_t nit = n_items;
-    if (tid == 0 && single < 0) nit = atomicAdd(&ctr->merge_next, 1u);
+    // look ahead (thread 64, in a wave that is idle while wave 0 computes
+    // the first tile's shares): take the next item now; its extent and
+    // stream are read while this block is decoded, and published to LDS at
+    // the first tile's count (or when the block ends early)
+    Lookahead la{n_items, make_uint2(0, 0), BlockExt{}, nullptr, nullptr};
+    if (tid == kWave && single < 0) la.item = atomicAdd(&ctr->merge_next, 1u);
     const JobDev &J = jobs[item.x];
     load_block<C>(J, recs + it, ext, scratch, scratch_words, sm);
-    uint2 nitem = make_uint2(0, 0);
-    BlockExt next{};
-    if (tid == 0 && nit < n_items) {
-      nitem = items[nit];
-      next = load_ext(recs + nit);
+    if (tid == kWave && la.item < n_items) {
+      la.job_block = items[la.item];
+      la.ext = load_ext(recs + la.item);
+      la.in = la.ext.err ? nullptr : jobs[la.job_block.x].in;
+      la.rec = reinterpret_cast<const uint8_t *>(recs + la.item);
     }
-    decode_block<C>(J, ext, scratch, scratch_words, sm);
-    if (tid == 0) {
-      sm.item = nit;
-      sm.nxt_item = nitem;
-      sm.nxt = next;
-    }
+    decode_block<C>(J, ext, scratch, scratch_words, sm, la);
     lds_barrier();
   }
 }
