@@ -177,7 +177,8 @@ typedef struct {
   uint32_t merge_variant;      /* merge kernel variant (see pivco_merge_variants) */
   uint64_t max_scratch_words;  /* rANS scratch words per batch */
   uint32_t keep_outputs;       /* 1: never recycle output space (for checking results) */
-  uint32_t reserved;
+  uint32_t max_tiles;          /* 32Ki-symbol tiles of split blocks per batch (blocks of
+                                  more than 64Ki symbols decode as tiles); 0 = 8192 */
 } pivco_server_opts;
 
 typedef struct {

@@ -82,23 +82,25 @@ pivco_status parse_stream_header(const uint8_t *h, uint64_t avail, StreamHdr *o)
 struct HostPlan {
   uint32_t count = 0;
   std::vector<JobDev> jobs;
-  std::vector<uint2> items;    // (job, block), largest blocks first
-  std::vector<uint2> ritems;   // blocks of jobs that contain rANS nodes
+  WorkLists w;                 // blocks, rANS blocks, split blocks, merge items
   std::vector<int32_t> status0;
   uint64_t scratch_words = 0;
   // workspace layout (byte offsets)
-  uint64_t off_ctr = 0, off_jobs = 0, off_items = 0, off_ritems = 0, off_status0 = 0,
-           off_recs = 0, off_scratch = 0, total = 0;
+  uint64_t off_ctr = 0, off_jobs = 0, off_blocks = 0, off_items = 0, off_ritems = 0,
+           off_tiled = 0, off_status0 = 0, off_recs = 0, off_tab = 0, off_scratch = 0, total = 0;
 };
 
 void layout(HostPlan &p) {
   uint64_t o = 0;
   p.off_ctr = o; o += 256;
   p.off_jobs = o; o = align_up(o + sizeof(JobDev) * p.count, 256);
-  p.off_items = o; o = align_up(o + 8 * p.items.size(), 256);
-  p.off_ritems = o; o = align_up(o + 8 * p.ritems.size(), 256);
+  p.off_blocks = o; o = align_up(o + 8 * p.w.blocks.size(), 256);
+  p.off_items = o; o = align_up(o + 8 * p.w.items.size(), 256);
+  p.off_ritems = o; o = align_up(o + 8 * p.w.ritems.size(), 256);
+  p.off_tiled = o; o = align_up(o + sizeof(TiledBlock) * p.w.tiled.size(), 256);
   p.off_status0 = o; o = align_up(o + 4ull * p.count, 256);
-  p.off_recs = o; o = align_up(o + static_cast<uint64_t>(kParsedBlockBytes) * p.items.size(), 256);
+  p.off_recs = o; o = align_up(o + static_cast<uint64_t>(kParsedBlockBytes) * p.w.blocks.size(), 256);
+  p.off_tab = o; o = align_up(o + 8 * p.w.tab_entries, 256);
   p.off_scratch = o; o = align_up(o + 4 * p.scratch_words + 64, 256);
   // header gathering reuses the start of the workspace before the upload
   const uint64_t gather = align_up(sizeof(pivco_job) * p.count, 256) + kHeaderBytes * p.count;
@@ -146,10 +148,8 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
   p.count = count;
   p.jobs.assign(count, JobDev{});
   p.status0.assign(count, PIVCO_OK);
-  p.items.clear();
-  p.ritems.clear();
+  p.w.clear();
   uint64_t sw = 0;
-  std::vector<std::pair<uint64_t, uint2>> sized;
   for (uint32_t j = 0; j < count; ++j) {
     const pivco_job &jb = h_jobs[j];
     StreamHdr sh;
@@ -171,21 +171,12 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
     d.max_len = sh.max_len;
     d.chunk_log2 = sh.chunk_log2;
     d.scratch_base = sw;
+    d.ans_words = sh.ans_words;
     sw = align_up(sw + sh.ans_words, 4);
-    for (uint32_t b = 0; b < sh.n_blocks; ++b) {
-      const uint64_t start = static_cast<uint64_t>(b) * sh.block_size;
-      const uint64_t sz = std::min<uint64_t>(sh.block_size, sh.n_total - start);
-      sized.push_back({sz, make_uint2(j, b)});
-      if (sh.ans_words) p.ritems.push_back(make_uint2(j, b));
-    }
+    p.w.add_job(j, sh.n_total, sh.n_blocks, sh.block_size, sh.ans_words != 0);
   }
-  std::stable_sort(sized.begin(), sized.end(),
-                   [](const std::pair<uint64_t, uint2> &a, const std::pair<uint64_t, uint2> &b) {
-                     return a.first > b.first;
-                   });
-  p.items.reserve(sized.size());
-  for (auto &x : sized) p.items.push_back(x.second);
-  if (p.items.size() > 0xFFFFFFF0ull) return PIVCO_E_UNSUPPORTED;
+  p.w.finish();
+  if (p.w.items.size() > 0xFFFFFFF0ull || p.w.blocks.size() > 0xFFFFFFF0ull) return PIVCO_E_UNSUPPORTED;
   p.scratch_words = sw;
   layout(p);
   return PIVCO_OK;
@@ -197,8 +188,10 @@ pivco_status upload_plan(const HostPlan &p, void *d_ws, hipStream_t s) {
     return n == 0 || hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
   };
   if (!cp(p.off_jobs, p.jobs.data(), sizeof(JobDev) * p.count) ||
-      !cp(p.off_items, p.items.data(), 8 * p.items.size()) ||
-      !cp(p.off_ritems, p.ritems.data(), 8 * p.ritems.size()) ||
+      !cp(p.off_blocks, p.w.blocks.data(), 8 * p.w.blocks.size()) ||
+      !cp(p.off_items, p.w.items.data(), 8 * p.w.items.size()) ||
+      !cp(p.off_ritems, p.w.ritems.data(), 8 * p.w.ritems.size()) ||
+      !cp(p.off_tiled, p.w.tiled.data(), sizeof(TiledBlock) * p.w.tiled.size()) ||
       !cp(p.off_status0, p.status0.data(), 4ull * p.count))
     return PIVCO_E_DEVICE;
   return PIVCO_OK;
@@ -207,9 +200,11 @@ pivco_status upload_plan(const HostPlan &p, void *d_ws, hipStream_t s) {
 struct Dev {
   Counters *ctr;
   const JobDev *jobs;
-  const uint2 *items, *ritems;
+  const uint2 *blocks, *items, *ritems;
+  const TiledBlock *tiled;
   const int32_t *status0;
   void *recs;
+  uint2 *tab;
   uint32_t *scratch;
 };
 
@@ -218,8 +213,11 @@ Dev dev_ptrs(const HostPlan &p, void *d_ws) {
   Dev d;
   d.ctr = reinterpret_cast<Counters *>(ws + p.off_ctr);
   d.jobs = reinterpret_cast<const JobDev *>(ws + p.off_jobs);
+  d.blocks = reinterpret_cast<const uint2 *>(ws + p.off_blocks);
   d.items = reinterpret_cast<const uint2 *>(ws + p.off_items);
   d.ritems = reinterpret_cast<const uint2 *>(ws + p.off_ritems);
+  d.tiled = reinterpret_cast<const TiledBlock *>(ws + p.off_tiled);
+  d.tab = reinterpret_cast<uint2 *>(ws + p.off_tab);
   d.status0 = reinterpret_cast<const int32_t *>(ws + p.off_status0);
   d.recs = ws + p.off_recs;
   d.scratch = reinterpret_cast<uint32_t *>(ws + p.off_scratch);
@@ -240,18 +238,22 @@ pivco_tune default_tune(uint32_t n_items, uint32_t n_ritems) {
 pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, const pivco_tune &t,
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   Dev d = dev_ptrs(p, d_ws);
+  const WorkLists &w = p.w;
   if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
-  if (launch_plan(s, d.jobs, d.items, static_cast<uint32_t>(p.items.size()), d.recs) != hipSuccess)
+  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs) != hipSuccess)
     return PIVCO_E_DEVICE;
-  if (!p.ritems.empty() &&
-      launch_rans(t.rans_grid, s, d.jobs, d.ritems, static_cast<uint32_t>(p.ritems.size()), d.ctr,
+  if (!w.ritems.empty() &&
+      launch_rans(t.rans_grid, s, d.jobs, d.ritems, static_cast<uint32_t>(w.ritems.size()), d.ctr,
                   d.scratch, -1) != hipSuccess)
     return PIVCO_E_DEVICE;
+  if (launch_tiles(s, d.jobs, d.blocks, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
+                   d.scratch, p.scratch_words, d.tab) != hipSuccess)
+    return PIVCO_E_DEVICE;
   if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PIVCO_E_DEVICE;
-  if (!p.items.empty() &&
-      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.items, d.recs,
-                   static_cast<uint32_t>(p.items.size()), d.ctr, d.scratch, p.scratch_words,
-                   -1) != hipSuccess)
+  if (!w.items.empty() &&
+      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.blocks, d.items, d.recs, d.tiled,
+                   d.tab, static_cast<uint32_t>(w.items.size()), d.ctr, d.scratch,
+                   p.scratch_words, -1) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return PIVCO_E_DEVICE;
   return PIVCO_OK;
@@ -330,8 +332,8 @@ pivco_status pivco_decode_batch(const pivco_job *h_jobs, uint32_t count, int32_t
   pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
   if (st) return st;
   if (count == 0) return PIVCO_OK;
-  const pivco_tune t = default_tune(static_cast<uint32_t>(p.items.size()),
-                                    static_cast<uint32_t>(p.ritems.size()));
+  const pivco_tune t = default_tune(static_cast<uint32_t>(p.w.items.size()),
+                                    static_cast<uint32_t>(p.w.ritems.size()));
   return enqueue_batch(p, d_ws, d_status, t, s, nullptr, nullptr);
 }
 
@@ -348,30 +350,30 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
   if (st) return st;
   if (count == 0) return PIVCO_OK;
   Dev d = dev_ptrs(p, d_ws);
+  const WorkLists &w = p.w;
   if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
-  if (launch_plan(s, d.jobs, d.items, static_cast<uint32_t>(p.items.size()), d.recs) != hipSuccess)
+  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs) != hipSuccess)
     return PIVCO_E_DEVICE;
-  // one launch per block, in stream order: rANS first when the job has any
-  std::vector<uint32_t> idx(p.items.size());
+  // one launch per block (rANS), then the boundaries of split blocks, then
+  // one merge launch per item, in stream order
+  for (size_t r = 0; r < w.ritems.size(); ++r)
+    if (launch_rans(1, s, d.jobs, d.ritems, static_cast<uint32_t>(w.ritems.size()), d.ctr,
+                    d.scratch, static_cast<int32_t>(r)) != hipSuccess)
+      return PIVCO_E_DEVICE;
+  if (launch_tiles(s, d.jobs, d.blocks, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
+                   d.scratch, p.scratch_words, d.tab) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  std::vector<uint32_t> idx(w.items.size());
   for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
   std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
-    return p.items[a].x != p.items[b].x ? p.items[a].x < p.items[b].x : p.items[a].y < p.items[b].y;
+    return w.items[a].x != w.items[b].x ? w.items[a].x < w.items[b].x
+                                        : (w.items[a].y & 255) < (w.items[b].y & 255);
   });
-  size_t r = 0;
-  for (uint32_t i : idx) {
-    const uint2 it = p.items[i];
-    while (r < p.ritems.size() &&
-           (p.ritems[r].x < it.x || (p.ritems[r].x == it.x && p.ritems[r].y < it.y)))
-      ++r;
-    if (r < p.ritems.size() && p.ritems[r].x == it.x && p.ritems[r].y == it.y) {
-      if (launch_rans(1, s, d.jobs, d.ritems, static_cast<uint32_t>(p.ritems.size()), d.ctr,
-                      d.scratch, static_cast<int32_t>(r)) != hipSuccess)
-        return PIVCO_E_DEVICE;
-    }
-    if (launch_merge(0, 1, s, d.jobs, d.items, d.recs, static_cast<uint32_t>(p.items.size()), d.ctr,
-                     d.scratch, p.scratch_words, static_cast<int32_t>(i)) != hipSuccess)
+  for (uint32_t i : idx)
+    if (launch_merge(0, 1, s, d.jobs, d.blocks, d.items, d.recs, d.tiled, d.tab,
+                     static_cast<uint32_t>(w.items.size()), d.ctr, d.scratch, p.scratch_words,
+                     static_cast<int32_t>(i)) != hipSuccess)
       return PIVCO_E_DEVICE;
-  }
   return PIVCO_OK;
 }
 
@@ -388,8 +390,8 @@ pivco_status pivco_batch_plan_create(const pivco_job *h_jobs, uint32_t count, in
   if (st) { delete bp; return st; }
   bp->ws = d_ws;
   bp->status = d_status;
-  bp->tune = tune ? *tune : default_tune(static_cast<uint32_t>(bp->plan.items.size()),
-                                         static_cast<uint32_t>(bp->plan.ritems.size()));
+  bp->tune = tune ? *tune : default_tune(static_cast<uint32_t>(bp->plan.w.items.size()),
+                                         static_cast<uint32_t>(bp->plan.w.ritems.size()));
   if (bp->tune.merge_variant >= merge_variant_count() || bp->tune.merge_grid == 0 ||
       bp->tune.rans_grid == 0) {
     delete bp;
@@ -441,9 +443,9 @@ pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_
   HostPlan p;
   pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
   if (st) return st;
-  pivco_tune best = default_tune(static_cast<uint32_t>(p.items.size()),
-                                 static_cast<uint32_t>(p.ritems.size()));
-  if (p.items.empty()) { *out = best; return PIVCO_OK; }
+  pivco_tune best = default_tune(static_cast<uint32_t>(p.w.items.size()),
+                                 static_cast<uint32_t>(p.w.ritems.size()));
+  if (p.w.items.empty()) { *out = best; return PIVCO_OK; }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PIVCO_E_DEVICE;
   float best_ms = 1e30f;
@@ -454,7 +456,7 @@ pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_
       pivco_tune t = best;
       t.merge_variant = v;
       t.merge_grid = std::max<uint32_t>(1, std::min<uint32_t>(cus * occ * frac / 4,
-                                                              static_cast<uint32_t>(p.items.size())));
+                                                              static_cast<uint32_t>(p.w.items.size())));
       float ms_min = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
         if (hipEventRecord(e0, s) != hipSuccess) return PIVCO_E_DEVICE;

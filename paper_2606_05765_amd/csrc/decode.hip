@@ -173,7 +173,7 @@ __device__ void parse_offsets(const JobDev &J, uint32_t b, BlockHdr &h) {
   const uint64_t a0 = tab[nb + 1 + b], a1 = tab[nb + 2 + b];
   int32_t err = 0;
   if (off < tab_end || end < off || end > J.in_len || (off & 3) || end - off < kBlockFixed ||
-      end - off > 0xFFFFFFF0ull || a1 < a0 || a1 - a0 > 0xFFFFFFFFull)
+      end - off > 0xFFFFFFF0ull || a1 < a0 || a1 > J.ans_words || a1 - a0 > 0xFFFFFFFFull)
     err = PIVCO_E_CORRUPT;
   h.blk = off;
   h.end = err ? off : end;
@@ -473,12 +473,17 @@ __device__ void rans_chunk(const JobDev &J, const RansChunk &c, uint32_t *scratc
     const uint64_t m = __ballot(need);
     const uint32_t cnt = __popcll(m);
     if (pos + cnt > wend) {       // refill the window (wave-uniform branch)
-      wstart = pos;
-      wend = pos + kRansWin < c.nw ? pos + kRansWin : c.nw;
+      // a corrupt chunk can ask for more words than it holds: the window
+      // never starts past the chunk's end, and decoding stops
+      wstart = pos < c.nw ? pos : c.nw;
+      wend = c.nw - wstart > kRansWin ? wstart + kRansWin : c.nw;
       for (uint32_t i = lane; i < wend - wstart; i += kWave) win[i] = words[wstart + i];
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (pos + cnt > wend) werr = PIVCO_E_CORRUPT;
+      if (pos + cnt > wend) {
+        werr = PIVCO_E_CORRUPT;
+        break;
+      }
     }
     if (need) {
       const uint32_t idx = pos + __popcll(m & lanemask_lt);
@@ -612,8 +617,9 @@ struct NodeRec {
 template <class C>
 struct MergeSmem {
   ParsedBlock pb;          // h and t of the current block
-  BlockExt nxt;            // extent of the next block (looked ahead)
-  uint2 nxt_item;
+  BlockExt nxt;            // extent of the next item's block (looked ahead)
+  uint2 nxt_item;          // next item: record, tile
+  uint32_t nxt_job;
   uint32_t cur[256];       // bits of the node consumed by earlier tiles
   uint32_t tv[256];        // node's share of the current tile
   union {
@@ -1164,8 +1170,9 @@ __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockE
 // thread (64) from the start of a block until publish_next puts it in LDS.
 struct Lookahead {
   uint32_t item;             // next work item (n_items: none)
-  uint2 job_block;
-  BlockExt ext;
+  uint2 rt;                  // its (record, tile) pair
+  uint32_t job;
+  BlockExt ext;              // its block's extent
   const uint8_t *in;         // its stream (null: nothing to warm)
   const uint8_t *rec;        // its record
 };
@@ -1174,7 +1181,8 @@ template <class C>
 __device__ __forceinline__ void publish_next(MergeSmem<C> &sm, const Lookahead &la) {
   if (threadIdx.x != kWave) return;
   sm.item = la.item;
-  sm.nxt_item = la.job_block;
+  sm.nxt_item = la.rt;
+  sm.nxt_job = la.job;
   sm.nxt = la.ext;
   sm.warm_in = la.in;
   sm.warm_rec = la.rec;
@@ -1201,6 +1209,83 @@ __device__ void warm_next(MergeSmem<C> &sm) {
   if (acc == 0x9E3779B9u) sm.warm_sink = acc;   // keeps the reads; the value is irrelevant
 }
 
+// Selector for v_perm_b32(R, L, sel) per 4 bitmap bits: output byte k takes
+// the left sequence's next byte (values 0-3) or the right one's (values 4-7).
+template <class C>
+__device__ __forceinline__ void init_sel(MergeSmem<C> &sm) {
+  const uint32_t tid = threadIdx.x;
+  if (tid < 16) {
+    uint32_t s = 0, ones = 0;
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t bit = (tid >> k) & 1;
+      const uint32_t v = bit ? 4 + ones : k - ones;
+      s |= v << (8 * k);
+      ones += bit;
+    }
+    sm.sel[tid] = s;
+  }
+}
+
+// n copies of symbol c at out (a constant block or tile).
+template <class C>
+__device__ void fill_constant(uint8_t *out, uint32_t n, uint32_t c) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t c4 = c * 0x01010101u;
+  const uint32_t head = static_cast<uint32_t>((4 - (reinterpret_cast<uintptr_t>(out) & 3)) & 3);
+  for (uint32_t i = tid; i < n && i < head; i += C::NT) out[i] = static_cast<uint8_t>(c);
+  if (n > head) {
+    uint32_t *o4 = reinterpret_cast<uint32_t *>(out + head);
+    const uint32_t nd = (n - head) / 4;
+    for (uint32_t i = tid; i < nd; i += C::NT) o4[i] = c4;
+    for (uint32_t i = head + 4 * nd + tid; i < n; i += C::NT) out[i] = static_cast<uint8_t>(c);
+  }
+}
+
+// Rank directory over the first body_dw words of sm.body: per 256-bit
+// superblock the 1 bits before it, per 64-bit word the 1 bits of its
+// superblock before it; then every node's rank at its first bit (sm.abit).
+// Ends with a barrier.
+template <class C>
+__device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  const uint32_t nsb = (body_dw + 7) / 8 + 1;
+  const uint32_t per = (nsb + C::NT - 1) / C::NT;
+  const uint32_t s0 = tid * per;
+  uint32_t loc = 0;
+  for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
+    const uint4 a = *reinterpret_cast<const uint4 *>(&sm.body[8 * k]);
+    const uint4 c = *reinterpret_cast<const uint4 *>(&sm.body[8 * k + 4]);
+    const uint32_t w0 = __popc(a.x) + __popc(a.y), w1 = __popc(a.z) + __popc(a.w);
+    const uint32_t w2 = __popc(c.x) + __popc(c.y), w3 = __popc(c.z) + __popc(c.w);
+    sm.rel[4 * k] = 0;
+    sm.rel[4 * k + 1] = static_cast<uint8_t>(w0);
+    sm.rel[4 * k + 2] = static_cast<uint8_t>(w0 + w1);
+    sm.rel[4 * k + 3] = static_cast<uint8_t>(w0 + w1 + w2);
+    const uint32_t cnt = w0 + w1 + w2 + w3;
+    sm.sup[k] = cnt;
+    loc += cnt;
+  }
+  const uint32_t inc = wave_incl_scan(loc);
+  if (lane == kWave - 1) sm.scan_tot[wave] = inc;
+  lds_barrier();
+  uint32_t run = inc - loc;
+  for (uint32_t w = 0; w < wave; ++w) run += sm.scan_tot[w];
+  for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
+    const uint32_t c = sm.sup[k];
+    sm.sup[k] = run;
+    run += c;
+  }
+  lds_barrier();
+  for (uint32_t i = tid; i < I; i += C::NT) {
+    const uint32_t r = rank_at(sm.body, sm.sup, sm.rel, sm.abit[i]);
+    sm.r0[i] = r;
+    sm.arank[i] = r;
+  }
+  lds_barrier();
+}
+
 // Decodes the block whose record (and, when resident, body) load_block put
 // into LDS, with the whole workgroup.
 template <class C>
@@ -1208,7 +1293,6 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
                              uint64_t scratch_words, MergeSmem<C> &sm, const Lookahead &la) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
-  const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
   const bool resident = block_resident<C>(ext);
@@ -1223,15 +1307,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
   const uint32_t n = h.n;
   if (h.mode == 1) {                 // constant block
     publish_next<C>(sm, la);
-    const uint32_t c4 = h.csym * 0x01010101u;
-    const uint32_t head = static_cast<uint32_t>((4 - (reinterpret_cast<uintptr_t>(out) & 3)) & 3);
-    for (uint32_t i = tid; i < n && i < head; i += C::NT) out[i] = static_cast<uint8_t>(h.csym);
-    if (n > head) {
-      uint32_t *o4 = reinterpret_cast<uint32_t *>(out + head);
-      const uint32_t nd = (n - head) / 4;
-      for (uint32_t i = tid; i < nd; i += C::NT) o4[i] = c4;
-      for (uint32_t i = head + 4 * nd + tid; i < n; i += C::NT) out[i] = static_cast<uint8_t>(h.csym);
-    }
+    fill_constant<C>(out, n, h.csym);
     return;
   }
   const uint32_t I = h.I;
@@ -1241,18 +1317,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     for (uint32_t i = tid; i < I; i += C::NT)
       sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : lb + t.boff[i]);
   }
-  if (tid < 16) {
-    // selector for v_perm_b32(R, L, sel): output byte k takes the left
-    // sequence's next byte (values 0-3) or the right one's (values 4-7)
-    uint32_t s = 0, ones = 0;
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t bit = (tid >> k) & 1;
-      const uint32_t v = bit ? 4 + ones : k - ones;
-      s |= v << (8 * k);
-      ones += bit;
-    }
-    sm.sel[tid] = s;
-  }
+  init_sel<C>(sm);
   for (uint32_t i = tid; i < I; i += C::NT) {
     sm.cur[i] = 0;
     sm.tv[i] = 0;
@@ -1263,45 +1328,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
   }
   lds_barrier();
-  if (resident) {
-    // rank directory: per 256-bit superblock the 1 bits before it, per
-    // 64-bit word the 1 bits of its superblock before it
-    const uint32_t body_dw = static_cast<uint32_t>(span >> 2) + h.ans_words;
-    const uint32_t nsb = (body_dw + 7) / 8 + 1;
-    const uint32_t per = (nsb + C::NT - 1) / C::NT;
-    const uint32_t s0 = tid * per;
-    uint32_t loc = 0;
-    for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
-      const uint4 a = *reinterpret_cast<const uint4 *>(&sm.body[8 * k]);
-      const uint4 c = *reinterpret_cast<const uint4 *>(&sm.body[8 * k + 4]);
-      const uint32_t w0 = __popc(a.x) + __popc(a.y), w1 = __popc(a.z) + __popc(a.w);
-      const uint32_t w2 = __popc(c.x) + __popc(c.y), w3 = __popc(c.z) + __popc(c.w);
-      sm.rel[4 * k] = 0;
-      sm.rel[4 * k + 1] = static_cast<uint8_t>(w0);
-      sm.rel[4 * k + 2] = static_cast<uint8_t>(w0 + w1);
-      sm.rel[4 * k + 3] = static_cast<uint8_t>(w0 + w1 + w2);
-      const uint32_t cnt = w0 + w1 + w2 + w3;
-      sm.sup[k] = cnt;
-      loc += cnt;
-    }
-    const uint32_t inc = wave_incl_scan(loc);
-    if (lane == kWave - 1) sm.scan_tot[wave] = inc;
-    lds_barrier();
-    uint32_t run = inc - loc;
-    for (int w = 0; w < wave; ++w) run += sm.scan_tot[w];
-    for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
-      const uint32_t c = sm.sup[k];
-      sm.sup[k] = run;
-      run += c;
-    }
-    lds_barrier();
-    for (uint32_t i = tid; i < I; i += C::NT) {
-      const uint32_t r = rank_at(sm.body, sm.sup, sm.rel, sm.abit[i]);
-      sm.r0[i] = r;
-      sm.arank[i] = r;
-    }
-  }
-  lds_barrier();
+  if (resident) build_directory<C>(sm, static_cast<uint32_t>(span >> 2) + h.ans_words, I);
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
   bool bad = false;
@@ -1351,11 +1378,146 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
   if (tid == 0 && h.err) set_err(J.status, h.err);
 }
 
+// A tile of a split block: the block's record and the tile's two boundary
+// rows (each node's position at the tile's start and end), then every node's
+// share of the tile -- the covering 16-byte chunks of its bitmap, from the
+// stream or from the rANS scratch -- copied into LDS node after node.  Ends
+// with a barrier; sm.cur and sm.tv hold the shares, sm.abit the LDS bit
+// address of each share's first bit, sm.stage_top the staged words.
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *items,
-                                                  const ParsedBlock *recs, uint32_t n_items,
-                                                  Counters *ctr, const uint32_t *scratch,
-                                                  uint64_t scratch_words, int32_t single) {
+__device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *tab, uint32_t k,
+                          const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
+  const uint8_t *rb = reinterpret_cast<const uint8_t *>(rec);
+  uint32_t *pbw = reinterpret_cast<uint32_t *>(&sm.pb);
+  for (uint32_t base = kWave * wave; base < kRec16; base += kWave * C::NW)
+    if (base + lane < kRec16)
+      __builtin_amdgcn_global_load_lds(rb + 16ull * (base + lane), &pbw[4 * base], 16, 0, 0);
+  for (uint32_t v = tid; v < kTabCols; v += C::NT) {
+    const uint32_t a = tab[static_cast<uint64_t>(k) * kTabCols + v].x;
+    const uint32_t b = tab[static_cast<uint64_t>(k + 1) * kTabCols + v].x;
+    sm.cur[v] = a;
+    sm.tv[v] = b > a ? b - a : 0u;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  BlockHdr &h = sm.pb.h;
+  NodeTab &t = sm.pb.t;
+  if (h.err || h.mode == 1) return;     // decode_tile reports or fills
+  const uint32_t I = h.I;
+  // chunk counts and their exclusive prefix over the nodes (block scan)
+  uint32_t nch = 0;
+  uint64_t a16 = 0, gb = 0;
+  if (static_cast<uint32_t>(tid) < I && sm.tv[tid]) {
+    gb = (t.kind[tid] ? 32ull * (h.ans_word0 + t.boff[tid]) : 8ull * (h.blk + t.boff[tid])) + sm.cur[tid];
+    a16 = (gb >> 3) & ~15ull;
+    const uint64_t b16 = (((gb + sm.tv[tid] + 7) >> 3) + 15) & ~15ull;
+    nch = static_cast<uint32_t>((b16 - a16) >> 4);
+  }
+  const uint32_t inc = tid < 256 ? wave_incl_scan(nch) : 0u;
+  if (tid < 256 && lane == kWave - 1) sm.scan_tot[wave] = inc;
+  lds_barrier();
+  if (static_cast<uint32_t>(tid) < I) {
+    uint32_t off = inc - nch;
+    for (int w = 0; w < wave; ++w) off += sm.scan_tot[w];
+    sm.stg[tid] = off;                  // first staged chunk of the node
+    sm.ones[tid] = nch;                 // its chunks
+  }
+  if (tid == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < 4; ++w) tot += sm.scan_tot[w];
+    sm.stage_top = tot;
+  }
+  lds_barrier();
+  const uint32_t total = sm.stage_top;
+  if (16ull * total + 64 > static_cast<uint64_t>(C::BODY)) {   // cannot happen for 12-bit codes
+    if (tid == 0) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_UNSUPPORTED));
+    lds_barrier();
+    return;
+  }
+  // copy: one wave per node, 64 chunks per step, direct to LDS where the
+  // source chunk lies inside its buffer, guarded byte loads otherwise
+  for (uint32_t v = wave; v < I; v += C::NW) {
+    const uint32_t cnt = sm.ones[v];
+    if (!cnt) continue;
+    const uint32_t off = sm.stg[v];
+    const uint64_t g = (t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v])) + sm.cur[v];
+    const uint64_t s16 = (g >> 3) & ~15ull;
+    const uint8_t *src = t.kind[v] ? reinterpret_cast<const uint8_t *>(scratch) : J.in;
+    const uint64_t lim = t.kind[v] ? 4ull * scratch_words : J.in_len;
+    for (uint32_t c0 = 0; c0 < cnt; c0 += kWave) {
+      const uint32_t c = c0 + lane;
+      const uint64_t q = s16 + 16ull * c;
+      if (c < cnt && q + 16 <= lim) {
+        __builtin_amdgcn_global_load_lds(src + q, &sm.body[4 * (off + c0)], 16, 0, 0);
+      } else if (c < cnt) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          uint32_t x = 0;
+          for (int by = 0; by < 4; ++by) {
+            const uint64_t a = q + 4 * e + by;
+            if (a < lim) x |= static_cast<uint32_t>(src[a]) << (8 * by);
+          }
+          w[e] = x;
+        }
+        *reinterpret_cast<uint4 *>(&sm.body[4 * (off + c)]) = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  }
+  for (uint32_t i = 4 * total + tid; i < 4 * total + 16; i += C::NT) sm.body[i] = 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // LDS bit address of each share's first bit (abit shares its words with
+  // tone, not with stg or ones)
+  if (static_cast<uint32_t>(tid) < I)
+    sm.abit[tid] = sm.tv[tid] ? 128u * sm.stg[tid] + static_cast<uint32_t>(gb - 8 * a16) : 0u;
+  lds_barrier();
+}
+
+// Decodes the tile load_tile put into LDS: its shares are known, so there is
+// no count phase and no end-of-block check (the boundary kernel validated the
+// block's bitmaps).
+template <class C>
+__device__ void decode_tile(const JobDev &J, uint32_t k, MergeSmem<C> &sm, const Lookahead &la) {
+  const int tid = threadIdx.x;
+  BlockHdr &h = sm.pb.h;
+  uint8_t *out = J.out + h.out_off + static_cast<uint64_t>(k) * kTileOut;
+  const uint32_t n = h.n;
+  const uint32_t troot = n - k * kTileOut < kTileOut ? n - k * kTileOut : kTileOut;
+  if (h.err) {
+    publish_next<C>(sm, la);
+    if (tid == 0) set_err(J.status, h.err);
+    return;
+  }
+  if (h.mode == 1) {
+    publish_next<C>(sm, la);
+    fill_constant<C>(out, troot, h.csym);
+    return;
+  }
+  const uint32_t I = h.I;
+  init_sel<C>(sm);
+  build_directory<C>(sm, 4 * sm.stage_top, I);
+  for (uint32_t i = tid; i < I; i += C::NT) sm.cur[i] = 0;
+  if (tid == 0) sm.act_run = 0;
+  publish_next<C>(sm, la);
+  lds_barrier();
+  tile_lists<C>(sm);
+  merge_tile<C, true>(sm, static_cast<int>(h.maxlen), out);
+}
+
+// Persistent merge: a workgroup takes items from the queue (largest first) --
+// whole blocks, or tiles of split blocks -- looking one item ahead.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *blocks,
+                                                  const uint2 *items, const ParsedBlock *recs,
+                                                  const TiledBlock *tiled, const uint2 *tab,
+                                                  uint32_t n_items, Counters *ctr,
+                                                  const uint32_t *scratch, uint64_t scratch_words,
+                                                  int32_t single) {
   __shared__ MergeSmem<C> sm;
   const int tid = threadIdx.x;
   for (int i = tid; i < 256; i += C::NT) sm.leafrow[i] = static_cast<uint32_t>(i) * 0x01010101u;
@@ -1363,34 +1525,210 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
     const uint32_t it = single >= 0 ? static_cast<uint32_t>(single) : atomicAdd(&ctr->merge_next, 1u);
     sm.item = it;
     if (it < n_items) {
-      sm.nxt_item = items[it];
-      sm.nxt = load_ext(recs + it);
+      const uint2 rt = items[it];
+      sm.nxt_item = rt;
+      sm.nxt_job = blocks[rt.x].x;
+      sm.nxt = load_ext(recs + rt.x);
     }
   }
   lds_barrier();
   for (;;) {
     const uint32_t it = sm.item;
     if (it >= n_items) break;
-    const uint2 item = sm.nxt_item;
+    const uint2 rt = sm.nxt_item;
+    const uint32_t job = sm.nxt_job;
     const BlockExt ext = sm.nxt;
     lds_barrier();                   // the look-ahead slots are rewritten below
     // look ahead (thread 64, in a wave that is idle while wave 0 computes
     // the first tile's shares): take the next item now; its extent and
-    // stream are read while this block is decoded, and published to LDS at
-    // the first tile's count (or when the block ends early)
-    Lookahead la{n_items, make_uint2(0, 0), BlockExt{}, nullptr, nullptr};
+    // stream are read while this item is decoded, and published to LDS
+    // before the merge (or when the item ends early)
+    Lookahead la{n_items, make_uint2(0, 0), 0u, BlockExt{}, nullptr, nullptr};
     if (tid == kWave && single < 0) la.item = atomicAdd(&ctr->merge_next, 1u);
-    const JobDev &J = jobs[item.x];
-    load_block<C>(J, recs + it, ext, scratch, scratch_words, sm);
-    if (tid == kWave && la.item < n_items) {
-      la.job_block = items[la.item];
-      la.ext = load_ext(recs + la.item);
-      la.in = la.ext.err ? nullptr : jobs[la.job_block.x].in;
-      la.rec = reinterpret_cast<const uint8_t *>(recs + la.item);
+    const JobDev &J = jobs[job];
+    const bool whole = rt.y == kWholeBlock;
+    if (whole) {
+      load_block<C>(J, recs + rt.x, ext, scratch, scratch_words, sm);
+    } else {
+      const TiledBlock tb = tiled[rt.y >> 8];
+      load_tile<C>(J, recs + rt.x, tab + tb.tab, rt.y & 255, scratch, scratch_words, sm);
     }
-    decode_block<C>(J, ext, scratch, scratch_words, sm, la);
+    if (tid == kWave && la.item < n_items) {
+      la.rt = items[la.item];
+      la.job = blocks[la.rt.x].x;
+      la.ext = load_ext(recs + la.rt.x);
+      la.in = la.ext.err || la.rt.y != kWholeBlock ? nullptr : jobs[la.job].in;
+      la.rec = reinterpret_cast<const uint8_t *>(recs + la.rt.x);
+    }
+    if (whole) decode_block<C>(J, ext, scratch, scratch_words, sm, la);
+    else decode_tile<C>(J, rt.y & 255, sm, la);
     lds_barrier();
   }
+}
+
+// Bits [b0, b1) of a 32-bit word whose first bit is bit wb.
+__device__ __forceinline__ uint32_t range_mask(uint64_t wb, uint64_t b0, uint64_t b1) {
+  const uint64_t lo = b0 > wb ? b0 - wb : 0;
+  const uint64_t hi = b1 >= wb + 32 ? 32 : (b1 > wb ? b1 - wb : 0);
+  if (hi <= lo) return 0u;
+  const uint32_t mh = hi >= 32 ? 0xFFFFFFFFu : (1u << hi) - 1;
+  return mh & ~((1u << lo) - 1);
+}
+
+// 1 bits among bits [b0, b1) of the little-endian bit string at p (16-byte
+// aligned, nbytes readable): the covering 16-byte chunks, masked.
+__device__ uint32_t popc_range(const uint8_t *p, uint64_t nbytes, uint64_t b0, uint64_t b1) {
+  if (b1 <= b0) return 0u;
+  const uint64_t q0 = (b0 >> 3) & ~15ull, q1 = ((b1 + 127) >> 7) << 4;
+  uint32_t c = 0;
+#pragma unroll 4
+  for (uint64_t q = q0; q < q1; q += 16) {
+    uint32_t w[4];
+    if (q + 16 <= nbytes) {
+      const uint4 x = *reinterpret_cast<const uint4 *>(p + q);
+      w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t x = 0;
+        for (uint32_t by = 0; by < 4; ++by)
+          if (q + 4 * e + by < nbytes) x |= static_cast<uint32_t>(p[q + 4 * e + by]) << (8 * by);
+        w[e] = x;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) c += __popc(w[e] & range_mask(8 * q + 32 * e, b0, b1));
+  }
+  return c;
+}
+
+// Boundaries of a split block (one workgroup per block).  First a rank
+// directory over all of the block's bitmaps: the 1 bits of every G-bit
+// superblock of every node, exclusive-scanned across the block, so that a
+// node's 1 bits before any position are two directory entries and one
+// popcount of less than G bits.  Then top-down by level, every node's
+// position at each tile boundary k (symbols of the block before the
+// boundary that pass the node) gives its rank there, and the rank its
+// children's positions -- all (node, boundary) pairs of a level at once.
+// The root's positions are k * kTileOut.  Table row k, column v holds
+// (position, rank).  A node whose bitmap holds a different number of 1 bits
+// than its header count marks the job corrupt; positions are clamped to the
+// nodes' sizes so that the tiles never read outside their bitmaps.
+constexpr int kTilesNT = 1024;
+constexpr uint32_t kTilesDir = 16384;     // directory entries (LDS)
+
+__global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const uint2 *blocks,
+                                                   const TiledBlock *tiled, uint32_t n_tiled,
+                                                   const ParsedBlock *recs, const uint32_t *scratch,
+                                                   uint64_t scratch_words, uint2 *tab) {
+  __shared__ ParsedBlock pb;
+  __shared__ uint32_t dir[kTilesDir + 1];
+  __shared__ uint32_t sbase[257];
+  __shared__ uint32_t tot[kTilesNT / kWave];
+  __shared__ int32_t err;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  constexpr uint32_t NW = kTilesNT / kWave;
+  const TiledBlock tb = tiled[blockIdx.x];
+  const JobDev &J = jobs[blocks[tb.rec].x];
+  {
+    const uint4 *src = reinterpret_cast<const uint4 *>(recs + tb.rec);
+    uint4 *dst = reinterpret_cast<uint4 *>(&pb);
+    for (uint32_t i = tid; i < sizeof(ParsedBlock) / 16; i += kTilesNT) dst[i] = src[i];
+  }
+  if (tid == 0) err = 0;
+  __syncthreads();
+  const BlockHdr &h = pb.h;
+  const NodeTab &t = pb.t;
+  if (h.err || h.mode == 1) return;                // the tiles report or fill
+  const uint32_t K = tb.ntiles, n = h.n, I = h.I;
+  uint2 *T = tab + tb.tab;
+  const uint8_t *scr = reinterpret_cast<const uint8_t *>(scratch);
+  const uint64_t scr_bytes = 4ull * scratch_words;
+  // superblock size: the smallest power of two (at least 2048 bits) whose
+  // directory fits; sum over nodes of ceil(n_v / G) <= bits / G + I
+  uint64_t bits = 0;
+  for (uint32_t d = 0; d < h.maxlen; ++d) bits += h.lvl_total[d];
+  uint32_t G = 2048;
+  while (bits / G + I + 1 > kTilesDir) G <<= 1;
+  // directory layout: node v owns entries [sbase[v], sbase[v + 1])
+  {
+    const uint32_t ns = tid < I ? (t.nv[tid] + G - 1) / G : 0u;
+    const uint32_t inc = wave_incl_scan(ns);
+    if (lane == kWave - 1) tot[wave] = inc;
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t ex = inc - ns;
+      for (uint32_t w = 0; w < wave; ++w) ex += tot[w];
+      sbase[tid] = ex;
+      if (tid == 255) sbase[256] = ex + ns;
+    }
+  }
+  __syncthreads();
+  const uint32_t S = sbase[256];
+  for (uint32_t f = tid; f < S; f += kTilesNT) {
+    uint32_t lo = 0, hi = I;                       // last v with sbase[v] <= f
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (sbase[mid] <= f) lo = mid; else hi = mid;
+    }
+    const uint32_t v = lo, j = f - sbase[v];
+    const uint64_t b0 = static_cast<uint64_t>(j) * G;
+    const uint64_t b1 = b0 + G < t.nv[v] ? b0 + G : t.nv[v];
+    dir[f] = t.kind[v] ? popc_range(scr, scr_bytes, 32ull * (h.ans_word0 + t.boff[v]) + b0,
+                                    32ull * (h.ans_word0 + t.boff[v]) + b1)
+                       : popc_range(J.in, J.in_len, 8ull * (h.blk + t.boff[v]) + b0,
+                                    8ull * (h.blk + t.boff[v]) + b1);
+  }
+  for (uint32_t k = tid; k <= K; k += kTilesNT) {
+    const uint64_t s = static_cast<uint64_t>(k) * kTileOut;
+    T[static_cast<uint64_t>(k) * kTabCols] = make_uint2(s < n ? static_cast<uint32_t>(s) : n, 0u);
+  }
+  __syncthreads();
+  // exclusive scan of the directory (contiguous runs per thread), dir[S] = total
+  {
+    const uint32_t per = (S + kTilesNT - 1) / kTilesNT;
+    const uint32_t f0 = tid * per, f1 = f0 + per < S ? f0 + per : S;
+    uint32_t loc = 0;
+    for (uint32_t f = f0; f < f1; ++f) loc += dir[f];
+    const uint32_t inc = wave_incl_scan(loc);
+    if (lane == kWave - 1) tot[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - loc;
+    for (uint32_t w = 0; w < wave; ++w) run += tot[w];
+    for (uint32_t f = f0; f < f1; ++f) {
+      const uint32_t c = dir[f];
+      dir[f] = run;
+      run += c;
+    }
+    if (tid == kTilesNT - 1) {
+      uint32_t all = 0;
+      for (uint32_t w = 0; w < NW; ++w) all += tot[w];
+      dir[S] = all;
+    }
+  }
+  __syncthreads();
+  for (uint32_t d = 0; d < h.maxlen; ++d) {
+    const uint32_t v0 = h.lvl[d], m = h.lvl[d + 1] - v0;
+    for (uint32_t p = tid; p < m * (K + 1); p += kTilesNT) {
+      const uint32_t v = v0 + p / (K + 1), k = p % (K + 1);
+      uint2 *row = T + static_cast<uint64_t>(k) * kTabCols;
+      const uint32_t nv = t.nv[v];
+      const uint32_t s = row[v].x < nv ? row[v].x : nv;
+      const uint32_t j = s / G;
+      const uint64_t base = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
+      const uint32_t r = dir[sbase[v] + j] - dir[sbase[v]] +
+                         (t.kind[v] ? popc_range(scr, scr_bytes, base + static_cast<uint64_t>(j) * G, base + s)
+                                    : popc_range(J.in, J.in_len, base + static_cast<uint64_t>(j) * G, base + s));
+      row[v].y = r;
+      const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
+      const uint32_t c0 = cc & 0xFFFF, c1 = cc >> 16;
+      if (!(c0 & 0x8000)) row[c0].x = s - r < t.nv[c0] ? s - r : t.nv[c0];
+      if (!(c1 & 0x8000)) row[c1].x = r < t.nv[c1] ? r : t.nv[c1];
+      if (k == K && (r != t.nr[v] || s != nv)) atomicCAS(&err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && err) set_err(J.status, err);
 }
 
 // Plan: one wave per work item parses and validates the block's header from
@@ -1468,11 +1806,13 @@ struct MergeVariant {
 };
 
 template <class C>
-static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
-                                 const ParsedBlock *recs, uint32_t n_items, Counters *ctr,
-                                 const uint32_t *scratch, uint64_t scratch_words, int32_t single) {
-  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, items, recs, n_items, ctr, scratch,
-                     scratch_words, single);
+static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs, const uint2 *blocks,
+                                 const uint2 *items, const ParsedBlock *recs,
+                                 const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
+                                 Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
+                                 int32_t single) {
+  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, blocks, items, recs, tiled, tab,
+                     n_items, ctr, scratch, scratch_words, single);
   return hipGetLastError();
 }
 
@@ -1508,21 +1848,32 @@ int merge_variant_occupancy(uint32_t v) {
 }
 
 hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *items, const void *recs, uint32_t n_items, Counters *ctr,
-                        const uint32_t *scratch, uint64_t scratch_words, int32_t single) {
+                        const uint2 *blocks, const uint2 *items, const void *recs,
+                        const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
+                        Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
+                        int32_t single) {
   const ParsedBlock *r = static_cast<const ParsedBlock *>(recs);
   switch (variant) {
-    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, items, r, n_items, ctr, scratch, scratch_words, single);
-    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, items, r, n_items, ctr, scratch, scratch_words, single);
-    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, r, n_items, ctr, scratch, scratch_words, single);
+    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, blocks, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, blocks, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, blocks, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
   }
 }
 
-hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *items, uint32_t n_items,
+hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, uint32_t n_blocks,
                        void *recs) {
-  if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan, dim3((n_items + kPlanWaves - 1) / kPlanWaves), dim3(kWave * kPlanWaves), 0,
-                     s, jobs, items, n_items, static_cast<ParsedBlock *>(recs));
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan, dim3((n_blocks + kPlanWaves - 1) / kPlanWaves), dim3(kWave * kPlanWaves), 0,
+                     s, jobs, blocks, n_blocks, static_cast<ParsedBlock *>(recs));
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const uint2 *blocks,
+                        const TiledBlock *tiled, uint32_t n_tiled, const void *recs,
+                        const uint32_t *scratch, uint64_t scratch_words, uint2 *tab) {
+  if (n_tiled == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tiles, dim3(n_tiled), dim3(kTilesNT), 0, s, jobs, blocks, tiled, n_tiled,
+                     static_cast<const ParsedBlock *>(recs), scratch, scratch_words, tab);
   return hipGetLastError();
 }
 

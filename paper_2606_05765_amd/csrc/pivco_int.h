@@ -4,6 +4,10 @@
 #include <stdint.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <utility>
+#include <vector>
+
 #include "../../include/pivco.h"
 
 namespace pivco {
@@ -19,7 +23,32 @@ constexpr uint32_t kRansM = 4096;          // 12-bit probabilities
 constexpr uint32_t kRansL = 65536;         // lower state bound, 16-bit words
 constexpr uint32_t kRansLanes = 32;
 constexpr uint32_t kChunkHdr = 4 + 4 * 32; // n_words u32 + 32 lane states
-constexpr uint32_t kParsedBlockBytes = 5632; // per-item record written by the plan kernel
+constexpr uint32_t kParsedBlockBytes = 5632; // per-block record written by the plan kernel
+
+// Blocks of more than kSplitMin symbols (and at most kMaxTiles tiles) are
+// decoded as independent tiles of kTileOut symbols, each its own work item;
+// the others as one work item each.  A split block's boundary table holds,
+// per tile boundary k = 0..ntiles, one row of kTabCols (position, rank) pairs:
+// the symbols of the block before boundary k that pass node v, and the 1
+// bits among them.
+constexpr uint32_t kTileOut = 32768;
+constexpr uint32_t kSplitMin = 65536;
+constexpr uint32_t kMaxTiles = 128;
+constexpr uint32_t kTabCols = 256;
+constexpr uint32_t kWholeBlock = 0xFFFFFFFFu;
+static_assert(kMaxTiles <= 256, "tile index fits the low 8 bits of an item");
+
+__host__ __device__ inline uint32_t tiles_of_block(uint64_t n) {
+  const uint64_t k = (n + kTileOut - 1) / kTileOut;
+  return n > kSplitMin && k <= kMaxTiles ? static_cast<uint32_t>(k) : 0u;
+}
+
+// A split block: its record, tile count, and first boundary-table entry.
+struct TiledBlock {
+  uint32_t rec;
+  uint32_t ntiles;
+  uint64_t tab;
+};
 
 // One job as the kernels see it (80 bytes, read through the scalar cache).
 struct JobDev {
@@ -34,7 +63,7 @@ struct JobDev {
   uint32_t max_len;
   uint32_t chunk_log2;
   int32_t *status;
-  uint64_t pad;
+  uint64_t ans_words;      // scratch words of this job (its stream header's total)
 };
 static_assert(sizeof(JobDev) == 80, "JobDev layout");
 
@@ -47,17 +76,88 @@ struct Counters {
 
 __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
+// Work lists of one batched decode (host): blocks (job, block) for the plan
+// and rANS kernels, split blocks for the boundary kernel, and merge items
+// (record = index into blocks, kWholeBlock or split-block index << 8 | tile)
+// largest first.
+struct WorkLists {
+  std::vector<uint2> blocks, ritems, items;
+  std::vector<TiledBlock> tiled;
+  uint64_t tab_entries = 0;
+  std::vector<std::pair<uint64_t, uint2>> sized;   // (symbols, item) before ordering
+
+  void clear() {
+    blocks.clear(); ritems.clear(); items.clear(); tiled.clear(); sized.clear();
+    tab_entries = 0;
+  }
+  // Adds the blocks of job j (n_total symbols in blocks of block_size).
+  void add_job(uint32_t j, uint64_t n_total, uint32_t n_blocks, uint32_t block_size, bool ans) {
+    for (uint32_t b = 0; b < n_blocks; ++b) {
+      const uint64_t start = static_cast<uint64_t>(b) * block_size;
+      const uint64_t sz = std::min<uint64_t>(block_size, n_total - start);
+      const uint32_t rec = static_cast<uint32_t>(blocks.size());
+      blocks.push_back(make_uint2(j, b));
+      if (ans) ritems.push_back(make_uint2(j, b));
+      const uint32_t nt = tiles_of_block(sz);
+      if (nt == 0) {
+        sized.push_back({sz, make_uint2(rec, kWholeBlock)});
+      } else {
+        tiled.push_back(TiledBlock{rec, nt, tab_entries});
+        tab_entries += static_cast<uint64_t>(nt + 1) * kTabCols;
+        const uint32_t ti = static_cast<uint32_t>(tiled.size() - 1);
+        for (uint32_t k = 0; k < nt; ++k)   // item.y = split-block index << 8 | tile
+          sized.push_back({std::min<uint64_t>(kTileOut, sz - static_cast<uint64_t>(k) * kTileOut),
+                           make_uint2(rec, (ti << 8) | k)});
+      }
+    }
+  }
+  // What one job adds to the lists (for admission checks).
+  struct Need {
+    uint64_t items = 0, tiles = 0, split = 0, tab_entries = 0;
+  };
+  static Need need_of(uint64_t n_total, uint32_t n_blocks, uint32_t block_size) {
+    Need n;
+    for (uint32_t b = 0; b < n_blocks; ++b) {
+      const uint64_t sz = std::min<uint64_t>(block_size, n_total - static_cast<uint64_t>(b) * block_size);
+      const uint32_t nt = tiles_of_block(sz);
+      n.items += nt ? nt : 1;
+      if (nt) {
+        n.tiles += nt;
+        n.split += 1;
+        n.tab_entries += static_cast<uint64_t>(nt + 1) * kTabCols;
+      }
+    }
+    return n;
+  }
+  // Orders the merge items by decreasing size (longest first).
+  void finish() {
+    std::stable_sort(sized.begin(), sized.end(),
+                     [](const std::pair<uint64_t, uint2> &a, const std::pair<uint64_t, uint2> &b) {
+                       return a.first > b.first;
+                     });
+    items.clear();
+    items.reserve(sized.size());
+    for (auto &x : sized) items.push_back(x.second);
+  }
+};
+
 // Decode launchers (decode.hip), used by the batch planner and the server.
-// A launch is k_init, k_plan (records: kParsedBlockBytes per item), k_rans
-// when some block has rANS nodes, then k_merge.
+// A launch is k_init, k_plan over the blocks (records: kParsedBlockBytes per
+// block), k_rans when some block has rANS nodes, k_tiles over the split
+// blocks (boundary tables), then k_merge over the items.
 uint32_t merge_variant_count();
 const char *merge_variant_name(uint32_t v);
 int merge_variant_occupancy(uint32_t v);
-hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *items, uint32_t n_items,
+hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, uint32_t n_blocks,
                        void *recs);
+hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const uint2 *blocks,
+                        const TiledBlock *tiled, uint32_t n_tiled, const void *recs,
+                        const uint32_t *scratch, uint64_t scratch_words, uint2 *tab);
 hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *items, const void *recs, uint32_t n_items, Counters *ctr,
-                        const uint32_t *scratch, uint64_t scratch_words, int32_t single);
+                        const uint2 *blocks, const uint2 *items, const void *recs,
+                        const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
+                        Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
+                        int32_t single);
 hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
                        uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single);
 int rans_occupancy();

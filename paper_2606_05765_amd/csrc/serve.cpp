@@ -38,6 +38,7 @@ struct Registered {
   uint64_t in_len;
   uint64_t n_total, ans_words;
   uint32_t n_blocks, block_size, max_len, chunk_log2;
+  WorkLists::Need need;           // merge items, tiles and boundary-table entries
 };
 
 // First-fit allocator over [0, size) with coalescing on free.
@@ -103,11 +104,11 @@ struct pivco_server {
   std::vector<Slot> slots;
   uint64_t ws_bytes_per_slot = 0, pinned_bytes = 0;
   // workspace layout inside a slot
-  uint64_t off_ctr = 0, off_jobs = 0, off_items = 0, off_ritems = 0, off_status0 = 0,
-           off_status = 0, off_recs = 0, off_scratch = 0;
+  uint64_t off_ctr = 0, off_jobs = 0, off_status = 0, off_recs = 0, off_tab = 0, off_scratch = 0;
   uint64_t off_pstatus = 0;
-  uint32_t max_items = 0;
-  uint64_t max_scratch_words = 0;
+  uint32_t max_blocks = 0;
+  uint64_t max_tiles = 0, max_split = 0, max_tab = 0, max_scratch_words = 0;
+  WorkLists w;                    // reused by every admission round
 };
 
 extern "C" {
@@ -117,18 +118,28 @@ pivco_status pivco_server_create(const pivco_server_opts *o, pivco_server **out)
     return PIVCO_E_ARG;
   pivco_server *sv = new pivco_server();
   sv->opts = *o;
-  sv->max_items = o->max_blocks;
+  sv->max_blocks = o->max_blocks;
   sv->max_scratch_words = o->max_scratch_words;
+  // a split block has at least three tiles, so max_tiles / 3 split blocks
+  sv->max_tiles = o->max_tiles ? o->max_tiles : 8192;
+  sv->max_split = sv->max_tiles / 3 + 1;
+  sv->max_tab = (sv->max_tiles + sv->max_split) * kTabCols;
+  const uint64_t max_items = o->max_blocks + sv->max_tiles;
   uint64_t x = 0;
   sv->off_ctr = x; x += 256;
   sv->off_jobs = x; x = align_up(x + sizeof(JobDev) * o->max_batch, 256);
-  sv->off_items = x; x = align_up(x + 8ull * o->max_blocks, 256);
-  sv->off_ritems = x; x = align_up(x + 8ull * o->max_blocks, 256);
-  sv->off_status0 = x; x = align_up(x + 4ull * o->max_batch, 256);
-  const uint64_t pinned = x;          // job table .. status0 staged from pinned memory
+  // blocks, items, rANS blocks, split blocks and initial statuses follow the
+  // job table, packed per batch (capacity for the largest batch)
+  x = align_up(x + 8ull * o->max_blocks + 64, 64);
+  x = align_up(x + 8ull * max_items + 64, 64);
+  x = align_up(x + 8ull * o->max_blocks + 64, 64);
+  x = align_up(x + sizeof(TiledBlock) * sv->max_split + 64, 64);
+  x = align_up(x + 4ull * o->max_batch + 64, 256);
+  const uint64_t pinned = x;          // counters .. statuses staged from pinned memory
   sv->off_status = x; x = align_up(x + 4ull * o->max_batch, 256);
   sv->off_pstatus = pinned;           // statuses copied back into pinned memory
   sv->off_recs = x; x = align_up(x + static_cast<uint64_t>(kParsedBlockBytes) * o->max_blocks, 256);
+  sv->off_tab = x; x = align_up(x + 8ull * sv->max_tab, 256);
   sv->off_scratch = x; x = align_up(x + 4ull * o->max_scratch_words + 64, 256);
   sv->ws_bytes_per_slot = x;
   sv->pinned_bytes = pinned;
@@ -173,7 +184,9 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   pivco_status st = pivco_stream_info(h, kHeaderBytes, &n_total, &nb, &bs, &ans);
   if (st) return st;
   if (len < kHeaderBytes + 16ull * (nb + 1ull)) return PIVCO_E_CORRUPT;
-  if (nb > sv->max_items || ans > sv->max_scratch_words) return PIVCO_E_UNSUPPORTED;
+  if (nb > sv->max_blocks || ans > sv->max_scratch_words) return PIVCO_E_UNSUPPORTED;
+  const WorkLists::Need need = WorkLists::need_of(n_total, nb, bs);
+  if (need.tiles > sv->max_tiles) return PIVCO_E_UNSUPPORTED;
   Registered r;
   r.d_in = static_cast<const uint8_t *>(d_stream);
   r.in_len = len;
@@ -183,6 +196,7 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   r.block_size = bs;
   r.max_len = h[24];
   r.chunk_log2 = h[25];
+  r.need = need;
   *id = static_cast<uint32_t>(sv->reg.size());
   sv->reg.push_back(r);
   return PIVCO_OK;
@@ -249,7 +263,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
     for (auto &s : sv->slots) {
       if (s.busy || pending.empty()) continue;
       std::vector<uint32_t> batch;
-      uint64_t items = 0, scratch = 0;
+      uint64_t blocks = 0, tiles = 0, split = 0, tab = 0, scratch = 0;
       while (!pending.empty() && batch.size() < sv->opts.max_batch) {
         const uint32_t r = pending.front();
         const Registered &g = sv->reg[reqs[r].id];
@@ -262,7 +276,8 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
           progressed = true;
           continue;
         }
-        if (items + g.n_blocks > sv->max_items ||
+        if (blocks + g.n_blocks > sv->max_blocks || tiles + g.need.tiles > sv->max_tiles ||
+            split + g.need.split > sv->max_split || tab + g.need.tab_entries > sv->max_tab ||
             align_up(scratch + g.ans_words, 4) > sv->max_scratch_words)
           break;
         uint64_t off = 0;
@@ -270,7 +285,10 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         out_off[r] = off;
         res[r].d_out = pool_base + off;
         res[r].t_admit = now_s();
-        items += g.n_blocks;
+        blocks += g.n_blocks;
+        tiles += g.need.tiles;
+        split += g.need.split;
+        tab += g.need.tab_entries;
         scratch = align_up(scratch + g.ans_words, 4);
         batch.push_back(r);
         pending.pop_front();
@@ -279,11 +297,8 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
       peak = std::max(peak, pool.used());
       // plan the batch in pinned memory, then upload and launch
       JobDev *jobs = reinterpret_cast<JobDev *>(s.pinned + sv->off_jobs);
-      uint2 *it = reinterpret_cast<uint2 *>(s.pinned + sv->off_items);
-      uint2 *rit = reinterpret_cast<uint2 *>(s.pinned + sv->off_ritems);
-      int32_t *st0 = reinterpret_cast<int32_t *>(s.pinned + sv->off_status0);
-      std::vector<std::pair<uint64_t, uint2>> sized;
-      uint32_t nr = 0;
+      WorkLists &w = sv->w;
+      w.clear();
       uint64_t sw = 0;
       for (uint32_t k = 0; k < batch.size(); ++k) {
         const Registered &g = sv->reg[reqs[batch[k]].id];
@@ -294,46 +309,58 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         d.out_cap = g.n_total;
         d.n_total = g.n_total;
         d.scratch_base = sw;
+        d.ans_words = g.ans_words;
         d.n_blocks = g.n_blocks;
         d.block_size = g.block_size;
         d.max_len = g.max_len;
         d.chunk_log2 = g.chunk_log2;
         d.status = reinterpret_cast<int32_t *>(s.ws + sv->off_status) + k;
         jobs[k] = d;
-        st0[k] = PIVCO_OK;
         sw = align_up(sw + g.ans_words, 4);
-        for (uint32_t b = 0; b < g.n_blocks; ++b) {
-          const uint64_t start = static_cast<uint64_t>(b) * g.block_size;
-          sized.push_back({std::min<uint64_t>(g.block_size, g.n_total - start), make_uint2(k, b)});
-          if (g.ans_words) rit[nr++] = make_uint2(k, b);
-        }
+        w.add_job(k, g.n_total, g.n_blocks, g.block_size, g.ans_words != 0);
       }
-      std::stable_sort(sized.begin(), sized.end(),
-                       [](const std::pair<uint64_t, uint2> &a, const std::pair<uint64_t, uint2> &b) {
-                         return a.first > b.first;
-                       });
-      for (size_t i = 0; i < sized.size(); ++i) it[i] = sized[i].second;
-      const uint32_t ni = static_cast<uint32_t>(sized.size());
-      if (hipMemcpyAsync(s.ws, s.pinned, sv->pinned_bytes, hipMemcpyHostToDevice, s.stream) != hipSuccess)
+      w.finish();
+      const uint32_t nb = static_cast<uint32_t>(w.blocks.size());
+      const uint32_t ni = static_cast<uint32_t>(w.items.size());
+      const uint32_t nr = static_cast<uint32_t>(w.ritems.size());
+      const uint32_t nt = static_cast<uint32_t>(w.tiled.size());
+      // the lists packed behind the job table: one upload of what this batch uses
+      const uint64_t o_blocks = align_up(sv->off_jobs + sizeof(JobDev) * batch.size(), 64);
+      const uint64_t o_items = align_up(o_blocks + 8ull * nb, 64);
+      const uint64_t o_ritems = align_up(o_items + 8ull * ni, 64);
+      const uint64_t o_tiled = align_up(o_ritems + 8ull * nr, 64);
+      const uint64_t o_status0 = align_up(o_tiled + sizeof(TiledBlock) * nt, 64);
+      const uint64_t staged = o_status0 + 4ull * batch.size();
+      if (staged > sv->pinned_bytes) return PIVCO_E_UNSUPPORTED;   // admission keeps this false
+      std::memcpy(s.pinned + o_blocks, w.blocks.data(), 8ull * nb);
+      std::memcpy(s.pinned + o_items, w.items.data(), 8ull * ni);
+      std::memcpy(s.pinned + o_ritems, w.ritems.data(), 8ull * nr);
+      std::memcpy(s.pinned + o_tiled, w.tiled.data(), sizeof(TiledBlock) * nt);
+      int32_t *st0 = reinterpret_cast<int32_t *>(s.pinned + o_status0);
+      for (uint32_t k = 0; k < batch.size(); ++k) st0[k] = PIVCO_OK;
+      if (hipMemcpyAsync(s.ws, s.pinned, staged, hipMemcpyHostToDevice, s.stream) != hipSuccess)
         return PIVCO_E_DEVICE;
       Counters *ctr = reinterpret_cast<Counters *>(s.ws + sv->off_ctr);
       const JobDev *dj = reinterpret_cast<const JobDev *>(s.ws + sv->off_jobs);
       uint32_t *scr = reinterpret_cast<uint32_t *>(s.ws + sv->off_scratch);
       if (launch_init(s.stream, ctr, reinterpret_cast<int32_t *>(s.ws + sv->off_status),
-                      reinterpret_cast<const int32_t *>(s.ws + sv->off_status0),
+                      reinterpret_cast<const int32_t *>(s.ws + o_status0),
                       static_cast<uint32_t>(batch.size())) != hipSuccess)
         return PIVCO_E_DEVICE;
       void *recs = s.ws + sv->off_recs;
-      if (launch_plan(s.stream, dj, reinterpret_cast<const uint2 *>(s.ws + sv->off_items), ni, recs) !=
-          hipSuccess)
-        return PIVCO_E_DEVICE;
+      const uint2 *d_blocks = reinterpret_cast<const uint2 *>(s.ws + o_blocks);
+      const TiledBlock *d_tiled = reinterpret_cast<const TiledBlock *>(s.ws + o_tiled);
+      uint2 *d_tab = reinterpret_cast<uint2 *>(s.ws + sv->off_tab);
+      if (launch_plan(s.stream, dj, d_blocks, nb, recs) != hipSuccess) return PIVCO_E_DEVICE;
       if (nr && launch_rans(std::max<uint32_t>(1, std::min(rgrid_full, nr)), s.stream, dj,
-                            reinterpret_cast<const uint2 *>(s.ws + sv->off_ritems), nr, ctr, scr,
+                            reinterpret_cast<const uint2 *>(s.ws + o_ritems), nr, ctr, scr,
                             -1) != hipSuccess)
         return PIVCO_E_DEVICE;
+      if (launch_tiles(s.stream, dj, d_blocks, d_tiled, nt, recs, scr, sw, d_tab) != hipSuccess)
+        return PIVCO_E_DEVICE;
       if (ni && launch_merge(variant, std::max<uint32_t>(1, std::min(mgrid_full, ni)), s.stream, dj,
-                             reinterpret_cast<const uint2 *>(s.ws + sv->off_items), recs, ni, ctr,
-                             scr, sw, -1) != hipSuccess)
+                             d_blocks, reinterpret_cast<const uint2 *>(s.ws + o_items), recs,
+                             d_tiled, d_tab, ni, ctr, scr, sw, -1) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (hipMemcpyAsync(s.pinned + sv->off_pstatus, s.ws + sv->off_status, 4 * batch.size(),
                          hipMemcpyDeviceToHost, s.stream) != hipSuccess)

@@ -55,7 +55,7 @@ class ServerOpts(C.Structure):
     _fields_ = [("mem_budget", C.c_uint64), ("slots", C.c_uint32), ("max_batch", C.c_uint32),
                 ("max_blocks", C.c_uint32), ("merge_variant", C.c_uint32),
                 ("max_scratch_words", C.c_uint64), ("keep_outputs", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("max_tiles", C.c_uint32)]
 
 
 class Request(C.Structure):
@@ -331,9 +331,9 @@ class Server:
     """pivco_server_*: continuous-batching decode of resident streams."""
 
     def __init__(self, mem_budget, slots=4, max_batch=64, max_blocks=1 << 16,
-                 max_scratch_words=1 << 24, merge_variant=0, keep_outputs=False):
+                 max_scratch_words=1 << 24, merge_variant=0, keep_outputs=False, max_tiles=0):
         o = ServerOpts(int(mem_budget), slots, max_batch, max_blocks, merge_variant,
-                       max_scratch_words, 1 if keep_outputs else 0, 0)
+                       max_scratch_words, 1 if keep_outputs else 0, max_tiles)
         self.handle = C.c_void_p()
         _check(lib().pivco_server_create(C.byref(o), C.byref(self.handle)), "pivco_server_create")
         self.streams = []

@@ -25,11 +25,18 @@ def cases():
     out.append(("uniform256_64k", u, 64 << 10, 0, None))       # 8-bit codes: streaming path
     big = W.draw(r, W.geometric_p(0.97), 3 << 20)
     out.append(("geo97_3m_block", big, 3 << 20, 1, None))       # one big block, many tiles
+    # split-block limits: 128 tiles of 32Ki (the most a block is split
+    # into), one symbol more (decoded whole), and just above the split size
+    g4 = W.draw(r, W.geometric_p(0.9), (4 << 20) + 1)
+    out.append(("geo_4m_128_tiles", g4[:4 << 20], 4 << 20, 0, None))
+    out.append(("geo_4m_plus1_whole", g4, (4 << 20) + 1, 1, None))
+    out.append(("zipf_split_min_plus1", np.concatenate([z, z])[:(64 << 10) + 1], (64 << 10) + 1, 0, None))
     for n in [1, 2, 3, 31, 32, 33, 255, 256, 257, 4095, 4096, 4097, 70000]:
         k = int(r.integers(2, 40))
         out.append((f"tiny_{n}", r.integers(0, k, size=n).astype(np.uint8), 1 << 16, 0, None))
     out.append(("tiny_forced_1000", r.integers(0, 5, size=1000).astype(np.uint8), 333, 2, None))
     out.append(("constant", np.full(100_000, 7, np.uint8), 40_000, 0, None))
+    out.append(("constant_split", np.full(200_000, 9, np.uint8), 1 << 17, 0, None))
     out.append(("two_symbols", (r.random(150_000) < 0.03).astype(np.uint8), 1 << 16, 1, None))
     # deepest codes: Fibonacci-like counts reach the 11-bit limit
     fib = [1, 1]

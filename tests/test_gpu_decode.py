@@ -120,6 +120,10 @@ def _corruptions(st):
     muts.append(("truncated", st[:len(st) // 2].copy()))
     b = st.copy(); b[56:64] = np.frombuffer(np.uint64(len(st) + 4096).tobytes(), np.uint8)
     muts.append(("offset_past_end", b))
+    # last rANS offset (the table's final entry) past the stream's total of
+    # scratch words
+    b = st.copy(); b[off0 - 8:off0] = np.frombuffer(np.uint64(1 << 20).tobytes(), np.uint8)
+    muts.append(("ans_offset_past_total", b))
     return muts
 
 
@@ -151,3 +155,34 @@ def test_small_output_capacity_rejected():
     outs, status = P.pivco_decode_batch([dev(st)], [torch.empty(999, dtype=torch.uint8, device="cuda")])
     torch.cuda.synchronize()
     assert status[0] == P.E_CAPACITY
+
+
+def test_corrupt_split_blocks_flagged_and_isolated():
+    """Bit flips inside blocks decoded as tiles: the boundary pass must flag
+    every stream the oracle rejects, and the clean stream beside them must
+    still decode exactly."""
+    rng = np.random.default_rng(22)
+    import workloads as W
+    x = W.draw(rng, W.zipf_p(1.05, rng), 600_000)
+    for mode in (0, 2):
+        good = O.encode(x, 1 << 18, ans_mode=mode)
+        off0 = int(np.frombuffer(good[48:56].tobytes(), np.uint64)[0])
+        muts = []
+        for k in range(12):
+            b = good.copy()
+            pos = int(rng.integers(off0 + 200, len(good)))
+            b[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
+            muts.append((f"flip_{pos}", b))
+        streams = [dev(good)] + [dev(m) for _, m in muts]
+        outs = [torch.empty(x.size, dtype=torch.uint8, device="cuda") for _ in streams]
+        got, status = P.pivco_decode_batch(streams, outs)
+        torch.cuda.synchronize()
+        assert status[0] == 0 and np.array_equal(got[0].cpu().numpy(), x), mode
+        for (name, m), s in zip(muts, status[1:]):
+            try:
+                ok = np.array_equal(O.decode(m, n=x.size), x)
+            except O.OracleError:
+                ok = False
+            if not ok:
+                assert s != 0, (mode, name)
+
