@@ -150,13 +150,23 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
   p.status0.assign(count, PIVCO_OK);
   p.w.clear();
   uint64_t sw = 0;
+  std::vector<StreamHdr> hs(count);
+  std::vector<pivco_status> sts(count);
+  uint64_t batch_symbols = 0;
   for (uint32_t j = 0; j < count; ++j) {
     const pivco_job &jb = h_jobs[j];
-    StreamHdr sh;
+    StreamHdr &sh = hs[j];
     pivco_status st = parse_stream_header(&hdr[static_cast<size_t>(j) * kHeaderBytes],
                                           std::min<uint64_t>(jb.in_len, kHeaderBytes), &sh);
     if (st == PIVCO_OK && jb.in_len < kHeaderBytes + 16ull * (sh.n_blocks + 1ull)) st = PIVCO_E_CORRUPT;
     if (st == PIVCO_OK && sh.n_total > jb.out_cap) st = PIVCO_E_CAPACITY;
+    sts[j] = st;
+    if (st == PIVCO_OK) batch_symbols += sh.n_total;
+  }
+  for (uint32_t j = 0; j < count; ++j) {
+    const pivco_job &jb = h_jobs[j];
+    const StreamHdr &sh = hs[j];
+    const pivco_status st = sts[j];
     JobDev &d = p.jobs[j];
     d.in = static_cast<const uint8_t *>(jb.d_in);
     d.in_len = jb.in_len;
@@ -173,7 +183,8 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
     d.scratch_base = sw;
     d.ans_words = sh.ans_words;
     sw = align_up(sw + sh.ans_words, 4);
-    p.w.add_job(j, sh.n_total, sh.n_blocks, sh.block_size, sh.ans_words != 0);
+    p.w.add_job(j, sh.n_total, sh.n_blocks, sh.block_size, sh.ans_words != 0,
+                split_threshold(jb.in_len, sh.ans_words, sh.n_blocks, batch_symbols, device_cus()));
   }
   p.w.finish();
   if (p.w.items.size() > 0xFFFFFFF0ull || p.w.blocks.size() > 0xFFFFFFF0ull) return PIVCO_E_UNSUPPORTED;
@@ -251,7 +262,7 @@ pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, con
     return PIVCO_E_DEVICE;
   if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PIVCO_E_DEVICE;
   if (!w.items.empty() &&
-      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.blocks, d.items, d.recs, d.tiled,
+      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.items, d.recs, d.tiled,
                    d.tab, static_cast<uint32_t>(w.items.size()), d.ctr, d.scratch,
                    p.scratch_words, -1) != hipSuccess)
     return PIVCO_E_DEVICE;
@@ -370,7 +381,7 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
                                         : (w.items[a].y & 255) < (w.items[b].y & 255);
   });
   for (uint32_t i : idx)
-    if (launch_merge(0, 1, s, d.jobs, d.blocks, d.items, d.recs, d.tiled, d.tab,
+    if (launch_merge(0, 1, s, d.jobs, d.items, d.recs, d.tiled, d.tab,
                      static_cast<uint32_t>(w.items.size()), d.ctr, d.scratch, p.scratch_words,
                      static_cast<int32_t>(i)) != hipSuccess)
       return PIVCO_E_DEVICE;

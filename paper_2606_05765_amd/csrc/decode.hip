@@ -99,22 +99,28 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
 // ---------------------------------------------------------------------------
 // Block header state shared by the rANS and merge kernels
 // ---------------------------------------------------------------------------
-// The block's extent: the first 32 bytes of its header state, all the
-// merge kernel needs before it loads the rest.
+// The block's extent and owner: the first 48 bytes of its header state, all
+// the merge kernel needs before it loads the rest.
 struct BlockExt {
   uint64_t blk;        // byte offset of the block in the stream
   uint64_t end;        // byte offset of the next block
   uint64_t ans_word0;  // absolute scratch word of the block's first rANS node
   uint32_t ans_words;  // scratch words of its rANS nodes
   int32_t err;
+  const uint8_t *in;   // the job's stream
+  uint32_t job;        // the job's index in the batch
+  uint32_t pad;
 };
 
 struct BlockHdr {
-  uint64_t blk;        // (these five as in BlockExt)
+  uint64_t blk;        // (these seven as in BlockExt)
   uint64_t end;
   uint64_t ans_word0;
   uint32_t ans_words;
   int32_t err;
+  const uint8_t *in;
+  uint32_t job;
+  uint32_t pad;
   uint64_t out_off;    // first output byte of the block
   uint32_t comp, n, mode, csym, cw, I, maxlen, kb;
   uint32_t raw_base, raw_end, n_ans;
@@ -122,7 +128,7 @@ struct BlockHdr {
   uint32_t cnt[17], fc[18], lbase[17], lvl[18];
   uint64_t lvl_total[17];  // symbols passing each level (sum of n_v)
 };
-static_assert(offsetof(BlockHdr, err) == offsetof(BlockExt, err) && sizeof(BlockExt) == 32, "BlockExt prefix");
+static_assert(offsetof(BlockHdr, job) == offsetof(BlockExt, job) && sizeof(BlockExt) == 48, "BlockExt prefix");
 
 // Per-node tables (breadth-first node ids).
 struct NodeTab {
@@ -182,6 +188,15 @@ __device__ void parse_offsets(const JobDev &J, uint32_t b, BlockHdr &h) {
   h.ans_words = err ? 0u : static_cast<uint32_t>(a1 - a0);
   h.err = err;
   h.kraft = 0;
+}
+
+// The thread's index, opaque to loop-invariant code motion: the persistent
+// merge loop would otherwise keep every LDS address derived from it live
+// across items, and spill them.
+__device__ __forceinline__ uint32_t item_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
@@ -619,7 +634,6 @@ struct MergeSmem {
   ParsedBlock pb;          // h and t of the current block
   BlockExt nxt;            // extent of the next item's block (looked ahead)
   uint2 nxt_item;          // next item: record, tile
-  uint32_t nxt_job;
   uint32_t cur[256];       // bits of the node consumed by earlier tiles
   uint32_t tv[256];        // node's share of the current tile
   union {
@@ -829,7 +843,7 @@ __device__ void count_chain(MergeSmem<C> &sm) {
 template <class C>
 __device__ void count_last(MergeSmem<C> &sm) {
   const NodeTab &t = sm.pb.t;
-  for (uint32_t v = threadIdx.x; v < sm.pb.h.I; v += C::NT) {
+  for (uint32_t v = item_tid(); v < sm.pb.h.I; v += C::NT) {
     const uint32_t nv = t.nv[v];
     const uint32_t rest = nv - sm.cur[v];
     sm.tv[v] = rest;
@@ -846,7 +860,7 @@ __device__ void count_last(MergeSmem<C> &sm) {
 // the cursors advance.
 template <class C>
 __device__ void tile_lists(MergeSmem<C> &sm) {
-  const int tid = threadIdx.x;
+  const int tid = item_tid();
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
@@ -910,7 +924,7 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
 template <class C>
 __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_t d,
                                       const uint32_t *scratch, uint64_t scratch_words) {
-  const int wave = threadIdx.x >> 6;
+  const int wave = item_tid() >> 6;
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
@@ -1075,8 +1089,8 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
 // All levels of the tile, deepest first; one barrier per level.  A wave
 // takes up to C::LOCK of its windows of a level at once.
 template <class C, bool RESIDENT>
-__device__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
-  const uint32_t wave = threadIdx.x >> 6;
+__device__ __forceinline__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
+  const uint32_t wave = item_tid() >> 6;
   for (int d = maxd - 1; d >= 0; --d) {
     const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
     const uint32_t nwin = (ntask + kWave - 1) / kWave;
@@ -1092,16 +1106,19 @@ __device__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
   }
 }
 
-// The block's extent from the first 32 bytes of its record.
+// The block's extent and owner from the first 48 bytes of its record.
 __device__ __forceinline__ BlockExt load_ext(const ParsedBlock *rec) {
   const uint4 *p = reinterpret_cast<const uint4 *>(rec);
-  const uint4 a = p[0], c = p[1];
+  const uint4 a = p[0], c = p[1], o = p[2];
   BlockExt e;
   e.blk = (static_cast<uint64_t>(a.y) << 32) | a.x;
   e.end = (static_cast<uint64_t>(a.w) << 32) | a.z;
   e.ans_word0 = (static_cast<uint64_t>(c.y) << 32) | c.x;
   e.ans_words = c.z;
   e.err = static_cast<int32_t>(c.w);
+  e.in = reinterpret_cast<const uint8_t *>((static_cast<uint64_t>(o.y) << 32) | o.x);
+  e.job = o.z;
+  e.pad = 0;
   return e;
 }
 
@@ -1121,7 +1138,7 @@ __device__ __forceinline__ bool block_resident(const BlockExt &ext) {
 template <class C>
 __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockExt &ext,
                            const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
-  const int tid = threadIdx.x;
+  const int tid = item_tid();
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
   constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
@@ -1171,8 +1188,7 @@ __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockE
 struct Lookahead {
   uint32_t item;             // next work item (n_items: none)
   uint2 rt;                  // its (record, tile) pair
-  uint32_t job;
-  BlockExt ext;              // its block's extent
+  BlockExt ext;              // its block's extent and job
   const uint8_t *in;         // its stream (null: nothing to warm)
   const uint8_t *rec;        // its record
 };
@@ -1182,7 +1198,6 @@ __device__ __forceinline__ void publish_next(MergeSmem<C> &sm, const Lookahead &
   if (threadIdx.x != kWave) return;
   sm.item = la.item;
   sm.nxt_item = la.rt;
-  sm.nxt_job = la.job;
   sm.nxt = la.ext;
   sm.warm_in = la.in;
   sm.warm_rec = la.rec;
@@ -1247,7 +1262,7 @@ __device__ void fill_constant(uint8_t *out, uint32_t n, uint32_t c) {
 // Ends with a barrier.
 template <class C>
 __device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) {
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = item_tid();
   const uint32_t wave = tid >> 6;
   const uint32_t lane = lane_id();
   const uint32_t nsb = (body_dw + 7) / 8 + 1;
@@ -1287,15 +1302,20 @@ __device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) 
 }
 
 // Decodes the block whose record (and, when resident, body) load_block put
-// into LDS, with the whole workgroup.
+// into LDS, with the whole workgroup; or, for k != kWholeBlock, tile k of a
+// split block that load_tile put into LDS (its shares are known: there is no
+// count phase and no end-of-block check, the boundary kernel validated the
+// block's bitmaps).
 template <class C>
-__device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_t *scratch,
-                             uint64_t scratch_words, MergeSmem<C> &sm, const Lookahead &la) {
-  const int tid = threadIdx.x;
+__device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
+                             const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm,
+                             const Lookahead &la) {
+  const int tid = item_tid();
   const int wave = tid >> 6;
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
-  const bool resident = block_resident<C>(ext);
+  const bool tiled = k != kWholeBlock;
+  const bool resident = tiled || block_resident<C>(ext);
   const uint64_t g0 = ext.blk & ~15ull;
   const uint64_t span = ((ext.end + 15) & ~15ull) - g0;
   if (h.err) {
@@ -1304,31 +1324,40 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     return;
   }
   uint8_t *out = J.out + h.out_off;
-  const uint32_t n = h.n;
+  uint32_t n = h.n;
+  if (tiled) {
+    out += static_cast<uint64_t>(k) * kTileOut;
+    n = n - k * kTileOut < kTileOut ? n - k * kTileOut : kTileOut;
+  }
   if (h.mode == 1) {                 // constant block
     publish_next<C>(sm, la);
     fill_constant<C>(out, n, h.csym);
     return;
   }
   const uint32_t I = h.I;
-  if (resident) {
-    const uint32_t lb = static_cast<uint32_t>(h.blk - g0);
-    const uint32_t abase = static_cast<uint32_t>(span >> 2);
-    for (uint32_t i = tid; i < I; i += C::NT)
-      sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : lb + t.boff[i]);
+  if (tiled) {
+    for (uint32_t i = tid; i < I; i += C::NT) sm.cur[i] = 0;
+    if (tid == 0) sm.tile = C::T;
+    build_directory<C>(sm, 4 * sm.stage_top, I);
+  } else {
+    if (resident) {
+      const uint32_t lb = static_cast<uint32_t>(h.blk - g0);
+      const uint32_t abase = static_cast<uint32_t>(span >> 2);
+      for (uint32_t i = tid; i < I; i += C::NT)
+        sm.abit[i] = 8 * (t.kind[i] ? 4 * (abase + t.boff[i]) : lb + t.boff[i]);
+    }
+    for (uint32_t i = tid; i < I; i += C::NT) {
+      sm.cur[i] = 0;
+      sm.tv[i] = 0;
+      if (!resident) sm.ones[i] = 0;
+    }
+    if (tid == 0) {
+      sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
+      if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
+    }
+    lds_barrier();
+    if (resident) build_directory<C>(sm, static_cast<uint32_t>(span >> 2) + h.ans_words, I);
   }
-  init_sel<C>(sm);
-  for (uint32_t i = tid; i < I; i += C::NT) {
-    sm.cur[i] = 0;
-    sm.tv[i] = 0;
-    if (!resident) sm.ones[i] = 0;
-  }
-  if (tid == 0) {
-    sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
-    if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
-  }
-  lds_barrier();
-  if (resident) build_directory<C>(sm, static_cast<uint32_t>(span >> 2) + h.ans_words, I);
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
   bool bad = false;
@@ -1343,13 +1372,15 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
     }
     lds_barrier();
     if (resident) {
-      if (t0 + troot < n) {
-        if (wave == 0) count_chain<C>(sm);
-        else if (wave == 1 && t0 == 0) warm_next<C>(sm);
-      } else {
-        count_last<C>(sm);
+      if (!tiled) {
+        if (t0 + troot < n) {
+          if (wave == 0) count_chain<C>(sm);
+          else if (wave == 1 && t0 == 0) warm_next<C>(sm);
+        } else {
+          count_last<C>(sm);
+        }
+        lds_barrier();
       }
-      lds_barrier();
       tile_lists<C>(sm);
     } else {
       for (uint32_t d = 0; d < maxd; ++d) {
@@ -1367,7 +1398,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
       lds_barrier();
     }
   }
-  if (!bad) {
+  if (!bad && !tiled) {
     for (uint32_t i = tid; i < I; i += C::NT) {
       const uint32_t ones = resident ? sm.arank[i] - sm.r0[i] : sm.ones[i];
       if (sm.cur[i] != t.nv[i] || ones != t.nr[i])
@@ -1387,7 +1418,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, const uint32_
 template <class C>
 __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *tab, uint32_t k,
                           const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
-  const int tid = threadIdx.x;
+  const int tid = item_tid();
   const int wave = tid >> 6;
   const uint32_t lane = lane_id();
   constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
@@ -1406,7 +1437,7 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
   __syncthreads();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
-  if (h.err || h.mode == 1) return;     // decode_tile reports or fills
+  if (h.err || h.mode == 1) return;     // decode_block reports or fills
   const uint32_t I = h.I;
   // chunk counts and their exclusive prefix over the nodes (block scan)
   uint32_t nch = 0;
@@ -1478,42 +1509,11 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
   lds_barrier();
 }
 
-// Decodes the tile load_tile put into LDS: its shares are known, so there is
-// no count phase and no end-of-block check (the boundary kernel validated the
-// block's bitmaps).
-template <class C>
-__device__ void decode_tile(const JobDev &J, uint32_t k, MergeSmem<C> &sm, const Lookahead &la) {
-  const int tid = threadIdx.x;
-  BlockHdr &h = sm.pb.h;
-  uint8_t *out = J.out + h.out_off + static_cast<uint64_t>(k) * kTileOut;
-  const uint32_t n = h.n;
-  const uint32_t troot = n - k * kTileOut < kTileOut ? n - k * kTileOut : kTileOut;
-  if (h.err) {
-    publish_next<C>(sm, la);
-    if (tid == 0) set_err(J.status, h.err);
-    return;
-  }
-  if (h.mode == 1) {
-    publish_next<C>(sm, la);
-    fill_constant<C>(out, troot, h.csym);
-    return;
-  }
-  const uint32_t I = h.I;
-  init_sel<C>(sm);
-  build_directory<C>(sm, 4 * sm.stage_top, I);
-  for (uint32_t i = tid; i < I; i += C::NT) sm.cur[i] = 0;
-  if (tid == 0) sm.act_run = 0;
-  publish_next<C>(sm, la);
-  lds_barrier();
-  tile_lists<C>(sm);
-  merge_tile<C, true>(sm, static_cast<int>(h.maxlen), out);
-}
-
 // Persistent merge: a workgroup takes items from the queue (largest first) --
 // whole blocks, or tiles of split blocks -- looking one item ahead.
 template <class C>
-__global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *blocks,
-                                                  const uint2 *items, const ParsedBlock *recs,
+__global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *items,
+                                                  const ParsedBlock *recs,
                                                   const TiledBlock *tiled, const uint2 *tab,
                                                   uint32_t n_items, Counters *ctr,
                                                   const uint32_t *scratch, uint64_t scratch_words,
@@ -1521,13 +1521,13 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
   __shared__ MergeSmem<C> sm;
   const int tid = threadIdx.x;
   for (int i = tid; i < 256; i += C::NT) sm.leafrow[i] = static_cast<uint32_t>(i) * 0x01010101u;
+  init_sel<C>(sm);
   if (tid == 0) {
     const uint32_t it = single >= 0 ? static_cast<uint32_t>(single) : atomicAdd(&ctr->merge_next, 1u);
     sm.item = it;
     if (it < n_items) {
       const uint2 rt = items[it];
       sm.nxt_item = rt;
-      sm.nxt_job = blocks[rt.x].x;
       sm.nxt = load_ext(recs + rt.x);
     }
   }
@@ -1536,16 +1536,15 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
     const uint32_t it = sm.item;
     if (it >= n_items) break;
     const uint2 rt = sm.nxt_item;
-    const uint32_t job = sm.nxt_job;
     const BlockExt ext = sm.nxt;
     lds_barrier();                   // the look-ahead slots are rewritten below
     // look ahead (thread 64, in a wave that is idle while wave 0 computes
     // the first tile's shares): take the next item now; its extent and
     // stream are read while this item is decoded, and published to LDS
     // before the merge (or when the item ends early)
-    Lookahead la{n_items, make_uint2(0, 0), 0u, BlockExt{}, nullptr, nullptr};
+    Lookahead la{n_items, make_uint2(0, 0), BlockExt{}, nullptr, nullptr};
     if (tid == kWave && single < 0) la.item = atomicAdd(&ctr->merge_next, 1u);
-    const JobDev &J = jobs[job];
+    const JobDev &J = jobs[ext.job];
     const bool whole = rt.y == kWholeBlock;
     if (whole) {
       load_block<C>(J, recs + rt.x, ext, scratch, scratch_words, sm);
@@ -1555,13 +1554,11 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
     }
     if (tid == kWave && la.item < n_items) {
       la.rt = items[la.item];
-      la.job = blocks[la.rt.x].x;
       la.ext = load_ext(recs + la.rt.x);
-      la.in = la.ext.err || la.rt.y != kWholeBlock ? nullptr : jobs[la.job].in;
+      la.in = la.ext.err || la.rt.y != kWholeBlock ? nullptr : la.ext.in;
       la.rec = reinterpret_cast<const uint8_t *>(recs + la.rt.x);
     }
-    if (whole) decode_block<C>(J, ext, scratch, scratch_words, sm, la);
-    else decode_tile<C>(J, rt.y & 255, sm, la);
+    decode_block<C>(J, ext, whole ? kWholeBlock : rt.y & 255, scratch, scratch_words, sm, la);
     lds_barrier();
   }
 }
@@ -1750,7 +1747,12 @@ __global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs,
   const JobDev &J = jobs[item.x];
   BlockHdr &h = pb[wave].h;
   NodeTab &t = pb[wave].t;
-  if (lane == 0) parse_offsets(J, item.y, h);
+  if (lane == 0) {
+    parse_offsets(J, item.y, h);
+    h.in = J.in;
+    h.job = item.x;
+    h.pad = 0;
+  }
   wave_sync_lds();
   const uint64_t len = h.end - h.blk;
   const uint32_t hn = h.err ? 0u : static_cast<uint32_t>(len < kHdrMax ? len : kHdrMax);
@@ -1806,12 +1808,12 @@ struct MergeVariant {
 };
 
 template <class C>
-static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs, const uint2 *blocks,
+static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs,
                                  const uint2 *items, const ParsedBlock *recs,
                                  const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
                                  Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
                                  int32_t single) {
-  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, blocks, items, recs, tiled, tab,
+  hipLaunchKernelGGL(k_merge<C>, grid, dim3(C::NT), 0, s, jobs, items, recs, tiled, tab,
                      n_items, ctr, scratch, scratch_words, single);
   return hipGetLastError();
 }
@@ -1848,15 +1850,15 @@ int merge_variant_occupancy(uint32_t v) {
 }
 
 hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *blocks, const uint2 *items, const void *recs,
+                        const uint2 *items, const void *recs,
                         const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
                         Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
                         int32_t single) {
   const ParsedBlock *r = static_cast<const ParsedBlock *>(recs);
   switch (variant) {
-    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, blocks, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
-    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, blocks, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
-    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, blocks, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
   }
 }
 

@@ -23,11 +23,11 @@ constexpr uint32_t kRansM = 4096;          // 12-bit probabilities
 constexpr uint32_t kRansL = 65536;         // lower state bound, 16-bit words
 constexpr uint32_t kRansLanes = 32;
 constexpr uint32_t kChunkHdr = 4 + 4 * 32; // n_words u32 + 32 lane states
-constexpr uint32_t kParsedBlockBytes = 5632; // per-block record written by the plan kernel
+constexpr uint32_t kParsedBlockBytes = 5648; // per-block record written by the plan kernel
 
-// Blocks of more than kSplitMin symbols (and at most kMaxTiles tiles) are
-// decoded as independent tiles of kTileOut symbols, each its own work item;
-// the others as one work item each.  A split block's boundary table holds,
+// A block of more than split_min symbols (never fewer than kSplitMin) and at
+// most kMaxTiles tiles is decoded as independent tiles of kTileOut symbols,
+// each its own work item; the others as one work item each.  A split block's boundary table holds,
 // per tile boundary k = 0..ntiles, one row of kTabCols (position, rank) pairs:
 // the symbols of the block before boundary k that pass node v, and the 1
 // bits among them.
@@ -38,9 +38,22 @@ constexpr uint32_t kTabCols = 256;
 constexpr uint32_t kWholeBlock = 0xFFFFFFFFu;
 static_assert(kMaxTiles <= 256, "tile index fits the low 8 bits of an item");
 
-__host__ __device__ inline uint32_t tiles_of_block(uint64_t n) {
+__host__ __device__ inline uint32_t tiles_of_block(uint64_t n, uint64_t split_min = kSplitMin) {
   const uint64_t k = (n + kTileOut - 1) / kTileOut;
-  return n > kSplitMin && k <= kMaxTiles ? static_cast<uint32_t>(k) : 0u;
+  return n > kSplitMin && n > split_min && k <= kMaxTiles ? static_cast<uint32_t>(k) : 0u;
+}
+
+// Split threshold of a batched job.  A whole block decodes fastest when its
+// bytes and decoded rANS bitmaps fit in the merge kernel's LDS (estimated
+// from the job's average block); splitting then only adds the boundary pass.
+// Blocks that do not fit, and blocks large enough to hold back the batch
+// (more than half a compute unit's share of its symbols), are split.
+constexpr uint64_t kResidentGuess = 48 << 10;
+inline uint64_t split_threshold(uint64_t in_len, uint64_t ans_words, uint32_t n_blocks,
+                                uint64_t batch_symbols, int cus) {
+  if (n_blocks && (in_len + 4 * ans_words) / n_blocks > kResidentGuess) return kSplitMin;
+  const uint64_t share = batch_symbols / (2ull * static_cast<uint64_t>(cus > 0 ? cus : 1));
+  return share > kSplitMin ? share : kSplitMin;
 }
 
 // A split block: its record, tile count, and first boundary-table entry.
@@ -91,14 +104,15 @@ struct WorkLists {
     tab_entries = 0;
   }
   // Adds the blocks of job j (n_total symbols in blocks of block_size).
-  void add_job(uint32_t j, uint64_t n_total, uint32_t n_blocks, uint32_t block_size, bool ans) {
+  void add_job(uint32_t j, uint64_t n_total, uint32_t n_blocks, uint32_t block_size, bool ans,
+               uint64_t split_min = kSplitMin) {
     for (uint32_t b = 0; b < n_blocks; ++b) {
       const uint64_t start = static_cast<uint64_t>(b) * block_size;
       const uint64_t sz = std::min<uint64_t>(block_size, n_total - start);
       const uint32_t rec = static_cast<uint32_t>(blocks.size());
       blocks.push_back(make_uint2(j, b));
       if (ans) ritems.push_back(make_uint2(j, b));
-      const uint32_t nt = tiles_of_block(sz);
+      const uint32_t nt = tiles_of_block(sz, split_min);
       if (nt == 0) {
         sized.push_back({sz, make_uint2(rec, kWholeBlock)});
       } else {
@@ -154,7 +168,7 @@ hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const uint2 *blocks,
                         const TiledBlock *tiled, uint32_t n_tiled, const void *recs,
                         const uint32_t *scratch, uint64_t scratch_words, uint2 *tab);
 hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
-                        const uint2 *blocks, const uint2 *items, const void *recs,
+                        const uint2 *items, const void *recs,
                         const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
                         Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
                         int32_t single);

@@ -359,7 +359,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
       if (launch_tiles(s.stream, dj, d_blocks, d_tiled, nt, recs, scr, sw, d_tab) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (ni && launch_merge(variant, std::max<uint32_t>(1, std::min(mgrid_full, ni)), s.stream, dj,
-                             d_blocks, reinterpret_cast<const uint2 *>(s.ws + o_items), recs,
+                             reinterpret_cast<const uint2 *>(s.ws + o_items), recs,
                              d_tiled, d_tab, ni, ctr, scr, sw, -1) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (hipMemcpyAsync(s.pinned + sv->off_pstatus, s.ws + sv->off_status, 4 * batch.size(),
