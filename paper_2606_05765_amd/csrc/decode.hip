@@ -199,6 +199,11 @@ __device__ __forceinline__ uint32_t item_tid() {
   return t;
 }
 
+// The wave's index in the workgroup, as a scalar (wave-uniform) value.
+__device__ __forceinline__ uint32_t wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 // Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
 // does not wait for the wave's global loads and stores in flight (the merge
 // kernel's waves exchange data through LDS alone).
@@ -861,7 +866,7 @@ __device__ void count_last(MergeSmem<C> &sm) {
 template <class C>
 __device__ void tile_lists(MergeSmem<C> &sm) {
   const int tid = item_tid();
-  const int wave = tid >> 6;
+  const int wave = wave_id();
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
@@ -924,7 +929,7 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
 template <class C>
 __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_t d,
                                       const uint32_t *scratch, uint64_t scratch_words) {
-  const int wave = item_tid() >> 6;
+  const int wave = wave_id();
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
@@ -985,7 +990,7 @@ typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 // child windows, permutes), so that each stage's LDS reads of all N windows
 // are in flight together.  Lanes without a task read from clamped addresses
 // and store nothing.
-template <class C, bool RESIDENT, int N>
+template <class C, bool RESIDENT, int N, bool ROOT>
 __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t *w,
                                               uint32_t ntask, uint32_t abase, uint8_t *out) {
   const uint32_t lane = lane_id();
@@ -997,22 +1002,25 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
   NodeRec r[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
+    // the lane's node: the window's first slot + the node starts at window
+    // bits 1 .. lane.  A lane past the level's last task gets the window's
+    // last node and works on that node's first task (and stores nothing).
     const uint64_t B = sm.smask[d][w[i]];
     const uint32_t slot = sm.wstart[d][w[i]] + static_cast<uint32_t>(__popcll(B & upto));
     valid[i] = kWave * w[i] + lane < ntask;
-    r[i] = sm.rec[valid[i] ? abase + slot : 0u];
+    r[i] = sm.rec[abase + slot];
   }
   uint32_t j0[N], bits[N], r1[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     j0[i] = valid[i] ? C::K * (kWave * w[i] + lane - (r[i].ot >> 16)) : 0u;
     if (RESIDENT) {
-      const uint32_t x = valid[i] ? r[i].x0 + j0[i] : 0u;
+      const uint32_t x = r[i].x0 + j0[i];
       bits[i] = bits32_lds(sm.body, x);
       r1[i] = rank_at(sm.body, sm.sup, sm.rel, x) - r[i].arank;
     } else {
       const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
-      const uint2 wr = stage[valid[i] ? r[i].x0 + (j0[i] >> 5) : 0u];
+      const uint2 wr = stage[r[i].x0 + (j0[i] >> 5)];
       const uint32_t sh = j0[i] & 31;   // 0, or a multiple of K: staged words start at the node's cursor
       bits[i] = wr.x >> sh;
       r1[i] = wr.y + __popc(wr.x & ((1u << sh) - 1));
@@ -1025,10 +1033,13 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const uint32_t kl = r[i].kids & 0xFFFF, kr = r[i].kids >> 16;
-    const uint32_t mL = (kl & 0x8000) ? 0u : 1u, mR = (kr & 0x8000) ? 0u : 1u;
-    const uint32_t bL = !valid[i] ? 0u : mL ? cbase + (kl << C::CS) : lrow + 4 * (kl & 255);
-    const uint32_t bR = !valid[i] ? 0u : mR ? cbase + (kr << C::CS) : lrow + 4 * (kr & 255);
-    uint32_t r1g = valid[i] ? r1[i] : 0u, r0g = valid[i] ? j0[i] - r1[i] : 0u;
+    uint32_t mL = (kl & 0x8000) ? 0u : 1u, mR = (kr & 0x8000) ? 0u : 1u;
+    // opaque to the compiler: a 0/1 multiplier stays one v_mad_u32_u24
+    // instead of being turned into a select per group
+    asm volatile("" : "+v"(mL), "+v"(mR));
+    const uint32_t bL = mL ? cbase + (kl << C::CS) : lrow + 4 * (kl & 255);
+    const uint32_t bR = mR ? cbase + (kr << C::CS) : lrow + 4 * (kr & 255);
+    uint32_t r1g = r1[i], r0g = j0[i] - r1[i];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const uint32_t m = (bits[i] >> (4 * g)) & 15;
@@ -1052,7 +1063,7 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
     }
   }
   uint8_t *ldsw = reinterpret_cast<uint8_t *>(&sm);
-  const uint32_t tvv = d == 0 ? sm.tv[0] : 0u;
+  const uint32_t tvv = ROOT ? sm.tv[0] : 0u;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     uint32_t o[G];
@@ -1065,7 +1076,7 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
     if (!valid[i]) continue;
 #pragma unroll
     for (int c = 0; c < C::K / CB; ++c) {
-      if (d == 0) {
+      if (ROOT) {
         const uint32_t j = j0[i] + CB * c;
         uint8_t *dst = out + j;
         if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
@@ -1086,24 +1097,29 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
   }
 }
 
-// All levels of the tile, deepest first; one barrier per level.  A wave
-// takes up to C::LOCK of its windows of a level at once.
+// One level of a tile: a wave takes up to C::LOCK of its windows at once.
+template <class C, bool RESIDENT, bool ROOT>
+__device__ __forceinline__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
+  const uint32_t wave = wave_id();
+  const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
+  const uint32_t nwin = (ntask + kWave - 1) / kWave;
+  for (uint32_t w = wave; w < nwin; w += C::LOCK * C::NW) {
+    const uint32_t left = (nwin - w + C::NW - 1) / C::NW;   // windows of this wave from w on
+    const uint32_t ww[4] = {w, w + C::NW, w + 2 * C::NW, w + 3 * C::NW};
+    if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1), ROOT>(sm, d, ww, ntask, abase, out);
+    else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1), ROOT>(sm, d, ww, ntask, abase, out);
+    else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1), ROOT>(sm, d, ww, ntask, abase, out);
+    else merge_windows<C, RESIDENT, 1, ROOT>(sm, d, ww, ntask, abase, out);
+  }
+  lds_barrier();
+}
+
+// All levels of the tile, deepest first (into LDS), the root last (into
+// HBM); one barrier per level.
 template <class C, bool RESIDENT>
 __device__ __forceinline__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
-  const uint32_t wave = item_tid() >> 6;
-  for (int d = maxd - 1; d >= 0; --d) {
-    const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
-    const uint32_t nwin = (ntask + kWave - 1) / kWave;
-    for (uint32_t w = wave; w < nwin; w += C::LOCK * C::NW) {
-      const uint32_t left = (nwin - w + C::NW - 1) / C::NW;   // windows of this wave from w on
-      const uint32_t ww[4] = {w, w + C::NW, w + 2 * C::NW, w + 3 * C::NW};
-      if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1)>(sm, d, ww, ntask, abase, out);
-      else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1)>(sm, d, ww, ntask, abase, out);
-      else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1)>(sm, d, ww, ntask, abase, out);
-      else merge_windows<C, RESIDENT, 1>(sm, d, ww, ntask, abase, out);
-    }
-    lds_barrier();
-  }
+  for (int d = maxd - 1; d >= 1; --d) merge_level<C, RESIDENT, false>(sm, d, out);
+  merge_level<C, RESIDENT, true>(sm, 0, out);
 }
 
 // The block's extent and owner from the first 48 bytes of its record.
@@ -1139,7 +1155,7 @@ template <class C>
 __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockExt &ext,
                            const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
   const int tid = item_tid();
-  const int wave = tid >> 6;
+  const int wave = wave_id();
   const uint32_t lane = lane_id();
   constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
   const uint8_t *rb = reinterpret_cast<const uint8_t *>(rec);
@@ -1263,7 +1279,7 @@ __device__ void fill_constant(uint8_t *out, uint32_t n, uint32_t c) {
 template <class C>
 __device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) {
   const uint32_t tid = item_tid();
-  const uint32_t wave = tid >> 6;
+  const uint32_t wave = wave_id();
   const uint32_t lane = lane_id();
   const uint32_t nsb = (body_dw + 7) / 8 + 1;
   const uint32_t per = (nsb + C::NT - 1) / C::NT;
@@ -1311,7 +1327,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
                              const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm,
                              const Lookahead &la) {
   const int tid = item_tid();
-  const int wave = tid >> 6;
+  const int wave = wave_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
   const bool tiled = k != kWholeBlock;
@@ -1419,7 +1435,7 @@ template <class C>
 __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *tab, uint32_t k,
                           const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
   const int tid = item_tid();
-  const int wave = tid >> 6;
+  const int wave = wave_id();
   const uint32_t lane = lane_id();
   constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
   const uint8_t *rb = reinterpret_cast<const uint8_t *>(rec);
