@@ -257,7 +257,7 @@ pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, con
       launch_rans(t.rans_grid, s, d.jobs, d.ritems, static_cast<uint32_t>(w.ritems.size()), d.ctr,
                   d.scratch, -1) != hipSuccess)
     return PIVCO_E_DEVICE;
-  if (launch_tiles(s, d.jobs, d.blocks, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
+  if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PIVCO_E_DEVICE;
@@ -371,7 +371,7 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
     if (launch_rans(1, s, d.jobs, d.ritems, static_cast<uint32_t>(w.ritems.size()), d.ctr,
                     d.scratch, static_cast<int32_t>(r)) != hipSuccess)
       return PIVCO_E_DEVICE;
-  if (launch_tiles(s, d.jobs, d.blocks, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
+  if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
     return PIVCO_E_DEVICE;
   std::vector<uint32_t> idx(w.items.size());

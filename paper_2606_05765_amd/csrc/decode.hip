@@ -1588,113 +1588,235 @@ __device__ __forceinline__ uint32_t range_mask(uint64_t wb, uint64_t b0, uint64_
   return mh & ~((1u << lo) - 1);
 }
 
-// 1 bits among bits [b0, b1) of the little-endian bit string at p (16-byte
-// aligned, nbytes readable): the covering 16-byte chunks, masked.
-__device__ uint32_t popc_range(const uint8_t *p, uint64_t nbytes, uint64_t b0, uint64_t b1) {
-  if (b1 <= b0) return 0u;
-  const uint64_t q0 = (b0 >> 3) & ~15ull, q1 = ((b1 + 127) >> 7) << 4;
-  uint32_t c = 0;
-#pragma unroll 4
-  for (uint64_t q = q0; q < q1; q += 16) {
-    uint32_t w[4];
-    if (q + 16 <= nbytes) {
-      const uint4 x = *reinterpret_cast<const uint4 *>(p + q);
-      w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
-    } else {
+// The 16-byte chunk at byte q of p (16-byte aligned, nbytes >= 16
+// readable): an unconditional load (of the first chunk when q's chunk is not
+// wholly inside), so that a thread's chunk loads can all be in flight; then
+// the 1 bits of the chunk at q inside bits [b0, b1) (bit addresses relative
+// to p), with the rare chunk that straddles the end re-read byte by byte.
+__device__ __forceinline__ uint4 chunk_load(const uint8_t *p, uint64_t nbytes, uint64_t q) {
+  return *reinterpret_cast<const uint4 *>(p + (q + 16 <= nbytes ? q : 0));
+}
+__device__ __forceinline__ uint32_t chunk_popc(uint4 x, const uint8_t *p, uint64_t nbytes,
+                                               uint64_t q, uint64_t b0, uint64_t b1) {
+  uint32_t w[4] = {x.x, x.y, x.z, x.w};
+  if (q + 16 > nbytes) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        uint32_t x = 0;
-        for (uint32_t by = 0; by < 4; ++by)
-          if (q + 4 * e + by < nbytes) x |= static_cast<uint32_t>(p[q + 4 * e + by]) << (8 * by);
-        w[e] = x;
-      }
+    for (int e = 0; e < 4; ++e) {
+      uint32_t y = 0;
+      for (uint32_t by = 0; by < 4; ++by)
+        if (q + 4 * e + by < nbytes) y |= static_cast<uint32_t>(p[q + 4 * e + by]) << (8 * by);
+      w[e] = y;
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) c += __popc(w[e] & range_mask(8 * q + 32 * e, b0, b1));
   }
+  uint32_t c = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c += __popc(w[e] & range_mask(8 * q + 32 * e, b0, b1));
   return c;
 }
 
 // Boundaries of a split block (one workgroup per block).  First a rank
-// directory over all of the block's bitmaps: the 1 bits of every G-bit
-// superblock of every node, exclusive-scanned across the block, so that a
-// node's 1 bits before any position are two directory entries and one
-// popcount of less than G bits.  Then top-down by level, every node's
-// position at each tile boundary k (symbols of the block before the
-// boundary that pass the node) gives its rank there, and the rank its
-// children's positions -- all (node, boundary) pairs of a level at once.
-// The root's positions are k * kTileOut.  Table row k, column v holds
-// (position, rank).  A node whose bitmap holds a different number of 1 bits
-// than its header count marks the job corrupt; positions are clamped to the
-// nodes' sizes so that the tiles never read outside their bitmaps.
+// directory over all of the block's bitmaps: every node's bitmap is cut at
+// the absolute G-bit boundaries of its buffer (G = 512 .. 8192: the smallest
+// whose directory fits), the 1 bits of each piece are counted by a row of
+// G/128 lanes (one 16-byte chunk each, coalesced, four pieces per row in
+// flight) and exclusive-scanned across the block, so that a node's 1 bits
+// before any position are two directory entries plus one popcount of less
+// than G bits (G/128 chunk loads, eight in flight).  Then top-down by
+// level, every (node, boundary) pair of the level is one thread: node v's
+// position at boundary k (symbols of the block before k * kTileOut that
+// pass it) gives its rank there, and the rank gives the right child's
+// position (position - rank the left child's).  The root's positions are
+// k * kTileOut.  Positions live in LDS when the block's table fits, else in
+// the table itself.  Table row k, column v holds (position, rank).  A node
+// whose bitmap holds a different number of 1 bits than its header count
+// marks the job corrupt; positions are clamped to the nodes' sizes so that
+// the tiles never read outside their bitmaps.
 constexpr int kTilesNT = 1024;
 constexpr uint32_t kTilesDir = 16384;     // directory entries (LDS)
+constexpr uint32_t kTilesPos = 16384;     // positions kept in LDS
+constexpr int kTilesG = 5;                // piece sizes 512 << e, e < kTilesG
 
-__global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const uint2 *blocks,
-                                                   const TiledBlock *tiled, uint32_t n_tiled,
-                                                   const ParsedBlock *recs, const uint32_t *scratch,
-                                                   uint64_t scratch_words, uint2 *tab) {
-  __shared__ ParsedBlock pb;
-  __shared__ uint32_t dir[kTilesDir + 1];
-  __shared__ uint32_t sbase[257];
-  __shared__ uint32_t tot[kTilesNT / kWave];
-  __shared__ int32_t err;
-  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+struct TilesSmem {
+  ParsedBlock pb;
+  uint32_t dir[kTilesDir + 1];
+  uint32_t pos[kTilesPos];                // [v * (K + 1) + k] when (K + 1) * I fits
+  uint8_t snode[kTilesDir];               // node of each directory piece
+  uint32_t sbase[257];
+  uint32_t tot[kTilesG][kTilesNT / kWave];
+  int32_t err;
+};
+
+// The level loop of k_tiles (POS_LDS: positions in sm.pos, else in the table).
+template <bool POS_LDS>
+__device__ void tiles_levels(TilesSmem &sm, const JobDev &J, uint2 *T, uint32_t K, uint32_t LG,
+                             const uint8_t *scr, uint64_t scr_bytes) {
+  const BlockHdr &h = sm.pb.h;
+  const NodeTab &t = sm.pb.t;
+  const uint32_t tid = threadIdx.x, spr = 1u << (LG - 7);
+  for (uint32_t d = 0; d < h.maxlen; ++d) {
+    const uint32_t v0 = h.lvl[d], m = h.lvl[d + 1] - v0;
+    for (uint32_t q = tid; q < m * (K + 1); q += kTilesNT) {
+      const uint32_t v = v0 + q / (K + 1), k = q % (K + 1);
+      uint2 *row = T + static_cast<uint64_t>(k) * kTabCols;
+      const uint32_t nv = t.nv[v];
+      const uint32_t sp = POS_LDS ? sm.pos[v * (K + 1) + k] : row[v].x;
+      const uint32_t s = sp < nv ? sp : nv;
+      const bool raw = !t.kind[v];
+      const uint8_t *p = raw ? J.in : scr;
+      const uint64_t nb = raw ? J.in_len : scr_bytes;
+      const uint64_t gb = raw ? 8ull * (h.blk + t.boff[v]) : 32ull * (h.ans_word0 + t.boff[v]);
+      const uint64_t a = gb + s, sb = (a >> LG) << LG;
+      const uint32_t j = static_cast<uint32_t>((a >> LG) - (gb >> LG));
+      uint32_t r = sm.dir[sm.sbase[v] + j] - sm.dir[sm.sbase[v]];
+      for (uint32_t c0 = 0; c0 < spr; c0 += 8) {   // the piece's bits before a
+        const uint32_t nc = spr - c0 < 8 ? spr - c0 : 8;
+        uint4 x[8];
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c)
+          x[c] = c < nc ? chunk_load(p, nb, (sb >> 3) + 16ull * (c0 + c)) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c)       // chunks at or after a count nothing
+          if (c < nc) r += chunk_popc(x[c], p, nb, (sb >> 3) + 16ull * (c0 + c), gb, a);
+      }
+      row[v] = make_uint2(s, r);
+      const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
+      const uint32_t c0 = cc & 0xFFFF, c1 = cc >> 16;
+      if (!(c0 & 0x8000)) {
+        const uint32_t x0 = s - r < t.nv[c0] ? s - r : t.nv[c0];
+        if (POS_LDS) sm.pos[c0 * (K + 1) + k] = x0; else row[c0].x = x0;
+      }
+      if (!(c1 & 0x8000)) {
+        const uint32_t x1 = r < t.nv[c1] ? r : t.nv[c1];
+        if (POS_LDS) sm.pos[c1 * (K + 1) + k] = x1; else row[c1].x = x1;
+      }
+      if (k == K && (r != t.nr[v] || s != nv)) atomicCAS(&sm.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+    }
+    if (POS_LDS) lds_barrier();
+    else __syncthreads();                          // the table's positions are read next
+  }
+}
+
+__global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const TiledBlock *tiled,
+                                                   uint32_t n_tiled, const ParsedBlock *recs,
+                                                   const uint32_t *scratch, uint64_t scratch_words,
+                                                   uint2 *tab) {
+  __shared__ TilesSmem sm;
+  const uint32_t tid = threadIdx.x, wave = wave_id(), lane = lane_id();
   constexpr uint32_t NW = kTilesNT / kWave;
   const TiledBlock tb = tiled[blockIdx.x];
-  const JobDev &J = jobs[blocks[tb.rec].x];
   {
     const uint4 *src = reinterpret_cast<const uint4 *>(recs + tb.rec);
-    uint4 *dst = reinterpret_cast<uint4 *>(&pb);
+    uint4 *dst = reinterpret_cast<uint4 *>(&sm.pb);
     for (uint32_t i = tid; i < sizeof(ParsedBlock) / 16; i += kTilesNT) dst[i] = src[i];
   }
-  if (tid == 0) err = 0;
+  if (tid == 0) sm.err = 0;
   __syncthreads();
-  const BlockHdr &h = pb.h;
-  const NodeTab &t = pb.t;
+  const BlockHdr &h = sm.pb.h;
+  const NodeTab &t = sm.pb.t;
+  const JobDev &J = jobs[h.job];
   if (h.err || h.mode == 1) return;                // the tiles report or fill
   const uint32_t K = tb.ntiles, n = h.n, I = h.I;
   uint2 *T = tab + tb.tab;
   const uint8_t *scr = reinterpret_cast<const uint8_t *>(scratch);
   const uint64_t scr_bytes = 4ull * scratch_words;
-  // superblock size: the smallest power of two (at least 2048 bits) whose
-  // directory fits; sum over nodes of ceil(n_v / G) <= bits / G + I
-  uint64_t bits = 0;
-  for (uint32_t d = 0; d < h.maxlen; ++d) bits += h.lvl_total[d];
-  uint32_t G = 2048;
-  while (bits / G + I + 1 > kTilesDir) G <<= 1;
-  // directory layout: node v owns entries [sbase[v], sbase[v + 1])
+  // pieces per node for G = 512 << e; pick the smallest G whose directory fits
+  uint32_t ns[kTilesG], inc[kTilesG];
   {
-    const uint32_t ns = tid < I ? (t.nv[tid] + G - 1) / G : 0u;
-    const uint32_t inc = wave_incl_scan(ns);
-    if (lane == kWave - 1) tot[wave] = inc;
-    __syncthreads();
-    if (tid < 256) {
-      uint32_t ex = inc - ns;
-      for (uint32_t w = 0; w < wave; ++w) ex += tot[w];
-      sbase[tid] = ex;
-      if (tid == 255) sbase[256] = ex + ns;
+    uint64_t gb = 0, ge = 0;
+    const bool has = tid < I && t.nv[tid];
+    if (has) {
+      gb = t.kind[tid] ? 32ull * (h.ans_word0 + t.boff[tid]) : 8ull * (h.blk + t.boff[tid]);
+      ge = gb + t.nv[tid] - 1;
+    }
+#pragma unroll
+    for (int e = 0; e < kTilesG; ++e) {
+      ns[e] = has ? static_cast<uint32_t>((ge >> (9 + e)) - (gb >> (9 + e)) + 1) : 0u;
+      inc[e] = wave_incl_scan(ns[e]);
+      if (lane == kWave - 1) sm.tot[e][wave] = inc[e];
     }
   }
   __syncthreads();
-  const uint32_t S = sbase[256];
-  for (uint32_t f = tid; f < S; f += kTilesNT) {
-    uint32_t lo = 0, hi = I;                       // last v with sbase[v] <= f
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (sbase[mid] <= f) lo = mid; else hi = mid;
+  uint32_t lg = 0, S = 0;                          // log2(G) - 9, pieces
+  {
+    uint32_t all[kTilesG];
+#pragma unroll
+    for (int e = 0; e < kTilesG; ++e) {
+      all[e] = 0;
+      for (uint32_t w = 0; w < NW; ++w) all[e] += sm.tot[e][w];
     }
-    const uint32_t v = lo, j = f - sbase[v];
-    const uint64_t b0 = static_cast<uint64_t>(j) * G;
-    const uint64_t b1 = b0 + G < t.nv[v] ? b0 + G : t.nv[v];
-    dir[f] = t.kind[v] ? popc_range(scr, scr_bytes, 32ull * (h.ans_word0 + t.boff[v]) + b0,
-                                    32ull * (h.ans_word0 + t.boff[v]) + b1)
-                       : popc_range(J.in, J.in_len, 8ull * (h.blk + t.boff[v]) + b0,
-                                    8ull * (h.blk + t.boff[v]) + b1);
+    while (lg + 1 < kTilesG && all[lg] > kTilesDir) ++lg;
+#pragma unroll
+    for (int e = 0; e < kTilesG; ++e)
+      if (e == static_cast<int>(lg)) S = all[e];
+    if (S > kTilesDir) {                           // more than 8192 * 16Ki bitmap bits
+      if (tid == 0) set_err(J.status, PIVCO_E_UNSUPPORTED);
+      return;
+    }
   }
+  if (tid < 256) {
+    uint32_t ex = 0, nsl = 0;
+#pragma unroll
+    for (int e = 0; e < kTilesG; ++e)
+      if (e == static_cast<int>(lg)) { ex = inc[e] - ns[e]; nsl = ns[e]; }
+    for (uint32_t w = 0; w < wave; ++w) ex += sm.tot[lg][w];
+    sm.sbase[tid] = ex;
+    if (tid == 255) sm.sbase[256] = ex + nsl;
+  }
+  const bool pos_lds = (K + 1) * I <= kTilesPos;
   for (uint32_t k = tid; k <= K; k += kTilesNT) {
     const uint64_t s = static_cast<uint64_t>(k) * kTileOut;
-    T[static_cast<uint64_t>(k) * kTabCols] = make_uint2(s < n ? static_cast<uint32_t>(s) : n, 0u);
+    const uint32_t x = s < n ? static_cast<uint32_t>(s) : n;
+    if (pos_lds) sm.pos[k] = x;
+    else T[static_cast<uint64_t>(k) * kTabCols] = make_uint2(x, 0u);
+  }
+  __syncthreads();
+  const uint32_t LG = 9 + lg, spr = 4u << lg;      // G = 1 << LG bits = spr chunks
+  // node of every piece: one search per thread for the start of its run
+  {
+    const uint32_t per = (S + kTilesNT - 1) / kTilesNT;
+    const uint32_t f0 = tid * per, f1 = f0 + per < S ? f0 + per : S;
+    if (f0 < f1) {
+      uint32_t lo = 0, hi = I;                     // last v with sbase[v] <= f0
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sm.sbase[mid] <= f0) lo = mid; else hi = mid;
+      }
+      for (uint32_t f = f0; f < f1; ++f) {
+        while (sm.sbase[lo + 1] <= f) ++lo;
+        sm.snode[f] = static_cast<uint8_t>(lo);
+      }
+    }
+  }
+  __syncthreads();
+  // counting pass: a row of spr lanes per piece, four pieces per row in flight
+  {
+    constexpr int U = 4;
+    const uint32_t rows = kWave / spr, row = lane / spr, rl = lane % spr;
+    for (uint32_t f0 = wave * rows; f0 < S; f0 += U * NW * rows) {
+      uint4 x[U];
+      uint64_t q[U], g0[U], g1[U];
+      const uint8_t *pp[U];
+      uint64_t nbs[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t f = f0 + u * NW * rows + row;
+        const uint32_t v = sm.snode[f < S ? f : 0];
+        const bool raw = !t.kind[v];
+        pp[u] = raw ? J.in : scr;
+        nbs[u] = raw ? J.in_len : scr_bytes;
+        g0[u] = raw ? 8ull * (h.blk + t.boff[v]) : 32ull * (h.ans_word0 + t.boff[v]);
+        g1[u] = f < S ? g0[u] + t.nv[v] : g0[u];   // no bits counted for f >= S
+        q[u] = ((((g0[u] >> LG) + (f < S ? f - sm.sbase[v] : 0u)) << LG) >> 3) + 16ull * rl;
+        x[u] = chunk_load(pp[u], nbs[u], q[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        uint32_t c = chunk_popc(x[u], pp[u], nbs[u], q[u], g0[u], g1[u]);
+        for (uint32_t m = spr >> 1; m >= 1; m >>= 1) c += __shfl_xor(c, static_cast<int>(m), static_cast<int>(spr));
+        const uint32_t f = f0 + u * NW * rows + row;
+        if (rl == 0 && f < S) sm.dir[f] = c;
+      }
+    }
   }
   __syncthreads();
   // exclusive scan of the directory (contiguous runs per thread), dir[S] = total
@@ -1702,46 +1824,27 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const ui
     const uint32_t per = (S + kTilesNT - 1) / kTilesNT;
     const uint32_t f0 = tid * per, f1 = f0 + per < S ? f0 + per : S;
     uint32_t loc = 0;
-    for (uint32_t f = f0; f < f1; ++f) loc += dir[f];
-    const uint32_t inc = wave_incl_scan(loc);
-    if (lane == kWave - 1) tot[wave] = inc;
+    for (uint32_t f = f0; f < f1; ++f) loc += sm.dir[f];
+    const uint32_t incl = wave_incl_scan(loc);
+    if (lane == kWave - 1) sm.tot[0][wave] = incl;
     __syncthreads();
-    uint32_t run = inc - loc;
-    for (uint32_t w = 0; w < wave; ++w) run += tot[w];
+    uint32_t run = incl - loc;
+    for (uint32_t w = 0; w < wave; ++w) run += sm.tot[0][w];
     for (uint32_t f = f0; f < f1; ++f) {
-      const uint32_t c = dir[f];
-      dir[f] = run;
+      const uint32_t c = sm.dir[f];
+      sm.dir[f] = run;
       run += c;
     }
     if (tid == kTilesNT - 1) {
       uint32_t all = 0;
-      for (uint32_t w = 0; w < NW; ++w) all += tot[w];
-      dir[S] = all;
+      for (uint32_t w = 0; w < NW; ++w) all += sm.tot[0][w];
+      sm.dir[S] = all;
     }
   }
   __syncthreads();
-  for (uint32_t d = 0; d < h.maxlen; ++d) {
-    const uint32_t v0 = h.lvl[d], m = h.lvl[d + 1] - v0;
-    for (uint32_t p = tid; p < m * (K + 1); p += kTilesNT) {
-      const uint32_t v = v0 + p / (K + 1), k = p % (K + 1);
-      uint2 *row = T + static_cast<uint64_t>(k) * kTabCols;
-      const uint32_t nv = t.nv[v];
-      const uint32_t s = row[v].x < nv ? row[v].x : nv;
-      const uint32_t j = s / G;
-      const uint64_t base = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
-      const uint32_t r = dir[sbase[v] + j] - dir[sbase[v]] +
-                         (t.kind[v] ? popc_range(scr, scr_bytes, base + static_cast<uint64_t>(j) * G, base + s)
-                                    : popc_range(J.in, J.in_len, base + static_cast<uint64_t>(j) * G, base + s));
-      row[v].y = r;
-      const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
-      const uint32_t c0 = cc & 0xFFFF, c1 = cc >> 16;
-      if (!(c0 & 0x8000)) row[c0].x = s - r < t.nv[c0] ? s - r : t.nv[c0];
-      if (!(c1 & 0x8000)) row[c1].x = r < t.nv[c1] ? r : t.nv[c1];
-      if (k == K && (r != t.nr[v] || s != nv)) atomicCAS(&err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && err) set_err(J.status, err);
+  if (pos_lds) tiles_levels<true>(sm, J, T, K, LG, scr, scr_bytes);
+  else tiles_levels<false>(sm, J, T, K, LG, scr, scr_bytes);
+  if (tid == 0 && sm.err) set_err(J.status, sm.err);
 }
 
 // Plan: one wave per work item parses and validates the block's header from
@@ -1886,11 +1989,11 @@ hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, u
   return hipGetLastError();
 }
 
-hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const uint2 *blocks,
-                        const TiledBlock *tiled, uint32_t n_tiled, const void *recs,
-                        const uint32_t *scratch, uint64_t scratch_words, uint2 *tab) {
+hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const TiledBlock *tiled,
+                        uint32_t n_tiled, const void *recs, const uint32_t *scratch,
+                        uint64_t scratch_words, uint2 *tab) {
   if (n_tiled == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tiles, dim3(n_tiled), dim3(kTilesNT), 0, s, jobs, blocks, tiled, n_tiled,
+  hipLaunchKernelGGL(k_tiles, dim3(n_tiled), dim3(kTilesNT), 0, s, jobs, tiled, n_tiled,
                      static_cast<const ParsedBlock *>(recs), scratch, scratch_words, tab);
   return hipGetLastError();
 }

@@ -164,9 +164,9 @@ const char *merge_variant_name(uint32_t v);
 int merge_variant_occupancy(uint32_t v);
 hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, uint32_t n_blocks,
                        void *recs);
-hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const uint2 *blocks,
-                        const TiledBlock *tiled, uint32_t n_tiled, const void *recs,
-                        const uint32_t *scratch, uint64_t scratch_words, uint2 *tab);
+hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const TiledBlock *tiled,
+                        uint32_t n_tiled, const void *recs, const uint32_t *scratch,
+                        uint64_t scratch_words, uint2 *tab);
 hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const JobDev *jobs,
                         const uint2 *items, const void *recs,
                         const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,

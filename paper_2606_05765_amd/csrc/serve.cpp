@@ -356,7 +356,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
                             reinterpret_cast<const uint2 *>(s.ws + o_ritems), nr, ctr, scr,
                             -1) != hipSuccess)
         return PIVCO_E_DEVICE;
-      if (launch_tiles(s.stream, dj, d_blocks, d_tiled, nt, recs, scr, sw, d_tab) != hipSuccess)
+      if (launch_tiles(s.stream, dj, d_tiled, nt, recs, scr, sw, d_tab) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (ni && launch_merge(variant, std::max<uint32_t>(1, std::min(mgrid_full, ni)), s.stream, dj,
                              reinterpret_cast<const uint2 *>(s.ws + o_items), recs,
