@@ -85,9 +85,11 @@ struct HostPlan {
   WorkLists w;                 // blocks, rANS blocks, split blocks, merge items
   std::vector<int32_t> status0;
   uint64_t scratch_words = 0;
+  uint64_t chunk_cap = 0;      // rANS chunk list capacity (bound over the jobs)
   // workspace layout (byte offsets)
   uint64_t off_ctr = 0, off_jobs = 0, off_blocks = 0, off_items = 0, off_ritems = 0,
-           off_tiled = 0, off_status0 = 0, off_recs = 0, off_tab = 0, off_scratch = 0, total = 0;
+           off_tiled = 0, off_status0 = 0, off_recs = 0, off_tab = 0, off_chunks = 0, off_scratch = 0,
+           total = 0;
 };
 
 void layout(HostPlan &p) {
@@ -101,6 +103,7 @@ void layout(HostPlan &p) {
   p.off_status0 = o; o = align_up(o + 4ull * p.count, 256);
   p.off_recs = o; o = align_up(o + static_cast<uint64_t>(kParsedBlockBytes) * p.w.blocks.size(), 256);
   p.off_tab = o; o = align_up(o + 8 * p.w.tab_entries, 256);
+  p.off_chunks = o; o = align_up(o + sizeof(RansChunk) * p.chunk_cap, 256);
   p.off_scratch = o; o = align_up(o + 4 * p.scratch_words + 64, 256);
   // header gathering reuses the start of the workspace before the upload
   const uint64_t gather = align_up(sizeof(pivco_job) * p.count, 256) + kHeaderBytes * p.count;
@@ -149,6 +152,7 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
   p.jobs.assign(count, JobDev{});
   p.status0.assign(count, PIVCO_OK);
   p.w.clear();
+  p.chunk_cap = 0;
   uint64_t sw = 0;
   std::vector<StreamHdr> hs(count);
   std::vector<pivco_status> sts(count);
@@ -183,6 +187,7 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
     d.scratch_base = sw;
     d.ans_words = sh.ans_words;
     sw = align_up(sw + sh.ans_words, 4);
+    p.chunk_cap += rans_chunk_bound(sh.ans_words, sh.n_blocks, sh.chunk_log2);
     p.w.add_job(j, sh.n_total, sh.n_blocks, sh.block_size, sh.ans_words != 0,
                 split_threshold(jb.in_len, sh.ans_words, sh.n_blocks, batch_symbols, device_cus()));
   }
@@ -216,6 +221,7 @@ struct Dev {
   const int32_t *status0;
   void *recs;
   uint2 *tab;
+  RansChunk *chunks;
   uint32_t *scratch;
 };
 
@@ -231,17 +237,22 @@ Dev dev_ptrs(const HostPlan &p, void *d_ws) {
   d.tab = reinterpret_cast<uint2 *>(ws + p.off_tab);
   d.status0 = reinterpret_cast<const int32_t *>(ws + p.off_status0);
   d.recs = ws + p.off_recs;
+  d.chunks = reinterpret_cast<RansChunk *>(ws + p.off_chunks);
   d.scratch = reinterpret_cast<uint32_t *>(ws + p.off_scratch);
   return d;
 }
 
-pivco_tune default_tune(uint32_t n_items, uint32_t n_ritems) {
+// rans_grid: workgroups of 4 waves, each wave decoding two chunks at a time;
+// two workgroups per CU, so that no SIMD runs more than two decoding waves
+// (a chunk is a chain of dependent steps: the waves that hold one set the
+// kernel's length, and more of them on one SIMD only slow each other).
+pivco_tune default_tune(uint32_t n_items, uint64_t chunk_cap) {
   pivco_tune t{};
   t.merge_variant = 0;
   const uint32_t g = static_cast<uint32_t>(device_cus() * merge_variant_occupancy(0));
   t.merge_grid = std::max<uint32_t>(1, std::min<uint32_t>(g, n_items ? n_items : 1));
-  const uint32_t rg = static_cast<uint32_t>(device_cus() * rans_occupancy());
-  t.rans_grid = std::max<uint32_t>(1, std::min<uint32_t>(rg, n_ritems ? n_ritems : 1));
+  const uint64_t rg = 2ull * device_cus();
+  t.rans_grid = static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(rg, (chunk_cap + 7) / 8)));
   return t;
 }
 
@@ -251,11 +262,12 @@ pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, con
   Dev d = dev_ptrs(p, d_ws);
   const WorkLists &w = p.w;
   if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
-  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs) != hipSuccess)
+  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs, d.ctr,
+                  d.chunks, p.chunk_cap) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (!w.ritems.empty() &&
-      launch_rans(t.rans_grid, s, d.jobs, d.ritems, static_cast<uint32_t>(w.ritems.size()), d.ctr,
-                  d.scratch, -1) != hipSuccess)
+      launch_rans(t.rans_grid, s, d.jobs, d.recs, d.ritems, d.ctr, d.chunks, p.chunk_cap, d.scratch,
+                  -1) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
@@ -343,8 +355,7 @@ pivco_status pivco_decode_batch(const pivco_job *h_jobs, uint32_t count, int32_t
   pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
   if (st) return st;
   if (count == 0) return PIVCO_OK;
-  const pivco_tune t = default_tune(static_cast<uint32_t>(p.w.items.size()),
-                                    static_cast<uint32_t>(p.w.ritems.size()));
+  const pivco_tune t = default_tune(static_cast<uint32_t>(p.w.items.size()), p.chunk_cap);
   return enqueue_batch(p, d_ws, d_status, t, s, nullptr, nullptr);
 }
 
@@ -363,13 +374,14 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
   Dev d = dev_ptrs(p, d_ws);
   const WorkLists &w = p.w;
   if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
-  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs) != hipSuccess)
+  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs, d.ctr,
+                  d.chunks, p.chunk_cap) != hipSuccess)
     return PIVCO_E_DEVICE;
   // one launch per block (rANS), then the boundaries of split blocks, then
   // one merge launch per item, in stream order
   for (size_t r = 0; r < w.ritems.size(); ++r)
-    if (launch_rans(1, s, d.jobs, d.ritems, static_cast<uint32_t>(w.ritems.size()), d.ctr,
-                    d.scratch, static_cast<int32_t>(r)) != hipSuccess)
+    if (launch_rans(1, s, d.jobs, d.recs, d.ritems, d.ctr, d.chunks, p.chunk_cap, d.scratch,
+                    static_cast<int32_t>(r)) != hipSuccess)
       return PIVCO_E_DEVICE;
   if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
@@ -402,7 +414,7 @@ pivco_status pivco_batch_plan_create(const pivco_job *h_jobs, uint32_t count, in
   bp->ws = d_ws;
   bp->status = d_status;
   bp->tune = tune ? *tune : default_tune(static_cast<uint32_t>(bp->plan.w.items.size()),
-                                         static_cast<uint32_t>(bp->plan.w.ritems.size()));
+                                         bp->plan.chunk_cap);
   if (bp->tune.merge_variant >= merge_variant_count() || bp->tune.merge_grid == 0 ||
       bp->tune.rans_grid == 0) {
     delete bp;
@@ -454,8 +466,7 @@ pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_
   HostPlan p;
   pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
   if (st) return st;
-  pivco_tune best = default_tune(static_cast<uint32_t>(p.w.items.size()),
-                                 static_cast<uint32_t>(p.w.ritems.size()));
+  pivco_tune best = default_tune(static_cast<uint32_t>(p.w.items.size()), p.chunk_cap);
   if (p.w.items.empty()) { *out = best; return PIVCO_OK; }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PIVCO_E_DEVICE;

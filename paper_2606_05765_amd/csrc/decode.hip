@@ -125,6 +125,7 @@ struct BlockHdr {
   uint32_t comp, n, mode, csym, cw, I, maxlen, kb;
   uint32_t raw_base, raw_end, n_ans;
   uint32_t kraft;
+  uint32_t chunk0, nchunk; // the block's rANS chunks in the batch's chunk list
   uint32_t cnt[17], fc[18], lbase[17], lvl[18];
   uint64_t lvl_total[17];  // symbols passing each level (sum of n_v)
 };
@@ -450,153 +451,196 @@ __device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t
 // ---------------------------------------------------------------------------
 // Kernel: rANS decode of entropy-coded node bitmaps into scratch
 // ---------------------------------------------------------------------------
+// The plan kernel lists every chunk of every rANS node (walk_rans); k_rans
+// decodes them two at a time per wave: lanes 0-31 run one chunk's 32
+// interleaved states, lanes 32-63 another's.  Per step every active lane
+// decodes one bit; lanes whose state fell below 2^16 read the chunk's next
+// 16-bit words in lane order (the cursor + their rank in the half-wave's
+// ballot) from a window of the chunk's words staged in LDS; the half-wave's
+// 32 decoded bits are its part of the ballot of the bits (bit i = lane i).
 constexpr int kRansNT = 256;
-constexpr int kRansWin = 2048;        // u16 words per wave window in LDS
-constexpr int kMaxChunks = 1024;
+constexpr int kRansWin = 1024;        // u16 words per half-wave window in LDS
 
-struct RansChunk {
-  uint64_t src;        // byte offset of the chunk in the stream
-  uint64_t dst;        // scratch word of the chunk's first output word
-  uint32_t nbits;
-  uint32_t nw;
-  uint32_t p1q;
-  uint32_t pad;
-};
-
-struct RansSmem {
-  BlockHdr h;
-  NodeTab t;
-  RansChunk ch[kMaxChunks];
-  uint32_t nch;
-  uint16_t win[kRansNT / kWave][kRansWin];
-};
-
-__device__ void rans_chunk(const JobDev &J, const RansChunk &c, uint32_t *scratch,
-                           uint16_t *win, int32_t &werr) {
-  const uint32_t lane = lane_id();
-  const uint8_t *base = J.in + c.src;
-  const bool lane_ok = lane < kRansLanes;
-  uint32_t x = lane_ok ? reinterpret_cast<const uint32_t *>(base)[1 + lane] : kRansL;
-  if (__ballot(x < kRansL)) werr = PIVCO_E_CORRUPT;
-  const uint16_t *words = reinterpret_cast<const uint16_t *>(base + kChunkHdr);
-  const uint32_t f0 = kRansM - c.p1q, f1 = c.p1q;
-  const uint32_t K = (c.nbits + 31) / 32;
-  uint32_t pos = 0, wstart = 0, wend = 0;
-  uint32_t *dst = scratch + c.dst;
-  const uint64_t lanemask_lt = (1ull << lane) - 1;
-  for (uint32_t k = 0; k < K; ++k) {
-    const bool act = lane_ok && (32 * k + lane < c.nbits);
-    const uint32_t slot = x & (kRansM - 1);
-    const bool bit = slot >= f0;
-    if (act) x = (bit ? f1 : f0) * (x >> 12) + slot - (bit ? f0 : 0u);
-    const bool need = act && x < kRansL;
-    const uint64_t m = __ballot(need);
-    const uint32_t cnt = __popcll(m);
-    if (pos + cnt > wend) {       // refill the window (wave-uniform branch)
-      // a corrupt chunk can ask for more words than it holds: the window
-      // never starts past the chunk's end, and decoding stops
-      wstart = pos < c.nw ? pos : c.nw;
-      wend = c.nw - wstart > kRansWin ? wstart + kRansWin : c.nw;
-      for (uint32_t i = lane; i < wend - wstart; i += kWave) win[i] = words[wstart + i];
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (pos + cnt > wend) {
-        werr = PIVCO_E_CORRUPT;
-        break;
+// Lists the rANS chunks of the block parsed in h/t (one lane): walks the
+// rANS bodies that follow the raw bodies (each: u16 probability, u16 zero,
+// u32 length, then per chunk of 2^chunk_log2 bits a u32 word count, the 32
+// u32 lane states and the words, padded to 4 bytes), checks every size, and
+// appends the chunks to the batch's list (a first pass counts them and
+// reserves their slots).  Returns a status.
+__device__ int32_t walk_rans(const JobDev &J, BlockHdr &h, const NodeTab &t, Counters *ctr,
+                             RansChunk *chunks, uint64_t cap) {
+  const uint8_t *bp = J.in + h.blk;
+  const uint64_t comp = h.comp, C = 1ull << J.chunk_log2;
+  for (int pass = 0; pass < 2; ++pass) {
+    uint32_t nch = 0;
+    uint64_t o = h.raw_end;
+    for (uint32_t i = 0; i < h.I; ++i) {
+      if (!t.kind[i]) continue;
+      while (o & 3) {
+        if (o >= comp || bp[o]) return PIVCO_E_CORRUPT;
+        ++o;
       }
-    }
-    if (need) {
-      const uint32_t idx = pos + __popcll(m & lanemask_lt);
-      const uint32_t w = idx < wend ? win[idx - wstart] : 0u;
-      x = (x << 16) | w;
-    }
-    pos += cnt;
-    const uint64_t bm = __ballot(act && bit);
-    if (lane == 0) dst[k] = static_cast<uint32_t>(bm);
-  }
-  if (pos != c.nw) werr = PIVCO_E_CORRUPT;
-  if (__ballot(lane_ok && x != kRansL)) werr = PIVCO_E_CORRUPT;
-  // zero padding after the last word
-  const uint32_t used = kChunkHdr + 2 * c.nw, size = (used + 3) & ~3u;
-  if (lane < size - used && base[used + lane] != 0) werr = PIVCO_E_CORRUPT;
-  __builtin_amdgcn_wave_barrier();
-}
-
-__global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const uint2 *items,
-                                                   uint32_t n_items, Counters *ctr,
-                                                   uint32_t *scratch, int32_t single) {
-  __shared__ RansSmem sm;
-  __shared__ uint32_t s_item;
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  for (bool first = true;; first = false) {
-    if (single >= 0 && !first) break;
-    if (tid == 0) s_item = single >= 0 ? static_cast<uint32_t>(single) : atomicAdd(&ctr->rans_next, 1u);
-    __syncthreads();
-    const uint32_t it = s_item;
-    __syncthreads();
-    if (it >= n_items) break;
-    const uint2 item = items[it];
-    const JobDev &J = jobs[item.x];
-    if (tid == 0) parse_offsets(J, item.y, sm.h);
-    __syncthreads();
-    parse_block<kRansNT>(J, item.y, sm.h, sm.t, GlbBytes{J.in + sm.h.blk});
-    if (sm.h.err) {
-      if (tid == 0) set_err(J.status, sm.h.err);
-      continue;
-    }
-    if (sm.h.mode == 1 || sm.h.n_ans == 0) continue;
-    // walk the rANS bodies: body headers and chunk headers (serial, thread 0)
-    if (tid == 0) {
-      int32_t err = 0;
-      uint32_t nch = 0;
-      const uint8_t *bp = J.in + sm.h.blk;
-      uint64_t o = sm.h.raw_end;
-      const uint64_t comp = sm.h.comp;
-      const uint64_t C = 1ull << J.chunk_log2;
-      for (uint32_t i = 0; i < sm.h.I && !err; ++i) {
-        if (!sm.t.kind[i]) continue;
-        while (o & 3) {
-          if (o >= comp || bp[o]) { err = PIVCO_E_CORRUPT; break; }
-          ++o;
-        }
-        if (err) break;
-        if (o + 8 > comp || sm.t.nv[i] == 0) { err = PIVCO_E_CORRUPT; break; }
-        const uint32_t p1q = bp[o] | (bp[o + 1] << 8);
-        const uint32_t pad = bp[o + 2] | (bp[o + 3] << 8);
-        const uint32_t blen = *reinterpret_cast<const uint32_t *>(bp + o + 4);
-        if (pad || p1q < 1 || p1q > 4095 || o + 8 + blen > comp) { err = PIVCO_E_CORRUPT; break; }
-        const uint64_t body = o + 8;
-        uint64_t co = 0;
-        const uint64_t nv = sm.t.nv[i];
-        for (uint64_t s = 0; s < nv; s += C) {
-          const uint64_t cl = nv - s < C ? nv - s : C;
-          if (co + kChunkHdr > blen) { err = PIVCO_E_CORRUPT; break; }
-          const uint32_t nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
-          const uint64_t size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
-          if (nw > C || co + size > blen) { err = PIVCO_E_CORRUPT; break; }
-          if (nch >= kMaxChunks) { err = PIVCO_E_UNSUPPORTED; break; }
-          RansChunk &c = sm.ch[nch++];
-          c.src = sm.h.blk + body + co;
-          c.dst = sm.h.ans_word0 + sm.t.boff[i] + s / 32;
-          c.nbits = static_cast<uint32_t>(cl);
+      if (o + 8 > comp || t.nv[i] == 0) return PIVCO_E_CORRUPT;
+      const uint32_t p1q = bp[o] | (bp[o + 1] << 8);
+      const uint32_t pad = bp[o + 2] | (bp[o + 3] << 8);
+      const uint32_t blen = *reinterpret_cast<const uint32_t *>(bp + o + 4);
+      if (pad || p1q < 1 || p1q > 4095 || o + 8 + blen > comp) return PIVCO_E_CORRUPT;
+      const uint64_t body = o + 8;
+      uint64_t co = 0;
+      const uint64_t nv = t.nv[i];
+      for (uint64_t s = 0; s < nv; s += C) {
+        if (co + kChunkHdr > blen) return PIVCO_E_CORRUPT;
+        const uint32_t nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
+        const uint64_t size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
+        if (nw > C || co + size > blen) return PIVCO_E_CORRUPT;
+        if (pass == 1) {
+          RansChunk c;
+          c.src = h.blk + body + co;
+          c.dst = h.ans_word0 + t.boff[i] + s / 32;
+          c.nbits = static_cast<uint32_t>(nv - s < C ? nv - s : C);
           c.nw = nw;
           c.p1q = p1q;
-          co += size;
+          c.job = h.job;
+          chunks[h.chunk0 + nch] = c;
         }
-        if (!err && co != blen) err = PIVCO_E_CORRUPT;
-        o = body + blen;
+        ++nch;
+        co += size;
       }
-      if (!err && o != comp) err = PIVCO_E_CORRUPT;
-      sm.nch = err ? 0 : nch;
-      if (err) set_err(J.status, err);
+      if (co != blen) return PIVCO_E_CORRUPT;
+      o = body + blen;
     }
-    __syncthreads();
-    int32_t werr = 0;
-    for (uint32_t c = wave; c < sm.nch; c += kRansNT / kWave)
-      rans_chunk(J, sm.ch[c], scratch, sm.win[wave], werr);
-    if (werr && lane_id() == 0) set_err(J.status, werr);
-    __syncthreads();
+    if (o != comp) return PIVCO_E_CORRUPT;
+    if (pass == 0) {
+      const uint32_t base = atomicAdd(&ctr->rans_chunks, nch);
+      if (static_cast<uint64_t>(base) + nch > cap) {
+        // slots reserved past the list's capacity stay unused (k_rans reads
+        // at most cap); the ones below it become empty chunks
+        for (uint64_t f = base; f < cap; ++f) chunks[f] = RansChunk{0, 0, 0, 0, 1, h.job};
+        return PIVCO_E_UNSUPPORTED;
+      }
+      h.chunk0 = base;
+      h.nchunk = nch;
+    }
+  }
+  return PIVCO_OK;
+}
+
+// Decodes chunks ia (lanes 0-31) and ib (lanes 32-63) of the list; an index
+// at or past `end`, or an empty chunk, leaves its half idle.  The step is
+// branch-free except for the window refill: an inactive lane keeps its
+// state, the window word is read at a clamped index and used only by lanes
+// that renormalise, and lane j of a half collects the half's decoded word of
+// every step k = j (mod 32) and stores it with the other lanes every 32
+// steps (one coalesced 128-byte store).
+typedef __attribute__((address_space(1))) const uint16_t GlobalCU16;
+
+__device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t ia, uint32_t ib,
+                          uint32_t end, uint32_t *scratch, uint16_t (*win)[kRansWin]) {
+  const uint32_t lane = lane_id(), half = lane >> 5, hl = lane & 31;
+  const uint32_t idx = half ? ib : ia;
+  RansChunk c = RansChunk{0, 0, 0, 0, 1, 0};
+  if (idx < end) c = chunks[idx];
+  const bool has = c.nbits != 0;
+  const uint8_t *base = has ? jobs[c.job].in + c.src : nullptr;
+  uint32_t x = has ? reinterpret_cast<const uint32_t *>(base)[1 + hl] : kRansL;
+  bool err = has && x < kRansL;
+  GlobalCU16 *words = has ? (GlobalCU16 *)(base + kChunkHdr) : nullptr;   // C cast: generic to global
+  uint16_t *w = win[half];
+  const uint32_t f0 = kRansM - c.p1q, f1 = c.p1q;
+  const uint32_t K = (c.nbits + 31) / 32;
+  const uint32_t ka = __builtin_amdgcn_readlane(K, 0), kb = __builtin_amdgcn_readlane(K, 32);
+  const uint32_t kmax = ka > kb ? ka : kb;
+  uint32_t pos = 0, wstart = 0, wend = 0, mine = 0;
+  uint32_t *dst = scratch + c.dst;
+  const uint32_t lt = (1u << hl) - 1;
+  for (uint32_t k = 0; k < kmax; ++k) {
+    const bool act = 32 * k + hl < c.nbits;
+    const uint32_t slot = x & (kRansM - 1);
+    const bool bit = slot >= f0;
+    const uint32_t xn = __umul24(bit ? f1 : f0, x >> 12) + slot - (bit ? f0 : 0u);
+    x = act ? xn : x;
+    const bool need = act && x < kRansL;
+    const uint64_t m = __ballot(need);
+    const uint32_t mh = half ? static_cast<uint32_t>(m >> 32) : static_cast<uint32_t>(m);
+    const uint32_t cnt = __popc(mh);
+    const bool refill = pos + cnt > wend;
+    if (__ballot(refill)) {                         // some half needs more words
+      if (refill) {
+        // a corrupt chunk can ask for more words than it holds: the window
+        // never starts past the chunk's end
+        wstart = pos < c.nw ? pos : c.nw;
+        wend = c.nw - wstart > kRansWin ? wstart + kRansWin : c.nw;
+        const uint32_t nwin = wend - wstart;
+        for (uint32_t i0 = 0; i0 < nwin; i0 += 32 * 8) {
+          uint16_t v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + 32 * u + hl;
+            v[u] = i < nwin ? words[wstart + i] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const uint32_t i = i0 + 32 * u + hl;
+            if (i < nwin) w[i] = v[u];
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (refill && pos + cnt > wend) err = true;
+    }
+    const uint32_t i = pos + __popc(mh & lt) - wstart;
+    const uint32_t wv = w[i < kRansWin ? i : 0u];
+    x = need ? ((x << 16) | (i < wend - wstart ? wv : 0u)) : x;
+    pos += cnt;
+    const uint64_t bm = __ballot(act && bit);
+    const uint32_t word = half ? static_cast<uint32_t>(bm >> 32) : static_cast<uint32_t>(bm);
+    mine = (k & 31) == hl ? word : mine;
+    if ((k & 31) == 31 || k + 1 == kmax) {          // store the last (up to) 32 steps' words
+      const uint32_t kk = (k & ~31u) + hl;
+      if (hl <= (k & 31) && kk < K) dst[kk] = mine;
+    }
+  }
+  if (has) {
+    if (pos != c.nw || x != kRansL) err = true;
+    const uint32_t used = kChunkHdr + 2 * c.nw, size = (used + 3) & ~3u;
+    if (hl < size - used && base[used + hl] != 0) err = true;
+  }
+  const uint64_t e = __ballot(err);
+  const uint32_t eh = half ? static_cast<uint32_t>(e >> 32) : static_cast<uint32_t>(e);
+  if (hl == 0 && eh) set_err(jobs[c.job].status, PIVCO_E_CORRUPT);
+}
+
+// Decodes the batch's listed chunks, a pair per wave from a shared counter;
+// or, for single >= 0, only the chunks of block ritems[single] with one
+// workgroup (the per-block launch mode).
+__global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const ParsedBlock *recs,
+                                                   const uint2 *ritems, Counters *ctr,
+                                                   const RansChunk *chunks, uint64_t cap,
+                                                   uint32_t *scratch, int32_t single) {
+  __shared__ uint16_t win[kRansNT / kWave][2][kRansWin];
+  const uint32_t wave = wave_id();
+  constexpr uint32_t NW = kRansNT / kWave;
+  uint32_t first = 0, end = 0;
+  if (single >= 0) {
+    const BlockHdr &h = recs[ritems[single].x].h;
+    if (!h.err) { first = h.chunk0; end = h.chunk0 + h.nchunk; }
+  } else {
+    const uint32_t n = ctr->rans_chunks;
+    end = n < cap ? n : static_cast<uint32_t>(cap);
+  }
+  for (uint32_t it = 0;; ++it) {
+    uint32_t pair;
+    if (single >= 0) {
+      pair = wave + NW * it;
+    } else {
+      uint32_t p = 0;
+      if (lane_id() == 0) p = atomicAdd(&ctr->rans_next, 1u);
+      pair = __builtin_amdgcn_readfirstlane(p);
+    }
+    const uint32_t ia = first + 2 * pair;
+    if (ia >= end) break;
+    rans_pair(jobs, chunks, ia, ia + 1, end, scratch, win[wave]);
   }
 }
 
@@ -1855,7 +1899,9 @@ constexpr int kPlanWaves = 4;
 constexpr uint32_t kHdrMax = kBlockFixed + kLenTable + 32 + 4 * kMaxInternal;   // largest header
 
 __global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs, const uint2 *items,
-                                                             uint32_t n_items, ParsedBlock *recs) {
+                                                             uint32_t n_items, ParsedBlock *recs,
+                                                             Counters *ctr, RansChunk *chunks,
+                                                             uint64_t chunk_cap) {
   __shared__ ParsedBlock pb[kPlanWaves];
   __shared__ uint32_t hdr[kPlanWaves][kHdrMax / 4 + 1];
   const uint32_t wave = threadIdx.x >> 6;
@@ -1888,6 +1934,15 @@ __global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs,
   }
   wave_sync_lds();
   parse_block_wave(J, item.y, h, t, SplitBytes{reinterpret_cast<const uint8_t *>(hdr[wave]), hn, g}, true);
+  if (lane == 0) {
+    h.chunk0 = 0;
+    h.nchunk = 0;
+    if (!h.err && h.mode == 0 && h.n_ans) {
+      const int32_t e = walk_rans(J, h, t, ctr, chunks, chunk_cap);
+      if (e) h.err = e;
+    }
+  }
+  wave_sync_lds();
   const uint4 *src = reinterpret_cast<const uint4 *>(&pb[wave]);
   uint4 *dst = reinterpret_cast<uint4 *>(recs + it);
   for (uint32_t i = lane; i < sizeof(ParsedBlock) / 16; i += kWave) dst[i] = src[i];
@@ -1897,7 +1952,7 @@ __global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs,
 // not a memset node).
 __global__ void k_init(Counters *ctr, int32_t *status, const int32_t *status0, uint32_t count) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) { ctr->merge_next = 0; ctr->rans_next = 0; }
+  if (i == 0) { ctr->merge_next = 0; ctr->rans_next = 0; ctr->rans_chunks = 0; }
   if (i < count) status[i] = status0[i];
 }
 
@@ -1982,10 +2037,10 @@ hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const Jo
 }
 
 hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, uint32_t n_blocks,
-                       void *recs) {
+                       void *recs, Counters *ctr, RansChunk *chunks, uint64_t chunk_cap) {
   if (n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan, dim3((n_blocks + kPlanWaves - 1) / kPlanWaves), dim3(kWave * kPlanWaves), 0,
-                     s, jobs, blocks, n_blocks, static_cast<ParsedBlock *>(recs));
+                     s, jobs, blocks, n_blocks, static_cast<ParsedBlock *>(recs), ctr, chunks, chunk_cap);
   return hipGetLastError();
 }
 
@@ -1998,9 +2053,11 @@ hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const TiledBlock *til
   return hipGetLastError();
 }
 
-hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
-                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single) {
-  hipLaunchKernelGGL(k_rans, dim3(grid), dim3(kRansNT), 0, s, jobs, items, n_items, ctr, scratch,
+hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const void *recs,
+                       const uint2 *ritems, Counters *ctr, const RansChunk *chunks,
+                       uint64_t chunk_cap, uint32_t *scratch, int32_t single) {
+  hipLaunchKernelGGL(k_rans, dim3(grid), dim3(kRansNT), 0, s, jobs,
+                     static_cast<const ParsedBlock *>(recs), ritems, ctr, chunks, chunk_cap, scratch,
                      single);
   return hipGetLastError();
 }

@@ -83,9 +83,32 @@ static_assert(sizeof(JobDev) == 80, "JobDev layout");
 // Counters at the head of the decode workspace.
 struct Counters {
   uint32_t merge_next;     // next merge work item
-  uint32_t rans_next;      // next rANS work item
-  uint32_t pad[14];
+  uint32_t rans_next;      // next pair of rANS chunks to decode
+  uint32_t rans_chunks;    // rANS chunks listed by the plan kernel
+  uint32_t pad[13];
 };
+
+// One rANS chunk of a node's bitmap, listed by the plan kernel: where its
+// 32 lane states and 16-bit words are, where its decoded bits go, how many.
+struct RansChunk {
+  uint64_t src;            // byte offset of the chunk in the job's stream
+  uint64_t dst;            // scratch word of its first decoded word
+  uint32_t nbits;          // bits it decodes (<= 2^chunk_log2)
+  uint32_t nw;             // 16-bit renormalisation words it holds
+  uint32_t p1q;            // 12-bit probability of a 1 bit
+  uint32_t job;
+};
+static_assert(sizeof(RansChunk) == 32, "RansChunk layout");
+
+// Upper bound on the rANS chunks of a job: a rANS node of n_v bits has
+// ceil(n_v / 2^chunk_log2) chunks and ceil(n_v / 32) scratch words, and a
+// block has at most 255 nodes.
+inline uint64_t rans_chunk_bound(uint64_t ans_words, uint32_t n_blocks, uint32_t chunk_log2) {
+  if (ans_words == 0) return 0;
+  const uint64_t per_bits = chunk_log2 >= 5 ? (ans_words << 5) >> chunk_log2 : ans_words << 5;
+  const uint64_t nodes = std::min<uint64_t>(255ull * n_blocks, ans_words);
+  return per_bits + nodes;
+}
 
 __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
@@ -111,7 +134,7 @@ struct WorkLists {
       const uint64_t sz = std::min<uint64_t>(block_size, n_total - start);
       const uint32_t rec = static_cast<uint32_t>(blocks.size());
       blocks.push_back(make_uint2(j, b));
-      if (ans) ritems.push_back(make_uint2(j, b));
+      if (ans) ritems.push_back(make_uint2(rec, 0u));   // record of a block with rANS nodes
       const uint32_t nt = tiles_of_block(sz, split_min);
       if (nt == 0) {
         sized.push_back({sz, make_uint2(rec, kWholeBlock)});
@@ -163,7 +186,7 @@ uint32_t merge_variant_count();
 const char *merge_variant_name(uint32_t v);
 int merge_variant_occupancy(uint32_t v);
 hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, uint32_t n_blocks,
-                       void *recs);
+                       void *recs, Counters *ctr, RansChunk *chunks, uint64_t chunk_cap);
 hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const TiledBlock *tiled,
                         uint32_t n_tiled, const void *recs, const uint32_t *scratch,
                         uint64_t scratch_words, uint2 *tab);
@@ -172,8 +195,9 @@ hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const Jo
                         const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
                         Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
                         int32_t single);
-hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
-                       uint32_t n_items, Counters *ctr, uint32_t *scratch, int32_t single);
+hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const void *recs,
+                       const uint2 *ritems, Counters *ctr, const RansChunk *chunks,
+                       uint64_t chunk_cap, uint32_t *scratch, int32_t single);
 int rans_occupancy();
 hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
                        uint32_t count);

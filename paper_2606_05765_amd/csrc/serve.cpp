@@ -39,6 +39,7 @@ struct Registered {
   uint64_t n_total, ans_words;
   uint32_t n_blocks, block_size, max_len, chunk_log2;
   WorkLists::Need need;           // merge items, tiles and boundary-table entries
+  uint64_t chunks;                // bound on its rANS chunks
 };
 
 // First-fit allocator over [0, size) with coalescing on free.
@@ -104,10 +105,12 @@ struct pivco_server {
   std::vector<Slot> slots;
   uint64_t ws_bytes_per_slot = 0, pinned_bytes = 0;
   // workspace layout inside a slot
-  uint64_t off_ctr = 0, off_jobs = 0, off_status = 0, off_recs = 0, off_tab = 0, off_scratch = 0;
+  uint64_t off_ctr = 0, off_jobs = 0, off_status = 0, off_recs = 0, off_tab = 0, off_chunks = 0,
+           off_scratch = 0;
   uint64_t off_pstatus = 0;
   uint32_t max_blocks = 0;
   uint64_t max_tiles = 0, max_split = 0, max_tab = 0, max_scratch_words = 0;
+  uint64_t max_chunks = 1u << 16;   // rANS chunks per batch (32 B each)
   WorkLists w;                    // reused by every admission round
 };
 
@@ -140,6 +143,7 @@ pivco_status pivco_server_create(const pivco_server_opts *o, pivco_server **out)
   sv->off_pstatus = pinned;           // statuses copied back into pinned memory
   sv->off_recs = x; x = align_up(x + static_cast<uint64_t>(kParsedBlockBytes) * o->max_blocks, 256);
   sv->off_tab = x; x = align_up(x + 8ull * sv->max_tab, 256);
+  sv->off_chunks = x; x = align_up(x + sizeof(RansChunk) * sv->max_chunks, 256);
   sv->off_scratch = x; x = align_up(x + 4ull * o->max_scratch_words + 64, 256);
   sv->ws_bytes_per_slot = x;
   sv->pinned_bytes = pinned;
@@ -187,6 +191,8 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   if (nb > sv->max_blocks || ans > sv->max_scratch_words) return PIVCO_E_UNSUPPORTED;
   const WorkLists::Need need = WorkLists::need_of(n_total, nb, bs);
   if (need.tiles > sv->max_tiles) return PIVCO_E_UNSUPPORTED;
+  const uint64_t chunks = rans_chunk_bound(ans, nb, h[25]);
+  if (chunks > sv->max_chunks) return PIVCO_E_UNSUPPORTED;
   Registered r;
   r.d_in = static_cast<const uint8_t *>(d_stream);
   r.in_len = len;
@@ -197,6 +203,7 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   r.max_len = h[24];
   r.chunk_log2 = h[25];
   r.need = need;
+  r.chunks = chunks;
   *id = static_cast<uint32_t>(sv->reg.size());
   sv->reg.push_back(r);
   return PIVCO_OK;
@@ -221,7 +228,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
   }();
   const uint32_t variant = sv->opts.merge_variant < merge_variant_count() ? sv->opts.merge_variant : 0;
   const uint32_t mgrid_full = static_cast<uint32_t>(cus * merge_variant_occupancy(variant));
-  const uint32_t rgrid_full = static_cast<uint32_t>(cus * rans_occupancy());
+  const uint32_t rgrid_full = static_cast<uint32_t>(2 * cus);   // two rANS workgroups per CU
   std::vector<uint64_t> out_off(n_req, 0);
   std::deque<uint32_t> pending;
   uint32_t next = 0, done = 0;
@@ -263,7 +270,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
     for (auto &s : sv->slots) {
       if (s.busy || pending.empty()) continue;
       std::vector<uint32_t> batch;
-      uint64_t blocks = 0, tiles = 0, split = 0, tab = 0, scratch = 0;
+      uint64_t blocks = 0, tiles = 0, split = 0, tab = 0, scratch = 0, chunks = 0;
       while (!pending.empty() && batch.size() < sv->opts.max_batch) {
         const uint32_t r = pending.front();
         const Registered &g = sv->reg[reqs[r].id];
@@ -278,6 +285,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         }
         if (blocks + g.n_blocks > sv->max_blocks || tiles + g.need.tiles > sv->max_tiles ||
             split + g.need.split > sv->max_split || tab + g.need.tab_entries > sv->max_tab ||
+            chunks + g.chunks > sv->max_chunks ||
             align_up(scratch + g.ans_words, 4) > sv->max_scratch_words)
           break;
         uint64_t off = 0;
@@ -289,6 +297,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         tiles += g.need.tiles;
         split += g.need.split;
         tab += g.need.tab_entries;
+        chunks += g.chunks;
         scratch = align_up(scratch + g.ans_words, 4);
         batch.push_back(r);
         pending.pop_front();
@@ -351,10 +360,12 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
       const uint2 *d_blocks = reinterpret_cast<const uint2 *>(s.ws + o_blocks);
       const TiledBlock *d_tiled = reinterpret_cast<const TiledBlock *>(s.ws + o_tiled);
       uint2 *d_tab = reinterpret_cast<uint2 *>(s.ws + sv->off_tab);
-      if (launch_plan(s.stream, dj, d_blocks, nb, recs) != hipSuccess) return PIVCO_E_DEVICE;
-      if (nr && launch_rans(std::max<uint32_t>(1, std::min(rgrid_full, nr)), s.stream, dj,
-                            reinterpret_cast<const uint2 *>(s.ws + o_ritems), nr, ctr, scr,
-                            -1) != hipSuccess)
+      RansChunk *d_chunks = reinterpret_cast<RansChunk *>(s.ws + sv->off_chunks);
+      if (launch_plan(s.stream, dj, d_blocks, nb, recs, ctr, d_chunks, chunks) != hipSuccess)
+        return PIVCO_E_DEVICE;
+      if (nr && launch_rans(std::max<uint32_t>(1, std::min<uint32_t>(rgrid_full, static_cast<uint32_t>((chunks + 7) / 8))),
+                            s.stream, dj, recs, reinterpret_cast<const uint2 *>(s.ws + o_ritems), ctr,
+                            d_chunks, chunks, scr, -1) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (launch_tiles(s.stream, dj, d_tiled, nt, recs, scr, sw, d_tab) != hipSuccess)
         return PIVCO_E_DEVICE;
