@@ -1632,71 +1632,124 @@ __device__ __forceinline__ uint32_t range_mask(uint64_t wb, uint64_t b0, uint64_
   return mh & ~((1u << lo) - 1);
 }
 
-// The 16-byte chunk at byte q of p (16-byte aligned, nbytes >= 16
-// readable): an unconditional load (of the first chunk when q's chunk is not
-// wholly inside), so that a thread's chunk loads can all be in flight; then
-// the 1 bits of the chunk at q inside bits [b0, b1) (bit addresses relative
-// to p), with the rare chunk that straddles the end re-read byte by byte.
-__device__ __forceinline__ uint4 chunk_load(const uint8_t *p, uint64_t nbytes, uint64_t q) {
-  return *reinterpret_cast<const uint4 *>(p + (q + 16 <= nbytes ? q : 0));
-}
-__device__ __forceinline__ uint32_t chunk_popc(uint4 x, const uint8_t *p, uint64_t nbytes,
-                                               uint64_t q, uint64_t b0, uint64_t b1) {
-  uint32_t w[4] = {x.x, x.y, x.z, x.w};
-  if (q + 16 > nbytes) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      uint32_t y = 0;
-      for (uint32_t by = 0; by < 4; ++by)
-        if (q + 4 * e + by < nbytes) y |= static_cast<uint32_t>(p[q + 4 * e + by]) << (8 * by);
-      w[e] = y;
-    }
-  }
-  uint32_t c = 0;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) c += __popc(w[e] & range_mask(8 * q + 32 * e, b0, b1));
+// The 16-byte chunk at byte q of p (16-byte aligned): one unconditional
+// load, so that a thread's chunk loads can all be in flight.  A chunk that
+// is not wholly inside the nbytes readable is loaded from the last 16 bytes
+// instead (the buffers hold at least 16), and chunk_popc counts only the
+// bits of the chunk at q that it holds.
+struct Chunk {
+  uint4 x;
+  uint64_t at;             // byte offset the 16 bytes were loaded from
+};
+__device__ __forceinline__ Chunk chunk_load(const uint8_t *p, uint64_t nbytes, uint64_t q) {
+  const uint64_t at = q + 16 <= nbytes ? q : (nbytes >= 16 ? nbytes - 16 : 0);
+  Chunk c;
+  c.x = *reinterpret_cast<const uint4 *>(p + at);
+  c.at = at;
   return c;
 }
+// 1 bits of the chunk at byte q inside bits [b0, b1) (bit addresses relative
+// to p; b1 never past the readable bytes): the range is cut to the chunk and
+// made relative to the loaded bytes, then each word's part is extracted.
+__device__ __forceinline__ uint32_t chunk_popc(const Chunk &c, uint64_t q, uint64_t b0, uint64_t b1) {
+  const int64_t base = 8 * static_cast<int64_t>(c.at);
+  const int64_t l64 = static_cast<int64_t>(b0 > 8 * q ? b0 : 8 * q) - base;
+  const int64_t h64 = static_cast<int64_t>(b1 < 8 * q + 128 ? b1 : 8 * q + 128) - base;
+  const int lo = static_cast<int>(l64 < 0 ? 0 : l64 > 128 ? 128 : l64);
+  const int hi = static_cast<int>(h64 < 0 ? 0 : h64 > 128 ? 128 : h64);
+  const uint32_t w[4] = {c.x.x, c.x.y, c.x.z, c.x.w};
+  uint32_t n = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int l = lo - 32 * e < 0 ? 0 : lo - 32 * e > 32 ? 32 : lo - 32 * e;
+    const int h = hi - 32 * e < 0 ? 0 : hi - 32 * e > 32 ? 32 : hi - 32 * e;
+    const int wd = h > l ? h - l : 0;
+    const uint32_t bits = wd >= 32 ? w[e] : __builtin_amdgcn_ubfe(w[e], static_cast<uint32_t>(l) & 31u,
+                                                                  static_cast<uint32_t>(wd));
+    n += __popc(bits);
+  }
+  return n;
+}
 
-// Boundaries of a split block (one workgroup per block).  First a rank
-// directory over all of the block's bitmaps: every node's bitmap is cut at
-// the absolute G-bit boundaries of its buffer (G = 512 .. 8192: the smallest
-// whose directory fits), the 1 bits of each piece are counted by a row of
-// G/128 lanes (one 16-byte chunk each, coalesced, four pieces per row in
-// flight) and exclusive-scanned across the block, so that a node's 1 bits
-// before any position are two directory entries plus one popcount of less
-// than G bits (G/128 chunk loads, eight in flight).  Then top-down by
-// level, every (node, boundary) pair of the level is one thread: node v's
-// position at boundary k (symbols of the block before k * kTileOut that
-// pass it) gives its rank there, and the rank gives the right child's
-// position (position - rank the left child's).  The root's positions are
-// k * kTileOut.  Positions live in LDS when the block's table fits, else in
-// the table itself.  Table row k, column v holds (position, rank).  A node
-// whose bitmap holds a different number of 1 bits than its header count
-// marks the job corrupt; positions are clamped to the nodes' sizes so that
-// the tiles never read outside their bitmaps.
+// chunk_popc with a fast path for a chunk wholly inside [b0, b1).
+__device__ __forceinline__ uint32_t chunk_count(const Chunk &c, uint64_t q, uint64_t b0, uint64_t b1) {
+  if (c.at == q && 8 * q >= b0 && 8 * q + 128 <= b1)
+    return __popc(c.x.x) + __popc(c.x.y) + __popc(c.x.z) + __popc(c.x.w);
+  return chunk_popc(c, q, b0, b1);
+}
+
+// Boundaries of a split block (one workgroup per block).  A node's rank at
+// a position (its 1 bits before it) is a difference of prefix counts over
+// the region its bitmap lies in: the raw bitmaps follow each other in the
+// block (their padding bits are zero), and so do the decoded rANS bitmaps in
+// the scratch buffer (decoded words end in zero bits).  So the kernel first
+// builds one rank directory per region: the region is cut at the absolute
+// G-bit boundaries of its buffer (G = 512 .. 8192: the smallest whose
+// directory fits), the 1 bits of each piece are counted by spr = G/128
+// consecutive lanes (one 16-byte chunk each: the region is streamed with
+// coalesced loads, four steps in flight) and exclusive-scanned.  Then P(x),
+// the region's 1 bits before bit x, is a directory entry plus one popcount
+// of less than G bits (at most spr chunk loads, eight in flight), and node
+// v's rank at position s is P(start_v + s) - P(start_v).  Top-down by level,
+// every (node, boundary) pair of the level is one thread: node v's position
+// at boundary k (symbols of the block before k * kTileOut that pass it)
+// gives its rank there, and the rank the right child's position (position -
+// rank the left child's).  The root's positions are k * kTileOut.
+// Positions live in LDS when the block's table fits, else in the table
+// itself.  Table row k, column v holds (position, rank).  A node whose
+// bitmap holds a different number of 1 bits than its header count marks the
+// job corrupt; positions are clamped to the nodes' sizes so that the tiles
+// never read outside their bitmaps.
 constexpr int kTilesNT = 1024;
 constexpr uint32_t kTilesDir = 16384;     // directory entries (LDS)
 constexpr uint32_t kTilesPos = 16384;     // positions kept in LDS
 constexpr int kTilesG = 5;                // piece sizes 512 << e, e < kTilesG
 
+// A bit region of a split block: bits [b0, b1) of buffer p (nb readable).
+struct TileRegion {
+  const uint8_t *p;
+  uint64_t nb, b0, b1;
+  uint32_t d0;             // its first directory entry
+  uint32_t np;             // its pieces
+};
+
 struct TilesSmem {
   ParsedBlock pb;
   uint32_t dir[kTilesDir + 1];
   uint32_t pos[kTilesPos];                // [v * (K + 1) + k] when (K + 1) * I fits
-  uint8_t snode[kTilesDir];               // node of each directory piece
-  uint32_t sbase[257];
-  uint32_t tot[kTilesG][kTilesNT / kWave];
+  uint32_t pstart[256];                   // P(start of node v's bitmap)
   int32_t err;
 };
 
+// The region's 1 bits before bit x (b0 <= x <= b1): the directory entry of
+// x's piece (of the last piece when x is the region's end on a piece
+// boundary) and the piece's bits before x.
+__device__ __forceinline__ uint32_t region_prefix(const TilesSmem &sm, const TileRegion &r,
+                                                  uint32_t LG, uint64_t x) {
+  if (r.np == 0) return 0u;
+  const uint32_t spr = 1u << (LG - 7);
+  uint32_t j = static_cast<uint32_t>((x >> LG) - (r.b0 >> LG));
+  j = j < r.np ? j : r.np - 1;
+  const uint64_t sb = ((r.b0 >> LG) + j) << LG, lo = sb > r.b0 ? sb : r.b0;
+  uint32_t n = sm.dir[r.d0 + j];
+  for (uint32_t c0 = 0; c0 < spr; c0 += 8) {       // the piece's bits before x
+    const uint32_t nc = spr - c0 < 8 ? spr - c0 : 8;
+    Chunk ch[8];
+#pragma unroll
+    for (uint32_t c = 0; c < 8; ++c) ch[c] = chunk_load(r.p, r.nb, (sb >> 3) + 16ull * (c0 + (c < nc ? c : 0u)));
+#pragma unroll
+    for (uint32_t c = 0; c < 8; ++c)               // chunks at or after x count nothing
+      if (c < nc) n += chunk_count(ch[c], (sb >> 3) + 16ull * (c0 + c), lo, x);
+  }
+  return n;
+}
+
 // The level loop of k_tiles (POS_LDS: positions in sm.pos, else in the table).
 template <bool POS_LDS>
-__device__ void tiles_levels(TilesSmem &sm, const JobDev &J, uint2 *T, uint32_t K, uint32_t LG,
-                             const uint8_t *scr, uint64_t scr_bytes) {
+__device__ void tiles_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uint32_t K, uint32_t LG) {
   const BlockHdr &h = sm.pb.h;
   const NodeTab &t = sm.pb.t;
-  const uint32_t tid = threadIdx.x, spr = 1u << (LG - 7);
+  const uint32_t tid = threadIdx.x;
   for (uint32_t d = 0; d < h.maxlen; ++d) {
     const uint32_t v0 = h.lvl[d], m = h.lvl[d + 1] - v0;
     for (uint32_t q = tid; q < m * (K + 1); q += kTilesNT) {
@@ -1705,35 +1758,21 @@ __device__ void tiles_levels(TilesSmem &sm, const JobDev &J, uint2 *T, uint32_t 
       const uint32_t nv = t.nv[v];
       const uint32_t sp = POS_LDS ? sm.pos[v * (K + 1) + k] : row[v].x;
       const uint32_t s = sp < nv ? sp : nv;
-      const bool raw = !t.kind[v];
-      const uint8_t *p = raw ? J.in : scr;
-      const uint64_t nb = raw ? J.in_len : scr_bytes;
-      const uint64_t gb = raw ? 8ull * (h.blk + t.boff[v]) : 32ull * (h.ans_word0 + t.boff[v]);
-      const uint64_t a = gb + s, sb = (a >> LG) << LG;
-      const uint32_t j = static_cast<uint32_t>((a >> LG) - (gb >> LG));
-      uint32_t r = sm.dir[sm.sbase[v] + j] - sm.dir[sm.sbase[v]];
-      for (uint32_t c0 = 0; c0 < spr; c0 += 8) {   // the piece's bits before a
-        const uint32_t nc = spr - c0 < 8 ? spr - c0 : 8;
-        uint4 x[8];
-#pragma unroll
-        for (uint32_t c = 0; c < 8; ++c)
-          x[c] = c < nc ? chunk_load(p, nb, (sb >> 3) + 16ull * (c0 + c)) : make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (uint32_t c = 0; c < 8; ++c)       // chunks at or after a count nothing
-          if (c < nc) r += chunk_popc(x[c], p, nb, (sb >> 3) + 16ull * (c0 + c), gb, a);
-      }
-      row[v] = make_uint2(s, r);
+      const TileRegion &r = reg[t.kind[v] ? 1 : 0];
+      const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
+      const uint32_t rk = region_prefix(sm, r, LG, gb + s) - sm.pstart[v];
+      row[v] = make_uint2(s, rk);
       const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
       const uint32_t c0 = cc & 0xFFFF, c1 = cc >> 16;
       if (!(c0 & 0x8000)) {
-        const uint32_t x0 = s - r < t.nv[c0] ? s - r : t.nv[c0];
+        const uint32_t x0 = s - rk < t.nv[c0] ? s - rk : t.nv[c0];
         if (POS_LDS) sm.pos[c0 * (K + 1) + k] = x0; else row[c0].x = x0;
       }
       if (!(c1 & 0x8000)) {
-        const uint32_t x1 = r < t.nv[c1] ? r : t.nv[c1];
+        const uint32_t x1 = rk < t.nv[c1] ? rk : t.nv[c1];
         if (POS_LDS) sm.pos[c1 * (K + 1) + k] = x1; else row[c1].x = x1;
       }
-      if (k == K && (r != t.nr[v] || s != nv)) atomicCAS(&sm.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+      if (k == K && (rk != t.nr[v] || s != nv)) atomicCAS(&sm.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
     }
     if (POS_LDS) lds_barrier();
     else __syncthreads();                          // the table's positions are read next
@@ -1761,51 +1800,34 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
   if (h.err || h.mode == 1) return;                // the tiles report or fill
   const uint32_t K = tb.ntiles, n = h.n, I = h.I;
   uint2 *T = tab + tb.tab;
-  const uint8_t *scr = reinterpret_cast<const uint8_t *>(scratch);
-  const uint64_t scr_bytes = 4ull * scratch_words;
-  // pieces per node for G = 512 << e; pick the smallest G whose directory fits
-  uint32_t ns[kTilesG], inc[kTilesG];
-  {
-    uint64_t gb = 0, ge = 0;
-    const bool has = tid < I && t.nv[tid];
-    if (has) {
-      gb = t.kind[tid] ? 32ull * (h.ans_word0 + t.boff[tid]) : 8ull * (h.blk + t.boff[tid]);
-      ge = gb + t.nv[tid] - 1;
-    }
-#pragma unroll
-    for (int e = 0; e < kTilesG; ++e) {
-      ns[e] = has ? static_cast<uint32_t>((ge >> (9 + e)) - (gb >> (9 + e)) + 1) : 0u;
-      inc[e] = wave_incl_scan(ns[e]);
-      if (lane == kWave - 1) sm.tot[e][wave] = inc[e];
-    }
+  // the two regions (the job's stream is read once: the table stores below
+  // would otherwise make the compiler reload it from the job table)
+  TileRegion reg[2];
+  reg[0].p = J.in;
+  reg[0].nb = J.in_len;
+  reg[0].b0 = 8ull * (h.blk + h.raw_base);
+  reg[0].b1 = 8ull * (h.blk + h.raw_end);
+  reg[1].p = reinterpret_cast<const uint8_t *>(scratch);
+  reg[1].nb = 4ull * scratch_words;
+  reg[1].b0 = 32ull * h.ans_word0;
+  reg[1].b1 = 32ull * (h.ans_word0 + h.ans_words);
+  // the smallest piece size whose directory fits
+  uint32_t lg = 0, S = 0;
+  for (;; ++lg) {
+    S = 0;
+    for (int i = 0; i < 2; ++i)
+      if (reg[i].b1 > reg[i].b0) S += static_cast<uint32_t>(((reg[i].b1 - 1) >> (9 + lg)) - (reg[i].b0 >> (9 + lg)) + 1);
+    if (S <= kTilesDir || lg + 1 == kTilesG) break;
   }
-  __syncthreads();
-  uint32_t lg = 0, S = 0;                          // log2(G) - 9, pieces
-  {
-    uint32_t all[kTilesG];
-#pragma unroll
-    for (int e = 0; e < kTilesG; ++e) {
-      all[e] = 0;
-      for (uint32_t w = 0; w < NW; ++w) all[e] += sm.tot[e][w];
-    }
-    while (lg + 1 < kTilesG && all[lg] > kTilesDir) ++lg;
-#pragma unroll
-    for (int e = 0; e < kTilesG; ++e)
-      if (e == static_cast<int>(lg)) S = all[e];
-    if (S > kTilesDir) {                           // more than 8192 * 16Ki bitmap bits
-      if (tid == 0) set_err(J.status, PIVCO_E_UNSUPPORTED);
-      return;
-    }
+  if (S > kTilesDir) {                             // more than 8192 * 16Ki bitmap bits
+    if (tid == 0) set_err(J.status, PIVCO_E_UNSUPPORTED);
+    return;
   }
-  if (tid < 256) {
-    uint32_t ex = 0, nsl = 0;
-#pragma unroll
-    for (int e = 0; e < kTilesG; ++e)
-      if (e == static_cast<int>(lg)) { ex = inc[e] - ns[e]; nsl = ns[e]; }
-    for (uint32_t w = 0; w < wave; ++w) ex += sm.tot[lg][w];
-    sm.sbase[tid] = ex;
-    if (tid == 255) sm.sbase[256] = ex + nsl;
-  }
+  const uint32_t LG = 9 + lg, spr = 4u << lg;      // G = 1 << LG bits = spr chunks
+  reg[0].d0 = 0;
+  reg[0].np = reg[0].b1 > reg[0].b0 ? static_cast<uint32_t>(((reg[0].b1 - 1) >> LG) - (reg[0].b0 >> LG) + 1) : 0u;
+  reg[1].d0 = reg[0].np;
+  reg[1].np = S - reg[0].np;
   const bool pos_lds = (K + 1) * I <= kTilesPos;
   for (uint32_t k = tid; k <= K; k += kTilesNT) {
     const uint64_t s = static_cast<uint64_t>(k) * kTileOut;
@@ -1813,81 +1835,70 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
     if (pos_lds) sm.pos[k] = x;
     else T[static_cast<uint64_t>(k) * kTabCols] = make_uint2(x, 0u);
   }
-  __syncthreads();
-  const uint32_t LG = 9 + lg, spr = 4u << lg;      // G = 1 << LG bits = spr chunks
-  // node of every piece: one search per thread for the start of its run
+  // counting pass: the pieces' chunks, region after region, 64 consecutive
+  // chunks a wave step (coalesced), U steps in flight; spr consecutive lanes
+  // add up one piece
   {
-    const uint32_t per = (S + kTilesNT - 1) / kTilesNT;
-    const uint32_t f0 = tid * per, f1 = f0 + per < S ? f0 + per : S;
-    if (f0 < f1) {
-      uint32_t lo = 0, hi = I;                     // last v with sbase[v] <= f0
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (sm.sbase[mid] <= f0) lo = mid; else hi = mid;
+    constexpr uint32_t U = 4, STEP = kWave * U;
+    const uint32_t CT = S * spr, c1 = reg[0].np * spr;
+    for (uint32_t base = wave * STEP; base < CT; base += NW * STEP) {
+      Chunk x[U];
+      uint64_t q[U], lo[U], hi[U];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t c = base + u * kWave + lane;
+        const bool second = c >= c1;
+        const TileRegion &r = reg[second ? 1 : 0];
+        const uint32_t cr = second ? c - c1 : c;
+        q[u] = ((r.b0 >> LG) << (LG - 3)) + 16ull * cr;
+        lo[u] = r.b0;
+        hi[u] = c < CT ? r.b1 : r.b0;              // past the last piece: no bits
+        x[u] = chunk_load(second ? reg[1].p : reg[0].p, second ? reg[1].nb : reg[0].nb, q[u]);
       }
-      for (uint32_t f = f0; f < f1; ++f) {
-        while (sm.sbase[lo + 1] <= f) ++lo;
-        sm.snode[f] = static_cast<uint8_t>(lo);
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        uint32_t m = chunk_count(x[u], q[u], lo[u], hi[u]);
+        for (uint32_t sh = spr >> 1; sh >= 1; sh >>= 1) m += __shfl_xor(m, static_cast<int>(sh), static_cast<int>(spr));
+        const uint32_t c = base + u * kWave + lane;
+        if (c % spr == 0 && c < CT) sm.dir[c / spr] = m;
       }
     }
   }
   __syncthreads();
-  // counting pass: a row of spr lanes per piece, four pieces per row in flight
-  {
-    constexpr int U = 4;
-    const uint32_t rows = kWave / spr, row = lane / spr, rl = lane % spr;
-    for (uint32_t f0 = wave * rows; f0 < S; f0 += U * NW * rows) {
-      uint4 x[U];
-      uint64_t q[U], g0[U], g1[U];
-      const uint8_t *pp[U];
-      uint64_t nbs[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t f = f0 + u * NW * rows + row;
-        const uint32_t v = sm.snode[f < S ? f : 0];
-        const bool raw = !t.kind[v];
-        pp[u] = raw ? J.in : scr;
-        nbs[u] = raw ? J.in_len : scr_bytes;
-        g0[u] = raw ? 8ull * (h.blk + t.boff[v]) : 32ull * (h.ans_word0 + t.boff[v]);
-        g1[u] = f < S ? g0[u] + t.nv[v] : g0[u];   // no bits counted for f >= S
-        q[u] = ((((g0[u] >> LG) + (f < S ? f - sm.sbase[v] : 0u)) << LG) >> 3) + 16ull * rl;
-        x[u] = chunk_load(pp[u], nbs[u], q[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        uint32_t c = chunk_popc(x[u], pp[u], nbs[u], q[u], g0[u], g1[u]);
-        for (uint32_t m = spr >> 1; m >= 1; m >>= 1) c += __shfl_xor(c, static_cast<int>(m), static_cast<int>(spr));
-        const uint32_t f = f0 + u * NW * rows + row;
-        if (rl == 0 && f < S) sm.dir[f] = c;
-      }
-    }
-  }
-  __syncthreads();
-  // exclusive scan of the directory (contiguous runs per thread), dir[S] = total
+  // exclusive scan of the directory per region (contiguous runs per thread)
   {
     const uint32_t per = (S + kTilesNT - 1) / kTilesNT;
     const uint32_t f0 = tid * per, f1 = f0 + per < S ? f0 + per : S;
     uint32_t loc = 0;
     for (uint32_t f = f0; f < f1; ++f) loc += sm.dir[f];
     const uint32_t incl = wave_incl_scan(loc);
-    if (lane == kWave - 1) sm.tot[0][wave] = incl;
+    __shared__ uint32_t tot[kTilesNT / kWave];
+    if (lane == kWave - 1) tot[wave] = incl;
     __syncthreads();
     uint32_t run = incl - loc;
-    for (uint32_t w = 0; w < wave; ++w) run += sm.tot[0][w];
+    for (uint32_t w = 0; w < wave; ++w) run += tot[w];
+    __syncthreads();
     for (uint32_t f = f0; f < f1; ++f) {
       const uint32_t c = sm.dir[f];
       sm.dir[f] = run;
       run += c;
     }
-    if (tid == kTilesNT - 1) {
-      uint32_t all = 0;
-      for (uint32_t w = 0; w < NW; ++w) all += sm.tot[0][w];
-      sm.dir[S] = all;
-    }
+    __syncthreads();
+    // the second region's prefix starts from its own first piece
+    const uint32_t base1 = reg[1].np ? sm.dir[reg[1].d0] : 0u;
+    __syncthreads();
+    for (uint32_t f = reg[1].d0 + tid; f < S; f += kTilesNT) sm.dir[f] -= base1;
   }
   __syncthreads();
-  if (pos_lds) tiles_levels<true>(sm, J, T, K, LG, scr, scr_bytes);
-  else tiles_levels<false>(sm, J, T, K, LG, scr, scr_bytes);
+  // every node's prefix at its bitmap's start
+  for (uint32_t v = tid; v < I; v += kTilesNT) {
+    const TileRegion &r = reg[t.kind[v] ? 1 : 0];
+    const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
+    sm.pstart[v] = region_prefix(sm, r, LG, gb);
+  }
+  __syncthreads();
+  if (pos_lds) tiles_levels<true>(sm, reg, T, K, LG);
+  else tiles_levels<false>(sm, reg, T, K, LG);
   if (tid == 0 && sm.err) set_err(J.status, sm.err);
 }
 
