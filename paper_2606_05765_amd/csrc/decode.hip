@@ -1724,29 +1724,28 @@ struct TilesSmem {
 // The region's 1 bits before bit x (b0 <= x <= b1): the directory entry of
 // x's piece (of the last piece when x is the region's end on a piece
 // boundary) and the piece's bits before x.
-__device__ __forceinline__ uint32_t region_prefix(const TilesSmem &sm, const TileRegion &r,
-                                                  uint32_t LG, uint64_t x) {
+template <uint32_t SPR>                            // chunks per piece: G = 128 * SPR
+__device__ __forceinline__ uint32_t region_prefix(const TilesSmem &sm, const TileRegion &r, uint64_t x) {
+  constexpr uint32_t LG = 31 - __builtin_clz(SPR) + 7, B = SPR < 8 ? SPR : 8;
   if (r.np == 0) return 0u;
-  const uint32_t spr = 1u << (LG - 7);
   uint32_t j = static_cast<uint32_t>((x >> LG) - (r.b0 >> LG));
   j = j < r.np ? j : r.np - 1;
   const uint64_t sb = ((r.b0 >> LG) + j) << LG, lo = sb > r.b0 ? sb : r.b0;
   uint32_t n = sm.dir[r.d0 + j];
-  for (uint32_t c0 = 0; c0 < spr; c0 += 8) {       // the piece's bits before x
-    const uint32_t nc = spr - c0 < 8 ? spr - c0 : 8;
-    Chunk ch[8];
+  for (uint32_t c0 = 0; c0 < SPR; c0 += B) {       // the piece's bits before x, B chunks in flight
+    Chunk ch[B];
 #pragma unroll
-    for (uint32_t c = 0; c < 8; ++c) ch[c] = chunk_load(r.p, r.nb, (sb >> 3) + 16ull * (c0 + (c < nc ? c : 0u)));
+    for (uint32_t c = 0; c < B; ++c) ch[c] = chunk_load(r.p, r.nb, (sb >> 3) + 16ull * (c0 + c));
 #pragma unroll
-    for (uint32_t c = 0; c < 8; ++c)               // chunks at or after x count nothing
-      if (c < nc) n += chunk_count(ch[c], (sb >> 3) + 16ull * (c0 + c), lo, x);
+    for (uint32_t c = 0; c < B; ++c)               // chunks at or after x count nothing
+      n += chunk_count(ch[c], (sb >> 3) + 16ull * (c0 + c), lo, x);
   }
   return n;
 }
 
 // The level loop of k_tiles (POS_LDS: positions in sm.pos, else in the table).
-template <bool POS_LDS>
-__device__ void tiles_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uint32_t K, uint32_t LG) {
+template <bool POS_LDS, uint32_t SPR>
+__device__ void tiles_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uint32_t K) {
   const BlockHdr &h = sm.pb.h;
   const NodeTab &t = sm.pb.t;
   const uint32_t tid = threadIdx.x;
@@ -1760,7 +1759,7 @@ __device__ void tiles_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uin
       const uint32_t s = sp < nv ? sp : nv;
       const TileRegion &r = reg[t.kind[v] ? 1 : 0];
       const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
-      const uint32_t rk = region_prefix(sm, r, LG, gb + s) - sm.pstart[v];
+      const uint32_t rk = region_prefix<SPR>(sm, r, gb + s) - sm.pstart[v];
       row[v] = make_uint2(s, rk);
       const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
       const uint32_t c0 = cc & 0xFFFF, c1 = cc >> 16;
@@ -1777,6 +1776,22 @@ __device__ void tiles_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uin
     if (POS_LDS) lds_barrier();
     else __syncthreads();                          // the table's positions are read next
   }
+}
+
+// Every node's prefix at its bitmap's start, then the levels.
+template <uint32_t SPR>
+__device__ void tiles_prefix_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uint32_t K,
+                                    bool pos_lds) {
+  const BlockHdr &h = sm.pb.h;
+  const NodeTab &t = sm.pb.t;
+  for (uint32_t v = threadIdx.x; v < h.I; v += kTilesNT) {
+    const TileRegion &r = reg[t.kind[v] ? 1 : 0];
+    const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
+    sm.pstart[v] = region_prefix<SPR>(sm, r, gb);
+  }
+  __syncthreads();
+  if (pos_lds) tiles_levels<true, SPR>(sm, reg, T, K);
+  else tiles_levels<false, SPR>(sm, reg, T, K);
 }
 
 __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const TiledBlock *tiled,
@@ -1890,15 +1905,13 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
     for (uint32_t f = reg[1].d0 + tid; f < S; f += kTilesNT) sm.dir[f] -= base1;
   }
   __syncthreads();
-  // every node's prefix at its bitmap's start
-  for (uint32_t v = tid; v < I; v += kTilesNT) {
-    const TileRegion &r = reg[t.kind[v] ? 1 : 0];
-    const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
-    sm.pstart[v] = region_prefix(sm, r, LG, gb);
+  switch (lg) {
+    case 0: tiles_prefix_levels<4>(sm, reg, T, K, pos_lds); break;
+    case 1: tiles_prefix_levels<8>(sm, reg, T, K, pos_lds); break;
+    case 2: tiles_prefix_levels<16>(sm, reg, T, K, pos_lds); break;
+    case 3: tiles_prefix_levels<32>(sm, reg, T, K, pos_lds); break;
+    default: tiles_prefix_levels<64>(sm, reg, T, K, pos_lds); break;
   }
-  __syncthreads();
-  if (pos_lds) tiles_levels<true>(sm, reg, T, K, LG);
-  else tiles_levels<false>(sm, reg, T, K, LG);
   if (tid == 0 && sm.err) set_err(J.status, sm.err);
 }
 
