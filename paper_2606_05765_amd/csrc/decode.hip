@@ -653,7 +653,6 @@ struct MergeCfg {
   static constexpr int T = T_;                        // output symbols per tile
   static constexpr int BODY = BODY_;                  // resident block bytes
   static constexpr int K = K_;                        // outputs per merge task (8, 16 or 32)
-  static constexpr int CS = K < 16 ? 3 : 4;           // child output offsets are stored >> CS
   static constexpr int LOCK = LOCK_;                  // windows a wave merges at once (1, 2 or 4)
   static_assert(LOCK == 1 || LOCK == 2 || LOCK == 4, "windows per wave step");
   static constexpr int NW = NT / kWave;
@@ -669,8 +668,8 @@ struct MergeCfg {
 // What a merge lane needs about a node with work in the current tile (16
 // bytes): where its bits start (resident: LDS bit address; streaming: first
 // staged word), the 1 bits before that point, its output offset in its level
-// buffer | its first task in the level << 16, and per child either the
-// child's output offset / 16 or 0x8000 | leaf symbol.
+// buffer | its first task in the level << 16, and one 16-bit code per child
+// (kid_code).
 struct NodeRec {
   uint32_t x0;
   uint32_t arank;
@@ -718,6 +717,19 @@ struct MergeSmem {
   uint8_t rel[C::REL];     // resident: 1 bits of the superblock before each 64-bit word
   uint32_t body[C::BODY / 4 + 16] __attribute__((aligned(16)));
 };
+
+// Code of a child in a NodeRec: the LDS byte address of its sequence / 4 in
+// bits 0-14, and bit 15 set for an internal child (whose sequence advances
+// with its rank) or clear for a leaf (whose constant row is read at the same
+// address for every output).  `off` is the internal child's output offset in
+// the level buffer of parity p.
+template <class C>
+__device__ __forceinline__ uint32_t kid_code(const MergeSmem<C> &sm, uint32_t c, uint32_t p, uint32_t off) {
+  static_assert(offsetof(MergeSmem<C>, sup) <= (1u << 17), "leaf rows and level buffers below 128 KiB");
+  const uint8_t *base = reinterpret_cast<const uint8_t *>(&sm);
+  if (c & 0x8000) return static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(&sm.leafrow[c & 255]) - base) >> 2;
+  return 0x8000u | ((static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[p]) - base) + off) >> 2);
+}
 
 // Streaming tile: largest multiple of 1024 (at most C::T) whose staged words fit.
 template <class C>
@@ -818,12 +830,12 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
       for (int bb = 0; bb < 2; ++bb) {
         uint32_t code;
         if (ch[bb] & 0x8000) {
-          code = ch[bb];
+          code = kid_code<C>(sm, ch[bb], 0, 0);
         } else {
           const uint32_t cob = ob + (bb ? o0 : 0u);
           sm.tv[ch[bb]] = tc[bb];
           sm.obase[ch[bb]] = cob;
-          code = cob >> C::CS;
+          code = kid_code<C>(sm, ch[bb], (d + 1) & 1, cob);
         }
         kids |= code << (16 * bb);
       }
@@ -944,7 +956,7 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       const uint32_t c = (cc >> (16 * bb)) & 0xFFFF;
-      const uint32_t code = (c & 0x8000) ? c : static_cast<uint32_t>(pfx[c] - base1) >> C::CS;
+      const uint32_t code = kid_code<C>(sm, c, (d + 1) & 1, (c & 0x8000) ? 0u : static_cast<uint32_t>(pfx[c] - base1));
       kids |= code << (16 * bb);
     }
     if (tvv) {
@@ -1070,19 +1082,16 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
       r1[i] = wr.y + __popc(wr.x & ((1u << sh) - 1));
     }
   }
-  const uint32_t cbase = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[(d + 1) & 1]) - lds);
-  const uint32_t lrow = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.leafrow) - lds);
   uint32_t aL[N][G], aR[N][G], sel[N][G];
   uint2 wl[N][G], wr[N][G];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const uint32_t kl = r[i].kids & 0xFFFF, kr = r[i].kids >> 16;
-    uint32_t mL = (kl & 0x8000) ? 0u : 1u, mR = (kr & 0x8000) ? 0u : 1u;
+    const uint32_t kd = r[i].kids;
+    uint32_t mL = (kd >> 15) & 1u, mR = kd >> 31;
     // opaque to the compiler: a 0/1 multiplier stays one v_mad_u32_u24
     // instead of being turned into a select per group
     asm volatile("" : "+v"(mL), "+v"(mR));
-    const uint32_t bL = mL ? cbase + (kl << C::CS) : lrow + 4 * (kl & 255);
-    const uint32_t bR = mR ? cbase + (kr << C::CS) : lrow + 4 * (kr & 255);
+    const uint32_t bL = (kd & 0x7FFFu) << 2, bR = (kd >> 14) & 0x1FFFCu;
     uint32_t r1g = r1[i], r0g = j0[i] - r1[i];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
