@@ -867,36 +867,44 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
 // Resident count for a tile that ends inside the block, run by one wave:
 // top-down, a node's share and the 1 bits in it (rank directory at the
 // share's end) give the children's shares.  A child that would receive more
-// symbols than it has left marks the block corrupt and gets none.
+// symbols than it has left marks the block corrupt and gets none.  Per level
+// two dependent LDS round trips: the shares, then the ranks together with
+// the children's cursors and sizes (read unconditionally; a leaf reads slot
+// 0 and ignores it).  The rank at the share's end equals the node's rank
+// when the share is empty.
 template <class C>
 __device__ void count_chain(MergeSmem<C> &sm) {
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
   const uint32_t maxd = h.maxlen;
+  const uint32_t lb = lane <= maxd ? h.lvl[lane] : 0u;    // lane d: first node of level d
+  bool bad = false;
   for (uint32_t d = 0; d < maxd; ++d) {
-    const uint32_t hi = h.lvl[d + 1];
-    for (uint32_t v = h.lvl[d] + lane; v < hi; v += kWave) {
+    const uint32_t lo = __builtin_amdgcn_readlane(lb, d), hi = __builtin_amdgcn_readlane(lb, d + 1);
+    for (uint32_t v = lo + lane; v < hi; v += kWave) {
       const uint32_t tvv = sm.tv[v], ar = sm.arank[v];
       const uint32_t x0 = sm.abit[v] + sm.cur[v];
       const uint32_t cc = *reinterpret_cast<const uint32_t *>(t.child[v]);
-      const uint32_t e = tvv ? rank_at(sm.body, sm.sup, sm.rel, x0 + tvv) : ar;
+      const uint32_t cl = cc & 0xFFFF, cr = cc >> 16;
+      const uint32_t il = (cl & 0x8000) ? 0u : cl, ir = (cr & 0x8000) ? 0u : cr;
+      const uint32_t e = rank_at(sm.body, sm.sup, sm.rel, x0 + tvv);
+      const uint32_t curl = sm.cur[il], nvl = t.nv[il], curr = sm.cur[ir], nvr = t.nv[ir];
       sm.aend[v] = e;
-      const uint32_t ones = e - ar;
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb) {
-        const uint32_t c = (cc >> (16 * bb)) & 0xFFFF;
-        if (c & 0x8000) continue;
-        uint32_t tc = bb ? ones : tvv - ones;
-        if (sm.cur[c] + tc > t.nv[c]) {
-          atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
-          tc = 0;
-        }
-        sm.tv[c] = tc;
+      const uint32_t ones = e - ar, zeros = tvv - ones;
+      const bool okl = curl + zeros <= nvl, okr = curr + ones <= nvr;
+      if (!(cl & 0x8000)) {
+        sm.tv[cl] = okl ? zeros : 0u;
+        bad |= !okl;
+      }
+      if (!(cr & 0x8000)) {
+        sm.tv[cr] = okr ? ones : 0u;
+        bad |= !okr;
       }
     }
     wave_sync_lds();
   }
+  if (bad) atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
 }
 
 // Resident count for the block's last tile (all threads): every node's
@@ -1283,13 +1291,25 @@ __device__ void warm_next(MergeSmem<C> &sm) {
   if (!in) return;
   const uint8_t *rec = sm.warm_rec;
   const uint64_t blk = sm.nxt.blk, end = sm.nxt.end;
-  uint32_t acc = 0;
-  if (end > blk && end - blk <= static_cast<uint64_t>(C::BODY)) {
-    for (uint64_t a = (blk & ~127ull) + 128ull * lane; a < end; a += 128ull * kWave)
-      acc ^= *reinterpret_cast<const uint32_t *>(in + a);
+  // every load is issued before any is consumed (one memory round trip)
+  constexpr int NB = (C::BODY + 127) / (128 * kWave) + 1;            // lines per lane: block
+  constexpr int NR = (sizeof(ParsedBlock) + 128 * kWave - 1) / (128 * kWave);   // and record
+  uint32_t v[NB + NR];
+  const bool fits = end > blk && end - blk <= static_cast<uint64_t>(C::BODY);
+  const uint64_t a0 = (blk & ~127ull) + 128ull * lane;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const uint64_t a = a0 + 128ull * kWave * k;
+    v[k] = fits && a < end ? *reinterpret_cast<const uint32_t *>(in + a) : 0u;
   }
-  for (uint32_t a = 128 * lane; a < sizeof(ParsedBlock); a += 128 * kWave)
-    acc ^= *reinterpret_cast<const uint32_t *>(rec + a);
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const uint32_t a = 128 * (lane + kWave * k);
+    v[NB + k] = a < sizeof(ParsedBlock) ? *reinterpret_cast<const uint32_t *>(rec + a) : 0u;
+  }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NB + NR; ++k) acc ^= v[k];
   if (acc == 0x9E3779B9u) sm.warm_sink = acc;   // keeps the reads; the value is irrelevant
 }
 
