@@ -936,21 +936,23 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
   NodeTab &t = sm.pb.t;
   const uint32_t I = h.I;
   uint64_t *pfx = reinterpret_cast<uint64_t *>(sm.lvl[0]);   // level buffers are idle here
-  uint64_t *wtot = pfx + 260;
-  uint64_t pk = 0, inc = 0;
   for (int i = tid; i < C::LEVELS * C::WIN; i += C::NT) (&sm.smask[0][0])[i] = 0;
-  if (tid < 256) {
-    const uint32_t tvv = static_cast<uint32_t>(tid) < I ? sm.tv[tid] : 0u;
-    pk = ((tvv + C::K - 1) & ~(C::K - 1u)) | (static_cast<uint64_t>((tvv + C::K - 1) / C::K) << 32) |
-         (static_cast<uint64_t>(tvv ? 1u : 0u) << 48);
-    inc = wave_incl_scan64(pk);
-    if (lane == kWave - 1) wtot[wave] = inc;
-  }
-  lds_barrier();
-  if (tid < 256) {
-    uint64_t ex = inc - pk;
-    for (int w = 0; w < wave; ++w) ex += wtot[w];
-    pfx[tid] = ex;                       // pfx[I] is the total (I <= 255)
+  if (wave == 0) {                       // one wave, 4 consecutive nodes per lane
+    uint64_t pk[4], loc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t v = 4 * lane + k;
+      const uint32_t tvv = v < I ? sm.tv[v] : 0u;
+      pk[k] = ((tvv + C::K - 1) & ~(C::K - 1u)) | (static_cast<uint64_t>((tvv + C::K - 1) / C::K) << 32) |
+              (static_cast<uint64_t>(tvv ? 1u : 0u) << 48);
+      loc += pk[k];
+    }
+    uint64_t ex = wave_incl_scan64(loc) - loc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      pfx[4 * lane + k] = ex;            // pfx[I] is the total (I <= 255)
+      ex += pk[k];
+    }
   }
   lds_barrier();
   if (static_cast<uint32_t>(tid) < I) {
@@ -1444,8 +1446,9 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
       sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
       if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
     }
-    lds_barrier();
+    // build_directory's barriers order the writes above before their readers
     if (resident) build_directory<C>(sm, static_cast<uint32_t>(span >> 2) + h.ans_words, I);
+    else lds_barrier();
   }
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
@@ -1839,7 +1842,6 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
   if (tid == 0) sm.err = 0;
   __syncthreads();
   const BlockHdr &h = sm.pb.h;
-  const NodeTab &t = sm.pb.t;
   const JobDev &J = jobs[h.job];
   if (h.err || h.mode == 1) return;                // the tiles report or fill
   const uint32_t K = tb.ntiles, n = h.n, I = h.I;

@@ -38,6 +38,12 @@ def cases():
     out.append(("constant", np.full(100_000, 7, np.uint8), 40_000, 0, None))
     out.append(("constant_split", np.full(200_000, 9, np.uint8), 1 << 17, 0, None))
     out.append(("two_symbols", (r.random(150_000) < 0.03).astype(np.uint8), 1 << 16, 1, None))
+    # the first 32Ki-output tile holds only the most frequent symbol (a
+    # 1-bit code): every level below the root has no work in it, whole and split
+    tail = W.draw(r, W.geometric_p(0.97), 60_000)
+    front = np.concatenate([np.zeros(40_000, np.uint8), tail])
+    out.append(("front_loaded_whole", front[:1 << 16], 1 << 16, 0, None))
+    out.append(("front_loaded_split", front, front.size, 0, None))
     # deepest codes: Fibonacci-like counts reach the 11-bit limit
     fib = [1, 1]
     while len(fib) < 24:
