@@ -459,7 +459,8 @@ __device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t
 // ballot) from a window of the chunk's words staged in LDS; the half-wave's
 // 32 decoded bits are its part of the ballot of the bits (bit i = lane i).
 constexpr int kRansNT = 256;
-constexpr int kRansWin = 1024;        // u16 words per half-wave window in LDS
+constexpr int kRansWin = 2048;        // u16 words per half-wave window in LDS
+constexpr uint32_t kRansSteps = 32;   // steps per window check (one output word per lane)
 
 // Lists the rANS chunks of the block parsed in h/t (one lane): walks the
 // rANS bodies that follow the raw bodies (each: u16 probability, u16 zero,
@@ -534,8 +535,43 @@ __device__ int32_t walk_rans(const JobDev &J, BlockHdr &h, const NodeTab &t, Cou
 // steps (one coalesced 128-byte store).
 typedef __attribute__((address_space(1))) const uint16_t GlobalCU16;
 
+// One decode step of both half-waves (lane hl of half h: bit 32 k + hl of
+// its chunk).  FULL: every lane of both halves is active.  The cursors pa,
+// pb (words consumed per half) and the window starts wsa, wsb are
+// wave-uniform.  A lane whose state fell below 2^16 takes the word at its
+// half's cursor + its rank among the half's such lanes; the window index is
+// masked, so a corrupt chunk that runs past its words reads stale window
+// words and fails the final cursor check.  The step's ballot of decoded
+// bits (half 0 low, half 1 high) goes to stage[j].
+template <bool FULL>
+__device__ __forceinline__ void rans_step(uint32_t &x, uint64_t *stage, uint32_t &pa, uint32_t &pb,
+                                          uint32_t wsa, uint32_t wsb, uint32_t j, uint32_t k,
+                                          uint32_t hl, uint32_t half, uint32_t nbits, uint32_t f0,
+                                          uint32_t f1, const uint16_t *w) {
+  const bool act = FULL || 32 * k + hl < nbits;
+  const uint32_t slot = x & (kRansM - 1);
+  const bool bit = slot >= f0;
+  const uint32_t xn = __umul24(bit ? f1 : f0, x >> 12) + slot - (bit ? f0 : 0u);
+  x = act ? xn : x;
+  const bool need = act && x < kRansL;
+  const uint64_t m = __ballot(need);
+  if (m) {
+    const uint32_t mlo = static_cast<uint32_t>(m), mhi = static_cast<uint32_t>(m >> 32);
+    const uint32_t clo = __popc(mlo);
+    // lanes of the upper half count the lower half's bits too: subtract them
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
+    const uint32_t adj = half ? pb - wsb - clo : pa - wsa;
+    const uint32_t wv = w[(rank + adj) & (kRansWin - 1)];
+    x = need ? ((x << 16) | wv) : x;
+    pa += clo;
+    pb += __popc(mhi);
+  }
+  const uint64_t bm = __ballot(act && bit);
+  if (hl == 0 && half == 0) stage[j] = bm;
+}
+
 __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t ia, uint32_t ib,
-                          uint32_t end, uint32_t *scratch, uint16_t (*win)[kRansWin]) {
+                          uint32_t end, uint32_t *scratch, uint16_t (*win)[kRansWin], uint64_t *stage) {
   const uint32_t lane = lane_id(), half = lane >> 5, hl = lane & 31;
   const uint32_t idx = half ? ib : ia;
   RansChunk c = RansChunk{0, 0, 0, 0, 1, 0};
@@ -548,35 +584,30 @@ __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t 
   uint16_t *w = win[half];
   const uint32_t f0 = kRansM - c.p1q, f1 = c.p1q;
   const uint32_t K = (c.nbits + 31) / 32;
+  // per-half sizes, wave-uniform
   const uint32_t ka = __builtin_amdgcn_readlane(K, 0), kb = __builtin_amdgcn_readlane(K, 32);
   const uint32_t kmax = ka > kb ? ka : kb;
-  uint32_t pos = 0, wstart = 0, wend = 0, mine = 0;
+  const uint32_t nba = __builtin_amdgcn_readlane(c.nbits, 0), nbb = __builtin_amdgcn_readlane(c.nbits, 32);
+  const uint32_t nwa = __builtin_amdgcn_readlane(c.nw, 0), nwb = __builtin_amdgcn_readlane(c.nw, 32);
+  uint32_t pa = 0, pb = 0, wsa = 0, wsb = 0, wea = 0, web = 0;
   uint32_t *dst = scratch + c.dst;
-  const uint32_t lt = (1u << hl) - 1;
-  for (uint32_t k = 0; k < kmax; ++k) {
-    const bool act = 32 * k + hl < c.nbits;
-    const uint32_t slot = x & (kRansM - 1);
-    const bool bit = slot >= f0;
-    const uint32_t xn = __umul24(bit ? f1 : f0, x >> 12) + slot - (bit ? f0 : 0u);
-    x = act ? xn : x;
-    const bool need = act && x < kRansL;
-    const uint64_t m = __ballot(need);
-    const uint32_t mh = half ? static_cast<uint32_t>(m >> 32) : static_cast<uint32_t>(m);
-    const uint32_t cnt = __popc(mh);
-    const bool refill = pos + cnt > wend;
-    if (__ballot(refill)) {                         // some half needs more words
-      if (refill) {
-        // a corrupt chunk can ask for more words than it holds: the window
-        // never starts past the chunk's end
-        wstart = pos < c.nw ? pos : c.nw;
-        wend = c.nw - wstart > kRansWin ? wstart + kRansWin : c.nw;
-        const uint32_t nwin = wend - wstart;
+  constexpr uint32_t kAhead = kRansSteps * 32;   // most words a half takes in kRansSteps steps
+  static_assert(kAhead <= static_cast<uint32_t>(kRansWin), "a group's words fit the window");
+  for (uint32_t k0 = 0; k0 < kmax; k0 += kRansSteps) {
+    // slide a half's window to its cursor when fewer than kAhead of its
+    // words are staged ahead of it (and the chunk has more)
+    const bool ra = pa + kAhead > wea && wea < nwa, rb = pb + kAhead > web && web < nwb;
+    if (ra || rb) {
+      if (ra) { wsa = pa < nwa ? pa : nwa; wea = nwa - wsa > kRansWin ? wsa + kRansWin : nwa; }
+      if (rb) { wsb = pb < nwb ? pb : nwb; web = nwb - wsb > kRansWin ? wsb + kRansWin : nwb; }
+      if (half ? rb : ra) {
+        const uint32_t ws = half ? wsb : wsa, nwin = (half ? web : wea) - ws;
         for (uint32_t i0 = 0; i0 < nwin; i0 += 32 * 8) {
           uint16_t v[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const uint32_t i = i0 + 32 * u + hl;
-            v[u] = i < nwin ? words[wstart + i] : 0;
+            v[u] = i < nwin ? words[ws + i] : 0;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -585,24 +616,26 @@ __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t 
           }
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (refill && pos + cnt > wend) err = true;
     }
-    const uint32_t i = pos + __popc(mh & lt) - wstart;
-    const uint32_t wv = w[i < kRansWin ? i : 0u];
-    x = need ? ((x << 16) | (i < wend - wstart ? wv : 0u)) : x;
-    pos += cnt;
-    const uint64_t bm = __ballot(act && bit);
-    const uint32_t word = half ? static_cast<uint32_t>(bm >> 32) : static_cast<uint32_t>(bm);
-    mine = (k & 31) == hl ? word : mine;
-    if ((k & 31) == 31 || k + 1 == kmax) {          // store the last (up to) 32 steps' words
-      const uint32_t kk = (k & ~31u) + hl;
-      if (hl <= (k & 31) && kk < K) dst[kk] = mine;
+    const uint32_t full_bits = 32 * (k0 + kRansSteps);
+    if (full_bits <= nba && full_bits <= nbb) {
+#pragma unroll
+      for (uint32_t j = 0; j < kRansSteps; ++j)
+        rans_step<true>(x, stage, pa, pb, wsa, wsb, j, k0 + j, hl, half, c.nbits, f0, f1, w);
+    } else {
+      const uint32_t steps = kmax - k0 < kRansSteps ? kmax - k0 : kRansSteps;
+      for (uint32_t j = 0; j < steps; ++j)
+        rans_step<false>(x, stage, pa, pb, wsa, wsb, j, k0 + j, hl, half, c.nbits, f0, f1, w);
     }
+    // lane hl of half h: the half's bits of step k0 + hl (entries past the
+    // group's steps are never read: k0 + hl < K <= k0 + steps)
+    if (k0 + hl < K) dst[k0 + hl] = reinterpret_cast<const uint32_t *>(stage)[2 * hl + half];
   }
   if (has) {
-    if (pos != c.nw || x != kRansL) err = true;
+    if ((half ? pb : pa) != c.nw || x != kRansL) err = true;
     const uint32_t used = kChunkHdr + 2 * c.nw, size = (used + 3) & ~3u;
     if (hl < size - used && base[used + hl] != 0) err = true;
   }
@@ -619,6 +652,7 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const Pars
                                                    const RansChunk *chunks, uint64_t cap,
                                                    uint32_t *scratch, int32_t single) {
   __shared__ uint16_t win[kRansNT / kWave][2][kRansWin];
+  __shared__ uint64_t stage[kRansNT / kWave][kRansSteps];
   const uint32_t wave = wave_id();
   constexpr uint32_t NW = kRansNT / kWave;
   uint32_t first = 0, end = 0;
@@ -640,7 +674,7 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const Pars
     }
     const uint32_t ia = first + 2 * pair;
     if (ia >= end) break;
-    rans_pair(jobs, chunks, ia, ia + 1, end, scratch, win[wave]);
+    rans_pair(jobs, chunks, ia, ia + 1, end, scratch, win[wave], stage[wave]);
   }
 }
 
