@@ -138,7 +138,7 @@ def main():
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
               "(blocks are independent, so N GPUs would each decode their own share)",
               file=sys.stderr)
         sys.exit(2)

@@ -45,7 +45,7 @@ typedef enum {
   PIVCO_E_ARG = -1,          /* bad argument (returned synchronously) */
   PIVCO_E_CAPACITY = -2,     /* output or workspace too small */
   PIVCO_E_CORRUPT = -3,      /* stream fails validation */
-  PIVCO_E_UNSUPPORTED = -4,  /* valid stream outside this build's limits */
+  PIVCO_E_UNSUPPORTED = -4,  /* valid stream outside this library's limits */
   PIVCO_E_DEVICE = -5,       /* HIP runtime error */
   PIVCO_E_BUDGET = -6        /* serving: request larger than the memory budget */
 } pivco_status;

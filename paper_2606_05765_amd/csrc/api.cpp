@@ -315,7 +315,7 @@ const char *pivco_strerror(pivco_status st) {
     case PIVCO_E_ARG: return "invalid argument";
     case PIVCO_E_CAPACITY: return "output or workspace too small";
     case PIVCO_E_CORRUPT: return "corrupt stream";
-    case PIVCO_E_UNSUPPORTED: return "stream outside this build's limits";
+    case PIVCO_E_UNSUPPORTED: return "stream outside this library's limits";
     case PIVCO_E_DEVICE: return "HIP runtime error";
     case PIVCO_E_BUDGET: return "request exceeds the memory budget";
   }
