@@ -127,7 +127,7 @@ struct BlockHdr {
   uint32_t kraft;
   uint32_t chunk0, nchunk; // the block's rANS chunks in the batch's chunk list
   uint32_t cnt[17], fc[18], lbase[17], lvl[18];
-  uint64_t lvl_total[17];  // symbols passing each level (sum of n_v)
+  uint64_t lvl_total[17];  // symbols passing each level (sum of n_v); set by the merge kernel for streamed blocks
 };
 static_assert(offsetof(BlockHdr, job) == offsetof(BlockExt, job) && sizeof(BlockExt) == 48, "BlockExt prefix");
 
@@ -231,8 +231,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // breadth-first; child q of such a node is a leaf iff q < fc(d+1) + cnt(d+1),
 // and then it is the (q - fc(d+1))-th symbol of length d+1 by id.
 template <class Rd>
-__device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd,
-                                 bool totals) {
+__device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
   const uint32_t lane = lane_id();
   int32_t err = h.err;
   uint32_t mode = 0, csym = 0, cw = 0, comp = 0, n = 0;
@@ -374,19 +373,6 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
     }
     wave_sync_lds();
   }
-  if (totals) {
-    // symbols passing each level (only the streaming tile choice needs them)
-    uint64_t ltot = 0;                 // lane d: level d
-    for (uint32_t d = 0; d < maxlen; ++d) {
-      uint32_t s = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (4 * lane + k < I && dd[k] == d) s += t.nv[4 * lane + k];
-      const uint32_t tot = __shfl(wave_incl_scan(s), kWave - 1, kWave);  // < 2^32: n < 2^32
-      if (lane == d) ltot = tot;
-    }
-    if (lane < 17) h.lvl_total[lane] = lane < maxlen ? ltot : 0;
-  }
   // body offsets: lane owns nodes 4*lane .. 4*lane+3 (contiguous for the scan)
   uint32_t rawb[4], answ[4], lraw = 0, lans = 0;
 #pragma unroll
@@ -441,12 +427,6 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
   wave_sync_lds();
 }
 
-template <int NT, class Rd>
-__device__ void parse_block(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd,
-                            bool totals = false) {
-  if ((threadIdx.x >> 6) == 0) parse_block_wave(J, b, h, t, rd, totals);
-  __syncthreads();
-}
 
 // ---------------------------------------------------------------------------
 // Kernel: rANS decode of entropy-coded node bitmaps into scratch
@@ -1476,6 +1456,15 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
       sm.tv[i] = 0;
       if (!resident) sm.ones[i] = 0;
     }
+    if (!resident && wave == 0) {            // symbols passing each level, for the tile size
+      const uint32_t lane = lane_id();
+      if (lane < 17) h.lvl_total[lane] = 0;
+      wave_sync_lds();
+      for (uint32_t v = lane; v < I; v += kWave)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&h.lvl_total[t.depth[v]]),
+                  static_cast<unsigned long long>(t.nv[v]));
+      wave_sync_lds();
+    }
     if (tid == 0) {
       sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
       if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
@@ -2022,7 +2011,7 @@ __global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs,
     hdr[wave][i] = w;
   }
   wave_sync_lds();
-  parse_block_wave(J, item.y, h, t, SplitBytes{reinterpret_cast<const uint8_t *>(hdr[wave]), hn, g}, true);
+  parse_block_wave(J, item.y, h, t, SplitBytes{reinterpret_cast<const uint8_t *>(hdr[wave]), hn, g});
   if (lane == 0) {
     h.chunk0 = 0;
     h.nchunk = 0;
