@@ -166,8 +166,26 @@ struct WorkLists {
     }
     return n;
   }
-  // Orders the merge items by decreasing size (longest first).
+  // Orders the split blocks by decreasing tile count (the boundary kernel
+  // takes them in list order: longest first) and the merge items by
+  // decreasing size (longest first).
   void finish() {
+    if (tiled.size() > 1) {
+      std::vector<uint32_t> order(tiled.size()), pos(tiled.size());
+      for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [this](uint32_t a, uint32_t b) {
+        return tiled[a].ntiles > tiled[b].ntiles;
+      });
+      std::vector<TiledBlock> sorted;
+      sorted.reserve(tiled.size());
+      for (uint32_t i = 0; i < order.size(); ++i) {
+        sorted.push_back(tiled[order[i]]);
+        pos[order[i]] = i;
+      }
+      tiled.swap(sorted);
+      for (auto &x : sized)
+        if (x.second.y != kWholeBlock) x.second.y = (pos[x.second.y >> 8] << 8) | (x.second.y & 255);
+    }
     std::stable_sort(sized.begin(), sized.end(),
                      [](const std::pair<uint64_t, uint2> &a, const std::pair<uint64_t, uint2> &b) {
                        return a.first > b.first;
