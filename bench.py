@@ -11,6 +11,10 @@ the HBM roofline fraction of the merge kernel, the same decode as one launch
 per block ("plain"), the encode rate, and the CPU oracle timed on a sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+`--workload skew256m|mix4096|geo1m` times the other synthetic workloads the
+same way (batched decode and merge-kernel roofline only; the plain, serving
+and CPU legs belong to the default line).
 """
 import argparse
 import hashlib
@@ -122,6 +126,89 @@ def serving_leg(torch, dev, seconds=1.0, rate_hz=2000.0, n_pool=48, seed=11,
             "budget_GB": round(budget / 1e9, 1), "slots": 4}
 
 
+WORKLOAD_TEXT = {
+    "skew256m": "skew256m: 256 MiB uint8, p(0)=0.9 and 0.1 spread as 0.7^s over 1..255, 128 KiB blocks, "
+                "selective binary rANS (one-bit fraction < 0.1 or > 0.9)",
+    "mix4096": "mix4096: 4096 independent single-block streams, sizes log-uniform 4 KiB-4 MiB, "
+               "geometric / Zipf / uniform families, selective binary rANS",
+    "geo1m": "geo1m: 1 MiB uint8, p(s) ~ 0.8^s, one block, no ANS",
+}
+
+
+def other_workload(args, torch, dev):
+    """Batched decode of a non-default workload: GB/s and the merge kernel's
+    roofline on the same JSON shape (no plain, serving or CPU legs)."""
+    import workloads as W
+    from paper_2606_05765_amd import pivco as P
+    log(f"generating workload {args.workload} ...")
+    w = getattr(W, args.workload)(seed=args.seed)
+    xs = [np.ascontiguousarray(j) for j in w.jobs]
+    d_xs = [torch.from_numpy(x).to(dev) for x in xs]
+    bss = [w.block_size or max(x.size, 1) for x in xs]
+    streams = [P.pivco_encode(d, bs, max_len=11, ans_mode=w.ans_mode) for d, bs in zip(d_xs, bss)]
+    torch.cuda.synchronize()
+    n = sum(x.size for x in xs)
+    comp = sum(s.numel() for s in streams)
+    outs = [torch.empty(x.size, dtype=torch.uint8, device=dev) for x in xs]
+    if args.variant is not None:
+        tune = P.Tune()
+        tune.merge_variant = args.variant
+        tune.merge_grid = args.grid or 256
+        tune.rans_grid = 512
+    else:
+        tune = P.pivco_autotune(streams, outs)
+    plan = P.BatchPlan(streams, outs, tune=tune)
+    variant = P.pivco_merge_variants()[plan.tune.merge_variant]
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert (plan.statuses() == 0).all()
+    for o, d in zip(outs, d_xs):
+        assert torch.equal(o, d), "decoded bytes differ from the input"
+    ms_per_step = dt * 1e3 / args.steps
+    value = n / (dt / args.steps) / 1e9
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(); ev1.record()        # torch marks them recorded; the plan re-records them
+    torch.cuda.synchronize()
+    merge_ms = []
+    for _ in range(args.steps):
+        plan.launch_timed(ev0, ev1)
+        ev1.synchronize()
+        merge_ms.append(ev0.elapsed_time(ev1))
+    merge_avg = float(np.mean(merge_ms))
+    algo_bytes = comp + n
+    achieved = algo_bytes / (merge_avg * 1e-3) / 1e9
+    merges = sum(element_merges(x, bs) for x, bs in zip(xs, bss))
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "decode": "batched: one persistent HIP-graph launch over all blocks",
+                   "variant": variant, "tune": plan.tune.as_dict()},
+        "pct_hbm_roofline": round(achieved / HBM_PEAK_GBPS * 100, 2),
+        "compression_ratio": round(n / comp, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic(w.name, variant), "kernel": f"k_merge<{variant}>",
+                     "merge_ms_avg": round(merge_avg, 4), "algorithmic_bytes_per_launch": algo_bytes},
+        "alu_view": {"unit": "G element merges/s", "element_merges_per_launch": merges,
+                     "mean_code_len": round(merges / n, 4),
+                     "achieved": round(merges / (merge_avg * 1e-3) / 1e9, 1),
+                     "peak": round(VALU_LANE_OPS_PEAK_G, 1),
+                     "frac": round(merges / (merge_avg * 1e-3) / 1e9 / VALU_LANE_OPS_PEAK_G, 4)},
+    }
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +221,8 @@ def main():
     ap.add_argument("--variant", type=int, default=None, help="fixed merge variant (skips autotune)")
     ap.add_argument("--grid", type=int, default=None, help="fixed merge grid (with --variant)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) leg")
+    ap.add_argument("--workload", default="zipf256m",
+                    choices=["zipf256m", "skew256m", "mix4096", "geo1m"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -150,6 +239,9 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.workload != "zipf256m":
+        other_workload(args, torch, dev)
+        return
     log("generating workload zipf256m ...")
     w = W.zipf256m(seed=args.seed)
     x = w.jobs[0]
