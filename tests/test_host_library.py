@@ -70,3 +70,16 @@ def test_stream_info_on_oracle_stream():
     st = O.encode(x, 4096, ans_mode=1)
     info = P.pivco_stream_info(st.tobytes())
     assert info == O.stream_info(st)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: any --gpus other than 1 exits with status 2
+    and says so, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
