@@ -323,7 +323,7 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
   const uint32_t pa = fc_l | (cnt_l << 16), pb = lvl_l | (lbase_l << 16);
   uint32_t dd[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (int j = 1; j <= kMaxLenGpu; ++j) {
+  for (uint32_t j = 1; j <= kMaxLenGpu; ++j) {
     const uint32_t lj = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(lvl_l), j));
 #pragma unroll
     for (int k = 0; k < 4; ++k) dd[k] += (4 * lane + k >= lj) ? 1u : 0u;
@@ -1853,6 +1853,7 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
                                                    uint32_t n_tiled, const ParsedBlock *recs,
                                                    const uint32_t *scratch, uint64_t scratch_words,
                                                    uint2 *tab) {
+  if (blockIdx.x >= n_tiled) return;               // one workgroup per split block
   __shared__ TilesSmem sm;
   const uint32_t tid = threadIdx.x, wave = wave_id(), lane = lane_id();
   constexpr uint32_t NW = kTilesNT / kWave;
