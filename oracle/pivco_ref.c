@@ -650,42 +650,107 @@ static int check_stream(const uint8_t *in, uint64_t in_len, uint64_t *n_total, u
     return PVO_OK;
 }
 
-/* Listing 1, one cursor per internal node */
+/* Decoder A, from the definition of the pivoted layout (Sec. 2): the symbol at
+ * position i of a block is the one whose code is the sequence of bits that
+ * position left in the internal nodes on its path, and every internal node
+ * keeps its bits in stream order.  So the code of position i is read one bit
+ * at a time -- the next unread bit (a read count per node) of the internal
+ * node named by the code prefix read so far -- until the prefix equals a
+ * codeword of its length (the canonical codes of Sec. 1.1).  Internal nodes
+ * are numbered breadth-first: by depth, then by prefix value. */
+typedef struct {
+    uint16_t pfx[16][256];     /* internal-node prefixes at depth d, ascending */
+    int npfx[16], first[16];   /* their number; number of internal nodes above d */
+    uint16_t cw[16][256];      /* codewords of length d, ascending */
+    uint8_t cwsym[16][256];    /* their symbols */
+    int ncw[16];
+} codebook_t;
+
+/* index of v in the ascending array a[0..n), or -1 */
+static int find16(const uint16_t *a, int n, uint32_t v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) / 2;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && a[lo] == v) ? lo : -1;
+}
+
+/* insert v into the ascending array a[0..*n) unless present; returns its index */
+static int insert16(uint16_t *a, int *n, uint32_t v) {
+    int k = find16(a, *n, v);
+    if (k >= 0) return k;
+    int j = *n;
+    while (j > 0 && a[j - 1] > v) { a[j] = a[j - 1]; j--; }
+    a[j] = (uint16_t)v;
+    (*n)++;
+    return j;
+}
+
+static void build_codebook(const uint8_t len[256], codebook_t *cb) {
+    uint16_t code[256];
+    pivco_ref_codes(len, code);
+    memset(cb, 0, sizeof(*cb));
+    for (int s = 0; s < 256; s++) {
+        int l = len[s];
+        if (!l) continue;
+        for (int d = 0; d < l; d++) insert16(cb->pfx[d], &cb->npfx[d], (uint32_t)code[s] >> (l - d));
+        int k = insert16(cb->cw[l], &cb->ncw[l], code[s]);
+        for (int j = cb->ncw[l] - 1; j > k; j--) cb->cwsym[l][j] = cb->cwsym[l][j - 1];
+        cb->cwsym[l][k] = (uint8_t)s;
+    }
+    for (int d = 1; d < 16; d++) cb->first[d] = cb->first[d - 1] + cb->npfx[d - 1];
+}
+
 static void walk_block(const block_t *bk, uint8_t *out) {
     if (bk->mode == 1) { memset(out, bk->const_sym, (size_t)bk->n); return; }
-    const tree_t *t = bk->t;
+    codebook_t *cb = (codebook_t *)malloc(sizeof(codebook_t));
+    build_codebook(bk->len, cb);
     uint64_t cur[255];
     memset(cur, 0, sizeof(cur));
     for (uint64_t i = 0; i < bk->n; i++) {
-        int node = 0;
-        while (!t->nd[node].leaf) {
-            int id = t->nd[node].id;
-            int bit = getbit(bk->bm[id], cur[id]++);
-            node = bit ? t->nd[node].child[1] : t->nd[node].child[0];
+        uint32_t v = 0;                 /* code prefix read so far */
+        int d = 0;                      /* its length */
+        int sym = -1;
+        while (sym < 0 && d < 15) {
+            int id = cb->first[d] + find16(cb->pfx[d], cb->npfx[d], v);
+            v = 2 * v + (uint32_t)getbit(bk->bm[id], cur[id]++);
+            d++;
+            int k = find16(cb->cw[d], cb->ncw[d], v);
+            if (k >= 0) sym = cb->cwsym[d][k];
         }
-        out[i] = (uint8_t)t->nd[node].sym;
+        out[i] = (uint8_t)sym;         /* the block was validated: a codeword is always reached */
     }
+    free(cb);
 }
 
-/* Sec. 3: bottom-up merge; deepest internal nodes first (reverse BFS) */
+/* Decoder B, the bottom-up merge of Sec. 3: every internal node v, deepest
+ * first, forms the symbol sequence of its subtree; output j of v comes from
+ * the child its bitmap bit selects (0 left, 1 right), at the position given
+ * by the count of equal bits before j (a leaf child's sequence is its symbol
+ * repeated). */
 static void merge_block(const block_t *bk, uint8_t *out) {
     if (bk->mode == 1) { memset(out, bk->const_sym, (size_t)bk->n); return; }
     const tree_t *t = bk->t;
     uint8_t *seq[255];
     for (int i = (int)bk->I - 1; i >= 0; i--) {
         const tnode *v = &t->nd[t->bfs[i]];
+        const tnode *kid[2] = {&t->nd[v->child[0]], &t->nd[v->child[1]]};
         uint8_t *o = (i == 0) ? out : (uint8_t *)malloc((size_t)v->n + 1);
-        const tnode *l = &t->nd[v->child[0]], *r = &t->nd[v->child[1]];
-        const uint8_t *ls = l->leaf ? NULL : seq[l->id];
-        const uint8_t *rs = r->leaf ? NULL : seq[r->id];
-        uint64_t nl = 0, nr = 0;
+        /* ones[j] = 1 bits of the node's bitmap before position j */
+        uint64_t *ones = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)v->n + 1));
+        ones[0] = 0;
+        for (uint64_t j = 0; j < v->n; j++) ones[j + 1] = ones[j] + (uint64_t)getbit(bk->bm[i], j);
         for (uint64_t j = 0; j < v->n; j++) {
-            if (getbit(bk->bm[i], j)) o[j] = r->leaf ? (uint8_t)r->sym : rs[nr++];
-            else o[j] = l->leaf ? (uint8_t)l->sym : ls[nl++];
+            int b = getbit(bk->bm[i], j);
+            uint64_t rank = b ? ones[j] : j - ones[j];
+            const tnode *c = kid[b];
+            o[j] = c->leaf ? (uint8_t)c->sym : seq[c->id][rank];
         }
+        free(ones);
         seq[i] = o;
-        if (!l->leaf) free(seq[l->id]);
-        if (!r->leaf) free(seq[r->id]);
+        for (int b = 0; b < 2; b++)
+            if (!kid[b]->leaf) free(seq[kid[b]->id]);
     }
 }
 
@@ -776,7 +841,7 @@ int pivco_ref_classical_decode(const uint8_t *bits, uint64_t nbits, const uint8_
     uint64_t p = 0;
     for (uint64_t i = 0; i < n; i++) {
         int node = 0;
-        while (!t->nd[node].leaf) {                 /* Listing 1 */
+        while (!t->nd[node].leaf) {                 /* one tree edge per bit */
             if (p >= nbits) { free(t); return PVO_E_CORRUPT; }
             int bit = (bits[p >> 3] >> (7 - (p & 7))) & 1;
             p++;

@@ -8,7 +8,9 @@
  *
  * Every function follows a passage of the paper (Zukowski, "PivCo-Huffman",
  * v1.0, 2026):
- *   - Listing 1 (Sec. 1.1)        bit-by-bit tree walk, used by both decoders
+ *   - Sec. 1.1 (canonical codes)   codes read bit by bit; a bit-by-bit tree
+ *                                  walk (the decoding Listing 1 shows) is the
+ *                                  classical-stream cross-check
  *   - Sec. 2 / Fig. 2-3            one bitmap per internal node ("pivoting")
  *   - Sec. 3 / naive merge loop    bottom-up merge decoder
  *   - Sec. 4 / Table 11            encoder = build node bitmaps top-down
@@ -80,9 +82,10 @@ int pivco_ref_stream_info(const uint8_t *in, uint64_t in_len, uint64_t *n_total,
                           uint32_t *n_blocks, uint32_t *block_size,
                           uint64_t *ans_words);
 
-/* Decoder A: validates the stream, then for every output position walks the
- * tree from the root reading the next bit of each visited node (Listing 1
- * with one read cursor per node). */
+/* Decoder A: validates the stream, then reads the code of every output
+ * position bit by bit -- the next unread bit of the internal node named by
+ * the prefix read so far -- until the prefix is a canonical codeword
+ * (Sec. 1.1 and Sec. 2: a position's bits along its path are its code). */
 int pivco_ref_decode(const uint8_t *in, uint64_t in_len, uint8_t *out,
                      uint64_t cap, uint64_t *n_out);
 
@@ -102,7 +105,7 @@ int pivco_ref_decode_blocks(const uint8_t *in, uint64_t in_len, uint32_t b0,
  * MSB of each code first, bits packed MSB-first into bytes. */
 int pivco_ref_classical_encode(const uint8_t *in, uint64_t n, const uint8_t len[256],
                                uint8_t *out, uint64_t cap, uint64_t *nbits);
-/* Listing 1 applied to a classical stream. */
+/* Bit-by-bit tree walk (the decoding of Listing 1) over a classical stream. */
 int pivco_ref_classical_decode(const uint8_t *bits, uint64_t nbits,
                                const uint8_t len[256], uint8_t *out, uint64_t n);
 /* Convert the first block of a pivoted stream into the classical stream. */

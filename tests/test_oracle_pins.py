@@ -313,6 +313,21 @@ def test_selection_rule_boundaries():
     assert O.p1q(1 << 20, 1 << 19) == 2048
 
 
+def test_p1q_rounds_to_nearest():
+    # The rANS probability of a 1 bit is the node's one-bit fraction in 12-bit
+    # fixed point, rounded to nearest and clamped to [1, 4095] (the reading of
+    # the 12-bit binary coder written down for this format).  Values worked
+    # out by hand; truncation would give the numbers in the comments.
+    assert O.p1q(3, 2) == 2731        # 8192 / 3 = 2730.67 (floor: 2730)
+    assert O.p1q(5, 3) == 2458        # 12288 / 5 = 2457.6 (floor: 2457)
+    assert O.p1q(9, 7) == 3186        # 28672 / 9 = 3185.78 (floor: 3185)
+    assert O.p1q(3, 1) == 1365        # 4096 / 3 = 1365.33 rounds down
+    assert O.p1q(2, 1) == 2048        # exactly one half
+    assert O.p1q(8193, 1) == 1        # 0.4999 rounds to 0, clamped up to 1
+    assert O.p1q(10000, 9999) == 4095  # 4095.59 + 0.5 = 4096.09: 4096, clamped down
+    assert O.p1q(7, 0) == 1 and O.p1q(7, 7) == 4095
+
+
 # --------------------------------------------------------------------------
 # corrupt streams are rejected
 # --------------------------------------------------------------------------
