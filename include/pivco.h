@@ -201,6 +201,7 @@ typedef struct {
   uint64_t peak_pool_bytes;
   uint64_t batches;
   uint64_t max_batch;
+  uint64_t max_busy_slots;     /* most batches in flight at once (slots busy together) */
 } pivco_server_stats;
 
 typedef struct pivco_server pivco_server;
@@ -220,7 +221,10 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
  * (outputs are placed in d_pool, at most min(pool_bytes, mem_budget) bytes);
  * each admission round is one batched decode on a free slot, overlapping
  * with batches on other slots.  A request larger than the budget gets
- * PIVCO_E_BUDGET.  Returns when every request has completed. */
+ * PIVCO_E_BUDGET, and so does a request that does not fit in the pool while
+ * no batch is in flight (with keep_outputs, output space is never released,
+ * so requests after the pool has filled up fail this way).  Returns when
+ * every request has completed or failed. */
 pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint32_t n_req,
                               void *d_pool, uint64_t pool_bytes, pivco_request_result *res,
                               pivco_server_stats *stats);

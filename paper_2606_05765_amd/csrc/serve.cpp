@@ -188,7 +188,8 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   pivco_status st = pivco_stream_info(h, kHeaderBytes, &n_total, &nb, &bs, &ans);
   if (st) return st;
   if (len < kHeaderBytes + 16ull * (nb + 1ull)) return PIVCO_E_CORRUPT;
-  if (nb > sv->max_blocks || ans > sv->max_scratch_words) return PIVCO_E_UNSUPPORTED;
+  // a batch reserves its jobs' scratch in multiples of 4 words
+  if (nb > sv->max_blocks || align_up(ans, 4) > sv->max_scratch_words) return PIVCO_E_UNSUPPORTED;
   const WorkLists::Need need = WorkLists::need_of(n_total, nb, bs);
   if (need.tiles > sv->max_tiles) return PIVCO_E_UNSUPPORTED;
   const uint64_t chunks = rans_chunk_bound(ans, nb, h[25]);
@@ -232,7 +233,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
   std::vector<uint64_t> out_off(n_req, 0);
   std::deque<uint32_t> pending;
   uint32_t next = 0, done = 0;
-  uint64_t peak = 0, bytes_done = 0, batches = 0, max_batch_seen = 0;
+  uint64_t peak = 0, bytes_done = 0, batches = 0, max_batch_seen = 0, max_busy = 0;
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
   auto now_s = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
@@ -383,6 +384,20 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
       max_batch_seen = std::max<uint64_t>(max_batch_seen, batch.size());
       progressed = true;
     }
+    const uint64_t busy = static_cast<uint64_t>(
+        std::count_if(sv->slots.begin(), sv->slots.end(), [](const Slot &s) { return s.busy; }));
+    max_busy = std::max(max_busy, busy);
+    if (busy == 0 && !pending.empty()) {
+      // nothing is in flight, so no output space will be released: the head
+      // request does not fit in what is left of the pool (kept outputs of
+      // earlier requests hold the rest) and never will
+      const uint32_t r = pending.front();
+      pending.pop_front();
+      res[r].status = PIVCO_E_BUDGET;
+      res[r].t_admit = res[r].t_done = now_s();
+      ++done;
+      progressed = true;
+    }
     if (!progressed) {
       // nothing to do right now: wait for the next arrival or a completion
       const bool any_busy = std::any_of(sv->slots.begin(), sv->slots.end(), [](const Slot &s) { return s.busy; });
@@ -400,6 +415,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
     stats->peak_pool_bytes = peak;
     stats->batches = batches;
     stats->max_batch = max_batch_seen;
+    stats->max_busy_slots = max_busy;
   }
   return PIVCO_OK;
 }

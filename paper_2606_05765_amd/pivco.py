@@ -69,7 +69,8 @@ class RequestResult(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [("wall_s", C.c_double), ("bytes_decoded", C.c_uint64),
-                ("peak_pool_bytes", C.c_uint64), ("batches", C.c_uint64), ("max_batch", C.c_uint64)]
+                ("peak_pool_bytes", C.c_uint64), ("batches", C.c_uint64), ("max_batch", C.c_uint64),
+                ("max_busy_slots", C.c_uint64)]
 
 
 _lib = None
@@ -365,7 +366,7 @@ class Server:
                for i in range(n)]
         return out, {"wall_s": st.wall_s, "bytes_decoded": st.bytes_decoded,
                      "peak_pool_bytes": st.peak_pool_bytes, "batches": st.batches,
-                     "max_batch": st.max_batch}
+                     "max_batch": st.max_batch, "max_busy_slots": st.max_busy_slots}
 
     def close(self):
         if self.handle:

@@ -12,12 +12,73 @@ pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2606_05765_amd.pivco")
 
 
-def _requests(n_req=40, hi=2 << 20, seed=7):
-    w = W.serve_requests(seed=seed, n_req=n_req, hi=hi)
+def _requests(n_req=40, hi=2 << 20, seed=7, lo=16 << 10):
+    w = W.serve_requests(seed=seed, n_req=n_req, lo=lo, hi=hi)
     streams = [P.pivco_encode(torch.from_numpy(x).cuda(), w.block_size, ans_mode=w.ans_mode)
                for x in w.jobs]
     torch.cuda.synchronize()
     return w, streams
+
+
+def _full_range_requests():
+    """Requests over the whole serving size range, 16 KiB - 64 MiB: twelve
+    drawn log-uniformly (three of them 43-50 MiB), plus the two end points."""
+    w, streams = _requests(n_req=12, lo=16 << 10, hi=64 << 20, seed=26)
+    for seed, size in ((1, 16 << 10), (2, 64 << 20)):
+        e, es = _requests(n_req=1, lo=size, hi=size, seed=seed)
+        w.jobs += e.jobs
+        streams += es
+    return w, streams
+
+
+def test_full_size_range_same_alone_and_in_mix():
+    w, streams = _full_range_requests()
+    sizes = [int(x.size) for x in w.jobs]
+    print("request sizes (KiB)", sorted(s >> 10 for s in sizes), flush=True)
+    assert min(sizes) == 16 << 10 and max(sizes) == 64 << 20
+    assert sum(s >= 16 << 20 for s in sizes) >= 4
+    sv = P.Server(mem_budget=32 * 10**9, slots=4, max_batch=2, keep_outputs=True)
+    ids = [sv.register(s) for s in streams]
+    order = np.random.default_rng(4).permutation(ids)
+    arrivals = W.poisson_arrivals(6, 20000.0, len(order))   # all arrive within ~1 ms
+    pool = torch.empty(sum(sizes) + 256 * len(sizes), dtype=torch.uint8, device="cuda")
+    res, stats = sv.run(arrivals, order, pool)
+    torch.cuda.synchronize()
+    print("stats", stats, flush=True)
+    assert stats["max_busy_slots"] > 1                  # batches overlapped on the device
+    for k, r in enumerate(res):
+        i = int(order[k])
+        assert r["status"] == 0, (k, r)
+        got = P.view_output(pool, r["d_out"], r["n_out"])
+        alone, st = P.pivco_decode(streams[i])
+        assert st == 0
+        assert torch.equal(got, alone), (k, sizes[i])
+        assert np.array_equal(got.cpu().numpy(), w.jobs[i]), (k, sizes[i])
+    sv.close()
+
+
+def test_kept_outputs_fill_the_pool():
+    # with keep_outputs the pool is never recycled: once it is full, run()
+    # must still return, failing the requests that no longer fit
+    w, streams = _requests(n_req=10, hi=4 << 20, seed=9)
+    sizes = [int(x.size) for x in w.jobs]
+    sv = P.Server(mem_budget=1 << 30, slots=2, max_batch=2, keep_outputs=True)
+    ids = [sv.register(s) for s in streams]
+    order = list(ids) * 2
+    pool_bytes = sum(sizes) + 256 * len(sizes)          # room for each request once
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    arrivals = np.linspace(0, 0.002, len(order))
+    res, stats = sv.run(arrivals, order, pool)
+    torch.cuda.synchronize()
+    ok = [k for k, r in enumerate(res) if r["status"] == 0]
+    failed = [k for k, r in enumerate(res) if r["status"] != 0]
+    assert all(res[k]["status"] == P.E_BUDGET for k in failed)
+    assert failed and len(ok) >= len(ids)
+    assert sum((sizes[order[k]] + 255) // 256 * 256 for k in ok) <= pool_bytes
+    for k in ok:
+        got = P.view_output(pool, res[k]["d_out"], res[k]["n_out"]).cpu().numpy()
+        assert np.array_equal(got, w.jobs[order[k]]), k
+    sv.close()
 
 
 def test_results_same_alone_and_in_mix():
