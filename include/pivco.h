@@ -130,6 +130,23 @@ pivco_status pivco_decode_batch(const pivco_job *h_jobs, uint32_t count, int32_t
 pivco_status pivco_decode(const void *d_in, uint64_t in_len, void *d_out, uint64_t out_cap,
                           int32_t *d_status, void *d_ws, uint64_t ws_bytes, hipStream_t s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decode as pivco_decode, with its workspace in a fixed device array of
+ * PIVCO_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  Allocates no device memory.  Returns E_CAPACITY,
+ * before any device work, when the stream needs more workspace than that
+ * (pivco_decode_workspace gives the need: about 5.6 KB per block plus rANS
+ * scratch and the boundary tables of blocks of more than 64Ki symbols).  All
+ * calls on one GPU share the array: calls that overlap in time on one GPU
+ * (other streams or threads) race, so callers serialise them; the next call
+ * may start once this one's work on s has completed or is ordered after it
+ * on the same stream.  Otherwise as pivco_decode (synchronous up to the
+ * kernel launches, which read the stream header). */
+#define PIVCO_NOALLOC_SCRATCH_BYTES (32ull << 20)
+pivco_status pivco_decode_noalloc(const void *d_in, uint64_t in_len, void *d_out, uint64_t out_cap,
+                                  int32_t *d_status, hipStream_t s);
+
 /* Baseline for comparison: the same kernel launched once per block, one
  * launch after the other on s (no persistent queue, no graph). */
 pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,

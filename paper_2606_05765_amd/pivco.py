@@ -97,6 +97,7 @@ def lib():
             "pivco_decode_batch": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
             "pivco_decode": (i32, [vp, u64, vp, u64, vp, vp, u64, vp]),
             "pivco_decode_plain": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
+            "pivco_decode_noalloc": (i32, [vp, u64, vp, u64, vp, vp]),
             "pivco_merge_variants": (u32, []),
             "pivco_merge_variant_name": (C.c_char_p, [u32]),
             "pivco_batch_plan_create": (i32, [C.POINTER(Job), u32, vp, vp, u64, C.POINTER(Tune),
@@ -260,6 +261,22 @@ def pivco_decode_batch(streams, outs=None, ws=None, plain=False):
 def pivco_decode(stream, out=None, ws=None):
     outs, st = pivco_decode_batch([stream], None if out is None else [out], ws=ws)
     return outs[0], int(st[0])
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def pivco_decode_noalloc(stream, out, status):
+    """pivco_decode with the library's fixed device scratch: no workspace,
+    no allocation (out and status are caller tensors: uint8 and int32)."""
+    stream = _dev_u8(stream)
+    out = _dev_u8(out)
+    if not (status.is_cuda and status.dtype == torch.int32 and status.numel() >= 1):
+        raise TypeError("status: an int32 CUDA tensor")
+    _check(lib().pivco_decode_noalloc(C.c_void_p(stream.data_ptr()), stream.numel(),
+                                      C.c_void_p(out.data_ptr() if out.numel() else 0), out.numel(),
+                                      C.c_void_p(status.data_ptr()), _stream()),
+           "pivco_decode_noalloc")
 
 
 def pivco_decode_plain(streams, outs=None, ws=None):
