@@ -157,7 +157,9 @@ typedef struct {
   uint32_t merge_variant;    /* index into the compiled merge kernels */
   uint32_t merge_grid;       /* workgroups of the persistent merge kernel */
   uint32_t rans_grid;        /* workgroups of the rANS decode kernel */
-  uint32_t reserved;
+  uint32_t grid_mode;        /* 0: persistent merge kernel over the work queue;
+                                1: one non-persistent launch with a workgroup
+                                per work item (merge_grid ignored) */
 } pivco_tune;
 
 /* Number of compiled merge-kernel variants and a short description of one. */

@@ -273,10 +273,10 @@ pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, con
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PIVCO_E_DEVICE;
-  if (!w.items.empty() &&
-      launch_merge(t.merge_variant, t.merge_grid, s, d.jobs, d.items, d.recs, d.tiled,
-                   d.tab, static_cast<uint32_t>(w.items.size()), d.ctr, d.scratch,
-                   p.scratch_words, -1) != hipSuccess)
+  const uint32_t ni = static_cast<uint32_t>(w.items.size());
+  if (ni && launch_merge(t.merge_variant, t.grid_mode ? ni : t.merge_grid, s, d.jobs, d.items, d.recs,
+                         d.tiled, d.tab, ni, d.ctr, d.scratch, p.scratch_words,
+                         t.grid_mode ? kGridItems : kQueueItems) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return PIVCO_E_DEVICE;
   return PIVCO_OK;
@@ -416,7 +416,7 @@ pivco_status pivco_batch_plan_create(const pivco_job *h_jobs, uint32_t count, in
   bp->tune = tune ? *tune : default_tune(static_cast<uint32_t>(bp->plan.w.items.size()),
                                          bp->plan.chunk_cap);
   if (bp->tune.merge_variant >= merge_variant_count() || bp->tune.merge_grid == 0 ||
-      bp->tune.rans_grid == 0) {
+      bp->tune.rans_grid == 0 || bp->tune.grid_mode > 1) {
     delete bp;
     return PIVCO_E_ARG;
   }

@@ -1150,6 +1150,11 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
       const uint32_t r4 = __builtin_amdgcn_alignbyte(wr[i][g].y, wr[i][g].x, aR[i][g]);
       o[g] = __builtin_amdgcn_perm(r4, l4, sel[i][g]);
     }
+    // the outputs exist here for every lane: otherwise the compiler moves a
+    // window's LDS reads into the store branch below and waits for each one
+    // in turn
+#pragma unroll
+    for (int g = 0; g < G; ++g) asm volatile("" ::"v"(o[g]));
     if (!valid[i]) continue;
 #pragma unroll
     for (int c = 0; c < C::K / CB; ++c) {
@@ -1625,7 +1630,10 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
 }
 
 // Persistent merge: a workgroup takes items from the queue (largest first) --
-// whole blocks, or tiles of split blocks -- looking one item ahead.
+// whole blocks, or tiles of split blocks -- looking one item ahead.  `single`
+// selects the item source: kQueueItems (the persistent queue), kGridItems
+// (workgroup b decodes item b and exits: one non-persistent launch with a
+// workgroup per item), or an item index (one item, one workgroup).
 template <class C>
 __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2 *items,
                                                   const ParsedBlock *recs,
@@ -1638,7 +1646,9 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
   for (int i = tid; i < 256; i += C::NT) sm.leafrow[i] = static_cast<uint32_t>(i) * 0x01010101u;
   init_sel<C>(sm);
   if (tid == 0) {
-    const uint32_t it = single >= 0 ? static_cast<uint32_t>(single) : atomicAdd(&ctr->merge_next, 1u);
+    const uint32_t it = single >= 0            ? static_cast<uint32_t>(single)
+                        : single == kGridItems ? blockIdx.x
+                                               : atomicAdd(&ctr->merge_next, 1u);
     sm.item = it;
     if (it < n_items) {
       const uint2 rt = items[it];
@@ -1658,7 +1668,7 @@ __global__ __launch_bounds__(C::NT) void k_merge(const JobDev *jobs, const uint2
     // stream are read while this item is decoded, and published to LDS
     // before the merge (or when the item ends early)
     Lookahead la{n_items, make_uint2(0, 0), BlockExt{}, nullptr, nullptr};
-    if (tid == kWave && single < 0) la.item = atomicAdd(&ctr->merge_next, 1u);
+    if (tid == kWave && single == kQueueItems) la.item = atomicAdd(&ctr->merge_next, 1u);
     const JobDev &J = jobs[ext.job];
     const bool whole = rt.y == kWholeBlock;
     if (whole) {

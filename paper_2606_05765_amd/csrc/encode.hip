@@ -78,8 +78,11 @@ __global__ void k_fill_zero(uint32_t *p, uint64_t nwords) {
     p[i] = 0;
 }
 
+// Histogram of every block, one workgroup per slice of kHistSlice symbols:
+// the slice's counts go to its own row of slh (the split kernel's slices
+// start at the same boundaries) and are added to the block's row of hist.
 __global__ __launch_bounds__(256) void k_hist(const uint8_t *in, uint64_t n, uint32_t bs,
-                                              uint32_t spb, uint32_t *hist) {
+                                              uint32_t spb, uint32_t *hist, uint32_t *slh) {
   __shared__ uint32_t h[4][256];
   const int tid = threadIdx.x, w = tid >> 6;
   for (int i = tid; i < 1024; i += 256) (&h[0][0])[i] = 0;
@@ -108,8 +111,25 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t *in, uint64_t n, uin
   }
   __syncthreads();
   const uint32_t v = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+  slh[static_cast<uint64_t>(blockIdx.x) * 256 + tid] = v;
   if (v) atomicAdd(&hist[b * 256 + tid], v);
 }
+
+// Per block, the slice histograms become exclusive prefixes: row k holds the
+// count of each symbol in the block's slices before slice k (one thread per
+// symbol, one workgroup per block).
+__global__ __launch_bounds__(256) void k_slice_prefix(uint32_t *slh, uint32_t spb) {
+  uint32_t *row = slh + static_cast<uint64_t>(blockIdx.x) * spb * 256 + threadIdx.x;
+  uint32_t run = 0;
+  for (uint32_t k = 0; k < spb; ++k) {
+    const uint32_t c = row[256ull * k];
+    row[256ull * k] = run;
+    run += c;
+  }
+}
+
+static_assert(kSplitNT == 256, "the split kernel's prefix walk has one thread per symbol");
+static_assert(kHistSlice % kSplitT == 0, "split tiles never cross a slice");
 
 struct SplitSmem {
   EncBlock B;
@@ -121,13 +141,21 @@ struct SplitSmem {
   uint8_t buf[2][kSplitT];
 };
 
+// One workgroup per slice of kHistSlice symbols of a block (slice k of block
+// b is workgroup b * spb + k), so that large blocks are split by many
+// workgroups.  A node's bits from this slice start at the number of the
+// block's symbols before the slice that pass the node: the sum, over the
+// symbols on whose path the node lies, of their counts before the slice
+// (the slice's row of the prefix histograms).  Slices share bitmap words at
+// their edges: every word is written with atomicOr into zeroed scratch.
 __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const EncBlock *blocks,
-                                                    uint32_t nblocks, uint32_t *bmp) {
+                                                    uint32_t nblocks, uint32_t spb,
+                                                    const uint32_t *pre, uint32_t *bmp) {
   __shared__ SplitSmem sm;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const uint32_t lane = __lane_id();
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = blockIdx.x / spb, slice = blockIdx.x % spb;
   if (b >= nblocks) return;
   {
     const uint32_t *src = reinterpret_cast<const uint32_t *>(&blocks[b]);
@@ -136,12 +164,25 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
   }
   __syncthreads();
   const EncBlock &B = sm.B;
-  if (B.I == 0) return;
+  const uint32_t s_lo = slice * kHistSlice;
+  if (B.I == 0 || s_lo >= B.n) return;
+  const uint32_t s_hi = B.n - s_lo < kHistSlice ? B.n : s_lo + kHistSlice;
   for (uint32_t i = tid; i < 256; i += kSplitNT) sm.cur[i] = 0;
   __syncthreads();
+  if (slice) {   // bits of each node before this slice
+    const uint32_t s = tid;
+    const uint32_t c = pre[static_cast<uint64_t>(blockIdx.x) * 256 + s];
+    const uint32_t cl = B.code[s], len = cl >> 16, code = cl & 0xFFFF;
+    if (c && len)
+      for (uint32_t d = 0; d < len; ++d) {
+        const uint32_t p = code >> (len - d);
+        atomicAdd(&sm.cur[B.lvl[d] + (p - (B.fc[d] + B.cnt[d]))], c);
+      }
+    __syncthreads();
+  }
   const uint8_t *bin = in + B.in_off;
-  for (uint32_t t0 = 0; t0 < B.n; t0 += kSplitT) {
-    const uint32_t tn = B.n - t0 < kSplitT ? B.n - t0 : kSplitT;
+  for (uint32_t t0 = s_lo; t0 < s_hi; t0 += kSplitT) {
+    const uint32_t tn = s_hi - t0 < kSplitT ? s_hi - t0 : kSplitT;
     for (uint32_t i = tid; i < 256; i += kSplitNT) { sm.tv[i] = 0; sm.hist[i] = 0; }
     if (tid < 16) sm.top[tid] = 0;
     __syncthreads();
@@ -289,7 +330,7 @@ bool opts_ok(const pivco_encode_opts *o) {
 }
 
 struct WsLayout {
-  uint64_t hist, blocks, bmp, rjobs, rsizes, slots, staging, desc, total;
+  uint64_t hist, slh, blocks, bmp, rjobs, rsizes, slots, staging, desc, total;
 };
 
 // Generous sizes derived from n alone (the data is not known yet).
@@ -302,6 +343,7 @@ WsLayout ws_layout(uint64_t n, const pivco_encode_opts *o) {
   const uint64_t chunks = o->ans_mode ? bits / C + nodes + 1 : 0;
   uint64_t x = 0;
   L.hist = x; x = align_up(x + nb * 1024 + 16, 256);
+  L.slh = x; x = align_up(x + nb * div_up(o->block_size, kHistSlice) * 1024 + 16, 256);
   L.blocks = x; x = align_up(x + nb * sizeof(EncBlock), 256);
   L.bmp = x; x = align_up(x + 4 * (bits / 32 + nodes + 16), 256);
   L.rjobs = x; x = align_up(x + chunks * sizeof(RansJob), 256);
@@ -454,9 +496,14 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
     const uint32_t spb = static_cast<uint32_t>(div_up(bs, kHistSlice));
     const uint64_t grid = nb64 * spb;
     if (grid > 0x7FFFFFFFull) return PIVCO_E_UNSUPPORTED;
+    uint32_t *dslh = reinterpret_cast<uint32_t *>(ws + L.slh);
     hipLaunchKernelGGL(k_hist, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s, in, n,
-                       static_cast<uint32_t>(bs), spb, dh);
+                       static_cast<uint32_t>(bs), spb, dh, dslh);
     HIPCHK(hipGetLastError());
+    if (spb > 1) {
+      hipLaunchKernelGGL(k_slice_prefix, dim3(nb), dim3(256), 0, s, dslh, spb);
+      HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipMemcpyAsync(hist.data(), dh, hist.size() * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -506,8 +553,10 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
     HIPCHK(hipMemcpyAsync(ws + L.blocks, eb.data(), sizeof(EncBlock) * nb, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_fill_zero, dim3(std::min<uint64_t>(8192, div_up(bmp_words + 16, 256))), dim3(256), 0, s,
                        dbmp, bmp_words + 16);
-    hipLaunchKernelGGL(k_split, dim3(nb), dim3(kSplitNT), 0, s, in,
-                       reinterpret_cast<const EncBlock *>(ws + L.blocks), nb, dbmp);
+    const uint32_t spb = static_cast<uint32_t>(div_up(bs, kHistSlice));
+    hipLaunchKernelGGL(k_split, dim3(static_cast<uint32_t>(nb64 * spb)), dim3(kSplitNT), 0, s, in,
+                       reinterpret_cast<const EncBlock *>(ws + L.blocks), nb, spb,
+                       reinterpret_cast<const uint32_t *>(ws + L.slh), dbmp);
     HIPCHK(hipGetLastError());
   }
 

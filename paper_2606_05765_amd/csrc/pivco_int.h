@@ -196,6 +196,11 @@ struct WorkLists {
   }
 };
 
+// Item source of the merge kernel (its `single` argument): the persistent
+// queue, or one workgroup per item; values >= 0 decode that one item.
+constexpr int32_t kQueueItems = -1;
+constexpr int32_t kGridItems = -2;
+
 // Decode launchers (decode.hip), used by the batch planner and the server.
 // A launch is k_init, k_plan over the blocks (records: kParsedBlockBytes per
 // block), k_rans when some block has rANS nodes, k_tiles over the split

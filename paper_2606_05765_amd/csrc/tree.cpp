@@ -18,7 +18,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <vector>
 
 #include "pivco_int.h"
 
@@ -34,57 +33,65 @@ namespace pivco {
 // include it.
 pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]) {
   std::memset(len, 0, 256);
-  std::vector<int> sym;
-  for (int s = 0; s < 256; ++s)
-    if (counts[s]) sym.push_back(s);
-  const size_t m = sym.size();
-  if (m < 2 || max_len < 1 || max_len > 15 || (size_t(1) << max_len) < m) return PIVCO_E_ARG;
-  std::stable_sort(sym.begin(), sym.end(), [&](int a, int b) { return counts[a] < counts[b]; });
-  std::vector<uint64_t> w(m);
-  for (size_t i = 0; i < m; ++i) w[i] = counts[sym[i]];
-  // rows[r]: weights and single-coin flags, r = 1 (2^-1) .. max_len (2^-L)
-  std::vector<std::vector<uint64_t>> weight(max_len + 1);
-  std::vector<std::vector<uint8_t>> single(max_len + 1);
-  weight[max_len] = w;
-  single[max_len].assign(m, 1);
-  for (uint32_t r = max_len; r > 1; --r) {
-    const std::vector<uint64_t> &below = weight[r];
-    std::vector<uint64_t> &wr = weight[r - 1];
-    std::vector<uint8_t> &sr = single[r - 1];
-    const size_t np = below.size() / 2;
-    wr.reserve(m + np);
-    sr.reserve(m + np);
-    size_t a = 0, p = 0;
-    while (a < m || p < np) {
-      const uint64_t pw = p < np ? below[2 * p] + below[2 * p + 1] : 0;
-      if (p >= np || (a < m && w[a] <= pw)) {
-        wr.push_back(w[a++]);
-        sr.push_back(1);
-      } else {
-        wr.push_back(pw);
-        sr.push_back(0);
-        ++p;
-      }
-    }
+  // symbols by (count asc, id asc): one key per symbol (counts of a block
+  // stay far below 2^56)
+  uint64_t key[256];
+  size_t m = 0;
+  for (int s = 0; s < 256; ++s) {
+    if (counts[s] >> 56) return PIVCO_E_ARG;
+    if (counts[s]) key[m++] = (counts[s] << 8) | static_cast<uint64_t>(s);
   }
-  std::vector<uint32_t> depth(m, 0);
+  if (m < 2 || max_len < 1 || max_len > 15 || (size_t(1) << max_len) < m) return PIVCO_E_ARG;
+  std::sort(key, key + m);
+  uint64_t w[257];
+  for (size_t i = 0; i < m; ++i) w[i] = key[i] >> 8;
+  w[m] = ~uint64_t(0);                        // past the last single: never taken
+  // rows r = 1 (2^-1) .. max_len (2^-L): weights and single-coin flags; a
+  // row holds the m singles and at most m - 1 packages
+  uint64_t weight[16][512];
+  uint8_t single[16][512];
+  size_t rlen[16] = {0};
+  for (size_t i = 0; i < m; ++i) { weight[max_len][i] = w[i]; single[max_len][i] = 1; }
+  rlen[max_len] = m;
+  for (uint32_t r = max_len; r > 1; --r) {
+    const uint64_t *below = weight[r];
+    uint64_t *wr = weight[r - 1];
+    uint8_t *sr = single[r - 1];
+    const size_t np = rlen[r] / 2;
+    // branch-free merge (the comparison is data dependent): a single is
+    // taken when it weighs no more than the next package or no package is left
+    size_t a = 0, p = 0;
+    const size_t total = m + np;
+    for (size_t o = 0; o < total; ++o) {
+      const uint64_t pw = p < np ? below[2 * p] + below[2 * p + 1] : ~uint64_t(0);
+      const bool take = w[a] <= pw;
+      wr[o] = take ? w[a] : pw;
+      sr[o] = take;
+      a += take;
+      p += !take;
+    }
+    rlen[r - 1] = total;
+  }
+  uint32_t depth[256] = {0};
   size_t k = 2 * m - 2;                       // items bought in row 1
   for (uint32_t r = 1; r <= max_len && k; ++r) {
-    if (k > weight[r].size()) return PIVCO_E_ARG;
-    size_t singles = 0, packs = 0;
-    for (size_t i = 0; i < k; ++i) (single[r][i] ? singles : packs)++;
+    if (k > rlen[r]) return PIVCO_E_ARG;
+    size_t singles = 0;
+    for (size_t i = 0; i < k; ++i) singles += single[r][i];
+    const size_t packs = k - singles;
     for (size_t i = 0; i < singles; ++i) depth[i]++;
     k = 2 * packs;
   }
-  std::vector<uint32_t> pool(depth.begin(), depth.end());
-  std::sort(pool.begin(), pool.end());
-  std::vector<int> order(sym.begin(), sym.end());
-  std::sort(order.begin(), order.end(), [&](int x, int y) {
-    return counts[x] != counts[y] ? counts[x] > counts[y] : x < y;
-  });
+  std::sort(depth, depth + m);
+  // symbols by (count desc, id asc)
   for (size_t i = 0; i < m; ++i) {
-    if (pool[i] < 1 || pool[i] > max_len) return PIVCO_E_ARG;
-    len[order[i]] = static_cast<uint8_t>(pool[i]);
+    const uint64_t c = key[i] >> 8, sid = key[i] & 255;
+    key[i] = (((uint64_t(1) << 56) - 1 - c) << 8) | sid;
+  }
+  std::sort(key, key + m);
+  for (size_t i = 0; i < m; ++i) {
+    if (depth[i] < 1 || depth[i] > max_len) return PIVCO_E_ARG;
+    len[key[i] & 255] = static_cast<uint8_t>(depth[i]);
   }
   return PIVCO_OK;
 }

@@ -44,11 +44,11 @@ class Job(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("merge_variant", C.c_uint32), ("merge_grid", C.c_uint32),
-                ("rans_grid", C.c_uint32), ("reserved", C.c_uint32)]
+                ("rans_grid", C.c_uint32), ("grid_mode", C.c_uint32)]
 
     def as_dict(self):
         return {"merge_variant": self.merge_variant, "merge_grid": self.merge_grid,
-                "rans_grid": self.rans_grid}
+                "rans_grid": self.rans_grid, "grid_mode": self.grid_mode}
 
 
 class ServerOpts(C.Structure):

@@ -77,12 +77,16 @@ def test_batch_and_plain_and_graph_agree():
 def test_every_merge_variant():
     cs, streams, wants = _batch()
     outs = [torch.empty(w.size, dtype=torch.uint8, device="cuda") for w in wants]
-    for v in range(len(P.pivco_merge_variants())):
-        print("variant", v, flush=True)
+    nv = len(P.pivco_merge_variants())
+    # every variant on the persistent queue, then every variant as one
+    # non-persistent launch with a workgroup per work item
+    for v, mode in [(v, m) for m in (0, 1) for v in range(nv)]:
+        print("variant", v, "grid_mode", mode, flush=True)
         t = P.Tune()
         t.merge_variant = v
         t.merge_grid = 64
         t.rans_grid = 32
+        t.grid_mode = mode
         plan = P.BatchPlan(streams, outs, tune=t)
         for o in outs:
             o.fill_(0xAB)                       # a byte left unwritten cannot match by chance
@@ -91,7 +95,7 @@ def test_every_merge_variant():
         torch.cuda.synchronize()
         assert (plan.statuses() == 0).all()
         for c, o, w in zip(cs, outs, wants):
-            assert np.array_equal(o.cpu().numpy(), w), (v, c[0])
+            assert np.array_equal(o.cpu().numpy(), w), (v, mode, c[0])
         plan.close()
 
 

@@ -142,32 +142,44 @@ def skew256m(seed: int = 1, scale: int = 1) -> Workload:
                     labels=["p0=0.9+0.7^s"])
 
 
+def _mixed_item(child: np.random.SeedSequence, lo: int, hi: int):
+    """One independently seeded item of the mixed workloads: a log-uniform
+    size and a family drawn from its own stream, then its symbols."""
+    rng = np.random.default_rng(child)
+    size = log_uniform_size(rng, lo, hi)
+    label, p = family_p(rng)
+    return draw(rng, p, size), label
+
+
+def _mixed_items(seed: int, n: int, lo: int, hi: int, workers: int):
+    """Items 0..n-1 of the mixed workloads; every item has its own seed, so
+    drawing them in worker processes gives the same bytes as drawing them in
+    order here."""
+    children = np.random.SeedSequence(seed).spawn(n)
+    if workers <= 1 or n < 2:
+        out = [_mixed_item(c, lo, hi) for c in children]
+    else:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        # fork: the caller draws inputs before it initialises a GPU
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+            out = list(ex.map(_mixed_item, children, [lo] * n, [hi] * n,
+                              chunksize=max(1, n // (8 * workers))))
+    return [x for x, _ in out], [lab for _, lab in out]
+
+
 def mix4096(seed: int = 1, scale: int = 1, n_blocks: int = 4096,
-            lo: int = 4 * KiB, hi: int = 4 * MiB) -> Workload:
+            lo: int = 4 * KiB, hi: int = 4 * MiB, workers: int = 1) -> Workload:
     """``scale`` divides the block count (block sizes keep their range)."""
-    ss = np.random.SeedSequence(seed)
     nb = max(1, n_blocks // scale)
-    jobs, labels = [], []
-    for child in ss.spawn(nb):
-        rng = np.random.default_rng(child)
-        size = log_uniform_size(rng, lo, hi)
-        label, p = family_p(rng)
-        jobs.append(draw(rng, p, size))
-        labels.append(label)
-    w = Workload("mix4096", block_size=0, ans_mode=1, jobs=jobs, labels=labels)
-    return w
+    jobs, labels = _mixed_items(seed, nb, lo, hi, workers)
+    return Workload("mix4096", block_size=0, ans_mode=1, jobs=jobs, labels=labels)
 
 
-def serve_requests(seed: int = 1, n_req: int = 64, lo: int = 16 * KiB, hi: int = 64 * MiB):
+def serve_requests(seed: int = 1, n_req: int = 64, lo: int = 16 * KiB, hi: int = 64 * MiB,
+                   workers: int = 1):
     """Request payloads for the serving loop (block size 1 MiB each)."""
-    ss = np.random.SeedSequence(seed)
-    jobs, labels = [], []
-    for child in ss.spawn(n_req):
-        rng = np.random.default_rng(child)
-        size = log_uniform_size(rng, lo, hi)
-        label, p = family_p(rng)
-        jobs.append(draw(rng, p, size))
-        labels.append(label)
+    jobs, labels = _mixed_items(seed, n_req, lo, hi, workers)
     return Workload("serve", block_size=MiB, ans_mode=1, jobs=jobs, labels=labels)
 
 
