@@ -16,8 +16,9 @@ first.  Inputs are resident in HBM when the timed region starts.
 The JSON line reports decoded GB/s (10^9 B/s), the HBM roofline of the
 merge kernel (HIP events around it, on its stream) and of the whole step,
 the best run under the paper's App. C protocol, the same decode as one
-launch per block ("plain") and as one non-persistent launch with a
-workgroup per work item ("grid"), the encode rate, a serving leg (Poisson
+launch per block ("plain"), as one non-persistent launch with a workgroup
+per work item ("grid") and with the top-down partition/scatter scheme of
+Sec. 2.1 (an ablation, host-timed including its planning), the encode rate, a serving leg (Poisson
 arrivals at 2000 req/s and at a rate offering half the batched throughput),
 and the CPU oracle timed on the host's cores (one thread and all threads).
 
@@ -237,6 +238,43 @@ def serving_leg(torch, dev, rate_hz, seconds, pool_w, streams, ids, budget, seed
             "max_busy_slots": stats["max_busy_slots"]}
 
 
+def golomb_leg(torch, dev, n=64 << 20, block_size=1 << 16, seed=7, reps=5):
+    """PivCo-Golomb (App. G): unary-coded geometric values at the mean code
+    lengths the appendix measures (1.25 .. 5 bits), 64 Mi values each in
+    64 Ki-value blocks; GPU encode (checked against nothing here: the GPU
+    tests hold it to the oracle) and decode GB/s of values, best of reps,
+    and the decode's HBM roofline (stream read once + values written once)."""
+    from paper_2606_05765_amd import pivco as P
+    rng = np.random.default_rng(seed)
+    res = {}
+    for L in (1.25, 1.5, 2, 3, 4, 5):
+        q = 1.0 - 1.0 / L
+        x = np.minimum(rng.geometric(1.0 - q, size=n) - 1, 255).astype(np.uint8)
+        d = torch.from_numpy(x).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = P.pivco_golomb_encode(d, block_size)
+        torch.cuda.synchronize()
+        enc = time.perf_counter() - t0
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        best = 1e30
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, status = P.pivco_golomb_decode([st], [out])
+            best = min(best, time.perf_counter() - t0)
+            assert status[0] == 0
+        assert torch.equal(out, d), "golomb decode differs from the input"
+        gbps = n / best / 1e9
+        res[str(L)] = {"decode_GBps": round(gbps, 2), "encode_GBps": round(n / enc / 1e9, 2),
+                       "bits_per_value": round(st.numel() * 8 / n, 3),
+                       "decode_roofline_frac": round((st.numel() + n) / best / 1e9 / HBM_PEAK_GBPS, 4)}
+        log(f"golomb L={L}: {res[str(L)]}")
+        del d, out, st
+    return {"values": n, "block_values": block_size, "timing": "host clock around the synchronous "
+            "call (planning included), best of 5", "by_mean_code_len": res}
+
+
 def serving(torch, dev, batched_gbps, n_pool, seed=11, budget=32 * 10**9):
     """Continuous-batching server over a resident pool of requests (sizes
     log-uniform 16 KiB - 64 MiB, the mixed families, 1 MiB blocks), output
@@ -272,6 +310,7 @@ def main():
     ap.add_argument("--variant", type=int, default=None, help="fixed merge variant (skips autotune)")
     ap.add_argument("--grid", type=int, default=None, help="fixed merge grid (with --variant)")
     ap.add_argument("--serve-pool", type=int, default=128, help="resident serving requests")
+    ap.add_argument("--no-golomb", action="store_true", help="skip the PivCo-Golomb leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -353,7 +392,7 @@ def main():
         f"({achieved / HBM_PEAK_GBPS * 100:.1f}%); whole step {step_ach / HBM_PEAK_GBPS * 100:.1f}%")
     merges = element_merges(xs, bss)
 
-    plain = grid = None
+    plain = grid = topdown = None
     if not args.no_plain:
         out2 = [torch.empty(x.size, dtype=torch.uint8, device=dev) for x in xs]
         ws = P.Workspace(P.pivco_decode_workspace(streams, out2))
@@ -382,6 +421,20 @@ def main():
         grid = round(n / (gdt / args.steps) / 1e9, 2)
         gplan.close()
         log(f"one non-persistent launch (a workgroup per item): {grid} GB/s")
+        # ablation: the top-down (partition/scatter) decode of the same streams
+        best = 1e30
+        for _ in range(3):
+            for o in out2:
+                o.fill_(0xAB)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, tst = P.pivco_decode_topdown(streams, out2, ws=ws)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+            assert (tst == 0).all()
+        assert all(torch.equal(a, b) for a, b in zip(out2, outs))
+        topdown = round(n / best / 1e9, 2)
+        log(f"top-down decode (ablation): {best * 1e3:.2f} ms, {topdown} GB/s")
         del out2, ws
 
     if args.copy_probe:
@@ -399,6 +452,11 @@ def main():
         del outs
         serve = serving(torch, dev, value, args.serve_pool)
         log("serving:", serve)
+
+    golomb = None
+    if not args.no_golomb:
+        log("PivCo-Golomb leg ...")
+        golomb = golomb_leg(torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -421,11 +479,13 @@ def main():
         "app_c": app_c,
         "plain_per_block_GBps": plain,
         "one_grid_nonpersistent_GBps": grid,
+        "topdown_ablation_GBps": topdown,
         "encode_GBps": round(n / enc_s / 1e9, 3),
         "compression_ratio": round(n / comp, 4),
         "element_merges": {"per_launch": merges, "mean_code_len": round(merges / n, 4),
                            "G_per_s": round(merges / (merge_avg * 1e-3) / 1e9, 1)},
         "serving": serve,
+        "golomb": golomb,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -152,6 +152,15 @@ pivco_status pivco_decode_noalloc(const void *d_in, uint64_t in_len, void *d_out
 pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
                                 void *d_ws, uint64_t ws_bytes, hipStream_t s);
 
+/* Ablation: the same decode with the top-down scheme of Sec. 2.1 instead of
+ * the bottom-up merge of Sec. 3.  Per slice of 4096 outputs, every internal
+ * node splits the positions that reach it by its bits, stably, into its
+ * children's lists (partition), and a leaf writes its symbol at the
+ * positions that reach it (scatter).  Same jobs, workspace, statuses and
+ * validation as pivco_decode_batch; the decoded bytes are identical. */
+pivco_status pivco_decode_topdown(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                  void *d_ws, uint64_t ws_bytes, hipStream_t s);
+
 /* Launch configuration of the batched decode, chosen by pivco_autotune. */
 typedef struct {
   uint32_t merge_variant;    /* index into the compiled merge kernels */
@@ -179,10 +188,48 @@ pivco_status pivco_batch_plan_launch_timed(pivco_batch_plan *p, hipStream_t s,
                                            hipEvent_t merge_begin, hipEvent_t merge_end);
 void pivco_batch_plan_destroy(pivco_batch_plan *p);
 
-/* Time every merge variant and a few grid sizes on these jobs and return the
- * fastest configuration (synchronous; decodes the jobs several times). */
+/* The fastest launch configuration for these jobs: every merge variant
+ * (workgroup size, tile size of whole blocks, outputs per task) with three
+ * persistent grid sizes, then the rANS grid (one, two or four workgroups per
+ * CU) when the jobs have rANS nodes; each candidate is the best of three
+ * timed batched decodes.  The choice is cached per device architecture and
+ * workload bucket (work items per CU, mean symbols per item, share of tile
+ * items, rANS present): a later call for the same bucket returns it without
+ * timing.  Synchronous. */
 pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
                             void *d_ws, uint64_t ws_bytes, hipStream_t s, pivco_tune *out);
+/* Forgets every cached autotuner choice. */
+void pivco_autotune_cache_clear(void);
+
+/* ---------------------------------------------------------------------- */
+/* PivCo-Golomb (App. G)                                                  */
+/* ---------------------------------------------------------------------- */
+/* The pivoted layout applied to a unary code (App. G): instead of a tree, a
+ * list of bitmaps, one per code-bit position.  A value v (uint8) is coded as
+ * v 0-bits and a 1-bit; bitmap k holds, in stream order, the k-th code bit of
+ * every value >= k.  Stream format "PVG1" (little-endian): header 32 bytes
+ * (magic, version 1, flags 0, n_total u64, block_size u32, n_blocks u32,
+ * reserved u64), block offsets u64[n_blocks + 1], then per block (at a
+ * multiple of 4 bytes) comp_size u32, n u32, K u16 (bitmaps: largest value
+ * + 1), pad u16, the bitmap sizes n_1 .. n_{K-1} (u32), and the bitmaps
+ * (ceil(n_k / 8) bytes each, LSB first, zero padding bits). */
+uint64_t pivco_golomb_encode_bound(uint64_t n, uint32_t block_size);
+uint64_t pivco_golomb_encode_workspace(uint64_t n, uint32_t block_size);
+/* Encodes n values at d_in (synchronous; the stream length in *h_out_len).
+ * E_ARG on bad arguments (d_out must be 16-byte aligned), E_CAPACITY when
+ * out_cap or ws_bytes is too small. */
+pivco_status pivco_golomb_encode(const void *d_in, uint64_t n, uint32_t block_size, void *d_out,
+                                 uint64_t out_cap, uint64_t *h_out_len, void *d_ws, uint64_t ws_bytes,
+                                 hipStream_t s);
+/* Workspace for pivco_golomb_decode (reads the stream headers). */
+uint64_t pivco_golomb_decode_workspace(const pivco_job *h_jobs, uint32_t count, hipStream_t s);
+/* Decodes every job, one workgroup per block: bottom-up over the bitmap list
+ * (at bitmap k a 1 bit gives 0, a 0 bit 1 + the next bitmap's value: the
+ * merge_vec_cst_plus1 primitive), per job a status in d_status (E_CORRUPT
+ * for a stream that fails validation, E_CAPACITY for a small output).
+ * Synchronous. */
+pivco_status pivco_golomb_decode(const pivco_job *h_jobs, uint32_t count, int32_t *d_status, void *d_ws,
+                                 uint64_t ws_bytes, hipStream_t s);
 
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of decode requests                        */

@@ -119,6 +119,19 @@ int pivco_ref_block_info(const uint8_t *in, uint64_t in_len, uint32_t block,
                          uint8_t depth[255], uint64_t n_v[255],
                          uint64_t n_right[255], uint8_t kind[255]);
 
+/* PivCo-Golomb (App. G, golomb_ref.c): the pivoted layout applied to a
+ * unary code -- value v is v 0-bits and a 1-bit, bitmap k holds the k-th code
+ * bit of every value >= k.  Stream format "PVG1" documented in golomb_ref.c.
+ * Decoder A reads each value's code bit by bit with a cursor per bitmap;
+ * decoder B merges bottom-up from the last bitmap (merge_vec_cst_plus1). */
+uint64_t pivco_ref_golomb_bound(uint64_t n, uint32_t block_size);
+int pivco_ref_golomb_encode(const uint8_t *in, uint64_t n, uint32_t block_size, uint8_t *out,
+                            uint64_t cap, uint64_t *out_len);
+int pivco_ref_golomb_decode(const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t cap,
+                            uint64_t *n_out);
+int pivco_ref_golomb_decode_merge(const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t cap,
+                                  uint64_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

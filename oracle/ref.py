@@ -53,6 +53,10 @@ def lib():
             "pivco_ref_pivoted_to_classical": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
             "pivco_ref_block_info": (C.c_int, [u8p, C.c_uint64, C.c_uint32, u8p, u32p, u32p, u8p,
                                                u64p, u64p, u8p]),
+            "pivco_ref_golomb_bound": (C.c_uint64, [C.c_uint64, C.c_uint32]),
+            "pivco_ref_golomb_encode": (C.c_int, [u8p, C.c_uint64, C.c_uint32, u8p, C.c_uint64, u64p]),
+            "pivco_ref_golomb_decode": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
+            "pivco_ref_golomb_decode_merge": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -216,4 +220,41 @@ def block_info(stream, block):
 __all__ = ["OracleError", "lib", "lengths", "codes", "p1q", "select_ans", "rans_encode",
            "rans_decode", "encode_bound", "encode", "stream_info", "decode", "decode_blocks",
            "classical_encode", "classical_decode", "pivoted_to_classical", "block_info",
+           "golomb_encode", "golomb_decode", "golomb_decode_merge",
            "OK", "E_ARG", "E_CAPACITY", "E_CORRUPT", "E_UNSUPPORTED"]
+
+
+# --------------------------------------------------------------------------
+# PivCo-Golomb (App. G)
+# --------------------------------------------------------------------------
+
+def golomb_encode(values, block_size):
+    """Unary-coded values (uint8) in the pivoted list-of-bitmaps layout."""
+    x, xp = _u8(values)
+    cap = int(lib().pivco_ref_golomb_bound(x.size, block_size))
+    out = np.zeros(max(cap, 1), dtype=np.uint8)
+    olen = C.c_uint64(0)
+    _check(lib().pivco_ref_golomb_encode(xp, x.size, block_size,
+                                         out.ctypes.data_as(C.POINTER(C.c_uint8)), out.size,
+                                         C.byref(olen)), "golomb_encode")
+    return out[:olen.value].copy()
+
+
+def _golomb_dec(stream, fn, n):
+    s, sp = _u8(stream)
+    if n is None:
+        n = int.from_bytes(bytes(s[8:16]), "little") if s.size >= 16 else 0
+    out = np.zeros(max(n, 1), dtype=np.uint8)
+    got = C.c_uint64(0)
+    _check(fn(sp, s.size, out.ctypes.data_as(C.POINTER(C.c_uint8)), n, C.byref(got)), "golomb_decode")
+    return out[:got.value].copy()
+
+
+def golomb_decode(stream, n=None):
+    """Decoder A: each value's code read bit by bit (a cursor per bitmap)."""
+    return _golomb_dec(stream, lib().pivco_ref_golomb_decode, n)
+
+
+def golomb_decode_merge(stream, n=None):
+    """Decoder B: bottom-up merge from the last bitmap (merge_vec_cst_plus1)."""
+    return _golomb_dec(stream, lib().pivco_ref_golomb_decode_merge, n)

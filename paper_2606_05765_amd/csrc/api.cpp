@@ -6,7 +6,10 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "pivco_int.h"
@@ -298,6 +301,57 @@ pivco_status prepare(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
 
 }  // namespace
 
+namespace {
+
+// Autotuner cache: one choice per device architecture and workload bucket
+// (items per CU, mean symbols per item, share of tile items, rANS present),
+// so that batches of the same shape reuse a configuration without timing.
+struct TuneKey {
+  std::string arch;
+  uint32_t items_per_cu, mean_log2, tile_share, rans;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(arch, items_per_cu, mean_log2, tile_share, rans) <
+           std::tie(o.arch, o.items_per_cu, o.mean_log2, o.tile_share, o.rans);
+  }
+};
+
+std::mutex &tune_cache_mu() {
+  static std::mutex m;
+  return m;
+}
+std::map<TuneKey, pivco_tune> &tune_cache() {
+  static std::map<TuneKey, pivco_tune> c;
+  return c;
+}
+
+uint32_t log2_bucket(uint64_t x) {
+  uint32_t b = 0;
+  while (x > 1) { x >>= 1; ++b; }
+  return b;
+}
+
+TuneKey tune_key(const HostPlan &p) {
+  TuneKey k;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  k.arch = hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess
+               ? std::string(prop.gcnArchName)
+               : std::string("?");
+  uint64_t symbols = 0, tiles = 0;
+  for (auto &x : p.w.sized) {
+    symbols += x.first;
+    if (x.second.y != kWholeBlock) ++tiles;
+  }
+  const uint64_t ni = std::max<uint64_t>(1, p.w.items.size());
+  k.items_per_cu = log2_bucket(ni / static_cast<uint64_t>(device_cus()) + 1);
+  k.mean_log2 = log2_bucket(symbols / ni + 1);
+  k.tile_share = static_cast<uint32_t>(4 * tiles / ni);   // quarters
+  k.rans = p.w.ritems.empty() ? 0u : 1u;
+  return k;
+}
+
+}  // namespace
+
 struct pivco_batch_plan {
   HostPlan plan;
   void *ws = nullptr;
@@ -400,6 +454,34 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
   return PIVCO_OK;
 }
 
+pivco_status pivco_decode_topdown(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
+                                  void *d_ws, uint64_t ws_bytes, hipStream_t s) {
+  HostPlan p;
+  pivco_status st = prepare(h_jobs, count, d_status, d_ws, ws_bytes, s, p);
+  if (st) return st;
+  if (count == 0) return PIVCO_OK;
+  Dev d = dev_ptrs(p, d_ws);
+  const WorkLists &w = p.w;
+  const pivco_tune t = default_tune(static_cast<uint32_t>(w.items.size()), p.chunk_cap);
+  if (launch_init(s, d.ctr, d_status, d.status0, p.count) != hipSuccess) return PIVCO_E_DEVICE;
+  if (launch_plan(s, d.jobs, d.blocks, static_cast<uint32_t>(w.blocks.size()), d.recs, d.ctr,
+                  d.chunks, p.chunk_cap) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  if (!w.ritems.empty() &&
+      launch_rans(t.rans_grid, s, d.jobs, d.recs, d.ritems, d.ctr, d.chunks, p.chunk_cap, d.scratch,
+                  kQueueItems) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
+                   d.scratch, p.scratch_words, d.tab) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  const uint32_t ni = static_cast<uint32_t>(w.items.size());
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(ni, device_cus() * topdown_occupancy()));
+  if (ni && launch_topdown(grid, s, d.jobs, d.items, d.recs, d.tiled, d.tab, ni, d.ctr, d.scratch,
+                           kQueueItems) != hipSuccess)
+    return PIVCO_E_DEVICE;
+  return PIVCO_OK;
+}
+
 uint32_t pivco_merge_variants(void) { return merge_variant_count(); }
 const char *pivco_merge_variant_name(uint32_t v) { return merge_variant_name(v); }
 
@@ -468,38 +550,72 @@ pivco_status pivco_autotune(const pivco_job *h_jobs, uint32_t count, int32_t *d_
   if (st) return st;
   pivco_tune best = default_tune(static_cast<uint32_t>(p.w.items.size()), p.chunk_cap);
   if (p.w.items.empty()) { *out = best; return PIVCO_OK; }
+  const TuneKey key = tune_key(p);
+  {
+    std::lock_guard<std::mutex> lk(tune_cache_mu());
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) { *out = it->second; return PIVCO_OK; }
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PIVCO_E_DEVICE;
-  float best_ms = 1e30f;
   const int cus = device_cus();
+  const uint32_t ni = static_cast<uint32_t>(p.w.items.size());
+  // rANS grids: only when the batch has rANS chunks (one, two or four
+  // workgroups of four waves per CU)
+  std::vector<uint32_t> rgrids{best.rans_grid};
+  if (!p.w.ritems.empty())
+    for (uint32_t f : {1u, 4u}) rgrids.push_back(static_cast<uint32_t>(std::max<uint64_t>(
+        1, std::min<uint64_t>(static_cast<uint64_t>(f) * cus, (p.chunk_cap + 7) / 8))));
+  auto time_of = [&](const pivco_tune &t, float *ms_out) -> pivco_status {
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) return PIVCO_E_DEVICE;
+      const pivco_status e = enqueue_batch(p, d_ws, d_status, t, s, nullptr, nullptr);
+      if (e) return e;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return PIVCO_E_DEVICE;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    *ms_out = ms_min;
+    return PIVCO_OK;
+  };
+  float best_ms = 1e30f;
+  // merge variant (tile size, workgroup size, task width) x persistent grid
   for (uint32_t v = 0; v < merge_variant_count(); ++v) {
     const uint32_t occ = static_cast<uint32_t>(merge_variant_occupancy(v));
     for (uint32_t frac : {4u, 3u, 2u}) {
       pivco_tune t = best;
       t.merge_variant = v;
-      t.merge_grid = std::max<uint32_t>(1, std::min<uint32_t>(cus * occ * frac / 4,
-                                                              static_cast<uint32_t>(p.w.items.size())));
-      float ms_min = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
-        if (hipEventRecord(e0, s) != hipSuccess) return PIVCO_E_DEVICE;
-        st = enqueue_batch(p, d_ws, d_status, t, s, nullptr, nullptr);
-        if (st) return st;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-          return PIVCO_E_DEVICE;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms_min = std::min(ms_min, ms);
-      }
-      if (ms_min < best_ms) {
-        best_ms = ms_min;
-        best = t;
-      }
+      t.merge_grid = std::max<uint32_t>(1, std::min<uint32_t>(cus * occ * frac / 4, ni));
+      float ms = 0;
+      st = time_of(t, &ms);
+      if (st) return st;
+      if (ms < best_ms) { best_ms = ms; best = t; }
     }
+  }
+  // then the rANS grid for the chosen merge configuration
+  for (uint32_t rg : rgrids) {
+    pivco_tune t = best;
+    t.rans_grid = rg;
+    float ms = 0;
+    st = time_of(t, &ms);
+    if (st) return st;
+    if (ms < best_ms) { best_ms = ms; best = t; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(tune_cache_mu());
+    tune_cache()[key] = best;
+  }
   *out = best;
   return PIVCO_OK;
+}
+
+void pivco_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(tune_cache_mu());
+  tune_cache().clear();
 }
 
 uint64_t pivco_encode_bound(uint64_t n, const pivco_encode_opts *o) {

@@ -1446,7 +1446,13 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
   }
   const uint32_t I = h.I;
   if (tiled) {
-    for (uint32_t i = tid; i < I; i += C::NT) sm.cur[i] = 0;
+    // the tile's shares stand in for the nodes' sizes: a variant whose tiles
+    // are smaller than a split block's tile walks the shares sub-tile by
+    // sub-tile like a whole block
+    for (uint32_t i = tid; i < I; i += C::NT) {
+      sm.cur[i] = 0;
+      t.nv[i] = sm.tv[i];
+    }
     if (tid == 0) sm.tile = C::T;
     build_directory<C>(sm, 4 * sm.stage_top, I);
   } else {
@@ -1492,7 +1498,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
     }
     lds_barrier();
     if (resident) {
-      if (!tiled) {
+      if (!tiled || C::T < kTileOut) {
         if (t0 + troot < n) {
           if (wave == 0) count_chain<C>(sm);
           else if (wave == 1 && t0 == 0) warm_next<C>(sm);
@@ -2058,17 +2064,202 @@ __global__ void k_gather_headers(const pivco_job *jobs, uint32_t count, uint8_t 
 }
 
 // ---------------------------------------------------------------------------
+// Kernel: top-down decode (ablation of the bottom-up merge)
+// ---------------------------------------------------------------------------
+// The decoding of Sec. 2.1, before the paper turns it bottom-up (Sec. 3): for
+// a slice of output positions, the root splits the positions by its bits,
+// stably, into one list per child (the partition primitive); every internal
+// node does the same with the positions that reach it, reading its bitmap
+// from its cursor on; a leaf writes its symbol at the positions that reach
+// it (the scatter primitive).  Here a slice is kTdS outputs, the position
+// lists are 16-bit entries in LDS (two level buffers), the slice's output is
+// assembled in LDS and stored with 16-byte stores.  One wave per node: it
+// counts the node's 1 bits in the slice, reserves its children's lists, then
+// partitions with ballot + mbcnt ranks.  Work items are the merge kernel's:
+// whole blocks (cursors from 0) or tiles of split blocks (cursors from the
+// boundary table).
+constexpr int kTdNT = 256;
+constexpr uint32_t kTdS = 4096;
+
+struct TdSmem {
+  ParsedBlock pb;
+  uint32_t cur[256];         // node's bits consumed so far
+  uint32_t ones[256];        // of which 1 bits
+  uint32_t tv[256];          // node's positions in this slice
+  uint32_t seg[256];         // their list in the level buffer of the node's depth
+  uint32_t top[2];           // next free entry of each level buffer
+  uint32_t item;
+  int32_t err;
+  uint16_t pos[2][kTdS];
+  uint8_t out[kTdS] __attribute__((aligned(16)));
+};
+
+// Bit x of a node's bitmap: raw bodies are read byte-wise from the stream,
+// decoded rANS bitmaps word-wise from the scratch.
+__device__ __forceinline__ uint32_t td_bit(const uint8_t *in, const uint32_t *scr, bool rans,
+                                           uint64_t base, uint64_t x) {
+  const uint64_t b = base + x;
+  return rans ? (scr[b >> 5] >> (b & 31)) & 1u : (in[b >> 3] >> (b & 7)) & 1u;
+}
+
+__global__ __launch_bounds__(kTdNT) void k_topdown(const JobDev *jobs, const uint2 *items,
+                                                   const ParsedBlock *recs, const TiledBlock *tiled,
+                                                   const uint2 *tab, uint32_t n_items, Counters *ctr,
+                                                   const uint32_t *scratch, int32_t single) {
+  __shared__ TdSmem sm;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+  constexpr uint32_t NW = kTdNT / kWave;
+  const uint64_t lt = (1ull << lane) - 1;
+  for (uint32_t round = 0;; ++round) {
+    if (tid == 0)
+      sm.item = single >= 0 ? (round == 0 ? static_cast<uint32_t>(single) : n_items)
+                : single == kGridItems ? (round == 0 ? blockIdx.x : n_items)
+                                       : atomicAdd(&ctr->merge_next, 1u);
+    __syncthreads();
+    const uint32_t it = sm.item;
+    if (it >= n_items) break;
+    const uint2 rt = items[it];
+    {
+      const uint4 *src = reinterpret_cast<const uint4 *>(recs + rt.x);
+      uint4 *dst = reinterpret_cast<uint4 *>(&sm.pb);
+      for (uint32_t i = tid; i < sizeof(ParsedBlock) / 16; i += kTdNT) dst[i] = src[i];
+    }
+    if (tid == 0) sm.err = 0;
+    __syncthreads();
+    const BlockHdr &h = sm.pb.h;
+    const NodeTab &t = sm.pb.t;
+    const JobDev &J = jobs[h.job];
+    const bool whole = rt.y == kWholeBlock;
+    const uint32_t k = whole ? 0u : (rt.y & 255);
+    const uint32_t lo = whole ? 0u : k * kTileOut;
+    const uint32_t hi = whole ? h.n : (h.n - lo < kTileOut ? h.n : lo + kTileOut);
+    uint8_t *out = J.out + h.out_off;
+    if (h.err) {
+      if (tid == 0) set_err(J.status, h.err);
+      __syncthreads();
+      continue;
+    }
+    if (h.mode == 1) {
+      for (uint32_t i = lo + tid; i < hi; i += kTdNT) out[i] = static_cast<uint8_t>(h.csym);
+      __syncthreads();
+      continue;
+    }
+    const uint32_t I = h.I;
+    for (uint32_t v = tid; v < I; v += kTdNT) {
+      sm.cur[v] = whole ? 0u : tab[tiled[rt.y >> 8].tab + static_cast<uint64_t>(k) * kTabCols + v].x;
+      sm.ones[v] = 0;
+    }
+    __syncthreads();
+    for (uint32_t s0 = lo; s0 < hi; s0 += kTdS) {
+      const uint32_t S = hi - s0 < kTdS ? hi - s0 : kTdS;
+      for (uint32_t v = tid; v < I; v += kTdNT) sm.tv[v] = 0;
+      for (uint32_t i = tid; i < S; i += kTdNT) sm.pos[0][i] = static_cast<uint16_t>(i);
+      if (tid == 0) { sm.tv[0] = S; sm.seg[0] = 0; }
+      __syncthreads();
+      for (uint32_t d = 0; d < h.maxlen; ++d) {
+        if (tid == 0) sm.top[(d + 1) & 1] = 0;
+        __syncthreads();
+        const uint16_t *lp = sm.pos[d & 1];
+        uint16_t *cp = sm.pos[(d + 1) & 1];
+        for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += NW) {
+          const uint32_t tvv = sm.tv[v];
+          if (tvv == 0) continue;
+          const bool rans = t.kind[v] != 0;
+          const uint64_t base = rans ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
+          const uint32_t c0 = sm.cur[v];
+          // the node's 1 bits in this slice
+          uint32_t ones = 0;
+          for (uint32_t c = 0; c < tvv; c += kWave) {
+            const bool act = c + lane < tvv;
+            const uint32_t b = act ? td_bit(J.in, scratch, rans, base, c0 + c + lane) : 0u;
+            ones += __popcll(__ballot(b));
+          }
+          // the children's lists (a child may not receive more than it has left)
+          const uint32_t ch[2] = {t.child[v][0], t.child[v][1]};
+          const uint32_t want[2] = {tvv - ones, ones};
+          bool bad = false;
+          for (int bb = 0; bb < 2; ++bb)
+            if (!(ch[bb] & 0x8000) && sm.cur[ch[bb]] + want[bb] > t.nv[ch[bb]]) bad = true;
+          if (bad) {                       // its children get no positions: the item fails
+            if (lane == 0) atomicCAS(&sm.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+            continue;
+          }
+          uint32_t cseg[2] = {0, 0};
+          for (int bb = 0; bb < 2; ++bb) {
+            if (ch[bb] & 0x8000) continue;
+            uint32_t sg = 0;
+            if (lane == 0) {
+              sg = atomicAdd(&sm.top[(d + 1) & 1], want[bb]);
+              sm.seg[ch[bb]] = sg;
+              sm.tv[ch[bb]] = want[bb];
+            }
+            cseg[bb] = __builtin_amdgcn_readfirstlane(sg);
+          }
+          // partition: positions with a 0 bit to the left child, 1 to the right
+          // (a leaf child takes its symbol at them)
+          const uint32_t lseg = sm.seg[v];
+          uint32_t r[2] = {0, 0};
+          for (uint32_t c = 0; c < tvv; c += kWave) {
+            const bool act = c + lane < tvv;
+            const uint32_t p = act ? lp[lseg + c + lane] : 0u;
+            const uint32_t b = act ? td_bit(J.in, scratch, rans, base, c0 + c + lane) : 0u;
+            const uint64_t m1 = __ballot(b), m0 = __ballot(act && !b);
+            if (act) {
+              const uint32_t bb = b;
+              const uint32_t rank = r[bb] + static_cast<uint32_t>(__popcll((bb ? m1 : m0) & lt));
+              if (ch[bb] & 0x8000) sm.out[p] = static_cast<uint8_t>(ch[bb] & 255);
+              else cp[cseg[bb] + rank] = static_cast<uint16_t>(p);
+            }
+            r[0] += __popcll(m0);
+            r[1] += __popcll(m1);
+          }
+          if (lane == 0) {
+            sm.cur[v] = c0 + tvv;
+            sm.ones[v] += ones;
+          }
+        }
+        __syncthreads();
+      }
+      if (sm.err) break;
+      // the slice's output: 16-byte stores where the destination allows
+      uint8_t *dst = out + s0;
+      const uint32_t head = static_cast<uint32_t>((16 - (reinterpret_cast<uintptr_t>(dst) & 15)) & 15);
+      const uint32_t h0 = head < S ? head : S;
+      for (uint32_t i = tid; i < h0; i += kTdNT) dst[i] = sm.out[i];
+      const uint32_t n16 = (S - h0) / 16;
+      for (uint32_t i = tid; i < n16; i += kTdNT) {
+        const uint8_t *sp = sm.out + h0 + 16 * i;
+        uint4 q;
+        q.x = sp[0] | (sp[1] << 8) | (sp[2] << 16) | (static_cast<uint32_t>(sp[3]) << 24);
+        q.y = sp[4] | (sp[5] << 8) | (sp[6] << 16) | (static_cast<uint32_t>(sp[7]) << 24);
+        q.z = sp[8] | (sp[9] << 8) | (sp[10] << 16) | (static_cast<uint32_t>(sp[11]) << 24);
+        q.w = sp[12] | (sp[13] << 8) | (sp[14] << 16) | (static_cast<uint32_t>(sp[15]) << 24);
+        *reinterpret_cast<uint4 *>(dst + h0 + 16 * i) = q;
+      }
+      for (uint32_t i = h0 + 16 * n16 + tid; i < S; i += kTdNT) dst[i] = sm.out[i];
+      __syncthreads();
+    }
+    // a whole block must consume every node's bits, with its count of 1 bits
+    if (whole && !sm.err)
+      for (uint32_t v = tid; v < I; v += kTdNT)
+        if (sm.cur[v] != t.nv[v] || sm.ones[v] != t.nr[v]) atomicCAS(&sm.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+    __syncthreads();
+    if (tid == 0 && sm.err) set_err(J.status, sm.err);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch table
 // ---------------------------------------------------------------------------
+// Merge-kernel variants: workgroup size, tile of a whole block, resident
+// block bytes, outputs per task, windows per wave step.
 using Cfg0 = MergeCfg<1024, 32768, 57344, 16, 2>;
 using Cfg1 = MergeCfg<1024, 32768, 57344, 8, 2>;
 using Cfg2 = MergeCfg<1024, 32768, 55296, 32, 1>;
-
-struct MergeVariant {
-  const char *name;
-  const void *fn;
-  int nt;
-};
+using Cfg3 = MergeCfg<1024, 16384, 57344, 16, 2>;
+using Cfg4 = MergeCfg<512, 32768, 57344, 16, 2>;
+using Cfg5 = MergeCfg<512, 16384, 57344, 16, 2>;
 
 template <class C>
 static hipError_t launch_merge_t(dim3 grid, hipStream_t s, const JobDev *jobs,
@@ -2093,13 +2284,16 @@ static int occupancy_t() {
 // ---- entry points used by the host library (C++ linkage, internal) -------
 namespace pivco {
 
-uint32_t merge_variant_count() { return 3; }
+uint32_t merge_variant_count() { return 6; }
 
 const char *merge_variant_name(uint32_t v) {
   switch (v) {
     case 0: return "wg1024_tile32k_body56k_k16_x2";
     case 1: return "wg1024_tile32k_body56k_k8_x2";
     case 2: return "wg1024_tile32k_body54k_k32_x1";
+    case 3: return "wg1024_tile16k_body56k_k16_x2";
+    case 4: return "wg512_tile32k_body56k_k16_x2";
+    case 5: return "wg512_tile16k_body56k_k16_x2";
     default: return "?";
   }
 }
@@ -2108,7 +2302,10 @@ int merge_variant_occupancy(uint32_t v) {
   switch (v) {
     case 0: return occupancy_t<Cfg0>();
     case 1: return occupancy_t<Cfg1>();
-    default: return occupancy_t<Cfg2>();
+    case 2: return occupancy_t<Cfg2>();
+    case 3: return occupancy_t<Cfg3>();
+    case 4: return occupancy_t<Cfg4>();
+    default: return occupancy_t<Cfg5>();
   }
 }
 
@@ -2121,7 +2318,10 @@ hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const Jo
   switch (variant) {
     case 0: return launch_merge_t<Cfg0>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
     case 1: return launch_merge_t<Cfg1>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
-    default: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    case 2: return launch_merge_t<Cfg2>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    case 3: return launch_merge_t<Cfg3>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    case 4: return launch_merge_t<Cfg4>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
+    default: return launch_merge_t<Cfg5>(dim3(grid), s, jobs, items, r, tiled, tab, n_items, ctr, scratch, scratch_words, single);
   }
 }
 
@@ -2131,6 +2331,20 @@ hipError_t launch_plan(hipStream_t s, const JobDev *jobs, const uint2 *blocks, u
   hipLaunchKernelGGL(k_plan, dim3((n_blocks + kPlanWaves - 1) / kPlanWaves), dim3(kWave * kPlanWaves), 0,
                      s, jobs, blocks, n_blocks, static_cast<ParsedBlock *>(recs), ctr, chunks, chunk_cap);
   return hipGetLastError();
+}
+
+hipError_t launch_topdown(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
+                          const void *recs, const TiledBlock *tiled, const uint2 *tab,
+                          uint32_t n_items, Counters *ctr, const uint32_t *scratch, int32_t single) {
+  hipLaunchKernelGGL(k_topdown, dim3(grid), dim3(kTdNT), 0, s, jobs, items,
+                     static_cast<const ParsedBlock *>(recs), tiled, tab, n_items, ctr, scratch, single);
+  return hipGetLastError();
+}
+
+int topdown_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_topdown, kTdNT, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const TiledBlock *tiled,

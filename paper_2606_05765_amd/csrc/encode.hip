@@ -5,24 +5,40 @@
 // through it, emits one bit per symbol (its bitmap) and partitions the
 // symbols between its children (the enc_partition primitives of Table 11).
 // The driver:
-//   1. k_hist      symbol histogram of every block (end-to-end encode time is
-//                  dominated by this count, Sec. 4);
-//   2. host        optimal length-limited lengths per block (package-merge),
-//                  canonical codes, breadth-first node table, n_v / n_right
-//                  from the counts, the rANS selection rule;
-//   3. k_split     per block, tiles of input symbols: per level, one wave per
-//                  node turns 64 symbols at a time into a 64-bit ballot of
-//                  code bits (LSB first = stream order), ORs it into the
-//                  node's bitmap and scatters the symbols to the children's
-//                  segments in LDS with ballot + mbcnt ranks (stable);
-//   4. k_rans_enc  32-lane interleaved binary rANS of the selected bitmaps,
-//                  one wave per chunk, steps in reverse order;
-//   5. host        final layout (block and scratch offsets, headers);
-//   6. k_copy      place headers, raw bitmaps and rANS chunks in the stream.
+//   1. k_hist        symbol histogram of every block and of every 64Ki-symbol
+//                    slice of it (end-to-end encode time is dominated by this
+//                    count, Sec. 4); k_slice_prefix turns the slice counts
+//                    into per-slice prefixes;
+//   2. host          optimal length-limited lengths per block (package-merge,
+//                    threads over blocks): the one step on the host;
+//   3. k_layout      per block, from its lengths and histogram: canonical
+//                    codes, breadth-first node table, n_v and n_right, the
+//                    rANS selection rule, body sizes and offsets, and the
+//                    block header bytes;
+//   4. k_scan        offsets of every block's areas (exclusive scans);
+//   5. k_split       per slice of a block: per level, one wave per node turns
+//                    64 symbols at a time into a 64-bit ballot of code bits
+//                    (LSB first = stream order), ORs it into the node's
+//                    bitmap -- raw nodes straight into the block's byte-packed
+//                    raw image, rANS nodes into word-aligned scratch -- and
+//                    scatters the symbols to the children's segments in LDS
+//                    with ballot + mbcnt ranks (stable);
+//   6. k_chunks      the rANS chunk jobs; k_rans_enc codes them (32-lane
+//                    interleaved binary rANS, one wave per chunk, steps in
+//                    reverse order);
+//   7. k_sizes       block sizes from the rANS body sizes; k_scan2 the block
+//                    offsets and the stream size;
+//   8. k_assemble    stream header, offset tables, block headers and raw
+//                    images (aligned 4-byte words); k_assemble_rans the rANS
+//                    bodies.
+// The host waits twice: for the histograms (the trees are built on the host)
+// and for the stream size.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "pivco_int.h"
@@ -30,7 +46,6 @@
 namespace pivco {
 
 pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]);
-pivco_status canonical_codes(const uint8_t len[256], uint16_t code[256]);
 bool tree_is_complete(const uint8_t len[256], uint32_t max_len);
 
 namespace {
@@ -39,11 +54,14 @@ constexpr int kWaveE = 64;
 constexpr uint32_t kHistSlice = 1u << 16;
 constexpr int kSplitNT = 256;
 constexpr uint32_t kSplitT = 4096;      // input symbols per tile
+constexpr uint32_t kHdrStride = 1216;   // block header bytes: 12 + 128 + 32 + 4 * 255 <= this
+constexpr uint32_t kLayoutWaves = 4;
+constexpr uint32_t kAsmSeg = 16384;     // output words per assembling workgroup
+constexpr uint32_t kScanNT = 1024;
 
-// Per-block description for the split kernel (device copy).
+// Per-block description for the split kernel, written by k_layout.
 struct EncBlock {
   uint64_t in_off;        // first input symbol
-  uint64_t bmp_word;      // first bitmap scratch word of the block
   uint32_t n;             // symbols
   uint32_t I;             // internal nodes (0: constant block, nothing to split)
   uint32_t maxlen;
@@ -53,21 +71,97 @@ struct EncBlock {
   uint32_t cnt[17];       // symbols of each length
   uint32_t code[256];     // (len << 16) | code
   uint16_t child[256][2]; // internal id or 0x8000 | symbol
-  uint32_t word[256];     // node's first bitmap word, relative to bmp_word
+  uint32_t bit[256];      // node's first bit: in the block's raw image (raw
+                          // node) or in its rANS bitmap words (rANS node)
+  uint32_t kind[8];       // bit i: node i is rANS-coded
+  uint32_t pad2[4];
+};
+static_assert(sizeof(EncBlock) % 16 == 0, "EncBlock copies in 16-byte units");
+
+// Per-block layout (k_layout), offsets (k_scan) and size (k_sizes, k_scan2).
+struct BlockLay {
+  uint32_t n;             // symbols
+  uint32_t hlen;          // header bytes
+  uint32_t raw_bytes;     // raw bodies
+  uint32_t ans_words;     // words its rANS nodes decode into: sum of ceil(n_v / 32)
+  uint32_t n_rnodes;      // rANS-coded nodes
+  uint32_t n_chunks;      // their chunks
+  uint64_t slot_bytes;    // output slot bytes of its chunks
+  uint64_t img_off;       // its raw image in the image area (bytes, 16-aligned)
+  uint64_t rbm_off;       // its rANS bitmaps in the rANS bitmap area (words)
+  uint64_t chunk0;        // its first chunk job
+  uint64_t slot0;         // its first slot byte
+  uint64_t ans0;          // scratch words of the blocks before it (stream table)
+  uint64_t out_off;       // the block in the stream (bytes)
+  uint32_t comp;          // block bytes (comp_size)
+  uint32_t pad;
+};
+
+// A rANS-coded node of a block, in node order (k_layout; blen and boff by
+// k_sizes).
+struct RansNode {
+  uint32_t rword;         // first word of its bitmap among the block's rANS words
+  uint32_t nv;            // bits
+  uint32_t p1q;           // 12-bit probability of a 1 bit
+  uint32_t ch0;           // its first chunk among the block's chunks
+  uint64_t sl0;           // its first slot byte among the block's slots
+  uint32_t blen;          // body bytes (all its chunks)
+  uint32_t boff;          // offset of its 8-byte body header in the block
 };
 
 struct RansJob {
-  uint64_t bmp_word;      // absolute scratch word of the chunk's first bit
+  uint64_t bmp_word;      // word of the chunk's first bit in the rANS bitmap area
   uint64_t slot;          // byte offset of the chunk's output slot
   uint32_t nbits;
   uint32_t p1q;
+  uint32_t block;
+  uint32_t rnode;         // its node among the block's rANS nodes
+  uint32_t first;         // 1: first chunk of its node
+  uint32_t dst;           // byte offset of the chunk in its block (k_sizes)
 };
 
-struct CopyDesc {
-  uint64_t src;           // byte offset in the workspace
-  uint64_t dst;           // byte offset in the stream
-  uint64_t len;
+// Batch totals (k_scan, k_scan2).
+struct Totals {
+  uint64_t img_bytes, rbm_words, chunks, slot_bytes, ans_words, out_bytes;
+  uint64_t pad[2];
 };
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, false));
+  v += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, false));
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Probability of a 1 bit in 12-bit fixed point, rounded to nearest and
+// clamped to [1, 4095] (the format's reading of the 12-bit binary coder).
+__device__ __forceinline__ uint32_t p1q_of(uint32_t nv, uint32_t nr) {
+  const uint64_t q = (static_cast<uint64_t>(nr) * 4096 + nv / 2) / nv;
+  return static_cast<uint32_t>(q < 1 ? 1 : q > 4095 ? 4095 : q);
+}
+
+// The rANS selection rule: ans_mode 1 codes nodes whose one-bit fraction is
+// below 0.1 or above 0.9; 2 codes every node; nodes no symbol passes never.
+__device__ __forceinline__ bool select_ans(uint32_t mode, uint32_t nv, uint32_t nr) {
+  if (nv == 0) return false;
+  if (mode == 1) return 10ull * nr < nv || 10ull * nr > 9ull * nv;
+  return mode == 2;
+}
+
+// Output slot of a chunk of nbits bits: lane states, at most one 16-bit word
+// per bit, padding.
+__host__ __device__ __forceinline__ uint32_t slot_size(uint32_t nbits) {
+  return (kChunkHdr + 2 * nbits + 4 + 15) & ~15u;
+}
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -76,6 +170,17 @@ __global__ void k_fill_zero(uint32_t *p, uint64_t nwords) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nwords;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
     p[i] = 0;
+}
+
+// Zeroes the image and rANS bitmap areas up to the sizes k_scan found (the
+// split kernel ORs bits into them).
+__global__ void k_zero_areas(uint32_t *img, uint32_t *rbm, const Totals *tot) {
+  const uint64_t ni = tot->img_bytes / 4, nr = tot->rbm_words;
+  const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < ni + nr; i += step) {
+    if (i < ni) img[i] = 0;
+    else rbm[i - ni] = 0;
+  }
 }
 
 // Histogram of every block, one workgroup per slice of kHistSlice symbols:
@@ -128,6 +233,267 @@ __global__ __launch_bounds__(256) void k_slice_prefix(uint32_t *slh, uint32_t sp
   }
 }
 
+// Layout of one block per wave.  lenm holds, per block, its 256 code
+// lengths; modes its mode (0 coded, 1 | symbol << 8 constant).  The code is
+// canonical: with cnt(L) codes of length L and fc(L) the first of them,
+// fc(L+1) = 2 (fc(L) + cnt(L)); a symbol's code is fc(len) plus its rank
+// among the symbols of its length; the internal nodes at depth d are the
+// prefixes [fc(d) + cnt(d), 2^d) numbered breadth-first, and child q of such
+// a node is a leaf iff q < fc(d+1) + cnt(d+1).
+struct LayoutSmem {
+  uint32_t nv[256], nr[256];
+  uint32_t cnt[17], fc[18], lvl[18], lbase[17];
+  uint32_t maxlen, I;
+  uint8_t leafsym[256];
+};
+
+__global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
+    const uint8_t *lenm, const uint32_t *modes, const uint32_t *hist, uint32_t nb, uint64_t n,
+    uint32_t bs, uint32_t ans_mode, uint32_t chunk_log2, EncBlock *eb, BlockLay *lay,
+    RansNode *rnodes, uint8_t *hdr) {
+  __shared__ LayoutSmem smem[kLayoutWaves];
+  const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+  const uint32_t b = blockIdx.x * kLayoutWaves + wave;
+  if (b >= nb) return;
+  LayoutSmem &sm = smem[wave];
+  EncBlock &E = eb[b];
+  BlockLay &Lb = lay[b];
+  uint8_t *H = hdr + static_cast<uint64_t>(b) * kHdrStride;
+  const uint64_t start = static_cast<uint64_t>(b) * bs;
+  const uint32_t nblk = static_cast<uint32_t>(n - start < bs ? n - start : bs);
+  const uint32_t cw = nblk <= 65535 ? 2u : 4u;
+  const uint32_t mode = modes[b];
+  if (lane == 0) {
+    E.in_off = start;
+    E.n = nblk;
+    Lb.n = nblk;
+    *reinterpret_cast<uint32_t *>(H + 4) = nblk;
+    H[8] = static_cast<uint8_t>(mode & 1);
+    H[9] = static_cast<uint8_t>(mode >> 8);
+    H[10] = static_cast<uint8_t>(cw);
+    H[11] = 0;
+  }
+  if (mode & 1) {                        // constant block: its 12-byte header only
+    if (lane == 0) {
+      E.I = 0;
+      E.maxlen = 0;
+      Lb.hlen = kBlockFixed;
+      Lb.raw_bytes = Lb.ans_words = Lb.n_rnodes = Lb.n_chunks = 0;
+      Lb.slot_bytes = 0;
+    }
+    return;
+  }
+  // lane owns symbols 4 lane .. 4 lane + 3
+  const uint32_t lw = *reinterpret_cast<const uint32_t *>(lenm + 256ull * b + 4 * lane);
+  uint32_t l[4], c[4], rank[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    l[k] = (lw >> (8 * k)) & 255;
+    c[k] = hist[256ull * b + 4 * lane + k];
+  }
+  const uint64_t below = (1ull << lane) - 1;
+  for (uint32_t L = 1; L <= 15; ++L) {
+    uint64_t mk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mk[k] = __ballot(l[k] == L);
+    const uint32_t before = __popcll(mk[0] & below) + __popcll(mk[1] & below) +
+                            __popcll(mk[2] & below) + __popcll(mk[3] & below);
+    uint32_t own = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (l[k] == L) { rank[k] = before + own; ++own; }
+    if (lane == 0) sm.cnt[L] = __popcll(mk[0]) + __popcll(mk[1]) + __popcll(mk[2]) + __popcll(mk[3]);
+  }
+  if (lane == 0) {
+    sm.cnt[0] = 0;
+    sm.cnt[16] = 0;
+    uint32_t maxlen = 0, fcd = 0, lv = 0, lb = 0;
+    for (uint32_t L = 1; L <= 15; ++L)
+      if (sm.cnt[L]) maxlen = L;
+    for (uint32_t d = 0; d <= 16; ++d) {
+      const uint32_t cd = d <= 15 ? sm.cnt[d] : 0u;
+      sm.fc[d] = fcd;
+      sm.lvl[d] = lv;
+      if (d <= 16) sm.lbase[d] = lb;
+      lv += d < maxlen ? (1u << d) - fcd - cd : 0u;
+      lb += cd;
+      fcd = 2 * (fcd + cd);
+    }
+    sm.fc[17] = fcd;
+    sm.lvl[17] = lv;
+    sm.maxlen = maxlen;
+    sm.I = sm.lvl[maxlen];
+    E.maxlen = maxlen;
+    E.I = sm.lvl[maxlen];
+  }
+  wave_sync();
+  const uint32_t I = sm.I;
+  // canonical codes and the symbols in (length, symbol) order
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t s = 4 * lane + k;
+    const uint32_t code = l[k] ? sm.fc[l[k]] + rank[k] : 0u;
+    E.code[s] = (l[k] << 16) | code;
+    if (l[k]) sm.leafsym[sm.lbase[l[k]] + rank[k]] = static_cast<uint8_t>(s);
+    sm.nv[s] = 0;
+    sm.nr[s] = 0;
+    // (the code is kept for the path walk below)
+    rank[k] = code;
+  }
+  if (lane < 16) E.lvl[lane] = sm.lvl[lane];
+  if (lane < 17) { E.fc[lane] = sm.fc[lane]; E.cnt[lane] = sm.cnt[lane]; }
+  wave_sync();
+  // symbols passing each node and going right: walk each present symbol's path
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!c[k] || !l[k]) continue;
+    const uint32_t len = l[k], code = rank[k];
+    for (uint32_t d = 0; d < len; ++d) {
+      const uint32_t id = sm.lvl[d] + ((code >> (len - d)) - (sm.fc[d] + sm.cnt[d]));
+      atomicAdd(&sm.nv[id], c[k]);
+      if ((code >> (len - 1 - d)) & 1) atomicAdd(&sm.nr[id], c[k]);
+    }
+  }
+  wave_sync();
+  // lane owns nodes 4 lane .. 4 lane + 3: kind, sizes and their prefixes
+  const uint32_t C = 1u << chunk_log2;
+  uint32_t kd[4], rb[4], aw[4], ch[4], sl[4], nvk[4], nrk[4];
+  uint32_t lraw = 0, lans = 0, lrn = 0, lch = 0, lsl = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    nvk[k] = i < I ? sm.nv[i] : 0u;
+    nrk[k] = i < I ? sm.nr[i] : 0u;
+    kd[k] = i < I && select_ans(ans_mode, nvk[k], nrk[k]) ? 1u : 0u;
+    const uint32_t nch = kd[k] ? (nvk[k] + C - 1) / C : 0u;
+    const uint32_t rem = nvk[k] - (nch ? (nch - 1) * C : 0u);
+    rb[k] = lraw; aw[k] = lans; ch[k] = lch; sl[k] = lsl;
+    lraw += kd[k] || i >= I ? 0u : (nvk[k] + 7) / 8;
+    lans += kd[k] ? (nvk[k] + 31) / 32 : 0u;
+    lch += nch;
+    lsl += nch ? ((nch - 1) * slot_size(C) + slot_size(rem)) / 16 : 0u;   // 16-byte units
+    lrn += kd[k];
+  }
+  const uint32_t iraw = wave_incl_scan(lraw), ians = wave_incl_scan(lans), irn = wave_incl_scan(lrn);
+  const uint32_t ich = wave_incl_scan(lch), isl = wave_incl_scan(lsl);
+  uint32_t rn = irn - lrn;
+  uint32_t nib = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    nib |= kd[k] << k;
+    if (i >= I) continue;
+    const uint32_t raw_off = iraw - lraw + rb[k], rword = ians - lans + aw[k];
+    E.bit[i] = kd[k] ? rword : raw_off;
+    if (kd[k]) {
+      RansNode r;
+      r.rword = rword;
+      r.nv = nvk[k];
+      r.p1q = p1q_of(nvk[k], nrk[k]);
+      r.ch0 = ich - lch + ch[k];
+      r.sl0 = 16ull * (isl - lsl + sl[k]);
+      r.blen = 0;
+      r.boff = 0;
+      rnodes[255ull * b + rn] = r;
+      ++rn;
+    }
+  }
+  // header: code lengths (two nibbles a byte, symbol 2j low), kind bits, counts of 1 bits
+  const uint32_t kb = (I + 7) / 8;
+  H[12 + 2 * lane] = static_cast<uint8_t>(l[0] | (l[1] << 4));
+  H[12 + 2 * lane + 1] = static_cast<uint8_t>(l[2] | (l[3] << 4));
+  const uint32_t nib_hi = __shfl_down(nib, 1, kWaveE);
+  if ((lane & 1) == 0 && lane / 2 < kb) H[140 + lane / 2] = static_cast<uint8_t>(nib | (nib_hi << 4));
+  const uint64_t bm[4] = {__ballot(kd[0]), __ballot(kd[1]), __ballot(kd[2]), __ballot(kd[3])};
+  if (lane < 8) {                        // kind mask word: nodes 32 lane .. 32 lane + 31
+    uint32_t w = 0;
+    for (uint32_t j = 0; j < 32; ++j) w |= static_cast<uint32_t>((bm[j & 3] >> (8 * lane + j / 4)) & 1) << j;
+    E.kind[lane] = w;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    if (i >= I) continue;
+    uint8_t *q = H + 140 + kb + cw * i;
+    q[0] = static_cast<uint8_t>(nrk[k]);
+    q[1] = static_cast<uint8_t>(nrk[k] >> 8);
+    if (cw == 4) { q[2] = static_cast<uint8_t>(nrk[k] >> 16); q[3] = static_cast<uint8_t>(nrk[k] >> 24); }
+  }
+  // node table: lane owns nodes 4 lane .. 4 lane + 3
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    if (i >= I) continue;
+    uint32_t d = 0;
+    while (sm.lvl[d + 1] <= i) ++d;
+    const uint32_t p = sm.fc[d] + sm.cnt[d] + (i - sm.lvl[d]);
+    const uint32_t leafend = sm.fc[d + 1] + sm.cnt[d + 1];
+    for (int bb = 0; bb < 2; ++bb) {
+      const uint32_t q = 2 * p + bb;
+      E.child[i][bb] = static_cast<uint16_t>(q < leafend ? 0x8000u | sm.leafsym[sm.lbase[d + 1] + q - sm.fc[d + 1]]
+                                                         : sm.lvl[d + 1] + (q - leafend));
+    }
+  }
+  if (lane == kWaveE - 1) {
+    Lb.hlen = 140 + kb + cw * I;
+    Lb.raw_bytes = iraw;
+    Lb.ans_words = ians;
+    Lb.n_rnodes = irn;
+    Lb.n_chunks = ich;
+    Lb.slot_bytes = 16ull * isl;
+  }
+}
+
+// Exclusive scans over the blocks (one workgroup): image bytes (16-aligned,
+// with 16 bytes of slack), rANS bitmap words (multiples of 4), chunk jobs,
+// slot bytes and scratch words; their totals.
+__global__ __launch_bounds__(kScanNT) void k_scan(BlockLay *lay, uint32_t nb, Totals *tot) {
+  __shared__ uint64_t part[5][kScanNT];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (nb + kScanNT - 1) / kScanNT;
+  const uint32_t b0 = tid * per, b1 = b0 + per < nb ? b0 + per : nb;
+  uint64_t v[5] = {0, 0, 0, 0, 0};
+  for (uint32_t b = b0; b < b1; ++b) {
+    const BlockLay &L = lay[b];
+    v[0] += (static_cast<uint64_t>(L.raw_bytes) + 16 + 15) & ~15ull;
+    v[1] += (static_cast<uint64_t>(L.ans_words) + 3) & ~3ull;
+    v[2] += L.n_chunks;
+    v[3] += L.slot_bytes;
+    v[4] += L.ans_words;
+  }
+  for (int q = 0; q < 5; ++q) part[q][tid] = v[q];
+  __syncthreads();
+  for (uint32_t off = 1; off < kScanNT; off <<= 1) {   // inclusive scan (Hillis-Steele)
+    uint64_t a[5];
+    for (int q = 0; q < 5; ++q) a[q] = tid >= off ? part[q][tid - off] : 0ull;
+    __syncthreads();
+    for (int q = 0; q < 5; ++q) part[q][tid] += a[q];
+    __syncthreads();
+  }
+  uint64_t run[5];
+  for (int q = 0; q < 5; ++q) run[q] = part[q][tid] - v[q];
+  for (uint32_t b = b0; b < b1; ++b) {
+    BlockLay &L = lay[b];
+    L.img_off = run[0];
+    L.rbm_off = run[1];
+    L.chunk0 = run[2];
+    L.slot0 = run[3];
+    L.ans0 = run[4];
+    run[0] += (static_cast<uint64_t>(L.raw_bytes) + 16 + 15) & ~15ull;
+    run[1] += (static_cast<uint64_t>(L.ans_words) + 3) & ~3ull;
+    run[2] += L.n_chunks;
+    run[3] += L.slot_bytes;
+    run[4] += L.ans_words;
+  }
+  if (tid == kScanNT - 1) {
+    tot->img_bytes = part[0][tid];
+    tot->rbm_words = part[1][tid];
+    tot->chunks = part[2][tid];
+    tot->slot_bytes = part[3][tid];
+    tot->ans_words = part[4][tid];
+  }
+}
+
 static_assert(kSplitNT == 256, "the split kernel's prefix walk has one thread per symbol");
 static_assert(kHistSlice % kSplitT == 0, "split tiles never cross a slice");
 
@@ -146,11 +512,14 @@ struct SplitSmem {
 // workgroups.  A node's bits from this slice start at the number of the
 // block's symbols before the slice that pass the node: the sum, over the
 // symbols on whose path the node lies, of their counts before the slice
-// (the slice's row of the prefix histograms).  Slices share bitmap words at
-// their edges: every word is written with atomicOr into zeroed scratch.
+// (the slice's row of the prefix histograms).  A raw node's bitmap is
+// written at its byte offset in the block's raw image (the stream layout),
+// a rANS node's at its word in the block's rANS bitmap words.  Slices and
+// neighbouring nodes share words at their edges: every word is written with
+// atomicOr into zeroed memory.
 __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const EncBlock *blocks,
-                                                    uint32_t nblocks, uint32_t spb,
-                                                    const uint32_t *pre, uint32_t *bmp) {
+                                                    const BlockLay *lay, uint32_t nblocks, uint32_t spb,
+                                                    const uint32_t *pre, uint32_t *img, uint32_t *rbm) {
   __shared__ SplitSmem sm;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -158,15 +527,16 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
   const uint32_t b = blockIdx.x / spb, slice = blockIdx.x % spb;
   if (b >= nblocks) return;
   {
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(&blocks[b]);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&sm.B);
-    for (uint32_t i = tid; i < sizeof(EncBlock) / 4; i += kSplitNT) dst[i] = src[i];
+    const uint4 *src = reinterpret_cast<const uint4 *>(&blocks[b]);
+    uint4 *dst = reinterpret_cast<uint4 *>(&sm.B);
+    for (uint32_t i = tid; i < sizeof(EncBlock) / 16; i += kSplitNT) dst[i] = src[i];
   }
   __syncthreads();
   const EncBlock &B = sm.B;
   const uint32_t s_lo = slice * kHistSlice;
   if (B.I == 0 || s_lo >= B.n) return;
   const uint32_t s_hi = B.n - s_lo < kHistSlice ? B.n : s_lo + kHistSlice;
+  const uint64_t img_bit = 8ull * lay[b].img_off, rbm_bit = 32ull * lay[b].rbm_off;
   for (uint32_t i = tid; i < 256; i += kSplitNT) sm.cur[i] = 0;
   __syncthreads();
   if (slice) {   // bits of each node before this slice
@@ -221,8 +591,9 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
         const uint16_t c0 = B.child[v][0], c1 = B.child[v][1];
         uint32_t r0 = (c0 & 0x8000) ? 0u : sm.seg[c0];
         uint32_t r1 = (c1 & 0x8000) ? 0u : sm.seg[c1];
-        uint32_t *nb = bmp + B.bmp_word + B.word[v];
-        const uint32_t base_bit = sm.cur[v];
+        const bool rans = (B.kind[v >> 5] >> (v & 31)) & 1;
+        uint32_t *area = rans ? rbm : img;
+        const uint64_t base_bit = (rans ? rbm_bit + 32ull * B.bit[v] : img_bit + 8ull * B.bit[v]) + sm.cur[v];
         for (uint32_t c = 0; c < tvv; c += kWaveE) {
           const bool act = c + lane < tvv;
           const uint32_t s = act ? lb[seg + c + lane] : 0u;
@@ -232,14 +603,15 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
           const uint64_t m0 = __ballot(act && !bit);
           const uint64_t lt = (1ull << lane) - 1;
           // bitmap: 64 bits at bit position base_bit + c
-          const uint64_t P = static_cast<uint64_t>(base_bit) + c;
-          const uint32_t q = static_cast<uint32_t>(P >> 5), sh = static_cast<uint32_t>(P & 31);
+          const uint64_t P = base_bit + c;
+          const uint64_t q = P >> 5;
+          const uint32_t sh = static_cast<uint32_t>(P & 31);
           const uint32_t lo = static_cast<uint32_t>(m1), hi = static_cast<uint32_t>(m1 >> 32);
           uint32_t wv = 0;
           if (lane == 0) wv = lo << sh;
           if (lane == 1) wv = sh ? (lo >> (32 - sh)) | (hi << sh) : hi;
           if (lane == 2) wv = sh ? hi >> (32 - sh) : 0u;
-          if (lane < 3 && wv) atomicOr(&nb[q + lane], wv);
+          if (lane < 3 && wv) atomicOr(&area[q + lane], wv);
           // stable partition of the symbols into the children's segments
           if (act) {
             if (bit && !(c1 & 0x8000)) cb[r1 + __popcll(m1 & lt)] = static_cast<uint8_t>(s);
@@ -256,62 +628,235 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
   }
 }
 
-// One wave per chunk: encode steps k = K-1 .. 0; within a step the lanes
-// push their renormalisation words in the order lane 31 .. 0, the reverse of
-// the decoder's read order, so the decoder reads the pushed words backwards.
-__global__ __launch_bounds__(256) void k_rans_enc(const RansJob *jobs, uint32_t njobs,
+// The chunk jobs of every rANS node (one wave per block, a lane per node).
+__global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_chunks(const BlockLay *lay, const RansNode *rnodes,
+                                                                uint32_t nb, uint32_t chunk_log2,
+                                                                RansJob *jobs) {
+  const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
+  const uint32_t b = blockIdx.x * kLayoutWaves + wave;
+  if (b >= nb) return;
+  const BlockLay &L = lay[b];
+  const uint32_t C = 1u << chunk_log2;
+  for (uint32_t r = lane; r < L.n_rnodes; r += kWaveE) {
+    const RansNode rn = rnodes[255ull * b + r];
+    uint32_t k = 0;
+    for (uint32_t st = 0; st < rn.nv; st += C, ++k) {
+      RansJob j;
+      j.bmp_word = L.rbm_off + rn.rword + st / 32;
+      j.slot = L.slot0 + rn.sl0 + static_cast<uint64_t>(k) * slot_size(C);
+      j.nbits = rn.nv - st < C ? rn.nv - st : C;
+      j.p1q = rn.p1q;
+      j.block = b;
+      j.rnode = r;
+      j.first = st == 0;
+      j.dst = 0;
+      jobs[L.chunk0 + rn.ch0 + k] = j;
+    }
+  }
+}
+
+// One wave per chunk (persistent over the job list): encode steps k = K-1 ..
+// 0; within a step the lanes push their renormalisation words in the order
+// lane 31 .. 0, the reverse of the decoder's read order, so the decoder reads
+// the pushed words backwards.
+__global__ __launch_bounds__(256) void k_rans_enc(const RansJob *jobs, const Totals *tot,
                                                   const uint32_t *bmp, uint8_t *slots,
                                                   uint32_t *sizes) {
   const uint32_t lane = __lane_id();
-  const uint32_t j = blockIdx.x * (256 / kWaveE) + (threadIdx.x >> 6);
-  if (j >= njobs) return;
-  const RansJob J = jobs[j];
-  const uint32_t f0 = kRansM - J.p1q, f1 = J.p1q;
-  const uint32_t K = (J.nbits + 31) / 32;
-  uint8_t *slot = slots + J.slot;
-  uint16_t *words = reinterpret_cast<uint16_t *>(slot + kChunkHdr);
-  const uint32_t *bits = bmp + J.bmp_word;
-  uint32_t x = kRansL;
-  uint32_t pos = 0;
-  const uint64_t gt = lane < 63 ? ~((2ull << lane) - 1) : 0ull;   // lanes above this one
-  for (uint32_t k = K; k-- > 0;) {
-    const uint32_t w = bits[k];
-    const bool act = lane < kRansLanes && 32 * k + lane < J.nbits;
-    const bool bit = act && ((w >> (lane & 31)) & 1);
-    const uint32_t f = bit ? f1 : f0;
-    const bool need = act && x >= (f << 20);
-    const uint64_t m = __ballot(need);
-    if (need) {
-      words[pos + __popcll(m & gt)] = static_cast<uint16_t>(x & 0xFFFF);
-      x >>= 16;
+  const uint64_t njobs = tot->chunks;
+  const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (256 / kWaveE);
+  for (uint64_t j = blockIdx.x * (256 / kWaveE) + (threadIdx.x >> 6); j < njobs; j += nwaves) {
+    const RansJob J = jobs[j];
+    const uint32_t f0 = kRansM - J.p1q, f1 = J.p1q;
+    const uint32_t K = (J.nbits + 31) / 32;
+    uint8_t *slot = slots + J.slot;
+    uint16_t *words = reinterpret_cast<uint16_t *>(slot + kChunkHdr);
+    const uint32_t *bits = bmp + J.bmp_word;
+    uint32_t x = kRansL;
+    uint32_t pos = 0;
+    const uint64_t gt = lane < 63 ? ~((2ull << lane) - 1) : 0ull;   // lanes above this one
+    for (uint32_t k = K; k-- > 0;) {
+      const uint32_t w = bits[k];
+      const bool act = lane < kRansLanes && 32 * k + lane < J.nbits;
+      const bool bit = act && ((w >> (lane & 31)) & 1);
+      const uint32_t f = bit ? f1 : f0;
+      const bool need = act && x >= (f << 20);
+      const uint64_t m = __ballot(need);
+      if (need) {
+        words[pos + __popcll(m & gt)] = static_cast<uint16_t>(x & 0xFFFF);
+        x >>= 16;
+      }
+      pos += __popcll(m);
+      if (act) x = (x / f) * kRansM + (x % f) + (bit ? f0 : 0u);
     }
-    pos += __popcll(m);
-    if (act) x = (x / f) * kRansM + (x % f) + (bit ? f0 : 0u);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    __builtin_amdgcn_wave_barrier();
+    // reverse the pushed words in place: decoder order
+    for (uint32_t i = lane; i < pos / 2; i += kWaveE) {
+      const uint16_t a = words[i], c = words[pos - 1 - i];
+      words[i] = c;
+      words[pos - 1 - i] = a;
+    }
+    if (lane == 0) *reinterpret_cast<uint32_t *>(slot) = pos;
+    if (lane < kRansLanes) reinterpret_cast<uint32_t *>(slot)[1 + lane] = x;
+    const uint32_t used = kChunkHdr + 2 * pos, size = (used + 3) & ~3u;
+    if (lane < size - used) slot[used + lane] = 0;
+    if (lane == 0) sizes[j] = size;
+    __builtin_amdgcn_wave_barrier();
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-  __builtin_amdgcn_wave_barrier();
-  // reverse the pushed words in place: decoder order
-  for (uint32_t i = lane; i < pos / 2; i += kWaveE) {
-    const uint16_t a = words[i], c = words[pos - 1 - i];
-    words[i] = c;
-    words[pos - 1 - i] = a;
-  }
-  if (lane == 0) *reinterpret_cast<uint32_t *>(slot) = pos;
-  if (lane < kRansLanes) reinterpret_cast<uint32_t *>(slot)[1 + lane] = x;
-  const uint32_t used = kChunkHdr + 2 * pos, size = (used + 3) & ~3u;
-  if (lane < size - used) slot[used + lane] = 0;
-  if (lane == 0) sizes[j] = size;
 }
 
-// One wave per descriptor: byte copy from the workspace into the stream.
-__global__ __launch_bounds__(256) void k_copy(const CopyDesc *desc, uint64_t ndesc,
-                                              const uint8_t *ws, uint8_t *out) {
+// Block sizes (one thread per block): header, raw bodies, then every rANS
+// node at a multiple of 4 bytes with its 8-byte header and its chunks; the
+// chunks' places in the block go to their jobs, comp_size to the header.
+__global__ __launch_bounds__(256) void k_sizes(BlockLay *lay, RansNode *rnodes, RansJob *jobs,
+                                               const uint32_t *sizes, uint32_t nb, uint32_t chunk_log2,
+                                               uint8_t *hdr) {
+  const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  BlockLay &L = lay[b];
+  const uint32_t C = 1u << chunk_log2;
+  uint64_t off = static_cast<uint64_t>(L.hlen) + L.raw_bytes;
+  for (uint32_t r = 0; r < L.n_rnodes; ++r) {
+    RansNode &rn = rnodes[255ull * b + r];
+    off = (off + 3) & ~3ull;
+    rn.boff = static_cast<uint32_t>(off);
+    off += 8;
+    const uint32_t nch = (rn.nv + C - 1) / C;
+    uint32_t blen = 0;
+    for (uint32_t k = 0; k < nch; ++k) {
+      const uint64_t j = L.chunk0 + rn.ch0 + k;
+      jobs[j].dst = static_cast<uint32_t>(off + blen);
+      blen += sizes[j];
+    }
+    rn.blen = blen;
+    off += blen;
+  }
+  L.comp = static_cast<uint32_t>(off);
+  *reinterpret_cast<uint32_t *>(hdr + static_cast<uint64_t>(b) * kHdrStride) = static_cast<uint32_t>(off);
+}
+
+// Stream offsets of the blocks (one workgroup): each block starts at a
+// multiple of 4 bytes after the header and the two offset tables.
+__global__ __launch_bounds__(kScanNT) void k_scan2(BlockLay *lay, uint32_t nb, Totals *tot) {
+  __shared__ uint64_t part[kScanNT];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t per = (nb + kScanNT - 1) / kScanNT;
+  const uint32_t b0 = tid * per, b1 = b0 + per < nb ? b0 + per : nb;
+  uint64_t v = 0;
+  for (uint32_t b = b0; b < b1; ++b) v += (static_cast<uint64_t>(lay[b].comp) + 3) & ~3ull;
+  part[tid] = v;
+  __syncthreads();
+  for (uint32_t off = 1; off < kScanNT; off <<= 1) {
+    const uint64_t a = tid >= off ? part[tid - off] : 0ull;
+    __syncthreads();
+    part[tid] += a;
+    __syncthreads();
+  }
+  const uint64_t tab = kHeaderBytes + 16ull * (nb + 1);
+  uint64_t run = tab + part[tid] - v;
+  for (uint32_t b = b0; b < b1; ++b) {
+    lay[b].out_off = run;
+    run += (static_cast<uint64_t>(lay[b].comp) + 3) & ~3ull;
+  }
+  if (tid == kScanNT - 1) tot->out_bytes = tab + part[tid];
+}
+
+// Stream header and the two offset tables (block offsets, scratch-word
+// offsets), nothing written past out_cap.
+__global__ __launch_bounds__(256) void k_stream_head(const BlockLay *lay, const Totals *tot, uint32_t nb,
+                                                     uint64_t n, uint32_t bs, uint32_t max_len,
+                                                     uint32_t chunk_log2, uint8_t *out, uint64_t out_cap) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (tot->out_bytes > out_cap) return;
+  uint64_t *boff = reinterpret_cast<uint64_t *>(out + kHeaderBytes);
+  uint64_t *aoff = boff + nb + 1;
+  if (t <= nb) {
+    boff[t] = t < nb ? lay[t].out_off : tot->out_bytes;
+    aoff[t] = t < nb ? lay[t].ans0 : tot->ans_words;
+  }
+  if (t == 0) {
+    uint32_t *h = reinterpret_cast<uint32_t *>(out);
+    h[0] = kMagic;
+    h[1] = 1u;                                        // version 1, flags 0
+    h[2] = static_cast<uint32_t>(n);
+    h[3] = static_cast<uint32_t>(n >> 32);
+    h[4] = bs;
+    h[5] = nb;
+    h[6] = (max_len & 255) | ((chunk_log2 & 255) << 8);
+    h[7] = 0;
+    h[8] = static_cast<uint32_t>(tot->ans_words);
+    h[9] = static_cast<uint32_t>(tot->ans_words >> 32);
+    h[10] = 0;
+    h[11] = 0;
+  }
+}
+
+// Block header and raw image, as aligned 4-byte words (workgroup s of block b
+// writes words [s kAsmSeg, (s + 1) kAsmSeg) of them): a word inside the raw
+// bodies is a byte funnel of two image words, words at the edges are built
+// byte by byte (bytes past the raw bodies are zero: the padding before the
+// first rANS body or the next block).
+__global__ __launch_bounds__(256) void k_assemble(const BlockLay *lay, const Totals *tot, uint32_t nb,
+                                                  uint32_t segs, const uint8_t *hdr, const uint8_t *imgb,
+                                                  uint8_t *out, uint64_t out_cap) {
+  const uint32_t b = blockIdx.x / segs, s = blockIdx.x % segs;
+  if (b >= nb || tot->out_bytes > out_cap) return;
+  const BlockLay &L = lay[b];
+  const uint32_t hlen = L.hlen;
+  const uint64_t used = static_cast<uint64_t>(hlen) + L.raw_bytes;
+  const uint64_t W = (used + 3) / 4;
+  const uint64_t w0 = static_cast<uint64_t>(s) * kAsmSeg;
+  if (w0 >= W) return;
+  const uint64_t w1 = w0 + kAsmSeg < W ? w0 + kAsmSeg : W;
+  const uint8_t *H = hdr + static_cast<uint64_t>(b) * kHdrStride;
+  const uint8_t *img = imgb + L.img_off;
+  const uint32_t *img32 = reinterpret_cast<const uint32_t *>(imgb);
+  uint32_t *o32 = reinterpret_cast<uint32_t *>(out + L.out_off);
+  for (uint64_t q = w0 + threadIdx.x; q < w1; q += 256) {
+    const uint64_t x0 = 4 * q;
+    uint32_t w;
+    if (x0 + 4 <= hlen) {
+      w = *reinterpret_cast<const uint32_t *>(H + x0);
+    } else if (x0 >= hlen && x0 + 4 <= used) {
+      const uint64_t so = L.img_off + (x0 - hlen);
+      w = __builtin_amdgcn_alignbyte(img32[(so >> 2) + 1], img32[so >> 2], static_cast<uint32_t>(so & 3));
+    } else {
+      w = 0;
+      for (uint32_t e = 0; e < 4; ++e) {
+        const uint64_t x = x0 + e;
+        const uint32_t v = x < hlen ? H[x] : x < used ? img[x - hlen] : 0u;
+        w |= v << (8 * e);
+      }
+    }
+    o32[q] = w;
+  }
+}
+
+// rANS bodies: one wave per chunk copies its slot into the block; the first
+// chunk of a node also writes the node's 8-byte body header.
+__global__ __launch_bounds__(256) void k_assemble_rans(const BlockLay *lay, const RansNode *rnodes,
+                                                       const RansJob *jobs, const uint32_t *sizes,
+                                                       const Totals *tot, const uint8_t *slots,
+                                                       uint8_t *out, uint64_t out_cap) {
   const uint32_t lane = __lane_id();
-  for (uint64_t d = blockIdx.x * 4ull + (threadIdx.x >> 6); d < ndesc; d += gridDim.x * 4ull) {
-    const CopyDesc c = desc[d];
-    const uint8_t *s = ws + c.src;
-    uint8_t *o = out + c.dst;
-    for (uint64_t i = lane; i < c.len; i += kWaveE) o[i] = s[i];
+  if (tot->out_bytes > out_cap) return;
+  const uint64_t njobs = tot->chunks;
+  const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (256 / kWaveE);
+  for (uint64_t j = blockIdx.x * (256 / kWaveE) + (threadIdx.x >> 6); j < njobs; j += nwaves) {
+    const RansJob J = jobs[j];
+    const BlockLay &L = lay[J.block];
+    uint8_t *dst = out + L.out_off + J.dst;
+    if (J.first && lane == 0) {
+      const RansNode &rn = rnodes[255ull * J.block + J.rnode];
+      uint32_t *h = reinterpret_cast<uint32_t *>(dst - 8);
+      h[0] = J.p1q;                                    // p1q u16, pad u16
+      h[1] = rn.blen;
+    }
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(slots + J.slot);
+    uint32_t *d32 = reinterpret_cast<uint32_t *>(dst);
+    const uint32_t nw = sizes[j] / 4;
+    for (uint32_t i = lane; i < nw; i += kWaveE) d32[i] = src[i];
   }
 }
 
@@ -320,137 +865,88 @@ __global__ __launch_bounds__(256) void k_copy(const CopyDesc *desc, uint64_t nde
 // ---------------------------------------------------------------------------
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-void put16(uint8_t *p, uint32_t v) { p[0] = uint8_t(v); p[1] = uint8_t(v >> 8); }
-void put32(uint8_t *p, uint32_t v) { for (int i = 0; i < 4; ++i) p[i] = uint8_t(v >> (8 * i)); }
-void put64(uint8_t *p, uint64_t v) { for (int i = 0; i < 8; ++i) p[i] = uint8_t(v >> (8 * i)); }
-
 bool opts_ok(const pivco_encode_opts *o) {
-  return o && o->block_size >= 1 && o->max_len >= 1 && o->max_len <= kMaxLenGpu &&
-         o->ans_mode <= 2 && o->rans_chunk_log2 >= 5 && o->rans_chunk_log2 <= 24;
+  return o && o->block_size >= 1 && o->block_size <= (1u << 30) && o->max_len >= 1 &&
+         o->max_len <= kMaxLenGpu && o->ans_mode <= 2 && o->rans_chunk_log2 >= 5 &&
+         o->rans_chunk_log2 <= 24;
 }
 
 struct WsLayout {
-  uint64_t hist, slh, blocks, bmp, rjobs, rsizes, slots, staging, desc, total;
+  uint64_t hist, slh, lenm, modes, eb, lay, rnodes, hdr, img, rbm, jobs, sizes, slots, tot, total;
 };
 
-// Generous sizes derived from n alone (the data is not known yet).
+// Sizes from n and the options alone (the data is not known yet): every
+// area is bounded by the code-length limit and the block count.
 WsLayout ws_layout(uint64_t n, const pivco_encode_opts *o) {
   WsLayout L{};
   const uint64_t nb = div_up(n, o->block_size);
+  const uint64_t spb = div_up(o->block_size, kHistSlice);
   const uint64_t C = 1ull << o->rans_chunk_log2;
   const uint64_t bits = n * o->max_len;
-  const uint64_t nodes = nb * std::min<uint64_t>(255, std::max<uint64_t>(1, o->block_size));
-  const uint64_t chunks = o->ans_mode ? bits / C + nodes + 1 : 0;
+  const uint64_t chunks = o->ans_mode ? bits / C + nb * 255 + 1 : 0;
   uint64_t x = 0;
   L.hist = x; x = align_up(x + nb * 1024 + 16, 256);
-  L.slh = x; x = align_up(x + nb * div_up(o->block_size, kHistSlice) * 1024 + 16, 256);
-  L.blocks = x; x = align_up(x + nb * sizeof(EncBlock), 256);
-  L.bmp = x; x = align_up(x + 4 * (bits / 32 + nodes + 16), 256);
-  L.rjobs = x; x = align_up(x + chunks * sizeof(RansJob), 256);
-  L.rsizes = x; x = align_up(x + 4 * chunks, 256);
-  L.slots = x; x = align_up(x + (o->ans_mode ? 136 * chunks + 2 * bits + 64 : 0), 256);
-  L.staging = x; x = align_up(x + kHeaderBytes + 16 * (nb + 1) + nb * (12 + 128 + 32 + 4 * 255 + 8 * 255 + 16), 256);
-  L.desc = x; x = align_up(x + sizeof(CopyDesc) * (nb * (1 + 2 * 255) + chunks + 4), 256);
+  L.slh = x; x = align_up(x + nb * spb * 1024 + 16, 256);
+  L.lenm = x; x = align_up(x + nb * 256 + 16, 256);
+  L.modes = x; x = align_up(x + nb * 4 + 16, 256);
+  L.eb = x; x = align_up(x + nb * sizeof(EncBlock), 256);
+  L.lay = x; x = align_up(x + nb * sizeof(BlockLay), 256);
+  L.rnodes = x; x = align_up(x + (o->ans_mode ? nb * 255 * sizeof(RansNode) : 0), 256);
+  L.hdr = x; x = align_up(x + nb * kHdrStride, 256);
+  L.img = x; x = align_up(x + bits / 8 + nb * (255 + 32) + 64, 256);
+  L.rbm = x; x = align_up(x + (o->ans_mode ? 4 * (bits / 32 + nb * (255 + 4)) : 0) + 64, 256);
+  L.jobs = x; x = align_up(x + chunks * sizeof(RansJob), 256);
+  L.sizes = x; x = align_up(x + chunks * 4, 256);
+  L.slots = x; x = align_up(x + (o->ans_mode ? 2 * bits + chunks * 160 : 0) + 64, 256);
+  L.tot = x; x = align_up(x + sizeof(Totals), 256);
   L.total = x;
   return L;
 }
 
-struct HostNode {
-  uint64_t nv = 0, nr = 0;
-  uint16_t child[2] = {0, 0};
-  uint8_t kind = 0;
-};
+#define HIPCHK(x) do { if ((x) != hipSuccess) return PIVCO_E_DEVICE; } while (0)
 
-struct HostBlock {
-  uint64_t n = 0;
-  int mode = 0;              // 0 coded, 1 constant
-  uint8_t csym = 0;
-  uint8_t len[256];
-  std::vector<HostNode> nodes;
-  uint64_t bmp_word = 0;     // first bitmap word
-  std::vector<uint32_t> word;  // per node, relative
-  // filled after rANS: per rANS node, chunk ids
-  std::vector<std::vector<uint32_t>> chunks;
-  std::vector<uint32_t> p1q;
-};
-
-uint32_t p1q_of(uint64_t nv, uint64_t nr) {
-  if (nv == 0) return 2048;
-  uint64_t q = (nr * 4096 + nv / 2) / nv;
-  return static_cast<uint32_t>(std::min<uint64_t>(4095, std::max<uint64_t>(1, q)));
-}
-
-bool select_ans(uint32_t mode, uint64_t nv, uint64_t nr) {
-  if (nv == 0) return false;
-  if (mode == 1) return 10 * nr < nv || 10 * nr > 9 * nv;
-  return mode == 2;
-}
-
-// Builds the breadth-first node table of a canonical code and the device
-// description of the block.  Internal nodes at depth d are the prefixes
-// [fc(d) + cnt(d), 2^d) of a complete canonical code.
-void make_block(HostBlock &hb, const uint64_t counts[256], uint32_t ans_mode, EncBlock &eb) {
-  std::memset(&eb, 0, sizeof(eb));
-  uint16_t code[256];
-  canonical_codes(hb.len, code);
-  uint32_t cnt[17] = {0}, maxlen = 0;
-  for (int s = 0; s < 256; ++s)
-    if (hb.len[s]) { cnt[hb.len[s]]++; maxlen = std::max<uint32_t>(maxlen, hb.len[s]); }
-  uint32_t fc[18] = {0}, lvl[18] = {0};
-  cnt[0] = 0;
-  for (uint32_t d = 0; d <= 16; ++d) {
-    fc[d + 1] = 2 * (fc[d] + (d < 17 ? cnt[d] : 0));
-    const uint32_t Id = d < maxlen ? (1u << d) - fc[d] - cnt[d] : 0;
-    lvl[d + 1] = lvl[d] + Id;
-  }
-  const uint32_t I = lvl[maxlen];
-  hb.nodes.assign(I, HostNode{});
-  // symbols of each length in symbol order
-  std::vector<int> bylen[17];
-  for (int s = 0; s < 256; ++s)
-    if (hb.len[s]) bylen[hb.len[s]].push_back(s);
-  for (uint32_t d = 0; d < maxlen; ++d) {
-    for (uint32_t i = lvl[d]; i < lvl[d + 1]; ++i) {
-      const uint32_t p = fc[d] + cnt[d] + (i - lvl[d]);
-      const uint32_t leafend = fc[d + 1] + cnt[d + 1];
-      for (int b = 0; b < 2; ++b) {
-        const uint32_t q = 2 * p + b;
-        hb.nodes[i].child[b] = q < leafend ? uint16_t(0x8000 | bylen[d + 1][q - fc[d + 1]])
-                                           : uint16_t(lvl[d + 1] + (q - leafend));
+// Code lengths (or constant-block mode) of every block from its histogram:
+// package-merge per block, on up to 16 host threads.
+pivco_status build_trees(const std::vector<uint32_t> &hist, uint32_t nb, const pivco_encode_opts *o,
+                         std::vector<uint8_t> &lenm, std::vector<uint32_t> &modes) {
+  lenm.assign(static_cast<size_t>(nb) * 256, 0);
+  modes.assign(nb, 0);
+  std::atomic<int> err{PIVCO_OK};
+  auto work = [&](uint32_t b0, uint32_t b1) {
+    for (uint32_t b = b0; b < b1 && err.load(std::memory_order_relaxed) == PIVCO_OK; ++b) {
+      uint64_t counts[256];
+      int m = 0, last = 0;
+      for (int k = 0; k < 256; ++k) {
+        counts[k] = hist[static_cast<size_t>(b) * 256 + k];
+        if (counts[k]) { ++m; last = k; }
+      }
+      uint8_t *len = &lenm[static_cast<size_t>(b) * 256];
+      if (!o->tree && m == 1) {
+        modes[b] = 1u | (static_cast<uint32_t>(last) << 8);
+        continue;
+      }
+      if (o->tree) {
+        std::memcpy(len, o->tree->code_len, 256);
+        for (int k = 0; k < 256; ++k)
+          if (counts[k] && !len[k]) { err = PIVCO_E_ARG; return; }
+      } else {
+        const pivco_status st = lengths_from_counts(counts, o->max_len, len);
+        if (st) { err = st; return; }
       }
     }
+  };
+  const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const uint32_t nt = std::min<uint32_t>(hw, std::max<uint32_t>(1, nb / 64));
+  if (nt <= 1) {
+    work(0, nb);
+  } else {
+    std::vector<std::thread> th;
+    const uint32_t per = (nb + nt - 1) / nt;
+    for (uint32_t t = 0; t < nt; ++t) th.emplace_back(work, t * per, std::min(nb, (t + 1) * per));
+    for (auto &t : th) t.join();
   }
-  for (int s = 0; s < 256; ++s) {
-    const uint32_t L = hb.len[s];
-    if (!L || !counts[s]) continue;
-    for (uint32_t d = 0; d < L; ++d) {
-      const uint32_t p = code[s] >> (L - d);
-      const uint32_t id = lvl[d] + (p - (fc[d] + cnt[d]));
-      hb.nodes[id].nv += counts[s];
-      if ((code[s] >> (L - 1 - d)) & 1) hb.nodes[id].nr += counts[s];
-    }
-  }
-  hb.word.assign(I, 0);
-  uint32_t w = 0;
-  for (uint32_t i = 0; i < I; ++i) {
-    hb.nodes[i].kind = select_ans(ans_mode, hb.nodes[i].nv, hb.nodes[i].nr) ? 1 : 0;
-    hb.word[i] = w;
-    w += static_cast<uint32_t>(div_up(hb.nodes[i].nv, 32));
-  }
-  eb.n = static_cast<uint32_t>(hb.n);
-  eb.I = I;
-  eb.maxlen = maxlen;
-  for (uint32_t d = 0; d < 16; ++d) eb.lvl[d] = lvl[d];
-  for (uint32_t d = 0; d < 17; ++d) { eb.fc[d] = fc[d]; eb.cnt[d] = cnt[d]; }
-  for (int s = 0; s < 256; ++s) eb.code[s] = (uint32_t(hb.len[s]) << 16) | code[s];
-  for (uint32_t i = 0; i < I; ++i) {
-    eb.child[i][0] = hb.nodes[i].child[0];
-    eb.child[i][1] = hb.nodes[i].child[1];
-    eb.word[i] = hb.word[i];
-  }
+  return static_cast<pivco_status>(err.load());
 }
-
-#define HIPCHK(x) do { if ((x) != hipSuccess) return PIVCO_E_DEVICE; } while (0)
 
 }  // namespace
 
@@ -479,217 +975,102 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   if (o->tree && !tree_is_complete(o->tree->code_len, o->max_len)) return PIVCO_E_ARG;
   const uint64_t bs = o->block_size;
   const uint64_t nb64 = div_up(n, bs);
-  if (nb64 > 0xFFFFFFFFull) return PIVCO_E_ARG;
-  const uint32_t nb = static_cast<uint32_t>(nb64);
+  const uint64_t spb64 = div_up(bs, kHistSlice);
+  if (nb64 > 0xFFFFFFFFull || nb64 * spb64 > 0x7FFFFFFFull) return PIVCO_E_ARG;
+  const uint32_t nb = static_cast<uint32_t>(nb64), spb = static_cast<uint32_t>(spb64);
   const WsLayout L = ws_layout(n, o);
   if (ws_bytes < L.total || !d_ws) return PIVCO_E_CAPACITY;
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   const uint8_t *in = static_cast<const uint8_t *>(d_in);
   uint8_t *out = static_cast<uint8_t *>(d_out);
+  Totals *dtot = reinterpret_cast<Totals *>(ws + L.tot);
+  BlockLay *dlay = reinterpret_cast<BlockLay *>(ws + L.lay);
+  EncBlock *deb = reinterpret_cast<EncBlock *>(ws + L.eb);
+  RansNode *drn = reinterpret_cast<RansNode *>(ws + L.rnodes);
+  RansJob *djobs = reinterpret_cast<RansJob *>(ws + L.jobs);
+  uint32_t *dsizes = reinterpret_cast<uint32_t *>(ws + L.sizes);
 
-  // 1. histograms
+  if (nb == 0) {                         // header and the two one-entry tables
+    uint8_t h[kHeaderBytes + 16] = {0};
+    const uint32_t w[6] = {kMagic, 1u, 0u, 0u, static_cast<uint32_t>(bs), 0u};
+    std::memcpy(h, w, sizeof(w));
+    h[24] = static_cast<uint8_t>(o->max_len);
+    h[25] = static_cast<uint8_t>(o->rans_chunk_log2);
+    const uint64_t end = sizeof(h);
+    std::memcpy(h + kHeaderBytes, &end, 8);
+    if (out_cap < sizeof(h)) return PIVCO_E_CAPACITY;
+    HIPCHK(hipMemcpyAsync(out, h, sizeof(h), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *h_out_len = sizeof(h);
+    return PIVCO_OK;
+  }
+
+  // 1. histograms of the blocks and of their slices
   std::vector<uint32_t> hist(static_cast<size_t>(nb) * 256, 0);
-  if (nb) {
-    uint32_t *dh = reinterpret_cast<uint32_t *>(ws + L.hist);
-    hipLaunchKernelGGL(k_fill_zero, dim3(std::min<uint64_t>(4096, div_up(nb64 * 256, 256))), dim3(256), 0, s,
-                       dh, nb64 * 256);
-    const uint32_t spb = static_cast<uint32_t>(div_up(bs, kHistSlice));
-    const uint64_t grid = nb64 * spb;
-    if (grid > 0x7FFFFFFFull) return PIVCO_E_UNSUPPORTED;
-    uint32_t *dslh = reinterpret_cast<uint32_t *>(ws + L.slh);
-    hipLaunchKernelGGL(k_hist, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s, in, n,
-                       static_cast<uint32_t>(bs), spb, dh, dslh);
-    HIPCHK(hipGetLastError());
-    if (spb > 1) {
-      hipLaunchKernelGGL(k_slice_prefix, dim3(nb), dim3(256), 0, s, dslh, spb);
-      HIPCHK(hipGetLastError());
-    }
-    HIPCHK(hipMemcpyAsync(hist.data(), dh, hist.size() * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
-
-  // 2. trees and node tables
-  std::vector<HostBlock> hb(nb);
-  std::vector<EncBlock> eb(nb);
-  uint64_t bmp_words = 0;
-  for (uint32_t b = 0; b < nb; ++b) {
-    HostBlock &B = hb[b];
-    B.n = std::min<uint64_t>(bs, n - static_cast<uint64_t>(b) * bs);
-    uint64_t counts[256];
-    int m = 0, last = 0;
-    for (int k = 0; k < 256; ++k) {
-      counts[k] = hist[static_cast<size_t>(b) * 256 + k];
-      if (counts[k]) { ++m; last = k; }
-    }
-    std::memset(B.len, 0, 256);
-    if (!o->tree && m == 1) {
-      B.mode = 1;
-      B.csym = static_cast<uint8_t>(last);
-      std::memset(&eb[b], 0, sizeof(EncBlock));
-      eb[b].n = static_cast<uint32_t>(B.n);
-      eb[b].in_off = static_cast<uint64_t>(b) * bs;
-      continue;
-    }
-    if (o->tree) {
-      std::memcpy(B.len, o->tree->code_len, 256);
-      for (int k = 0; k < 256; ++k)
-        if (counts[k] && !B.len[k]) return PIVCO_E_ARG;
-    } else {
-      const pivco_status st = lengths_from_counts(counts, o->max_len, B.len);
-      if (st) return st;
-    }
-    make_block(B, counts, o->ans_mode, eb[b]);
-    eb[b].in_off = static_cast<uint64_t>(b) * bs;
-    B.bmp_word = bmp_words;
-    eb[b].bmp_word = bmp_words;
-    for (auto &nd : B.nodes) bmp_words += div_up(nd.nv, 32);
-    bmp_words = align_up(bmp_words, 4);
-  }
-  if ((L.rjobs - L.bmp) < 4 * bmp_words + 64) return PIVCO_E_CAPACITY;
-
-  // 3. split: node bitmaps into zeroed scratch
-  uint32_t *dbmp = reinterpret_cast<uint32_t *>(ws + L.bmp);
-  if (nb) {
-    HIPCHK(hipMemcpyAsync(ws + L.blocks, eb.data(), sizeof(EncBlock) * nb, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_zero, dim3(std::min<uint64_t>(8192, div_up(bmp_words + 16, 256))), dim3(256), 0, s,
-                       dbmp, bmp_words + 16);
-    const uint32_t spb = static_cast<uint32_t>(div_up(bs, kHistSlice));
-    hipLaunchKernelGGL(k_split, dim3(static_cast<uint32_t>(nb64 * spb)), dim3(kSplitNT), 0, s, in,
-                       reinterpret_cast<const EncBlock *>(ws + L.blocks), nb, spb,
-                       reinterpret_cast<const uint32_t *>(ws + L.slh), dbmp);
-    HIPCHK(hipGetLastError());
-  }
-
-  // 4. rANS of the selected bitmaps
-  const uint64_t C = 1ull << o->rans_chunk_log2;
-  std::vector<RansJob> rj;
-  uint64_t slot_bytes = 0;
-  for (uint32_t b = 0; b < nb; ++b) {
-    HostBlock &B = hb[b];
-    if (B.mode) continue;
-    B.chunks.assign(B.nodes.size(), {});
-    B.p1q.assign(B.nodes.size(), 0);
-    for (size_t i = 0; i < B.nodes.size(); ++i) {
-      if (!B.nodes[i].kind) continue;
-      B.p1q[i] = p1q_of(B.nodes[i].nv, B.nodes[i].nr);
-      for (uint64_t st = 0; st < B.nodes[i].nv; st += C) {
-        const uint64_t cl = std::min<uint64_t>(C, B.nodes[i].nv - st);
-        RansJob r;
-        r.bmp_word = B.bmp_word + B.word[i] + st / 32;
-        r.slot = slot_bytes;
-        r.nbits = static_cast<uint32_t>(cl);
-        r.p1q = B.p1q[i];
-        B.chunks[i].push_back(static_cast<uint32_t>(rj.size()));
-        rj.push_back(r);
-        slot_bytes += align_up(kChunkHdr + 2 * cl + 4, 16);
-      }
-    }
-  }
-  std::vector<uint32_t> rsize(rj.size(), 0);
-  if (!rj.empty()) {
-    if ((L.rsizes - L.rjobs) < sizeof(RansJob) * rj.size() || (L.staging - L.slots) < slot_bytes)
-      return PIVCO_E_CAPACITY;
-    HIPCHK(hipMemcpyAsync(ws + L.rjobs, rj.data(), sizeof(RansJob) * rj.size(), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_rans_enc, dim3(static_cast<uint32_t>(div_up(rj.size(), 4))), dim3(256), 0, s,
-                       reinterpret_cast<const RansJob *>(ws + L.rjobs), static_cast<uint32_t>(rj.size()),
-                       dbmp, ws + L.slots, reinterpret_cast<uint32_t *>(ws + L.rsizes));
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(rsize.data(), ws + L.rsizes, 4 * rsize.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
-
-  // 5. final layout: headers in a host staging buffer, copy descriptors
-  std::vector<uint8_t> stg;
-  std::vector<CopyDesc> desc;
-  const uint64_t tab = kHeaderBytes + 16ull * (nb + 1);
-  stg.resize(tab, 0);
-  put32(&stg[0], kMagic);
-  put16(&stg[4], 1);
-  put16(&stg[6], 0);
-  put64(&stg[8], n);
-  put32(&stg[16], static_cast<uint32_t>(bs));
-  put32(&stg[20], nb);
-  stg[24] = static_cast<uint8_t>(o->max_len);
-  stg[25] = static_cast<uint8_t>(o->rans_chunk_log2);
-  desc.push_back({L.staging, 0, tab});
-  uint64_t off = tab, ans_total = 0;
-  for (uint32_t b = 0; b < nb; ++b) {
-    HostBlock &B = hb[b];
-    put64(&stg[kHeaderBytes + 8ull * b], off);
-    put64(&stg[kHeaderBytes + 8ull * (nb + 1) + 8ull * b], ans_total);
-    const uint32_t cw = B.n <= 65535 ? 2 : 4;
-    const uint64_t hstart = stg.size();
-    if (B.mode == 1) {
-      stg.resize(hstart + 12, 0);
-      put32(&stg[hstart], 12);
-      put32(&stg[hstart + 4], static_cast<uint32_t>(B.n));
-      stg[hstart + 8] = 1;
-      stg[hstart + 9] = B.csym;
-      stg[hstart + 10] = static_cast<uint8_t>(cw);
-      desc.push_back({L.staging + hstart, off, 12});
-      off = align_up(off + 12, 4);
-      continue;
-    }
-    const uint32_t I = static_cast<uint32_t>(B.nodes.size());
-    const uint32_t kb = (I + 7) / 8;
-    const uint64_t hlen = 12 + 128 + kb + uint64_t(cw) * I;
-    stg.resize(hstart + hlen, 0);
-    uint8_t *h = &stg[hstart];
-    put32(h + 4, static_cast<uint32_t>(B.n));
-    h[10] = static_cast<uint8_t>(cw);
-    for (int j = 0; j < 128; ++j) h[12 + j] = static_cast<uint8_t>(B.len[2 * j] | (B.len[2 * j + 1] << 4));
-    for (uint32_t i = 0; i < I; ++i) {
-      if (B.nodes[i].kind) h[140 + i / 8] |= static_cast<uint8_t>(1u << (i % 8));
-      if (cw == 2) put16(h + 140 + kb + 2 * i, static_cast<uint32_t>(B.nodes[i].nr));
-      else put32(h + 140 + kb + 4 * i, static_cast<uint32_t>(B.nodes[i].nr));
-    }
-    uint64_t o2 = hlen;               // offset within the block
-    for (uint32_t i = 0; i < I; ++i) {
-      if (B.nodes[i].kind) continue;
-      const uint64_t nbytes = div_up(B.nodes[i].nv, 8);
-      if (nbytes) desc.push_back({L.bmp + 4 * (B.bmp_word + B.word[i]), off + o2, nbytes});
-      o2 += nbytes;
-    }
-    for (uint32_t i = 0; i < I; ++i) {
-      if (!B.nodes[i].kind) continue;
-      o2 = align_up(o2, 4);
-      uint64_t blen = 0;
-      for (uint32_t c : B.chunks[i]) blen += rsize[c];
-      const uint64_t bh = stg.size();
-      stg.resize(bh + 8, 0);
-      put16(&stg[bh], B.p1q[i]);
-      put32(&stg[bh + 4], static_cast<uint32_t>(blen));
-      desc.push_back({L.staging + bh, off + o2, 8});
-      o2 += 8;
-      for (uint32_t c : B.chunks[i]) {
-        desc.push_back({L.slots + rj[c].slot, off + o2, rsize[c]});
-        o2 += rsize[c];
-      }
-      ans_total += div_up(B.nodes[i].nv, 32);
-    }
-    put32(&stg[hstart], static_cast<uint32_t>(o2));
-    desc.push_back({L.staging + hstart, off, hlen});
-    off = align_up(off + o2, 4);
-  }
-  put64(&stg[kHeaderBytes + 8ull * nb], off);
-  put64(&stg[kHeaderBytes + 8ull * (nb + 1) + 8ull * nb], ans_total);
-  put64(&stg[32], ans_total);
-  // the header table was queued first with the final values now in place
-  if (off > out_cap) return PIVCO_E_CAPACITY;
-  if (stg.size() > L.desc - L.staging || sizeof(CopyDesc) * desc.size() > L.total - L.desc)
-    return PIVCO_E_CAPACITY;
-
-  // 6. assemble
-  HIPCHK(hipMemcpyAsync(ws + L.staging, stg.data(), stg.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ws + L.desc, desc.data(), sizeof(CopyDesc) * desc.size(), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_fill_zero, dim3(std::min<uint64_t>(8192, div_up(off / 4 + 1, 256))), dim3(256), 0, s,
-                     reinterpret_cast<uint32_t *>(out), off / 4);
-  hipLaunchKernelGGL(k_copy, dim3(static_cast<uint32_t>(std::min<uint64_t>(65535, div_up(desc.size(), 4)))),
-                     dim3(256), 0, s, reinterpret_cast<const CopyDesc *>(ws + L.desc),
-                     static_cast<uint64_t>(desc.size()), ws, out);
+  uint32_t *dh = reinterpret_cast<uint32_t *>(ws + L.hist);
+  uint32_t *dslh = reinterpret_cast<uint32_t *>(ws + L.slh);
+  hipLaunchKernelGGL(k_fill_zero, dim3(std::min<uint64_t>(4096, div_up(nb64 * 256, 256))), dim3(256), 0, s,
+                     dh, nb64 * 256);
+  hipLaunchKernelGGL(k_hist, dim3(nb * spb), dim3(256), 0, s, in, n, static_cast<uint32_t>(bs), spb, dh, dslh);
   HIPCHK(hipGetLastError());
+  if (spb > 1) hipLaunchKernelGGL(k_slice_prefix, dim3(nb), dim3(256), 0, s, dslh, spb);
+  HIPCHK(hipMemcpyAsync(hist.data(), dh, hist.size() * 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  *h_out_len = off;
+
+  // 2. code lengths (host)
+  std::vector<uint8_t> lenm;
+  std::vector<uint32_t> modes;
+  const pivco_status st = build_trees(hist, nb, o, lenm, modes);
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(ws + L.lenm, lenm.data(), lenm.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + L.modes, modes.data(), 4ull * nb, hipMemcpyHostToDevice, s));
+
+  // 3.-4. layout and offsets
+  const uint32_t gl = (nb + kLayoutWaves - 1) / kLayoutWaves;
+  hipLaunchKernelGGL(k_layout, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, ws + L.lenm,
+                     reinterpret_cast<const uint32_t *>(ws + L.modes), dh, nb, n, static_cast<uint32_t>(bs),
+                     o->ans_mode, o->rans_chunk_log2, deb, dlay, drn, ws + L.hdr);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanNT), 0, s, dlay, nb, dtot);
+  uint32_t *dimg = reinterpret_cast<uint32_t *>(ws + L.img);
+  uint32_t *drbm = reinterpret_cast<uint32_t *>(ws + L.rbm);
+  hipLaunchKernelGGL(k_zero_areas, dim3(4096), dim3(256), 0, s, dimg, drbm, dtot);
+  HIPCHK(hipGetLastError());
+
+  // 5. bitmaps
+  hipLaunchKernelGGL(k_split, dim3(nb * spb), dim3(kSplitNT), 0, s, in, deb, dlay, nb, spb, dslh, dimg, drbm);
+  HIPCHK(hipGetLastError());
+
+  // 6. rANS chunks
+  const bool ans = o->ans_mode != 0;
+  if (ans) {
+    hipLaunchKernelGGL(k_chunks, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, dlay, drn, nb,
+                       o->rans_chunk_log2, djobs);
+    hipLaunchKernelGGL(k_rans_enc, dim3(2048), dim3(256), 0, s, djobs, dtot, drbm, ws + L.slots, dsizes);
+    HIPCHK(hipGetLastError());
+  }
+
+  // 7. sizes and offsets
+  hipLaunchKernelGGL(k_sizes, dim3((nb + 255) / 256), dim3(256), 0, s, dlay, drn, djobs, dsizes, nb,
+                     o->rans_chunk_log2, ws + L.hdr);
+  hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kScanNT), 0, s, dlay, nb, dtot);
+
+  // 8. the stream (nothing is written when it would not fit)
+  hipLaunchKernelGGL(k_stream_head, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, dlay, dtot, nb, n,
+                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2, out, out_cap);
+  const uint64_t max_words = (kHdrStride + bs * o->max_len / 8 + 255 + 4) / 4 + 1;
+  const uint32_t segs = static_cast<uint32_t>(div_up(max_words, kAsmSeg));
+  if (static_cast<uint64_t>(nb) * segs > 0x7FFFFFFFull) return PIVCO_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_assemble, dim3(nb * segs), dim3(256), 0, s, dlay, dtot, nb, segs, ws + L.hdr,
+                     ws + L.img, out, out_cap);
+  if (ans)
+    hipLaunchKernelGGL(k_assemble_rans, dim3(2048), dim3(256), 0, s, dlay, drn, djobs, dsizes, dtot,
+                       ws + L.slots, out, out_cap);
+  HIPCHK(hipGetLastError());
+  uint64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, &dtot->out_bytes, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (total > out_cap) return PIVCO_E_CAPACITY;
+  *h_out_len = total;
   return PIVCO_OK;
 }
 

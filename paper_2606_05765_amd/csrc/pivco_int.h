@@ -222,6 +222,11 @@ hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const v
                        const uint2 *ritems, Counters *ctr, const RansChunk *chunks,
                        uint64_t chunk_cap, uint32_t *scratch, int32_t single);
 int rans_occupancy();
+// Top-down decode of the same work items (ablation of the merge kernel).
+hipError_t launch_topdown(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,
+                          const void *recs, const TiledBlock *tiled, const uint2 *tab,
+                          uint32_t n_items, Counters *ctr, const uint32_t *scratch, int32_t single);
+int topdown_occupancy();
 hipError_t launch_init(hipStream_t s, Counters *ctr, int32_t *status, const int32_t *status0,
                        uint32_t count);
 hipError_t launch_gather_headers(hipStream_t s, const pivco_job *jobs, uint32_t count, uint8_t *hdr);

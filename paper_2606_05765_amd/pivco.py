@@ -97,6 +97,7 @@ def lib():
             "pivco_decode_batch": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
             "pivco_decode": (i32, [vp, u64, vp, u64, vp, vp, u64, vp]),
             "pivco_decode_plain": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
+            "pivco_decode_topdown": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
             "pivco_decode_noalloc": (i32, [vp, u64, vp, u64, vp, vp]),
             "pivco_merge_variants": (u32, []),
             "pivco_merge_variant_name": (C.c_char_p, [u32]),
@@ -106,6 +107,12 @@ def lib():
             "pivco_batch_plan_launch_timed": (i32, [vp, vp, vp, vp]),
             "pivco_batch_plan_destroy": (None, [vp]),
             "pivco_autotune": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp, C.POINTER(Tune)]),
+            "pivco_autotune_cache_clear": (None, []),
+            "pivco_golomb_encode_bound": (u64, [u64, u32]),
+            "pivco_golomb_encode_workspace": (u64, [u64, u32]),
+            "pivco_golomb_encode": (i32, [vp, u64, u32, vp, u64, u64p, vp, u64, vp]),
+            "pivco_golomb_decode_workspace": (u64, [C.POINTER(Job), u32, vp]),
+            "pivco_golomb_decode": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
             "pivco_strerror": (C.c_char_p, [i32]),
             "pivco_server_create": (i32, [C.POINTER(ServerOpts), C.POINTER(vp)]),
             "pivco_server_destroy": (None, [vp]),
@@ -243,7 +250,7 @@ class Workspace:
         return self.tensor.numel()
 
 
-def pivco_decode_batch(streams, outs=None, ws=None, plain=False):
+def pivco_decode_batch(streams, outs=None, ws=None, plain=False, entry="pivco_decode_batch"):
     """Decode a list of streams in one batched launch.  Returns (outs, status)
     where status is a CPU int32 numpy array (one pivco status per job)."""
     streams = [_dev_u8(s) for s in streams]
@@ -252,10 +259,15 @@ def pivco_decode_batch(streams, outs=None, ws=None, plain=False):
     if ws is None:
         ws = Workspace(pivco_decode_workspace(streams, outs))
     status = torch.zeros(max(len(streams), 1), dtype=torch.int32, device="cuda")
-    f = lib().pivco_decode_plain if plain else lib().pivco_decode_batch
-    _check(f(jobs, len(streams), C.c_void_p(status.data_ptr()), ws.ptr, ws.nbytes, _stream()),
-           "pivco_decode_plain" if plain else "pivco_decode_batch")
+    name = "pivco_decode_plain" if plain else entry
+    _check(getattr(lib(), name)(jobs, len(streams), C.c_void_p(status.data_ptr()), ws.ptr, ws.nbytes,
+                                _stream()), name)
     return outs, status[:len(streams)].cpu().numpy()
+
+
+def pivco_decode_topdown(streams, outs=None, ws=None):
+    """The top-down (partition/scatter) decode of the same streams."""
+    return pivco_decode_batch(streams, outs, ws=ws, entry="pivco_decode_topdown")
 
 
 def pivco_decode(stream, out=None, ws=None):
@@ -298,6 +310,10 @@ def pivco_autotune(streams, outs, ws=None):
     _check(lib().pivco_autotune(jobs, len(streams), C.c_void_p(status.data_ptr()), ws.ptr,
                                 ws.nbytes, _stream(), C.byref(t)), "pivco_autotune")
     return t
+
+
+def pivco_autotune_cache_clear():
+    lib().pivco_autotune_cache_clear()
 
 
 class BatchPlan:
@@ -401,3 +417,43 @@ def view_output(pool, d_out, n):
     """The decoded bytes of one served request as a tensor view into pool."""
     off = int(d_out) - pool.data_ptr()
     return pool[off:off + n]
+
+
+# ---------------------------------------------------------------------------
+# PivCo-Golomb (App. G): unary codes in the pivoted list-of-bitmaps layout
+# ---------------------------------------------------------------------------
+
+def pivco_golomb_encode(data, block_size):
+    """Encode a uint8 CUDA tensor of values; returns the stream (CUDA tensor)."""
+    data = _dev_u8(data)
+    n = data.numel()
+    cap = int(lib().pivco_golomb_encode_bound(n, block_size))
+    wsb = int(lib().pivco_golomb_encode_workspace(n, block_size))
+    if cap == 0:
+        raise PivcoError(E_ARG, "pivco_golomb_encode_bound")
+    out = torch.empty(cap, dtype=torch.uint8, device=data.device)
+    ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=data.device)
+    olen = C.c_uint64(0)
+    _check(lib().pivco_golomb_encode(C.c_void_p(data.data_ptr() if n else 0), n, block_size,
+                                     C.c_void_p(out.data_ptr()), cap, C.byref(olen),
+                                     C.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+           "pivco_golomb_encode")
+    return out[:olen.value].clone()
+
+
+def pivco_golomb_decode(streams, outs=None):
+    """Decode PivCo-Golomb streams in one launch; returns (outs, status)."""
+    streams = [_dev_u8(s) for s in streams]
+    if outs is None:
+        outs = []
+        for s in streams:
+            n = int.from_bytes(bytes(s[8:16].cpu().numpy().tobytes()), "little")
+            outs.append(torch.empty(n, dtype=torch.uint8, device=s.device))
+    outs = [_dev_u8(o) for o in outs]
+    jobs = _jobs(streams, outs)
+    wsb = int(lib().pivco_golomb_decode_workspace(jobs, len(streams), _stream()))
+    ws = Workspace(wsb)
+    status = torch.zeros(max(len(streams), 1), dtype=torch.int32, device="cuda")
+    _check(lib().pivco_golomb_decode(jobs, len(streams), C.c_void_p(status.data_ptr()), ws.ptr,
+                                     ws.nbytes, _stream()), "pivco_golomb_decode")
+    return outs, status[:len(streams)].cpu().numpy()

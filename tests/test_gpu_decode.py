@@ -102,8 +102,11 @@ def test_every_merge_variant():
 def test_autotune_choice_is_correct():
     cs, streams, wants = _batch()
     outs = [torch.empty(w.size, dtype=torch.uint8, device="cuda") for w in wants]
+    P.pivco_autotune_cache_clear()
     t = P.pivco_autotune(streams, outs)
     assert t.merge_variant < len(P.pivco_merge_variants()) and t.merge_grid >= 1
+    again = P.pivco_autotune(streams, outs)               # the same bucket: cached choice
+    assert again.as_dict() == t.as_dict()
     plan = P.BatchPlan(streams, outs, tune=t)
     plan.launch()
     torch.cuda.synchronize()
