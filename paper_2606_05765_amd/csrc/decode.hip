@@ -132,14 +132,17 @@ struct BlockHdr {
 static_assert(offsetof(BlockHdr, job) == offsetof(BlockExt, job) && sizeof(BlockExt) == 48, "BlockExt prefix");
 
 // Per-node tables (breadth-first node ids).
+// Field order: what a tile of a split block needs first (bodies, children,
+// kinds, depths), then the sizes a whole block needs, then what only the
+// plan kernel uses; the merge kernel copies only the prefix it needs.
 struct NodeTab {
-  uint32_t nv[256];        // symbols passing the node
-  uint32_t nr[256];        // of which go right (1 bits)
   uint32_t boff[256];      // raw: byte offset of the body in the block;
                            // rANS: word offset in the block's scratch
   uint16_t child[256][2];  // internal id, or 0x8000 | symbol for a leaf
   uint8_t kind[256];       // 1 = rANS-coded
   uint8_t depth[256];
+  uint32_t nv[256];        // symbols passing the node
+  uint32_t nr[256];        // of which go right (1 bits)
   uint8_t len[256];
   uint8_t leafsym[256];    // symbols ordered by (length, symbol)
 };
@@ -151,6 +154,13 @@ struct alignas(16) ParsedBlock {
   NodeTab t;
 };
 static_assert(sizeof(ParsedBlock) == kParsedBlockBytes, "ParsedBlock layout");
+// Bytes of the record a whole block needs (all but the plan kernel's own
+// tables) and a tile of a split block needs (its shares come from the
+// boundary table, not from the node sizes).
+constexpr uint32_t kRecWhole16 = (offsetof(ParsedBlock, t) + offsetof(NodeTab, len) + 15) / 16;
+constexpr uint32_t kRecTile16 = (offsetof(ParsedBlock, t) + offsetof(NodeTab, nv) + 15) / 16;
+static_assert(offsetof(ParsedBlock, t) % 16 == 0 && offsetof(NodeTab, nv) % 16 == 0 &&
+              offsetof(NodeTab, len) % 16 == 0, "record prefixes in 16-byte units");
 
 // Byte readers for block-relative offsets: the block in global memory, or
 // a copy of it in LDS.
@@ -1239,7 +1249,7 @@ __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockE
   const int tid = item_tid();
   const int wave = wave_id();
   const uint32_t lane = lane_id();
-  constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
+  constexpr uint32_t kRec16 = kRecWhole16;
   const uint8_t *rb = reinterpret_cast<const uint8_t *>(rec);
   uint32_t *pbw = reinterpret_cast<uint32_t *>(&sm.pb);
   for (uint32_t base = kWave * wave; base < kRec16; base += kWave * C::NW)
@@ -1314,7 +1324,7 @@ __device__ void warm_next(MergeSmem<C> &sm) {
   const uint64_t blk = sm.nxt.blk, end = sm.nxt.end;
   // every load is issued before any is consumed (one memory round trip)
   constexpr int NB = (C::BODY + 127) / (128 * kWave) + 1;            // lines per lane: block
-  constexpr int NR = (sizeof(ParsedBlock) + 128 * kWave - 1) / (128 * kWave);   // and record
+  constexpr int NR = (16 * kRecWhole16 + 128 * kWave - 1) / (128 * kWave);        // and record
   uint32_t v[NB + NR];
   const bool fits = end > blk && end - blk <= static_cast<uint64_t>(C::BODY);
   const uint64_t a0 = (blk & ~127ull) + 128ull * lane;
@@ -1326,7 +1336,7 @@ __device__ void warm_next(MergeSmem<C> &sm) {
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const uint32_t a = 128 * (lane + kWave * k);
-    v[NB + k] = a < sizeof(ParsedBlock) ? *reinterpret_cast<const uint32_t *>(rec + a) : 0u;
+    v[NB + k] = a < 16 * kRecWhole16 ? *reinterpret_cast<const uint32_t *>(rec + a) : 0u;
   }
   uint32_t acc = 0;
 #pragma unroll
@@ -1547,7 +1557,7 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
   const int tid = item_tid();
   const int wave = wave_id();
   const uint32_t lane = lane_id();
-  constexpr uint32_t kRec16 = sizeof(ParsedBlock) / 16;
+  constexpr uint32_t kRec16 = kRecTile16;
   const uint8_t *rb = reinterpret_cast<const uint8_t *>(rec);
   uint32_t *pbw = reinterpret_cast<uint32_t *>(&sm.pb);
   for (uint32_t base = kWave * wave; base < kRec16; base += kWave * C::NW)
