@@ -33,6 +33,14 @@
  *     end of its last body.
  *   Internal nodes are numbered breadth-first: by depth, then left to right.
  *   Bit 0 = left child, bit 1 = right child (Listing 1).
+ *
+ * Wire format v2 (version u16 = 2) is v1 with the flat-subtree tree of
+ * Sec. 2.2.3-2.2.4 in place of the canonical one, derived from the same
+ * length table (build_flat_tree).  Its nodes are numbered the same way; a
+ * flat node of depth D keeps n_right = 0 and kind 0, and its raw body is
+ * ceil(n_v D / 8) bytes holding one D-bit field per passing symbol, field j
+ * at bits [jD, jD + D) (LSB first; bit k of the field is bit k of the
+ * value), whose value is the index of the symbol in the node's group.
  */
 #include "pivco_ref.h"
 
@@ -177,6 +185,8 @@ int pivco_ref_codes(const uint8_t len[256], uint16_t code[256]) {
 /* ------------------------------------------------------------------ */
 typedef struct {
     int leaf, sym, child[2], depth;
+    int flat, g0;        /* flat node: its depth D >= 2 and its group's first
+                            index in tree_t.order; 0 for other nodes */
     int id;              /* breadth-first index among internal nodes */
     uint64_t n, n_right; /* symbols passing / symbols going right */
 } tnode;
@@ -186,61 +196,177 @@ typedef struct {
     int nn;
     int bfs[255];        /* node index of internal node i (BFS order) */
     int ni;              /* number of internal nodes */
+    uint16_t code[256];  /* every symbol's code: the branch bits of its path
+                            from the root, then (below a flat node) its
+                            index in the node's group, D bits */
+    uint8_t order[256];  /* symbols ordered by (length, symbol) */
 } tree_t;
 
-/* Returns 0 if the lengths form a complete prefix code (Kraft sum == 1) with
- * at least two symbols, and builds the tree. */
-static int build_tree(const uint8_t len[256], tree_t *t) {
-    uint64_t kraft = 0;
-    int m = 0;
-    for (int s = 0; s < 256; s++) {
-        if (len[s] > 15) return PVO_E_CORRUPT;
-        if (len[s]) { kraft += (uint64_t)1 << (15 - len[s]); m++; }
-    }
-    if (m < 2 || kraft != ((uint64_t)1 << 15)) return PVO_E_CORRUPT;
-    uint16_t code[256];
-    if (pivco_ref_codes(len, code)) return PVO_E_CORRUPT;
-    memset(t, 0, sizeof(*t));
-    t->nn = 1;
-    t->nd[0].leaf = 0; t->nd[0].child[0] = t->nd[0].child[1] = -1; t->nd[0].depth = 0;
-    for (int s = 0; s < 256; s++) {
-        if (!len[s]) continue;
-        int cur = 0;
-        for (int d = 0; d < len[s]; d++) {
-            int b = (code[s] >> (len[s] - 1 - d)) & 1;
-            if (t->nd[cur].leaf) return PVO_E_CORRUPT;
-            int c = t->nd[cur].child[b];
-            if (d == len[s] - 1) {
-                if (c != -1) return PVO_E_CORRUPT;
-                c = t->nn++;
-                t->nd[c].leaf = 1; t->nd[c].sym = s; t->nd[c].depth = d + 1;
-                t->nd[c].child[0] = t->nd[c].child[1] = -1;
-                t->nd[cur].child[b] = c;
-            } else {
-                if (c == -1) {
-                    c = t->nn++;
-                    t->nd[c].leaf = 0; t->nd[c].depth = d + 1;
-                    t->nd[c].child[0] = t->nd[c].child[1] = -1;
-                    t->nd[cur].child[b] = c;
-                }
-                cur = c;
-            }
-        }
-    }
-    /* breadth-first numbering of internal nodes */
+/* Breadth-first numbering of the internal nodes (binary and flat; a flat
+ * node's leaves are not nodes of the tree).  Every binary node must have two
+ * children. */
+static int number_nodes(tree_t *t) {
     int queue[MAXNODE], qh = 0, qt = 0;
     queue[qt++] = 0;
     t->ni = 0;
     while (qh < qt) {
         int v = queue[qh++];
         if (t->nd[v].leaf) continue;
-        if (t->nd[v].child[0] < 0 || t->nd[v].child[1] < 0) return PVO_E_CORRUPT;
         t->nd[v].id = t->ni;
         t->bfs[t->ni++] = v;
+        if (t->nd[v].flat) continue;
+        if (t->nd[v].child[0] < 0 || t->nd[v].child[1] < 0) return PVO_E_CORRUPT;
         queue[qt++] = t->nd[v].child[0];
         queue[qt++] = t->nd[v].child[1];
     }
-    return (t->ni == m - 1) ? PVO_OK : PVO_E_CORRUPT;
+    return PVO_OK;
+}
+
+static int new_node(tree_t *t, int depth) {
+    int c = t->nn++;
+    memset(&t->nd[c], 0, sizeof(tnode));
+    t->nd[c].child[0] = t->nd[c].child[1] = -1;
+    t->nd[c].depth = depth;
+    return c;
+}
+
+/* Kraft sum of the lengths == 1 with at least two symbols. */
+static int complete_code(const uint8_t len[256]) {
+    uint64_t kraft = 0;
+    int m = 0;
+    for (int s = 0; s < 256; s++) {
+        if (len[s] > 15) return 0;
+        if (len[s]) { kraft += (uint64_t)1 << (15 - len[s]); m++; }
+    }
+    return m >= 2 && kraft == ((uint64_t)1 << 15);
+}
+
+/* Returns 0 if the lengths form a complete prefix code (Kraft sum == 1) with
+ * at least two symbols, and builds the canonical code tree. */
+static int build_tree(const uint8_t len[256], tree_t *t) {
+    if (!complete_code(len)) return PVO_E_CORRUPT;
+    memset(t, 0, sizeof(*t));
+    if (pivco_ref_codes(len, t->code)) return PVO_E_CORRUPT;
+    int no = 0;
+    for (int l = 1; l <= 15; l++)
+        for (int s = 0; s < 256; s++) if (len[s] == l) t->order[no++] = (uint8_t)s;
+    new_node(t, 0);
+    for (int s = 0; s < 256; s++) {
+        if (!len[s]) continue;
+        int cur = 0;
+        for (int d = 0; d < len[s]; d++) {
+            int b = (t->code[s] >> (len[s] - 1 - d)) & 1;
+            if (t->nd[cur].leaf) return PVO_E_CORRUPT;
+            int c = t->nd[cur].child[b];
+            if (d == len[s] - 1) {
+                if (c != -1) return PVO_E_CORRUPT;
+                c = new_node(t, d + 1);
+                t->nd[c].leaf = 1; t->nd[c].sym = s;
+                t->nd[cur].child[b] = c;
+            } else {
+                if (c == -1) { c = new_node(t, d + 1); t->nd[cur].child[b] = c; }
+                cur = c;
+            }
+        }
+    }
+    if (number_nodes(t)) return PVO_E_CORRUPT;
+    return (t->ni == no - 1) ? PVO_OK : PVO_E_CORRUPT;
+}
+
+/* ------------------------------------------------------------------ */
+/* Flat-subtree tree (Sec. 2.2.3 and 2.2.4)                            */
+/* ------------------------------------------------------------------ */
+/* The regrouping of Sec. 2.2.4, applied once the code lengths are fixed:
+ * the symbols of each length, in ascending order, are cut into groups, each
+ * the largest power of two of the symbols still left.  A group of 2^D
+ * symbols of length l stands for one subtree of depth D whose leaves all
+ * have length l, hanging at depth l - D.  These groups ("items") take
+ * canonical codes of their own depths, ordered by (depth, D descending), so
+ * the tree has the same code lengths as the canonical one and, usually, a
+ * different shape.  An item with D >= 2 is a flat node (Sec. 2.2.3): it
+ * keeps one D-bit value per passing symbol, the symbol's index in the group.
+ * An item with D = 1 is an ordinary internal node with two leaf children; an
+ * item with D = 0 is a leaf.  Grouping keeps the Kraft sum, so the items
+ * form a complete code. */
+typedef struct { int depth, d, first; } item_t;   /* first: index into order[] */
+
+static int flat_items(const uint8_t len[256], uint8_t order[256], item_t *it) {
+    int no = 0, n = 0;
+    for (int l = 1; l <= 15; l++) {
+        int pos = no;
+        for (int s = 0; s < 256; s++) if (len[s] == l) order[no++] = (uint8_t)s;
+        int left = no - pos;
+        while (left > 0) {
+            int d = 0;
+            while ((2 << d) <= left) d++;          /* 2^d: largest power of two <= left */
+            it[n].depth = l - d; it[n].d = d; it[n].first = pos; n++;
+            pos += 1 << d;
+            left -= 1 << d;
+        }
+    }
+    /* (depth ascending, D descending); stable insertion sort */
+    for (int i = 1; i < n; i++) {
+        item_t x = it[i];
+        int j = i - 1;
+        while (j >= 0 && (it[j].depth > x.depth || (it[j].depth == x.depth && it[j].d < x.d))) {
+            it[j + 1] = it[j];
+            j--;
+        }
+        it[j + 1] = x;
+    }
+    return n;
+}
+
+/* Canonical codes of the items: the first is 0; the next is (previous + 1)
+ * shifted left by the growth in depth. */
+static void item_codes(const item_t *it, int n, uint32_t *code) {
+    uint32_t c = 0;
+    for (int i = 0; i < n; i++) {
+        if (i) c = (c + 1) << (it[i].depth - it[i - 1].depth);
+        code[i] = c;
+    }
+}
+
+static int build_flat_tree(const uint8_t len[256], tree_t *t) {
+    if (!complete_code(len)) return PVO_E_CORRUPT;
+    memset(t, 0, sizeof(*t));
+    item_t it[256];
+    uint32_t icode[256];
+    int n = flat_items(len, t->order, it);
+    item_codes(it, n, icode);
+    new_node(t, 0);
+    for (int i = 0; i < n; i++) {
+        const item_t *x = &it[i];
+        if (icode[i] >> x->depth) return PVO_E_CORRUPT;     /* over-subscribed */
+        int cur = 0;
+        for (int k = 0; k < x->depth; k++) {
+            int b = (icode[i] >> (x->depth - 1 - k)) & 1;
+            if (t->nd[cur].leaf || t->nd[cur].flat) return PVO_E_CORRUPT;
+            int c = t->nd[cur].child[b];
+            if (c == -1) { c = new_node(t, k + 1); t->nd[cur].child[b] = c; }
+            cur = c;
+        }
+        tnode *v = &t->nd[cur];
+        if (v->leaf || v->flat || v->child[0] != -1 || v->child[1] != -1) return PVO_E_CORRUPT;
+        if (x->d == 0) {
+            v->leaf = 1;
+            v->sym = t->order[x->first];
+        } else if (x->d == 1) {
+            for (int b = 0; b < 2; b++) {
+                int c = new_node(t, x->depth + 1);
+                t->nd[c].leaf = 1;
+                t->nd[c].sym = t->order[x->first + b];
+                t->nd[cur].child[b] = c;
+            }
+        } else {
+            v->flat = x->d;
+            v->g0 = x->first;
+        }
+        /* a symbol's code: the item's code, then its index in the group */
+        for (int q = 0; q < (1 << x->d); q++)
+            t->code[t->order[x->first + q]] = (uint16_t)((icode[i] << x->d) | (uint32_t)q);
+    }
+    return number_nodes(t);
 }
 
 /* ------------------------------------------------------------------ */
@@ -366,8 +492,11 @@ uint64_t pivco_ref_encode_bound(uint64_t n, uint32_t block_size, uint32_t ans_mo
     return b;
 }
 
+/* Bits a node's raw body holds: one per passing symbol, D for a flat node. */
+static uint64_t body_bits(const tnode *v) { return v->flat ? v->n * (uint64_t)v->flat : v->n; }
+
 static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_t ans_mode,
-                        uint32_t chunk_log2, const uint8_t *tree_len, uint8_t *out,
+                        uint32_t chunk_log2, const uint8_t *tree_len, int flat, uint8_t *out,
                         uint64_t cap, uint64_t *out_len, uint64_t *ans_words) {
     uint64_t counts[256];
     memset(counts, 0, sizeof(counts));
@@ -395,16 +524,17 @@ static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_
         if (r) return r;
     }
     tree_t *t = (tree_t *)malloc(sizeof(tree_t));
-    if (build_tree(len, t)) { free(t); return PVO_E_ARG; }
-    uint16_t code[256];
-    pivco_ref_codes(len, code);
-    /* n_v and n_right from the symbol counts */
+    if (flat ? build_flat_tree(len, t) : build_tree(len, t)) { free(t); return PVO_E_ARG; }
+    const uint16_t *code = t->code;
+    /* n_v and n_right from the symbol counts: a symbol passes every node on
+     * its path; below a flat node there are no more nodes */
     for (int s = 0; s < 256; s++) {
         if (!len[s] || !counts[s]) continue;
         int cur = 0;
-        for (int d = 0; d < len[s]; d++) {
-            int b = (code[s] >> (len[s] - 1 - d)) & 1;
+        for (int d = 0; !t->nd[cur].leaf; d++) {
             t->nd[cur].n += counts[s];
+            if (t->nd[cur].flat) break;
+            int b = (code[s] >> (len[s] - 1 - d)) & 1;
             if (b) t->nd[cur].n_right += counts[s];
             cur = t->nd[cur].child[b];
         }
@@ -413,18 +543,28 @@ static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_
     uint8_t *bm[255];
     uint64_t cur_pos[255];
     for (int i = 0; i < I; i++) {
-        bm[i] = (uint8_t *)calloc((size_t)((t->nd[t->bfs[i]].n + 7) / 8 + 1), 1);
+        bm[i] = (uint8_t *)calloc((size_t)((body_bits(&t->nd[t->bfs[i]]) + 7) / 8 + 1), 1);
         cur_pos[i] = 0;
     }
-    /* bitmaps: each symbol appends one bit to every internal node on its path */
+    /* bitmaps: each symbol appends one bit to every binary node on its path
+     * (the branch it takes) and, at a flat node of depth D, the D bits of its
+     * index in the node's group (the packN step of Table 11) */
     for (uint64_t i = 0; i < n; i++) {
         int s = in[i], cur = 0;
-        for (int d = 0; d < len[s]; d++) {
+        for (int d = 0; !t->nd[cur].leaf; d++) {
+            const tnode *v = &t->nd[cur];
+            int id = v->id;
+            if (v->flat) {
+                uint32_t q = code[s] & ((1u << v->flat) - 1);
+                for (int k = 0; k < v->flat; k++)
+                    if ((q >> k) & 1) setbit(bm[id], cur_pos[id] * (uint64_t)v->flat + (uint64_t)k);
+                cur_pos[id]++;
+                break;
+            }
             int b = (code[s] >> (len[s] - 1 - d)) & 1;
-            int id = t->nd[cur].id;
             if (b) setbit(bm[id], cur_pos[id]);
             cur_pos[id]++;
-            cur = t->nd[cur].child[b];
+            cur = v->child[b];
         }
     }
     int rc = PVO_OK;
@@ -436,7 +576,7 @@ static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_
     uint8_t kind[255];
     for (int i = 0; i < I; i++) {
         tnode *v = &t->nd[t->bfs[i]];
-        kind[i] = (uint8_t)pivco_ref_select_ans(ans_mode, v->n, v->n_right);
+        kind[i] = v->flat ? 0 : (uint8_t)pivco_ref_select_ans(ans_mode, v->n, v->n_right);
     }
     uint64_t kb = ((uint64_t)I + 7) / 8;
     if (o + kb + (uint64_t)cw * I > cap) { rc = PVO_E_CAPACITY; goto done; }
@@ -450,7 +590,7 @@ static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_
     }
     for (int i = 0; i < I; i++) {
         if (kind[i]) continue;
-        uint64_t nb = (t->nd[t->bfs[i]].n + 7) / 8;
+        uint64_t nb = (body_bits(&t->nd[t->bfs[i]]) + 7) / 8;
         if (o + nb > cap) { rc = PVO_E_CAPACITY; goto done; }
         memcpy(out + o, bm[i], (size_t)nb);
         o += nb;
@@ -476,10 +616,10 @@ done:
     return rc;
 }
 
-int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
-                     uint32_t max_len, uint32_t ans_mode, uint32_t chunk_log2,
-                     const uint8_t *tree_len, uint8_t *out, uint64_t cap,
-                     uint64_t *out_len) {
+static int encode_stream(const uint8_t *in, uint64_t n, uint32_t block_size,
+                         uint32_t max_len, uint32_t ans_mode, uint32_t chunk_log2,
+                         const uint8_t *tree_len, int flat, uint8_t *out, uint64_t cap,
+                         uint64_t *out_len) {
     if ((!in && n) || !out || !out_len || block_size == 0 || max_len < 1 || max_len > 15 ||
         ans_mode > 2 || chunk_log2 < 5 || chunk_log2 > 24)
         return PVO_E_ARG;
@@ -490,7 +630,7 @@ int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
     if (o > cap) return PVO_E_CAPACITY;
     memset(out, 0, (size_t)o);
     put32(out, 0x31435650u);  /* "PVC1" */
-    put16(out + 4, 1); put16(out + 6, 0);
+    put16(out + 4, flat ? 2 : 1); put16(out + 6, 0);
     put64(out + 8, n);
     put32(out + 16, block_size); put32(out + 20, nb);
     out[24] = (uint8_t)max_len; out[25] = (uint8_t)chunk_log2;
@@ -501,7 +641,7 @@ int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
         put64(out + HDR + 8 * (uint64_t)b, o);
         put64(out + HDR + 8 * ((uint64_t)nb + 1) + 8 * (uint64_t)b, ans_total);
         uint64_t bl, aw;
-        int rc = encode_block(in + start, bn, max_len, ans_mode, chunk_log2, tree_len,
+        int rc = encode_block(in + start, bn, max_len, ans_mode, chunk_log2, tree_len, flat,
                               out + o, cap - o, &bl, &aw);
         if (rc) return rc;
         o += bl;
@@ -513,6 +653,22 @@ int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
     put64(out + 32, ans_total);
     *out_len = o;
     return PVO_OK;
+}
+
+int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
+                     uint32_t max_len, uint32_t ans_mode, uint32_t chunk_log2,
+                     const uint8_t *tree_len, uint8_t *out, uint64_t cap,
+                     uint64_t *out_len) {
+    return encode_stream(in, n, block_size, max_len, ans_mode, chunk_log2, tree_len, 0, out,
+                         cap, out_len);
+}
+
+int pivco_ref_encode_flat(const uint8_t *in, uint64_t n, uint32_t block_size,
+                          uint32_t max_len, uint32_t ans_mode, uint32_t chunk_log2,
+                          const uint8_t *tree_len, uint8_t *out, uint64_t cap,
+                          uint64_t *out_len) {
+    return encode_stream(in, n, block_size, max_len, ans_mode, chunk_log2, tree_len, 1, out,
+                         cap, out_len);
 }
 
 /* ------------------------------------------------------------------ */
@@ -531,6 +687,7 @@ int pivco_ref_stream_info(const uint8_t *in, uint64_t in_len, uint64_t *n_total,
 
 typedef struct {
     uint32_t mode, cw, I;
+    uint32_t version;    /* 1: canonical tree, 2: flat-subtree tree */
     uint8_t const_sym;
     uint8_t len[256];
     tree_t *t;
@@ -550,8 +707,11 @@ static void free_block(block_t *bk) {
 /* Parse and fully validate block b; all node bitmaps decoded into bk->bm. */
 static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *bk) {
     memset(bk, 0, sizeof(*bk));
-    if (in_len < HDR || get32(in) != 0x31435650u || get16(in + 4) != 1 || get16(in + 6) != 0)
+    uint32_t version = in_len >= HDR ? get16(in + 4) : 0;
+    if (in_len < HDR || get32(in) != 0x31435650u || (version != 1 && version != 2) ||
+        get16(in + 6) != 0)
         return PVO_E_CORRUPT;
+    bk->version = version;
     uint64_t n_total = get64(in + 8);
     uint32_t bs = get32(in + 16), nb = get32(in + 20), max_len = in[24], cl2 = in[25];
     if (bs == 0 || max_len < 1 || max_len > 15 || cl2 < 5 || cl2 > 24) return PVO_E_CORRUPT;
@@ -578,12 +738,17 @@ static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *
     for (int j = 0; j < 128; j++) { bk->len[2 * j] = p[12 + j] & 15; bk->len[2 * j + 1] = p[12 + j] >> 4; }
     for (int s = 0; s < 256; s++) if (bk->len[s] > max_len) return PVO_E_CORRUPT;
     bk->t = (tree_t *)malloc(sizeof(tree_t));
-    if (build_tree(bk->len, bk->t)) { free(bk->t); bk->t = NULL; return PVO_E_CORRUPT; }
+    if (version == 2 ? build_flat_tree(bk->len, bk->t) : build_tree(bk->len, bk->t)) {
+        free(bk->t); bk->t = NULL; return PVO_E_CORRUPT;
+    }
     tree_t *t = bk->t;
     uint32_t I = (uint32_t)t->ni;
     uint64_t o = 140, kb = (I + 7) / 8;
     if (o + kb + (uint64_t)bk->cw * I > comp) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
-    for (uint32_t i = 0; i < I; i++) bk->kind[i] = (p[o + i / 8] >> (i % 8)) & 1;
+    for (uint32_t i = 0; i < I; i++) {
+        bk->kind[i] = (p[o + i / 8] >> (i % 8)) & 1;
+        if (bk->kind[i] && t->nd[t->bfs[i]].flat) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
+    }
     for (uint32_t i = I; i < kb * 8; i++)
         if ((p[o + i / 8] >> (i % 8)) & 1) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
     o += kb;
@@ -593,7 +758,8 @@ static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *
         tnode *v = &t->nd[t->bfs[i]];
         v->n_right = bk->cw == 2 ? get16(p + o) : get32(p + o);
         o += bk->cw;
-        if (v->n_right > v->n) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
+        if (v->n_right > v->n || (v->flat && v->n_right)) { free(t); bk->t = NULL; return PVO_E_CORRUPT; }
+        if (v->flat) continue;                 /* its leaves need no sizes */
         t->nd[v->child[0]].n = v->n - v->n_right;
         t->nd[v->child[1]].n = v->n_right;
     }
@@ -603,12 +769,13 @@ static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *
     uint64_t aw = 0;
     for (uint32_t i = 0; i < I; i++) {
         tnode *v = &t->nd[t->bfs[i]];
-        bk->bm[i] = (uint8_t *)calloc((size_t)((v->n + 7) / 8 + 1), 1);
+        uint64_t nbits = body_bits(v);
+        bk->bm[i] = (uint8_t *)calloc((size_t)((nbits + 7) / 8 + 1), 1);
         if (bk->kind[i]) continue;
-        uint64_t nbytes = (v->n + 7) / 8;
+        uint64_t nbytes = (nbits + 7) / 8;
         if (o + nbytes > comp) { rc = PVO_E_CORRUPT; goto fail; }
         memcpy(bk->bm[i], p + o, (size_t)nbytes);
-        if ((v->n & 7) && (p[o + nbytes - 1] >> (v->n & 7))) { rc = PVO_E_CORRUPT; goto fail; }
+        if ((nbits & 7) && (p[o + nbytes - 1] >> (nbits & 7))) { rc = PVO_E_CORRUPT; goto fail; }
         o += nbytes;
     }
     for (uint32_t i = 0; i < I; i++) {
@@ -623,9 +790,11 @@ static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *
         aw += (v->n + 31) / 32;
     }
     if (o != comp || aw != a1 - a0) { rc = PVO_E_CORRUPT; goto fail; }
-    /* every node's bitmap must hold exactly n_right ones */
+    /* every binary node's bitmap must hold exactly n_right ones (any D-bit
+     * value of a flat node names a symbol of its group) */
     for (uint32_t i = 0; i < I; i++) {
         tnode *v = &t->nd[t->bfs[i]];
+        if (v->flat) continue;
         uint64_t ones = 0;
         for (uint64_t j = 0; j < v->n; j++) ones += (uint64_t)getbit(bk->bm[i], j);
         if (ones != v->n_right) { rc = PVO_E_CORRUPT; goto fail; }
@@ -638,7 +807,8 @@ fail:
 
 static int check_stream(const uint8_t *in, uint64_t in_len, uint64_t *n_total, uint32_t *nb,
                         uint32_t *bs) {
-    if (!in || in_len < HDR || get32(in) != 0x31435650u || get16(in + 4) != 1 || get16(in + 6) != 0)
+    if (!in || in_len < HDR || get32(in) != 0x31435650u || (get16(in + 4) != 1 && get16(in + 4) != 2) ||
+        get16(in + 6) != 0)
         return PVO_E_CORRUPT;
     *n_total = get64(in + 8); *bs = get32(in + 16); *nb = get32(in + 20);
     if (*bs == 0 || (*n_total + *bs - 1) / *bs != *nb) return PVO_E_CORRUPT;
@@ -724,6 +894,67 @@ static void walk_block(const block_t *bk, uint8_t *out) {
     free(cb);
 }
 
+/* Decoder A for a v2 block: the same reading with the items of Sec. 2.2.4
+ * (build_flat_tree) in place of the symbols.  The code of position i is read
+ * bit by bit from the binary nodes named by the prefix read so far until the
+ * prefix is an item's code; an item with D >= 1 is itself a node, whose next
+ * D-bit value is the index of the symbol in its group (D = 1: one bit). */
+typedef struct {
+    uint16_t pfx[16][256];     /* node prefixes at depth d (binary and group nodes), ascending */
+    int npfx[16], first[16];   /* their number; number of nodes above d */
+    uint16_t ic[16][256];      /* item codes of depth d, ascending */
+    item_t item[16][256];      /* their items */
+    int nic[16];
+} itembook_t;
+
+static void build_itembook(const uint8_t len[256], uint8_t order[256], itembook_t *ib) {
+    item_t it[256];
+    uint32_t code[256];
+    int n = flat_items(len, order, it);
+    item_codes(it, n, code);
+    memset(ib, 0, sizeof(*ib));
+    for (int i = 0; i < n; i++) {
+        int m = it[i].depth;
+        for (int d = 0; d < m; d++) insert16(ib->pfx[d], &ib->npfx[d], code[i] >> (m - d));
+        if (it[i].d >= 1) insert16(ib->pfx[m], &ib->npfx[m], code[i]);
+        int k = insert16(ib->ic[m], &ib->nic[m], code[i]);
+        for (int j = ib->nic[m] - 1; j > k; j--) ib->item[m][j] = ib->item[m][j - 1];
+        ib->item[m][k] = it[i];
+    }
+    for (int d = 1; d < 16; d++) ib->first[d] = ib->first[d - 1] + ib->npfx[d - 1];
+}
+
+static void walk_flat_block(const block_t *bk, uint8_t *out) {
+    itembook_t *ib = (itembook_t *)malloc(sizeof(itembook_t));
+    uint8_t order[256];
+    build_itembook(bk->len, order, ib);
+    uint64_t cur[255];
+    memset(cur, 0, sizeof(cur));
+    for (uint64_t i = 0; i < bk->n; i++) {
+        uint32_t v = 0;                 /* item-code prefix read so far */
+        int d = 0;                      /* its length */
+        for (;;) {
+            int k = find16(ib->ic[d], ib->nic[d], v);
+            if (k >= 0) {
+                const item_t *x = &ib->item[d][k];
+                uint32_t q = 0;
+                if (x->d) {
+                    int id = ib->first[d] + find16(ib->pfx[d], ib->npfx[d], v);
+                    for (int b = 0; b < x->d; b++)
+                        q |= (uint32_t)getbit(bk->bm[id], cur[id] * (uint64_t)x->d + (uint64_t)b) << b;
+                    cur[id]++;
+                }
+                out[i] = order[x->first + (int)q];
+                break;
+            }
+            int id = ib->first[d] + find16(ib->pfx[d], ib->npfx[d], v);
+            v = 2 * v + (uint32_t)getbit(bk->bm[id], cur[id]++);
+            d++;                        /* the block was validated: an item is always reached */
+        }
+    }
+    free(ib);
+}
+
 /* Decoder B, the bottom-up merge of Sec. 3: every internal node v, deepest
  * first, forms the symbol sequence of its subtree; output j of v comes from
  * the child its bitmap bit selects (0 left, 1 right), at the position given
@@ -735,8 +966,20 @@ static void merge_block(const block_t *bk, uint8_t *out) {
     uint8_t *seq[255];
     for (int i = (int)bk->I - 1; i >= 0; i--) {
         const tnode *v = &t->nd[t->bfs[i]];
-        const tnode *kid[2] = {&t->nd[v->child[0]], &t->nd[v->child[1]]};
         uint8_t *o = (i == 0) ? out : (uint8_t *)malloc((size_t)v->n + 1);
+        if (v->flat) {
+            /* merge_flat_D (Sec. 3.2): output j is the group's symbol named by
+             * the node's j-th D-bit value */
+            for (uint64_t j = 0; j < v->n; j++) {
+                uint32_t q = 0;
+                for (int b = 0; b < v->flat; b++)
+                    q |= (uint32_t)getbit(bk->bm[i], j * (uint64_t)v->flat + (uint64_t)b) << b;
+                o[j] = t->order[v->g0 + (int)q];
+            }
+            seq[i] = o;
+            continue;
+        }
+        const tnode *kid[2] = {&t->nd[v->child[0]], &t->nd[v->child[1]]};
         /* ones[j] = 1 bits of the node's bitmap before position j */
         uint64_t *ones = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)v->n + 1));
         ones[0] = 0;
@@ -767,7 +1010,9 @@ static int decode_range(const uint8_t *in, uint64_t in_len, uint32_t b0, uint32_
         rc = parse_block(in, in_len, b, &bk);
         if (rc) return rc;
         if (o + bk.n > cap) { free_block(&bk); return PVO_E_CAPACITY; }
-        if (merge) merge_block(&bk, out + o); else walk_block(&bk, out + o);
+        if (merge) merge_block(&bk, out + o);
+        else if (bk.version == 2 && bk.mode == 0) walk_flat_block(&bk, out + o);
+        else walk_block(&bk, out + o);
         o += bk.n;
         free_block(&bk);
     }
@@ -792,7 +1037,8 @@ int pivco_ref_decode_blocks(const uint8_t *in, uint64_t in_len, uint32_t b0, uin
 
 int pivco_ref_block_info(const uint8_t *in, uint64_t in_len, uint32_t block, uint8_t len[256],
                          uint32_t *mode, uint32_t *n_internal, uint8_t depth[255],
-                         uint64_t n_v[255], uint64_t n_right[255], uint8_t kind[255]) {
+                         uint64_t n_v[255], uint64_t n_right[255], uint8_t kind[255],
+                         uint8_t flat[255]) {
     uint64_t n_total; uint32_t nb, bs;
     int rc = check_stream(in, in_len, &n_total, &nb, &bs);
     if (rc) return rc;
@@ -805,6 +1051,7 @@ int pivco_ref_block_info(const uint8_t *in, uint64_t in_len, uint32_t block, uin
     for (uint32_t i = 0; i < *n_internal; i++) {
         const tnode *v = &bk.t->nd[bk.t->bfs[i]];
         depth[i] = (uint8_t)v->depth; n_v[i] = v->n; n_right[i] = v->n_right; kind[i] = bk.kind[i];
+        if (flat) flat[i] = (uint8_t)v->flat;
     }
     free_block(&bk);
     return PVO_OK;
@@ -862,7 +1109,7 @@ int pivco_ref_pivoted_to_classical(const uint8_t *in, uint64_t in_len, uint8_t *
     block_t bk;
     rc = parse_block(in, in_len, 0, &bk);
     if (rc) return rc;
-    if (bk.mode != 0) { free_block(&bk); return PVO_E_UNSUPPORTED; }
+    if (bk.mode != 0 || bk.version != 1) { free_block(&bk); return PVO_E_UNSUPPORTED; }
     const tree_t *t = bk.t;
     uint64_t cur[255], p = 0;
     memset(cur, 0, sizeof(cur));

@@ -13,6 +13,8 @@
  *                                  classical-stream cross-check
  *   - Sec. 2 / Fig. 2-3            one bitmap per internal node ("pivoting")
  *   - Sec. 3 / naive merge loop    bottom-up merge decoder
+ *   - Sec. 2.2.3-2.2.4, 3.2        flat subtrees and the non-canonical
+ *                                  regrouping (v2 streams, merge_flat_D)
  *   - Sec. 4 / Table 11            encoder = build node bitmaps top-down
  *   - App. D                       128-byte 4-bit code-length table, blocks,
  *                                  per-node records in traversal order
@@ -77,6 +79,17 @@ int pivco_ref_encode(const uint8_t *in, uint64_t n, uint32_t block_size,
                      const uint8_t *tree_len, uint8_t *out, uint64_t cap,
                      uint64_t *out_len);
 
+/* The same, writing a v2 stream: every coded block uses the flat-subtree
+ * tree that Sec. 2.2.3-2.2.4 derive from its code lengths (the symbols of
+ * each length cut into power-of-two groups, largest first; a group of 2^D
+ * >= 4 symbols is one flat node holding a D-bit index per passing symbol).
+ * Both decoders read v1 and v2 streams; on v2, decoder B merges flat nodes
+ * with merge_flat_D (Sec. 3.2). */
+int pivco_ref_encode_flat(const uint8_t *in, uint64_t n, uint32_t block_size,
+                          uint32_t max_len, uint32_t ans_mode, uint32_t chunk_log2,
+                          const uint8_t *tree_len, uint8_t *out, uint64_t cap,
+                          uint64_t *out_len);
+
 /* Stream header fields (no validation beyond the magic). */
 int pivco_ref_stream_info(const uint8_t *in, uint64_t in_len, uint64_t *n_total,
                           uint32_t *n_blocks, uint32_t *block_size,
@@ -113,11 +126,12 @@ int pivco_ref_pivoted_to_classical(const uint8_t *in, uint64_t in_len,
                                    uint8_t *out, uint64_t cap, uint64_t *nbits);
 
 /* Per-block introspection of a stream: code lengths, internal-node count,
- * per-node (BFS order) depth, n_v, n_right and coding kind. Arrays of 255. */
+ * per-node (BFS order) depth, n_v, n_right, coding kind and flat depth D (0
+ * for binary nodes; may be NULL). Arrays of 255. */
 int pivco_ref_block_info(const uint8_t *in, uint64_t in_len, uint32_t block,
                          uint8_t len[256], uint32_t *mode, uint32_t *n_internal,
                          uint8_t depth[255], uint64_t n_v[255],
-                         uint64_t n_right[255], uint8_t kind[255]);
+                         uint64_t n_right[255], uint8_t kind[255], uint8_t flat[255]);
 
 /* PivCo-Golomb (App. G, golomb_ref.c): the pivoted layout applied to a
  * unary code -- value v is v 0-bits and a 1-bit, bitmap k holds the k-th code

@@ -43,6 +43,8 @@ def lib():
             "pivco_ref_encode_bound": (C.c_uint64, [C.c_uint64, C.c_uint32, C.c_uint32]),
             "pivco_ref_encode": (C.c_int, [u8p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                            C.c_uint32, u8p, u8p, C.c_uint64, u64p]),
+            "pivco_ref_encode_flat": (C.c_int, [u8p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                                C.c_uint32, u8p, u8p, C.c_uint64, u64p]),
             "pivco_ref_stream_info": (C.c_int, [u8p, C.c_uint64, u64p, u32p, u32p, u64p]),
             "pivco_ref_decode": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
             "pivco_ref_decode_merge": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
@@ -52,7 +54,7 @@ def lib():
             "pivco_ref_classical_decode": (C.c_int, [u8p, C.c_uint64, u8p, u8p, C.c_uint64]),
             "pivco_ref_pivoted_to_classical": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
             "pivco_ref_block_info": (C.c_int, [u8p, C.c_uint64, C.c_uint32, u8p, u32p, u32p, u8p,
-                                               u64p, u64p, u8p]),
+                                               u64p, u64p, u8p, u8p]),
             "pivco_ref_golomb_bound": (C.c_uint64, [C.c_uint64, C.c_uint32]),
             "pivco_ref_golomb_encode": (C.c_int, [u8p, C.c_uint64, C.c_uint32, u8p, C.c_uint64, u64p]),
             "pivco_ref_golomb_decode": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
@@ -123,8 +125,9 @@ def encode_bound(n, block_size, ans_mode=0):
     return int(lib().pivco_ref_encode_bound(n, block_size, ans_mode))
 
 
-def encode(data, block_size, max_len=11, ans_mode=0, chunk_log2=16, tree_len=None):
-    """Encode a uint8 array; returns the stream as a uint8 numpy array."""
+def encode(data, block_size, max_len=11, ans_mode=0, chunk_log2=16, tree_len=None, flat=False):
+    """Encode a uint8 array; returns the stream as a uint8 numpy array
+    (v1, or v2 with flat-subtree trees when flat=True)."""
     d, dp = _u8(data)
     n = d.size
     cap = encode_bound(n, block_size, ans_mode) + 64
@@ -133,9 +136,9 @@ def encode(data, block_size, max_len=11, ans_mode=0, chunk_log2=16, tree_len=Non
     tp = None
     if tree_len is not None:
         t, tp = _u8(np.asarray(tree_len, dtype=np.uint8).reshape(256))
-    _check(lib().pivco_ref_encode(dp if n else None, n, block_size, max_len, ans_mode, chunk_log2,
-                                  tp, out.ctypes.data_as(C.POINTER(C.c_uint8)), cap,
-                                  C.byref(ol)), "encode")
+    f = lib().pivco_ref_encode_flat if flat else lib().pivco_ref_encode
+    _check(f(dp if n else None, n, block_size, max_len, ans_mode, chunk_log2,
+             tp, out.ctypes.data_as(C.POINTER(C.c_uint8)), cap, C.byref(ol)), "encode")
     return out[:ol.value].copy()
 
 
@@ -206,15 +209,18 @@ def block_info(stream, block):
     ln = np.zeros(256, dtype=np.uint8)
     mode = C.c_uint32(0); ni = C.c_uint32(0)
     depth = np.zeros(255, dtype=np.uint8); kind = np.zeros(255, dtype=np.uint8)
+    flat = np.zeros(255, dtype=np.uint8)
     nv = np.zeros(255, dtype=np.uint64); nr = np.zeros(255, dtype=np.uint64)
     P8, P64 = C.POINTER(C.c_uint8), C.POINTER(C.c_uint64)
     _check(lib().pivco_ref_block_info(sp, s.size, block, ln.ctypes.data_as(P8), C.byref(mode),
                                       C.byref(ni), depth.ctypes.data_as(P8), nv.ctypes.data_as(P64),
-                                      nr.ctypes.data_as(P64), kind.ctypes.data_as(P8)),
+                                      nr.ctypes.data_as(P64), kind.ctypes.data_as(P8),
+                                      flat.ctypes.data_as(P8)),
            "block_info")
     k = ni.value
     return {"len": ln, "mode": mode.value, "n_internal": k, "depth": depth[:k].copy(),
-            "n_v": nv[:k].copy(), "n_right": nr[:k].copy(), "kind": kind[:k].copy()}
+            "n_v": nv[:k].copy(), "n_right": nr[:k].copy(), "kind": kind[:k].copy(),
+            "flat": flat[:k].copy()}
 
 
 __all__ = ["OracleError", "lib", "lengths", "codes", "p1q", "select_ans", "rans_encode",

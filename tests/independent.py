@@ -7,7 +7,11 @@ fast enough for small inputs.
 * ``canonical``         canonical code numbering (ref. [5] of the paper)
 * ``decode_stream``     a second reader of the v1 wire format that walks the
                         code tree bit by bit as in Listing 1 (Sec. 1.1), with
-                        its own binary-rANS reader for entropy-coded nodes
+                        its own binary-rANS reader for entropy-coded nodes;
+                        v2 streams (flat subtrees, Sec. 2.2.3-2.2.4) through
+                        ``flat_tree``
+* ``flat_tree``         the regrouped tree from code lengths: each length
+                        class split by the binary digits of its size
 """
 import heapq
 import itertools
@@ -78,11 +82,52 @@ def _rans_bits(body, nbits, p1q, chunk_log2):
     return bits
 
 
+def flat_tree(lens):
+    """The flat-subtree tree of a length vector.
+
+    Returns (nodes, leaf): nodes maps (depth, prefix) -> D for every node
+    (0 for a binary node, D >= 2 for a flat one; a group of two symbols is a
+    binary node), and leaf maps (depth, prefix) -> symbol for the leaves
+    that hang below binary nodes.  A flat node's symbols are listed in
+    ``groups[(depth, prefix)]`` (third value returned)."""
+    by_len = {}
+    for sym, l in enumerate(lens):
+        if l:
+            by_len.setdefault(l, []).append(sym)
+    items = []                                   # (depth, -D, symbols)
+    for l, syms in by_len.items():
+        pos = 0
+        for d in range(8, -1, -1):               # binary digits of the class size, high first
+            if len(syms) >> d & 1:
+                items.append((l - d, -d, syms[pos:pos + (1 << d)]))
+                pos += 1 << d
+    items.sort(key=lambda t: (t[0], t[1]))
+    nodes, leaf, groups = {}, {}, {}
+    code, prev = 0, None
+    for i, (m, negd, syms) in enumerate(items):
+        if i:
+            code = (code + 1) << (m - prev)
+        prev = m
+        for k in range(m):
+            nodes[(k, code >> (m - k))] = 0
+        d = -negd
+        if d == 0:
+            leaf[(m, code)] = syms[0]
+        elif d == 1:
+            nodes[(m, code)] = 0
+            leaf[(m + 1, 2 * code)] = syms[0]
+            leaf[(m + 1, 2 * code + 1)] = syms[1]
+        else:
+            nodes[(m, code)] = d
+            groups[(m, code)] = syms
+    return nodes, leaf, groups
+
+
 def decode_stream(stream):
-    """Decode a v1 stream (small inputs only)."""
+    """Decode a v1 or v2 stream (small inputs only)."""
     s = bytes(stream)
     magic, ver, flags, n_total, bs, nb, max_len, cl2 = struct.unpack_from("<IHHQIIBB", s, 0)
-    assert magic == 0x31435650 and ver == 1 and flags == 0
+    assert magic == 0x31435650 and ver in (1, 2) and flags == 0
     offs = struct.unpack_from(f"<{nb + 1}Q", s, 48)
     out = bytearray()
     for b in range(nb):
@@ -94,10 +139,15 @@ def decode_stream(stream):
         lens = []
         for j in range(128):
             lens += [s[p + 12 + j] & 15, s[p + 12 + j] >> 4]
-        codes = canonical(lens)
-        # the code tree: internal nodes keyed by (depth, prefix)
-        internal = sorted({(d, code >> (l - d)) for code, l in codes.values() for d in range(l)})
-        leaf = {(l, code): sym for sym, (code, l) in codes.items()}
+        if ver == 1:
+            codes = canonical(lens)
+            # the code tree: internal nodes keyed by (depth, prefix)
+            nodes = {(d, code >> (l - d)): 0 for code, l in codes.values() for d in range(l)}
+            leaf = {(l, code): sym for sym, (code, l) in codes.items()}
+            groups = {}
+        else:
+            nodes, leaf, groups = flat_tree(lens)
+        internal = sorted(nodes)
         I = len(internal)
         q = p + 140
         kind = [(s[q + i // 8] >> (i % 8)) & 1 for i in range(I)]
@@ -108,15 +158,18 @@ def decode_stream(stream):
         nv = {internal[0]: n}
         for i, (d, pre) in enumerate(internal):
             v = nv[(d, pre)]
+            if nodes[(d, pre)]:
+                assert n_right[i] == 0 and kind[i] == 0
+                continue
             nv[(d + 1, 2 * pre)] = v - n_right[i]
             nv[(d + 1, 2 * pre + 1)] = n_right[i]
         bitmaps = {}
         for i, node in enumerate(internal):
             if kind[i]:
                 continue
-            m = (nv[node] + 7) // 8
-            bitmaps[node] = [(s[q + j // 8] >> (j % 8)) & 1 for j in range(nv[node])]
-            q += m
+            nbits = nv[node] * max(nodes[node], 1)
+            bitmaps[node] = [(s[q + j // 8] >> (j % 8)) & 1 for j in range(nbits)]
+            q += (nbits + 7) // 8
         for i, node in enumerate(internal):
             if not kind[i]:
                 continue
@@ -128,8 +181,15 @@ def decode_stream(stream):
         for _ in range(n):                       # Listing 1
             d, pre = 0, 0
             while (d, pre) not in leaf:
-                bit = bitmaps[(d, pre)][cursor[(d, pre)]]
+                D = nodes[(d, pre)]
+                c = cursor[(d, pre)]
                 cursor[(d, pre)] += 1
+                if D:                            # flat node: a D-bit index, LSB first
+                    bits = bitmaps[(d, pre)][D * c:D * c + D]
+                    out.append(groups[(d, pre)][sum(b << k for k, b in enumerate(bits))])
+                    break
+                bit = bitmaps[(d, pre)][c]
                 d, pre = d + 1, 2 * pre + bit
-            out.append(leaf[(d, pre)])
+            else:
+                out.append(leaf[(d, pre)])
     return bytes(out)
