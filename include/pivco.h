@@ -65,6 +65,10 @@ typedef struct {
   uint32_t rans_chunk_log2;  /* bits per rANS chunk = 2^this; 16 */
   const pivco_tree *tree;    /* NULL: one optimal tree per block from its
                                 histogram; else this tree for every block */
+  uint32_t tree_shape;       /* 0: canonical trees (a v1 stream); 1: the
+                                flat-subtree trees of Sec. 2.2.3-2.2.4 built
+                                from the same code lengths (a v2 stream) */
+  uint32_t reserved;         /* 0 */
 } pivco_encode_opts;
 
 /* One decode job: a whole stream. */

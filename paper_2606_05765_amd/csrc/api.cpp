@@ -61,13 +61,15 @@ int device_cus() {
 
 struct StreamHdr {
   uint64_t n_total = 0, ans_words = 0;
-  uint32_t block_size = 0, n_blocks = 0, max_len = 0, chunk_log2 = 0;
+  uint32_t block_size = 0, n_blocks = 0, max_len = 0, chunk_log2 = 0, version = 1;
 };
 
 // Parses the 48-byte stream header; returns PIVCO_OK or PIVCO_E_CORRUPT.
 pivco_status parse_stream_header(const uint8_t *h, uint64_t avail, StreamHdr *o) {
   if (avail < kHeaderBytes) return PIVCO_E_CORRUPT;
-  if (rd32(h) != kMagic || rd16(h + 4) != 1 || rd16(h + 6) != 0) return PIVCO_E_CORRUPT;
+  const uint32_t ver = rd16(h + 4);
+  if (rd32(h) != kMagic || (ver != 1 && ver != 2) || rd16(h + 6) != 0) return PIVCO_E_CORRUPT;
+  o->version = ver;
   o->n_total = rd64(h + 8);
   o->block_size = rd32(h + 16);
   o->n_blocks = rd32(h + 20);
@@ -185,8 +187,9 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
     d.n_total = sh.n_total;
     d.n_blocks = sh.n_blocks;
     d.block_size = sh.block_size;
-    d.max_len = sh.max_len;
-    d.chunk_log2 = sh.chunk_log2;
+    d.max_len = static_cast<uint16_t>(sh.max_len);
+    d.chunk_log2 = static_cast<uint16_t>(sh.chunk_log2);
+    d.version = sh.version;
     d.scratch_base = sw;
     d.ans_words = sh.ans_words;
     sw = align_up(sw + sh.ans_words, 4);

@@ -127,24 +127,32 @@ struct BlockHdr {
   uint32_t kraft;
   uint32_t chunk0, nchunk; // the block's rANS chunks in the batch's chunk list
   uint32_t cnt[17], fc[18], lbase[17], lvl[18];
-  uint64_t lvl_total[17];  // symbols passing each level (sum of n_v); set by the merge kernel for streamed blocks
+  uint16_t ci[18];         // per depth: items (leaves and groups; up to 256 in a canonical tree)
+  uint8_t gn[18];          // per depth: group nodes (groups of two or more symbols)
+  uint8_t nfl[18];         // per level: flat nodes (the level's first nodes)
+  uint64_t lvl_total[17];  // bits staged per level (sum of n_v D); set by the merge kernel for streamed blocks
+  uint32_t pad2[2];        // the node tables start at a multiple of 16 bytes
 };
 static_assert(offsetof(BlockHdr, job) == offsetof(BlockExt, job) && sizeof(BlockExt) == 48, "BlockExt prefix");
 
 // Per-node tables (breadth-first node ids).
 // Field order: what a tile of a split block needs first (bodies, children,
-// kinds, depths), then the sizes a whole block needs, then what only the
-// plan kernel uses; the merge kernel copies only the prefix it needs.
+// kinds, depths, flat nodes and their symbols), then the sizes a whole block
+// needs, then what only the plan kernel uses; the merge kernel copies only
+// the prefix it needs.
 struct NodeTab {
   uint32_t boff[256];      // raw: byte offset of the body in the block;
                            // rANS: word offset in the block's scratch
-  uint16_t child[256][2];  // internal id, or 0x8000 | symbol for a leaf
+  uint16_t child[256][2];  // internal id, or 0x8000 | symbol for a leaf; a
+                           // flat node: 0x8000 | its group's first index in
+                           // leafsym, 0x8000 | D (no children)
   uint8_t kind[256];       // 1 = rANS-coded
   uint8_t depth[256];
-  uint32_t nv[256];        // symbols passing the node
-  uint32_t nr[256];        // of which go right (1 bits)
-  uint8_t len[256];
+  uint8_t fd[256];         // flat node: its depth D (>= 2); 0: binary node
   uint8_t leafsym[256];    // symbols ordered by (length, symbol)
+  uint32_t nv[256];        // symbols passing the node
+  uint32_t nr[256];        // of which go right (1 bits; 0 for a flat node)
+  uint8_t len[256];
 };
 
 // A block's parsed and validated header, written by the plan kernel and
@@ -239,7 +247,11 @@ __device__ __forceinline__ void wave_sync_lds() {
 // and fc(L) the first of them, fc(L+1) = 2 (fc(L) + cnt(L)), the internal
 // nodes at depth d are the prefixes [fc(d) + cnt(d), 2^d), numbered
 // breadth-first; child q of such a node is a leaf iff q < fc(d+1) + cnt(d+1),
-// and then it is the (q - fc(d+1))-th symbol of length d+1 by id.
+// and then it is the (q - fc(d+1))-th symbol of length d+1 by id.  A v2
+// stream's flat-subtree tree (Sec. 2.2.3-2.2.4) follows the same closed form
+// with its items (single symbols and power-of-two groups of one length) in
+// place of the symbols; a group of two is a binary node over two leaves, a
+// larger group a flat node.
 template <class Rd>
 __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeTab &t, const Rd &rd) {
   const uint32_t lane = lane_id();
@@ -294,28 +306,63 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
   if (maxlen > J.max_len) err = PIVCO_E_CORRUPT;
   else if (m < 2 || kraft != (1u << 15)) err = PIVCO_E_CORRUPT;
   else if (maxlen > kMaxLenGpu) err = PIVCO_E_UNSUPPORTED;
-  // canonical structure: lbase(L) = codes shorter than L; fc(d+1) =
-  // 2 (fc(d) + cnt(d)); lvl(d) = internal nodes above depth d
+  const bool flat = J.version == 2;
   const uint32_t lbase_l = wave_incl_scan(lane <= 16 ? cnt_l : 0u) - cnt_l;
-  uint32_t fc_l = 0, lvl_l = 0, fcd = 0, lvd = 0, lvl_max = 0;
+  // The tree's leaves and groups ("items") per depth: lane d holds the
+  // number of items at depth d (ci), of groups of two or more symbols (gn,
+  // which are nodes) and of flat ones (nf).  Canonical tree: every symbol is
+  // an item.  Flat-subtree tree (Sec. 2.2.4): the symbols of length l are cut
+  // by the binary digits of their number cnt(l), largest group first; a
+  // group of 2^D hangs at depth l - D, so depth d has one item for each D
+  // with bit D of cnt(d + D) set, ordered by D descending.
+  uint32_t ci_l = cnt_l, gn_l = 0, nf_l = 0;
+  if (flat) {
+    ci_l = 0;
+#pragma unroll
+    for (uint32_t D = 0; D <= 8; ++D) {
+      const uint32_t src = lane + D;
+      const uint32_t c = static_cast<uint32_t>(__shfl(static_cast<int>(cnt_l), static_cast<int>(src & 63), kWave));
+      if (src <= 15 && ((c >> D) & 1)) {
+        ++ci_l;
+        gn_l += D >= 1 ? 1u : 0u;
+        nf_l += D >= 2 ? 1u : 0u;
+      }
+    }
+  }
+  const uint64_t has_items = __ballot(lane <= 15 && ci_l != 0);
+  const uint32_t maxitem = has_items ? 63u - static_cast<uint32_t>(__clzll(static_cast<long long>(has_items))) : 0u;
+  // canonical codes of the items: fc(d+1) = 2 (fc(d) + ci(d)); below the
+  // deepest items every other code of a depth is an internal (binary) node;
+  // lvl(d) = nodes above depth d (groups of two or more, and internal nodes)
+  uint32_t fc_l = 0, lvl_l = 0, fcd = 0, lvd = 0;
 #pragma unroll
   for (uint32_t d = 0; d <= 16; ++d) {
-    const uint32_t cd = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(cnt_l), d));
-    const uint32_t Id = d < maxlen ? (1u << d) - fcd - cd : 0u;
+    const uint32_t cd = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(ci_l), d));
+    const uint32_t gd = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(gn_l), d));
+    const uint32_t Id = d < maxitem ? (1u << d) - fcd - cd : 0u;
     fcd = 2 * (fcd + cd);
-    lvd += Id;
+    lvd += gd + Id;
     if (lane == d + 1) { fc_l = fcd; lvl_l = lvd; }
-    if (d + 1 == maxlen) lvl_max = lvd;
   }
-  const uint32_t I = m >= 2 ? m - 1 : 0;
-  if (!err && lvl_max != I) err = PIVCO_E_CORRUPT;
+  // node levels: the internal nodes above the deepest items, and the groups
+  // at that depth
+  const uint32_t gmax = static_cast<uint32_t>(__shfl(static_cast<int>(gn_l), static_cast<int>(maxitem), kWave));
+  const uint32_t levels = maxitem + (gmax ? 1u : 0u);
+  const uint32_t I = static_cast<uint32_t>(__shfl(static_cast<int>(lvl_l), static_cast<int>(levels), kWave));
+  if (!err && (I == 0 || I > kMaxInternal || (!flat && I != m - 1))) err = PIVCO_E_CORRUPT;
   const uint32_t kb = (I + 7) / 8;
   const uint32_t raw_base = kBlockFixed + kLenTable + kb + cw * I;
   if (!err && raw_base > comp) err = PIVCO_E_CORRUPT;
   if (lane < 17) { h.cnt[lane] = cnt_l; h.lbase[lane] = lbase_l; }
-  if (lane < 18) { h.fc[lane] = fc_l; h.lvl[lane] = lvl_l; }
+  if (lane < 18) {
+    h.fc[lane] = fc_l;
+    h.lvl[lane] = lvl_l;
+    h.ci[lane] = static_cast<uint16_t>(lane <= 15 ? ci_l : 0u);
+    h.gn[lane] = static_cast<uint8_t>(gn_l);
+    h.nfl[lane] = static_cast<uint8_t>(nf_l);
+  }
   if (lane == 0) {
-    h.I = I; h.maxlen = maxlen; h.kb = kb; h.raw_base = raw_base; h.err = err; h.kraft = kraft;
+    h.I = I; h.maxlen = levels; h.kb = kb; h.raw_base = raw_base; h.err = err; h.kraft = kraft;
   }
   if (err) { wave_sync_lds(); return; }
   // symbols in canonical order
@@ -327,10 +374,9 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
 #pragma unroll
   for (int k = 0; k < 4; ++k) t.len[4 * lane + k] = static_cast<uint8_t>(l[k]);
   // node table: lane owns nodes 4*lane .. 4*lane+3.  A node's depth is the
-  // number of levels that start at or before it; the per-depth values come
-  // from the lanes holding them (fc | cnt << 16 and lvl | lbase << 16, all
-  // below 2^14 for depths up to the length limit + 1).
-  const uint32_t pa = fc_l | (cnt_l << 16), pb = lvl_l | (lbase_l << 16);
+  // number of levels that start at or before it.  At depth d the first
+  // gn(d) nodes are the groups, in item order (flat ones first), then the
+  // internal nodes, whose codes follow the items'.
   uint32_t dd[4] = {0, 0, 0, 0};
 #pragma unroll
   for (uint32_t j = 1; j <= kMaxLenGpu; ++j) {
@@ -338,32 +384,54 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
 #pragma unroll
     for (int k = 0; k < 4; ++k) dd[k] += (4 * lane + k >= lj) ? 1u : 0u;
   }
-  wave_sync_lds();                       // leaf symbols written
+  wave_sync_lds();                       // leaf symbols and per-depth values written
   const uint32_t kbase = kBlockFixed + kLenTable;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = 4 * lane + k;
-    const uint32_t d = dd[k];
-    const uint32_t a0 = __shfl(pa, d, kWave), b0 = __shfl(pb, d, kWave);
-    const uint32_t a1 = __shfl(pa, d + 1, kWave), b1 = __shfl(pb, d + 1, kWave);
     if (i >= I) continue;
-    const uint32_t fcd = a0 & 0xFFFF, cntd = a0 >> 16, lvd = b0 & 0xFFFF;
-    const uint32_t fcd1 = a1 & 0xFFFF, cntd1 = a1 >> 16, lvd1 = b1 & 0xFFFF, lbd1 = b1 >> 16;
-    const uint32_t p = fcd + cntd + (i - lvd);
-    const uint32_t leafend = fcd1 + cntd1;
-    uint32_t cc = 0;
-    for (int bb = 0; bb < 2; ++bb) {
-      const uint32_t q = 2 * p + bb;
-      const uint32_t c = q < leafend ? 0x8000u | t.leafsym[lbd1 + q - fcd1] : lvd1 + (q - leafend);
-      cc |= c << (16 * bb);
+    const uint32_t d = dd[k];
+    const uint32_t r = i - h.lvl[d];
+    uint32_t cc = 0, fdv = 0;
+    if (r < h.gn[d]) {
+      // group r of depth d: the r-th D >= 1 with bit D of cnt(d + D) set, D descending
+      uint32_t D = 0, left = r;
+      for (uint32_t e = 8; e >= 1; --e) {
+        const uint32_t le = d + e;
+        if (le <= 15 && ((h.cnt[le] >> e) & 1)) {
+          if (left == 0) { D = e; break; }
+          --left;
+        }
+      }
+      const uint32_t l0 = d + D;
+      const uint32_t first = D ? h.lbase[l0] + (h.cnt[l0] & ~((2u << D) - 1)) : 0u;
+      if (D == 0) err = PIVCO_E_CORRUPT;
+      else if (D == 1) cc = (0x8000u | t.leafsym[first]) | ((0x8000u | t.leafsym[first + 1]) << 16);
+      else { cc = (0x8000u | first) | ((0x8000u | D) << 16); fdv = D; }
+    } else {
+      const uint32_t p = h.fc[d] + h.ci[d] + (r - h.gn[d]);
+      const uint32_t d1 = d + 1;
+      // the D = 0 items of depth d+1: canonical tree, every symbol of length
+      // d+1; flat-subtree tree, the one symbol left after the groups
+      const uint32_t leaf0 = h.lbase[d1] + (flat ? (h.cnt[d1] & ~1u) : 0u);
+      for (int bb = 0; bb < 2; ++bb) {
+        const uint32_t q = 2 * p + bb;
+        const uint32_t rq = q - h.fc[d1];
+        const uint32_t c = rq < h.gn[d1] ? h.lvl[d1] + rq
+                           : rq < h.ci[d1] ? 0x8000u | t.leafsym[leaf0 + rq - h.gn[d1]]
+                                           : h.lvl[d1] + h.gn[d1] + (q - h.fc[d1] - h.ci[d1]);
+        cc |= c << (16 * bb);
+      }
     }
     *reinterpret_cast<uint32_t *>(t.child[i]) = cc;
     t.depth[i] = static_cast<uint8_t>(d);
+    t.fd[i] = static_cast<uint8_t>(fdv);
     t.kind[i] = (rd.u8(kbase + (i >> 3)) >> (i & 7)) & 1;
     const uint32_t co = kbase + kb + cw * i;
-    uint32_t r = rd.u8(co) | (rd.u8(co + 1) << 8);
-    if (cw == 4) r |= (rd.u8(co + 2) << 16) | (rd.u8(co + 3) << 24);
-    t.nr[i] = r;
+    uint32_t nr = rd.u8(co) | (rd.u8(co + 1) << 8);
+    if (cw == 4) nr |= (rd.u8(co + 2) << 16) | (rd.u8(co + 3) << 24);
+    if (fdv && (nr || t.kind[i])) err = PIVCO_E_CORRUPT;   // a flat node has no 1-bit count and is raw
+    t.nr[i] = nr;
   }
   if ((I & 7) && (rd.u8(kbase + (I >> 3)) >> (I & 7))) err = PIVCO_E_CORRUPT;  // unused kind bits
   if (lane == 0) t.nv[0] = n;
@@ -391,7 +459,8 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
     uint32_t rb = 0, aw = 0;
     if (i < I) {
       const uint32_t v = t.nv[i];
-      if (t.kind[i]) aw = (v + 31) / 32; else rb = (v + 7) / 8;
+      const uint64_t bits = static_cast<uint64_t>(v) * (t.fd[i] ? t.fd[i] : 1u);
+      if (t.kind[i]) aw = (v + 31) / 32; else rb = static_cast<uint32_t>((bits + 7) / 8);
     }
     rawb[k] = lraw; answ[k] = lans;
     lraw += rb; lans += aw;
@@ -417,9 +486,10 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t i = 4 * lane + k;
-      if (i < I && !t.kind[i] && (t.nv[i] & 7)) {
-        const uint32_t last = rd.u8(t.boff[i] + (t.nv[i] >> 3));
-        if (last >> (t.nv[i] & 7)) err = PIVCO_E_CORRUPT;
+      const uint64_t bits = i < I ? static_cast<uint64_t>(t.nv[i]) * (t.fd[i] ? t.fd[i] : 1u) : 0u;
+      if (i < I && !t.kind[i] && (bits & 7)) {
+        const uint32_t last = rd.u8(t.boff[i] + static_cast<uint32_t>(bits >> 3));
+        if (last >> (bits & 7)) err = PIVCO_E_CORRUPT;
       }
     }
   }
@@ -691,9 +761,9 @@ struct MergeCfg {
 
 // What a merge lane needs about a node with work in the current tile (16
 // bytes): where its bits start (resident: LDS bit address; streaming: first
-// staged word), the 1 bits before that point, its output offset in its level
-// buffer | its first task in the level << 16, and one 16-bit code per child
-// (kid_code).
+// staged word), the 1 bits before that point (a flat node: flat_tag), its
+// output offset in its level buffer | its first task in the level << 16, and
+// one 16-bit code per child (kid_code).
 struct NodeRec {
   uint32_t x0;
   uint32_t arank;
@@ -726,6 +796,7 @@ struct MergeSmem {
   uint64_t smask[C::LEVELS][C::WIN];  // bit i of window w: a node's first task is 64 w + i
   uint8_t wstart[C::LEVELS][C::WIN];  // level slot of the node holding task 64 w
   uint32_t ntask[C::LEVELS];          // 16-output tasks of the level
+  uint32_t nftask[C::LEVELS];         // of which belong to flat nodes (the first ones)
   uint32_t actbase[C::LEVELS];        // slots of the levels above
   uint32_t act_run;
   uint32_t warm_sink;
@@ -755,14 +826,29 @@ __device__ __forceinline__ uint32_t kid_code(const MergeSmem<C> &sm, uint32_t c,
   return 0x8000u | ((static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[p]) - base) + off) >> 2);
 }
 
+// In a flat node's record, in place of the rank: bit 31 set, D in bits
+// 24-27, and the LDS byte address of its group's symbols (the D-bit values
+// index them).
+template <class C>
+__device__ __forceinline__ uint32_t flat_tag(const MergeSmem<C> &sm, const NodeTab &t, uint32_t v) {
+  const uint8_t *base = reinterpret_cast<const uint8_t *>(&sm);
+  const uint32_t a = static_cast<uint32_t>(&t.leafsym[t.child[v][0] & 255] - base);
+  return 0x80000000u | (static_cast<uint32_t>(t.fd[v]) << 24) | a;
+}
+
 // Streaming tile: largest multiple of 1024 (at most C::T) whose staged words fit.
 template <class C>
-__device__ uint32_t pick_tile_streaming(const BlockHdr &h) {
+__device__ uint32_t pick_tile_streaming(const BlockHdr &h, const NodeTab &t) {
   uint32_t T = C::T;
   for (; T > 1024; T -= 1024) {
     uint64_t need = h.I + h.maxlen + 1;
     for (uint32_t d = 0; d < h.maxlen; ++d) {
-      const uint64_t ld = h.lvl_total[d] < T ? h.lvl_total[d] : T;
+      // a tile's share of a level is at most T symbols, D bits each at a
+      // flat node (the level's flat nodes come first; the first has the
+      // largest D)
+      const uint32_t dmax = h.nfl[d] ? t.fd[h.lvl[d]] : 1u;
+      const uint64_t cap = static_cast<uint64_t>(T) * dmax;
+      const uint64_t ld = h.lvl_total[d] < cap ? h.lvl_total[d] : cap;
       need += div_up(ld, 32) + (h.lvl[d + 1] - h.lvl[d]);
     }
     if (need <= static_cast<uint64_t>(C::STG)) break;
@@ -815,7 +901,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
   NodeTab &t = sm.pb.t;
-  uint32_t out_top = 0, task_top = 0, act_top = 0;
+  uint32_t out_top = 0, task_top = 0, act_top = 0, ftask = 0;
   for (uint32_t i = lane; i < static_cast<uint32_t>(C::WIN); i += kWave) sm.smask[d][i] = 0;
   const uint32_t act_base = sm.act_run;
   wave_sync_lds();
@@ -848,6 +934,10 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
                         (static_cast<uint64_t>(isact) << 48);
     uint64_t tot;
     const uint64_t ex = wave_excl_scan64(pk, tot);
+    // the level's flat nodes are its first nfl nodes: their tasks are the
+    // tasks before lane nfl of the first pass
+    if (v0 == h.lvl[d])
+      ftask = static_cast<uint32_t>(__shfl(ex, static_cast<int>(h.nfl[d]), kWave) >> 32) & 0xFFFF;
     if (valid) {
       const uint32_t ob = out_top + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
       uint32_t kids = 0;
@@ -868,7 +958,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
         const uint32_t tp = task_top + static_cast<uint32_t>((ex >> 32) & 0xFFFF);
         NodeRec r;
         r.x0 = x0;
-        r.arank = 0;
+        r.arank = t.fd[v] ? flat_tag<C>(sm, t, v) : 0u;
         r.ot = sm.obase[v] | (tp << 16);
         r.kids = kids;
         list_node<C>(sm, d, ai, act_base + ai, tp, tasks, r);
@@ -882,6 +972,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
   }
   if (lane == 0) {
     sm.ntask[d] = task_top;
+    sm.nftask[d] = ftask;
     sm.actbase[d] = act_base;
     sm.act_run = act_base + act_top;
   }
@@ -995,9 +1086,10 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
     }
     if (tvv) {
       const uint32_t tp = static_cast<uint32_t>(rel >> 32) & 0xFFFF;
+      const uint32_t fdv = t.fd[v];
       NodeRec r;
-      r.x0 = sm.abit[v] + sm.cur[v];
-      r.arank = sm.arank[v];
+      r.x0 = sm.abit[v] + (fdv ? fdv : 1u) * sm.cur[v];     // a flat node keeps D bits per symbol
+      r.arank = fdv ? flat_tag<C>(sm, t, v) : sm.arank[v];
       r.ot = static_cast<uint32_t>(rel) | (tp << 16);
       r.kids = kids;
       list_node<C>(sm, d, static_cast<uint32_t>(rel >> 48), static_cast<uint32_t>(pfx[v] >> 48), tp,
@@ -1008,7 +1100,9 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
   }
   if (static_cast<uint32_t>(tid) < h.maxlen) {
     const uint64_t tot = pfx[h.lvl[tid + 1]] - pfx[h.lvl[tid]];
+    const uint64_t ftot = pfx[h.lvl[tid] + h.nfl[tid]] - pfx[h.lvl[tid]];   // the level's flat nodes come first
     sm.ntask[tid] = static_cast<uint32_t>(tot >> 32) & 0xFFFF;
+    sm.nftask[tid] = static_cast<uint32_t>(ftot >> 32) & 0xFFFF;
     sm.actbase[tid] = static_cast<uint32_t>(pfx[h.lvl[tid]] >> 48);
   }
   lds_barrier();
@@ -1028,7 +1122,9 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
   const uint64_t in_dw = J.in_len >> 2;
   for (uint32_t v = h.lvl[d] + wave; v < h.lvl[d + 1]; v += C::NW) {
     const uint32_t tvv = sm.tv[v];
-    const uint32_t nwords = (tvv + 31) / 32;
+    const uint32_t dv = t.fd[v] ? t.fd[v] : 1u;     // bits per symbol
+    const uint32_t nbits = dv * tvv;
+    const uint32_t nwords = (nbits + 31) / 32;
     uint32_t base = 0;
     if (lane == 0 && nwords) base = atomicAdd(&sm.stage_top, nwords);
     base = __builtin_amdgcn_readfirstlane(base);
@@ -1040,16 +1136,16 @@ __device__ void stage_level_streaming(const JobDev &J, MergeSmem<C> &sm, uint32_
       }
       continue;
     }
-    const uint32_t s0 = sm.cur[v];
+    const uint64_t s0 = static_cast<uint64_t>(dv) * sm.cur[v];
     uint32_t carry = 0;
     for (uint32_t q0 = 0; q0 < nwords; q0 += kWave) {
       const uint32_t q = q0 + lane;
       uint32_t w = 0;
       if (q < nwords) {
-        const uint32_t p = s0 + 32 * q;
+        const uint64_t p = s0 + 32ull * q;
         if (t.kind[v]) w = bits32_glb(scratch, 32 * (h.ans_word0 + t.boff[v]) + p, scratch_words);
         else w = bits32_glb(gin32, 8 * (h.blk + t.boff[v]) + p, in_dw);
-        const uint32_t rem = tvv - 32 * q;
+        const uint32_t rem = nbits - 32 * q;
         if (rem < 32) w &= (1u << rem) - 1;
       }
       const uint32_t pc = __popc(w);
@@ -1080,12 +1176,87 @@ typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 // child windows, permutes), so that each stage's LDS reads of all N windows
 // are in flight together.  Lanes without a task read from clamped addresses
 // and store nothing.
+// Stores the K outputs of task j0 of a node (o: K/4 words): into the level
+// buffer of level d at the node's offset, or at the root into HBM (16 bytes
+// at a time where aligned and inside the tile).
+template <class C, bool ROOT>
+__device__ __forceinline__ void store_task(MergeSmem<C> &sm, int d, uint32_t ot, uint32_t j0,
+                                           const uint32_t *o, uint32_t tvv, uint8_t *out) {
+  constexpr int CB = C::K < 16 ? C::K : 16;    // bytes per store
+  uint8_t *ldsw = reinterpret_cast<uint8_t *>(&sm);
+#pragma unroll
+  for (int c = 0; c < C::K / CB; ++c) {
+    if (ROOT) {
+      const uint32_t j = j0 + CB * c;
+      uint8_t *dst = out + j;
+      if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
+        if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};   // C cast: generic to global
+        else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
+      } else if (j < tvv) {
+        const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
+        GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
+        for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[(CB * c + e) >> 2] >> (8 * (e & 3)));
+      }
+    } else {
+      const uint32_t dst = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[d & 1]) - ldsw) +
+                           (ot & 0xFFFF) + j0 + CB * c;
+      if (CB == 16) *reinterpret_cast<uint4 *>(ldsw + dst) = make_uint4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
+      else *reinterpret_cast<uint2 *>(ldsw + dst) = make_uint2(o[0], o[1]);
+    }
+  }
+}
+
+// merge_flat_D (Sec. 3.2) for one window of a level's flat tasks (tasks
+// [0, nft)): a task reads K D-bit values of its flat node, 4 at a time from
+// one 32-bit window of the node's bits, and looks each up in the node's
+// group of symbols in LDS.  Lanes without a flat task read from the node
+// record's start with D = 2 and an in-range table and store nothing.
+template <class C, bool RESIDENT, bool ROOT>
+__device__ __forceinline__ void merge_flat_window(MergeSmem<C> &sm, int d, uint32_t w, uint32_t nft,
+                                                  uint32_t abase, uint8_t *out) {
+  const uint32_t lane = lane_id();
+  constexpr int G = C::K / 4;
+  const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
+  const uint64_t upto = ((2ull << lane) - 1) & ~1ull;
+  const uint64_t B = sm.smask[d][w];
+  const uint32_t slot = sm.wstart[d][w] + static_cast<uint32_t>(__popcll(B & upto));
+  const NodeRec r = sm.rec[abase + slot];
+  const bool valid = kWave * w + lane < nft && (r.arank >> 31);
+  const uint32_t D = valid ? (r.arank >> 24) & 15 : 2u;
+  const uint32_t tab = valid ? (r.arank & 0xFFFFFFu)
+                             : static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.pb.t.leafsym) - lds);
+  const uint32_t j0 = valid ? C::K * (kWave * w + lane - (r.ot >> 16)) : 0u;
+  const uint2 *stage = reinterpret_cast<const uint2 *>(sm.body);
+  uint32_t bits[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const uint32_t b = D * (j0 + 4 * g);       // from the node's first bit in this tile
+    if (RESIDENT) {
+      bits[g] = bits32_lds(sm.body, r.x0 + b);
+    } else {                                   // staged words start at the node's cursor
+      const uint32_t q = r.x0 + (b >> 5);
+      bits[g] = __builtin_amdgcn_alignbit(stage[q + 1].x, stage[q].x, b & 31);
+    }
+  }
+  uint32_t o[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t q = __builtin_amdgcn_ubfe(bits[g], D * e, D);
+      v |= static_cast<uint32_t>(lds[tab + q]) << (8 * e);
+    }
+    o[g] = v;
+  }
+  if (valid) store_task<C, ROOT>(sm, d, r.ot, j0, o, ROOT ? sm.tv[0] : 0u, out);
+}
+
 template <class C, bool RESIDENT, int N, bool ROOT>
-__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t *w,
+__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t *w, uint32_t tlo,
                                               uint32_t ntask, uint32_t abase, uint8_t *out) {
   const uint32_t lane = lane_id();
   constexpr int G = C::K / 4;                  // groups of 4 outputs
-  constexpr int CB = C::K < 16 ? C::K : 16;    // bytes per store
   const uint8_t *lds = reinterpret_cast<const uint8_t *>(&sm);
   const uint64_t upto = ((2ull << lane) - 1) & ~1ull;   // window bits 1 .. lane
   bool valid[N];
@@ -1097,7 +1268,7 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
     // last node and works on that node's first task (and stores nothing).
     const uint64_t B = sm.smask[d][w[i]];
     const uint32_t slot = sm.wstart[d][w[i]] + static_cast<uint32_t>(__popcll(B & upto));
-    valid[i] = kWave * w[i] + lane < ntask;
+    valid[i] = kWave * w[i] + lane < ntask && kWave * w[i] + lane >= tlo;   // tasks below tlo are flat
     r[i] = sm.rec[abase + slot];
   }
   uint32_t j0[N], bits[N], r1[N];
@@ -1149,7 +1320,6 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
       sel[i][g] = sm.sel[sel[i][g]];
     }
   }
-  uint8_t *ldsw = reinterpret_cast<uint8_t *>(&sm);
   const uint32_t tvv = ROOT ? sm.tv[0] : 0u;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -1166,42 +1336,30 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
 #pragma unroll
     for (int g = 0; g < G; ++g) asm volatile("" ::"v"(o[g]));
     if (!valid[i]) continue;
-#pragma unroll
-    for (int c = 0; c < C::K / CB; ++c) {
-      if (ROOT) {
-        const uint32_t j = j0[i] + CB * c;
-        uint8_t *dst = out + j;
-        if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
-          if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};   // C cast: generic to global
-          else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
-        } else if (j < tvv) {
-          const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
-          GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
-          for (uint32_t e = 0; e < kk2; ++e) gd[e] = static_cast<uint8_t>(o[(CB * c + e) >> 2] >> (8 * (e & 3)));
-        }
-      } else {
-        const uint32_t dst = static_cast<uint32_t>(reinterpret_cast<const uint8_t *>(sm.lvl[d & 1]) - lds) +
-                             (r[i].ot & 0xFFFF) + j0[i] + CB * c;
-        if (CB == 16) *reinterpret_cast<uint4 *>(ldsw + dst) = make_uint4(o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]);
-        else *reinterpret_cast<uint2 *>(ldsw + dst) = make_uint2(o[0], o[1]);
-      }
-    }
+    store_task<C, ROOT>(sm, d, r[i].ot, j0[i], o, tvv, out);
   }
 }
 
-// One level of a tile: a wave takes up to C::LOCK of its windows at once.
+// One level of a tile: first the windows of its flat tasks (a prefix of the
+// level's tasks), then the binary tasks, a wave taking up to C::LOCK of
+// their windows at once; the window holding both kinds is visited by both
+// loops, each lane doing only its own kind.
 template <class C, bool RESIDENT, bool ROOT>
 __device__ __forceinline__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   const uint32_t wave = wave_id();
-  const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
+  const uint32_t ntask = sm.ntask[d], nft = sm.nftask[d], abase = sm.actbase[d];
   const uint32_t nwin = (ntask + kWave - 1) / kWave;
-  for (uint32_t w = wave; w < nwin; w += C::LOCK * C::NW) {
+  for (uint32_t w = wave; kWave * w < nft; w += C::NW) merge_flat_window<C, RESIDENT, ROOT>(sm, d, w, nft, abase, out);
+  // binary windows from the one holding task nft, dealt to the waves after the flat ones
+  const uint32_t w0 = nft / kWave, nfw = (nft + kWave - 1) / kWave;
+  const uint32_t wv = (wave + C::NW - nfw % C::NW) % C::NW;
+  for (uint32_t w = w0 + wv; w < nwin; w += C::LOCK * C::NW) {
     const uint32_t left = (nwin - w + C::NW - 1) / C::NW;   // windows of this wave from w on
     const uint32_t ww[4] = {w, w + C::NW, w + 2 * C::NW, w + 3 * C::NW};
-    if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1), ROOT>(sm, d, ww, ntask, abase, out);
-    else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1), ROOT>(sm, d, ww, ntask, abase, out);
-    else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1), ROOT>(sm, d, ww, ntask, abase, out);
-    else merge_windows<C, RESIDENT, 1, ROOT>(sm, d, ww, ntask, abase, out);
+    if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1), ROOT>(sm, d, ww, nft, ntask, abase, out);
+    else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1), ROOT>(sm, d, ww, nft, ntask, abase, out);
+    else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1), ROOT>(sm, d, ww, nft, ntask, abase, out);
+    else merge_windows<C, RESIDENT, 1, ROOT>(sm, d, ww, nft, ntask, abase, out);
   }
   lds_barrier();
 }
@@ -1483,11 +1641,11 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
       wave_sync_lds();
       for (uint32_t v = lane; v < I; v += kWave)
         atomicAdd(reinterpret_cast<unsigned long long *>(&h.lvl_total[t.depth[v]]),
-                  static_cast<unsigned long long>(t.nv[v]));
+                  static_cast<unsigned long long>(t.nv[v]) * (t.fd[v] ? t.fd[v] : 1u));
       wave_sync_lds();
     }
     if (tid == 0) {
-      sm.tile = resident ? C::T : pick_tile_streaming<C>(h);
+      sm.tile = resident ? C::T : pick_tile_streaming<C>(h, t);
       if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
     }
     // build_directory's barriers order the writes above before their readers
@@ -1537,7 +1695,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
   if (!bad && !tiled) {
     for (uint32_t i = tid; i < I; i += C::NT) {
       const uint32_t ones = resident ? sm.arank[i] - sm.r0[i] : sm.ones[i];
-      if (sm.cur[i] != t.nv[i] || ones != t.nr[i])
+      if (sm.cur[i] != t.nv[i] || (!t.fd[i] && ones != t.nr[i]))    // any D-bit value is a symbol
         atomicCAS(&h.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
     }
   }
@@ -1579,9 +1737,11 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
   uint32_t nch = 0;
   uint64_t a16 = 0, gb = 0;
   if (static_cast<uint32_t>(tid) < I && sm.tv[tid]) {
-    gb = (t.kind[tid] ? 32ull * (h.ans_word0 + t.boff[tid]) : 8ull * (h.blk + t.boff[tid])) + sm.cur[tid];
+    const uint32_t dv = t.fd[tid] ? t.fd[tid] : 1u;     // bits per symbol
+    gb = (t.kind[tid] ? 32ull * (h.ans_word0 + t.boff[tid]) : 8ull * (h.blk + t.boff[tid])) +
+         static_cast<uint64_t>(dv) * sm.cur[tid];
     a16 = (gb >> 3) & ~15ull;
-    const uint64_t b16 = (((gb + sm.tv[tid] + 7) >> 3) + 15) & ~15ull;
+    const uint64_t b16 = (((gb + static_cast<uint64_t>(dv) * sm.tv[tid] + 7) >> 3) + 15) & ~15ull;
     nch = static_cast<uint32_t>((b16 - a16) >> 4);
   }
   const uint32_t inc = tid < 256 ? wave_incl_scan(nch) : 0u;
@@ -1611,7 +1771,8 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
     const uint32_t cnt = sm.ones[v];
     if (!cnt) continue;
     const uint32_t off = sm.stg[v];
-    const uint64_t g = (t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v])) + sm.cur[v];
+    const uint64_t g = (t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v])) +
+                       static_cast<uint64_t>(t.fd[v] ? t.fd[v] : 1u) * sm.cur[v];
     const uint64_t s16 = (g >> 3) & ~15ull;
     const uint8_t *src = t.kind[v] ? reinterpret_cast<const uint8_t *>(scratch) : J.in;
     const uint64_t lim = t.kind[v] ? 4ull * scratch_words : J.in_len;
@@ -1780,7 +1941,8 @@ __device__ __forceinline__ uint32_t chunk_count(const Chunk &c, uint64_t q, uint
 // itself.  Table row k, column v holds (position, rank).  A node whose
 // bitmap holds a different number of 1 bits than its header count marks the
 // job corrupt; positions are clamped to the nodes' sizes so that the tiles
-// never read outside their bitmaps.
+// never read outside their bitmaps.  A flat node (v2 streams) has leaves
+// only: its positions are all a tile needs (D bits per position).
 constexpr int kTilesNT = 1024;
 constexpr uint32_t kTilesDir = 16384;     // directory entries (LDS)
 constexpr uint32_t kTilesPos = 16384;     // positions kept in LDS
@@ -1838,6 +2000,11 @@ __device__ void tiles_levels(TilesSmem &sm, const TileRegion *reg, uint2 *T, uin
       const uint32_t nv = t.nv[v];
       const uint32_t sp = POS_LDS ? sm.pos[v * (K + 1) + k] : row[v].x;
       const uint32_t s = sp < nv ? sp : nv;
+      if (t.fd[v]) {                     // a flat node: its position only (no children, no ranks)
+        row[v] = make_uint2(s, 0u);
+        if (k == K && s != nv) atomicCAS(&sm.err, 0, static_cast<int32_t>(PIVCO_E_CORRUPT));
+        continue;
+      }
       const TileRegion &r = reg[t.kind[v] ? 1 : 0];
       const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
       const uint32_t rk = region_prefix<SPR>(sm, r, gb + s) - sm.pstart[v];
@@ -1866,6 +2033,7 @@ __device__ void tiles_prefix_levels(TilesSmem &sm, const TileRegion *reg, uint2 
   const BlockHdr &h = sm.pb.h;
   const NodeTab &t = sm.pb.t;
   for (uint32_t v = threadIdx.x; v < h.I; v += kTilesNT) {
+    if (t.fd[v]) { sm.pstart[v] = 0; continue; }
     const TileRegion &r = reg[t.kind[v] ? 1 : 0];
     const uint64_t gb = t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v]);
     sm.pstart[v] = region_prefix<SPR>(sm, r, gb);
@@ -2154,6 +2322,11 @@ __global__ __launch_bounds__(kTdNT) void k_topdown(const JobDev *jobs, const uin
       __syncthreads();
       continue;
     }
+    if (J.version != 1) {                // the ablation decodes canonical trees only
+      if (tid == 0) set_err(J.status, PIVCO_E_UNSUPPORTED);
+      __syncthreads();
+      continue;
+    }
     const uint32_t I = h.I;
     for (uint32_t v = tid; v < I; v += kTdNT) {
       sm.cur[v] = whole ? 0u : tab[tiled[rt.y >> 8].tab + static_cast<uint64_t>(k) * kTabCols + v].x;
@@ -2265,7 +2438,7 @@ __global__ __launch_bounds__(kTdNT) void k_topdown(const JobDev *jobs, const uin
 // Merge-kernel variants: workgroup size, tile of a whole block, resident
 // block bytes, outputs per task, windows per wave step.
 using Cfg0 = MergeCfg<1024, 32768, 57344, 16, 2>;
-using Cfg1 = MergeCfg<1024, 32768, 57344, 8, 2>;
+using Cfg1 = MergeCfg<1024, 32768, 56320, 8, 2>;
 using Cfg2 = MergeCfg<1024, 32768, 55296, 32, 1>;
 using Cfg3 = MergeCfg<1024, 16384, 57344, 16, 2>;
 using Cfg4 = MergeCfg<512, 32768, 57344, 16, 2>;
@@ -2299,7 +2472,7 @@ uint32_t merge_variant_count() { return 6; }
 const char *merge_variant_name(uint32_t v) {
   switch (v) {
     case 0: return "wg1024_tile32k_body56k_k16_x2";
-    case 1: return "wg1024_tile32k_body56k_k8_x2";
+    case 1: return "wg1024_tile32k_body55k_k8_x2";
     case 2: return "wg1024_tile32k_body54k_k32_x1";
     case 3: return "wg1024_tile16k_body56k_k16_x2";
     case 4: return "wg512_tile32k_body56k_k16_x2";

@@ -64,19 +64,36 @@ struct EncBlock {
   uint64_t in_off;        // first input symbol
   uint32_t n;             // symbols
   uint32_t I;             // internal nodes (0: constant block, nothing to split)
-  uint32_t maxlen;
+  uint32_t maxlen;        // node levels
   uint32_t pad;
   uint32_t lvl[16];       // first node id of each depth
-  uint32_t fc[17];        // first canonical code of each length
-  uint32_t cnt[17];       // symbols of each length
-  uint32_t code[256];     // (len << 16) | code
-  uint16_t child[256][2]; // internal id or 0x8000 | symbol
+  uint32_t off[17];       // internal node at depth d with code prefix p: lvl[d] + p - off[d]
+  uint32_t code[256];     // code | len << 16 | D << 20 | group node << 24: a symbol
+                          // whose group of 2^D >= 2 symbols is a node ends its
+                          // path there (D = 0: no such node)
+  uint16_t child[256][2]; // internal id or 0x8000 | symbol (0x8000 for a flat node's)
   uint32_t bit[256];      // node's first bit: in the block's raw image (raw
                           // node) or in its rANS bitmap words (rANS node)
   uint32_t kind[8];       // bit i: node i is rANS-coded
-  uint32_t pad2[4];
+  uint8_t fd[256];        // flat node: its depth D (>= 2), 0 for binary nodes
+  uint32_t pad2;
 };
 static_assert(sizeof(EncBlock) % 16 == 0, "EncBlock copies in 16-byte units");
+
+// Node on a symbol's path at depth d (cl = EncBlock::code of the symbol; lvl
+// and off as in EncBlock):
+// above the symbol's group the internal node of its code prefix, at the
+// group's depth the group node.  The path has len - D + (D ? 1 : 0) nodes.
+__device__ __forceinline__ uint32_t path_node(const uint32_t *lvl, const uint32_t *off, uint32_t cl, uint32_t d) {
+  const uint32_t len = (cl >> 16) & 15, D = (cl >> 20) & 15;
+  if (D && d == len - D) return cl >> 24;
+  return lvl[d] + ((cl & 0xFFFF) >> (len - d)) - off[d];
+}
+
+__device__ __forceinline__ uint32_t path_len(uint32_t cl) {
+  const uint32_t len = (cl >> 16) & 15, D = (cl >> 20) & 15;
+  return len - D + (D ? 1u : 0u);
+}
 
 // Per-block layout (k_layout), offsets (k_scan) and size (k_sizes, k_scan2).
 struct BlockLay {
@@ -239,17 +256,22 @@ __global__ __launch_bounds__(256) void k_slice_prefix(uint32_t *slh, uint32_t sp
 // fc(L+1) = 2 (fc(L) + cnt(L)); a symbol's code is fc(len) plus its rank
 // among the symbols of its length; the internal nodes at depth d are the
 // prefixes [fc(d) + cnt(d), 2^d) numbered breadth-first, and child q of such
-// a node is a leaf iff q < fc(d+1) + cnt(d+1).
+// a node is a leaf iff q < fc(d+1) + cnt(d+1).  With flat-subtree trees
+// (shape 1, Sec. 2.2.3-2.2.4) the same closed form runs over the tree's
+// items: the symbols of length L are cut by the binary digits of cnt(L),
+// largest group first, a group of 2^D hanging at depth L - D; the items of a
+// depth are ordered by D descending; a group of two or more symbols is a
+// node (flat when D >= 2), numbered before the depth's internal nodes.
 struct LayoutSmem {
   uint32_t nv[256], nr[256];
-  uint32_t cnt[17], fc[18], lvl[18], lbase[17];
+  uint32_t cnt[17], fc[18], lvl[18], lbase[17], ci[18], gn[18], off[18];
   uint32_t maxlen, I;
   uint8_t leafsym[256];
 };
 
 __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
     const uint8_t *lenm, const uint32_t *modes, const uint32_t *hist, uint32_t nb, uint64_t n,
-    uint32_t bs, uint32_t ans_mode, uint32_t chunk_log2, EncBlock *eb, BlockLay *lay,
+    uint32_t bs, uint32_t ans_mode, uint32_t chunk_log2, uint32_t shape, EncBlock *eb, BlockLay *lay,
     RansNode *rnodes, uint8_t *hdr) {
   __shared__ LayoutSmem smem[kLayoutWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
@@ -307,54 +329,123 @@ __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
   if (lane == 0) {
     sm.cnt[0] = 0;
     sm.cnt[16] = 0;
-    uint32_t maxlen = 0, fcd = 0, lv = 0, lb = 0;
-    for (uint32_t L = 1; L <= 15; ++L)
-      if (sm.cnt[L]) maxlen = L;
-    for (uint32_t d = 0; d <= 16; ++d) {
-      const uint32_t cd = d <= 15 ? sm.cnt[d] : 0u;
+    // items per depth: every symbol (shape 0), or one per set binary digit D
+    // of cnt(d + D) (shape 1)
+    uint32_t maxitem = 0, lb = 0;
+    for (uint32_t d = 0; d <= 17; ++d) {
+      uint32_t ci = 0, gn = 0;
+      if (shape == 0) {
+        ci = d <= 16 ? sm.cnt[d] : 0u;
+      } else {
+        for (uint32_t D = 0; D <= 8; ++D)
+          if (d + D <= 15 && ((sm.cnt[d + D] >> D) & 1)) { ++ci; gn += D >= 1 ? 1u : 0u; }
+      }
+      sm.ci[d] = ci;
+      sm.gn[d] = gn;
+      if (ci) maxitem = d;
+      if (d <= 16) { sm.lbase[d] = lb; lb += sm.cnt[d]; }
+    }
+    uint32_t fcd = 0, lv = 0;
+    for (uint32_t d = 0; d <= 17; ++d) {
       sm.fc[d] = fcd;
       sm.lvl[d] = lv;
-      if (d <= 16) sm.lbase[d] = lb;
-      lv += d < maxlen ? (1u << d) - fcd - cd : 0u;
-      lb += cd;
-      fcd = 2 * (fcd + cd);
+      sm.off[d] = fcd + sm.ci[d] - sm.gn[d];
+      lv += sm.gn[d] + (d < maxitem ? (1u << d) - fcd - sm.ci[d] : 0u);
+      fcd = 2 * (fcd + sm.ci[d]);
     }
-    sm.fc[17] = fcd;
-    sm.lvl[17] = lv;
-    sm.maxlen = maxlen;
-    sm.I = sm.lvl[maxlen];
-    E.maxlen = maxlen;
-    E.I = sm.lvl[maxlen];
+    const uint32_t levels = maxitem + (sm.gn[maxitem] ? 1u : 0u);
+    sm.maxlen = levels;
+    sm.I = sm.lvl[levels];
+    E.maxlen = levels;
+    E.I = sm.lvl[levels];
   }
   wave_sync();
   const uint32_t I = sm.I;
-  // canonical codes and the symbols in (length, symbol) order
+  // codes and the symbols in (length, symbol) order
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t s = 4 * lane + k;
-    const uint32_t code = l[k] ? sm.fc[l[k]] + rank[k] : 0u;
-    E.code[s] = (l[k] << 16) | code;
-    if (l[k]) sm.leafsym[sm.lbase[l[k]] + rank[k]] = static_cast<uint8_t>(s);
+    uint32_t cl = 0;
+    if (l[k]) {
+      const uint32_t L = l[k], r = rank[k];
+      if (shape == 0) {
+        cl = (sm.fc[L] + r) | (L << 16);
+      } else {
+        // the symbol's group: binary digits of cnt(L), largest first
+        const uint32_t cn = sm.cnt[L];
+        uint32_t D = 0, hi = 0;
+        for (uint32_t e = 9; e-- > 0;) {
+          if (!((cn >> e) & 1)) continue;
+          if (r < hi + (1u << e)) { D = e; break; }
+          hi += 1u << e;
+        }
+        const uint32_t m = L - D;
+        uint32_t idx = 0;                  // items of depth m with a larger D
+        for (uint32_t e = D + 1; e <= 8; ++e)
+          if (m + e <= 15 && ((sm.cnt[m + e] >> e) & 1)) ++idx;
+        const uint32_t code = ((sm.fc[m] + idx) << D) | (r - hi);
+        cl = code | (L << 16) | (D << 20) | (D ? (sm.lvl[m] + idx) << 24 : 0u);
+      }
+      sm.leafsym[sm.lbase[L] + r] = static_cast<uint8_t>(s);
+    }
+    E.code[s] = cl;
     sm.nv[s] = 0;
     sm.nr[s] = 0;
-    // (the code is kept for the path walk below)
-    rank[k] = code;
+    rank[k] = cl;                        // kept for the path walk below
   }
   if (lane < 16) E.lvl[lane] = sm.lvl[lane];
-  if (lane < 17) { E.fc[lane] = sm.fc[lane]; E.cnt[lane] = sm.cnt[lane]; }
+  if (lane < 17) E.off[lane] = sm.off[lane];
   wave_sync();
   // symbols passing each node and going right: walk each present symbol's path
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (!c[k] || !l[k]) continue;
-    const uint32_t len = l[k], code = rank[k];
-    for (uint32_t d = 0; d < len; ++d) {
-      const uint32_t id = sm.lvl[d] + ((code >> (len - d)) - (sm.fc[d] + sm.cnt[d]));
+    const uint32_t cl = rank[k], len = l[k], D = (cl >> 20) & 15;
+    for (uint32_t d = 0; d < path_len(cl); ++d) {
+      const uint32_t id = path_node(sm.lvl, sm.off, cl, d);
       atomicAdd(&sm.nv[id], c[k]);
-      if ((code >> (len - 1 - d)) & 1) atomicAdd(&sm.nr[id], c[k]);
+      if (D >= 2 && d == len - D) break;  // a flat node has no right branch
+      if (((cl & 0xFFFF) >> (len - 1 - d)) & 1) atomicAdd(&sm.nr[id], c[k]);
     }
   }
   wave_sync();
+  // node table: lane owns nodes 4 lane .. 4 lane + 3
+  uint32_t fdk[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t i = 4 * lane + k;
+    if (i >= I) continue;
+    uint32_t d = 0;
+    while (sm.lvl[d + 1] <= i) ++d;
+    const uint32_t r = i - sm.lvl[d];
+    uint32_t cc = 0;
+    if (r < sm.gn[d]) {                  // group r of depth d (shape 1)
+      uint32_t D = 0, left = r;
+      for (uint32_t e = 8; e >= 1; --e)
+        if (d + e <= 15 && ((sm.cnt[d + e] >> e) & 1)) {
+          if (left == 0) { D = e; break; }
+          --left;
+        }
+      const uint32_t L = d + D;
+      const uint32_t first = sm.lbase[L] + (sm.cnt[L] & ~((2u << D) - 1));
+      if (D == 1) cc = (0x8000u | sm.leafsym[first]) | ((0x8000u | sm.leafsym[first + 1]) << 16);
+      else { cc = 0x80008000u; fdk[k] = D; }
+    } else {
+      const uint32_t p = sm.fc[d] + sm.ci[d] + (r - sm.gn[d]);
+      const uint32_t d1 = d + 1;
+      const uint32_t leaf0 = sm.lbase[d1] + (shape ? (sm.cnt[d1] & ~1u) : 0u);
+      for (int bb = 0; bb < 2; ++bb) {
+        const uint32_t q = 2 * p + bb;
+        const uint32_t rq = q - sm.fc[d1];
+        const uint32_t ch = rq < sm.gn[d1] ? sm.lvl[d1] + rq
+                            : rq < sm.ci[d1] ? 0x8000u | sm.leafsym[leaf0 + rq - sm.gn[d1]]
+                                             : sm.lvl[d1] + sm.gn[d1] + (q - sm.fc[d1] - sm.ci[d1]);
+        cc |= ch << (16 * bb);
+      }
+    }
+    *reinterpret_cast<uint32_t *>(E.child[i]) = cc;
+    E.fd[i] = static_cast<uint8_t>(fdk[k]);
+  }
   // lane owns nodes 4 lane .. 4 lane + 3: kind, sizes and their prefixes
   const uint32_t C = 1u << chunk_log2;
   uint32_t kd[4], rb[4], aw[4], ch[4], sl[4], nvk[4], nrk[4];
@@ -364,11 +455,12 @@ __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
     const uint32_t i = 4 * lane + k;
     nvk[k] = i < I ? sm.nv[i] : 0u;
     nrk[k] = i < I ? sm.nr[i] : 0u;
-    kd[k] = i < I && select_ans(ans_mode, nvk[k], nrk[k]) ? 1u : 0u;
+    kd[k] = i < I && !fdk[k] && select_ans(ans_mode, nvk[k], nrk[k]) ? 1u : 0u;
     const uint32_t nch = kd[k] ? (nvk[k] + C - 1) / C : 0u;
     const uint32_t rem = nvk[k] - (nch ? (nch - 1) * C : 0u);
+    const uint64_t bits = static_cast<uint64_t>(nvk[k]) * (fdk[k] ? fdk[k] : 1u);
     rb[k] = lraw; aw[k] = lans; ch[k] = lch; sl[k] = lsl;
-    lraw += kd[k] || i >= I ? 0u : (nvk[k] + 7) / 8;
+    lraw += kd[k] || i >= I ? 0u : static_cast<uint32_t>((bits + 7) / 8);
     lans += kd[k] ? (nvk[k] + 31) / 32 : 0u;
     lch += nch;
     lsl += nch ? ((nch - 1) * slot_size(C) + slot_size(rem)) / 16 : 0u;   // 16-byte units
@@ -418,21 +510,6 @@ __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
     q[0] = static_cast<uint8_t>(nrk[k]);
     q[1] = static_cast<uint8_t>(nrk[k] >> 8);
     if (cw == 4) { q[2] = static_cast<uint8_t>(nrk[k] >> 16); q[3] = static_cast<uint8_t>(nrk[k] >> 24); }
-  }
-  // node table: lane owns nodes 4 lane .. 4 lane + 3
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t i = 4 * lane + k;
-    if (i >= I) continue;
-    uint32_t d = 0;
-    while (sm.lvl[d + 1] <= i) ++d;
-    const uint32_t p = sm.fc[d] + sm.cnt[d] + (i - sm.lvl[d]);
-    const uint32_t leafend = sm.fc[d + 1] + sm.cnt[d + 1];
-    for (int bb = 0; bb < 2; ++bb) {
-      const uint32_t q = 2 * p + bb;
-      E.child[i][bb] = static_cast<uint16_t>(q < leafend ? 0x8000u | sm.leafsym[sm.lbase[d + 1] + q - sm.fc[d + 1]]
-                                                         : sm.lvl[d + 1] + (q - leafend));
-    }
   }
   if (lane == kWaveE - 1) {
     Lb.hlen = 140 + kb + cw * I;
@@ -499,11 +576,12 @@ static_assert(kHistSlice % kSplitT == 0, "split tiles never cross a slice");
 
 struct SplitSmem {
   EncBlock B;
-  uint32_t cur[256];      // bits written by earlier tiles
+  uint32_t cur[256];      // symbols of the node in earlier tiles
   uint32_t tv[256];       // node's symbols in this tile
   uint32_t seg[256];      // node's segment in its level buffer
   uint32_t top[16];
   uint32_t hist[256];
+  uint32_t fw[kSplitNT / kWaveE][20];   // per wave: a flat node's packed values (64 x D bits + 31)
   uint8_t buf[2][kSplitT];
 };
 
@@ -539,15 +617,12 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
   const uint64_t img_bit = 8ull * lay[b].img_off, rbm_bit = 32ull * lay[b].rbm_off;
   for (uint32_t i = tid; i < 256; i += kSplitNT) sm.cur[i] = 0;
   __syncthreads();
-  if (slice) {   // bits of each node before this slice
+  if (slice) {   // symbols of each node before this slice
     const uint32_t s = tid;
     const uint32_t c = pre[static_cast<uint64_t>(blockIdx.x) * 256 + s];
-    const uint32_t cl = B.code[s], len = cl >> 16, code = cl & 0xFFFF;
-    if (c && len)
-      for (uint32_t d = 0; d < len; ++d) {
-        const uint32_t p = code >> (len - d);
-        atomicAdd(&sm.cur[B.lvl[d] + (p - (B.fc[d] + B.cnt[d]))], c);
-      }
+    const uint32_t cl = B.code[s];
+    if (c && cl)
+      for (uint32_t d = 0; d < path_len(cl); ++d) atomicAdd(&sm.cur[path_node(B.lvl, B.off, cl, d)], c);
     __syncthreads();
   }
   const uint8_t *bin = in + B.in_off;
@@ -566,14 +641,9 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
     {
       const uint32_t s = tid;
       const uint32_t c = sm.hist[s];
-      const uint32_t cl = B.code[s], len = cl >> 16, code = cl & 0xFFFF;
-      if (c && len) {
-        for (uint32_t d = 0; d < len; ++d) {
-          const uint32_t p = code >> (len - d);
-          const uint32_t id = B.lvl[d] + (p - (B.fc[d] + B.cnt[d]));
-          atomicAdd(&sm.tv[id], c);
-        }
-      }
+      const uint32_t cl = B.code[s];
+      if (c && cl)
+        for (uint32_t d = 0; d < path_len(cl); ++d) atomicAdd(&sm.tv[path_node(B.lvl, B.off, cl, d)], c);
     }
     __syncthreads();
     for (uint32_t i = tid; i < B.I; i += kSplitNT) {
@@ -593,11 +663,38 @@ __global__ __launch_bounds__(kSplitNT) void k_split(const uint8_t *in, const Enc
         uint32_t r1 = (c1 & 0x8000) ? 0u : sm.seg[c1];
         const bool rans = (B.kind[v >> 5] >> (v & 31)) & 1;
         uint32_t *area = rans ? rbm : img;
+        const uint32_t D = B.fd[v];
+        if (D) {
+          // a flat node: each symbol's index in the node's group (its code's
+          // last D bits), as D-bit fields in stream order, gathered per 64
+          // symbols in LDS and ORed into the image word by word
+          const uint64_t base = img_bit + 8ull * B.bit[v] + static_cast<uint64_t>(D) * sm.cur[v];
+          uint32_t *fw = sm.fw[wave];
+          for (uint32_t c = 0; c < tvv; c += kWaveE) {
+            const bool act = c + lane < tvv;
+            const uint32_t s = act ? lb[seg + c + lane] : 0u;
+            const uint32_t q = B.code[s] & ((1u << D) - 1);
+            const uint64_t P = base + static_cast<uint64_t>(D) * c;
+            const uint32_t a = static_cast<uint32_t>(P & 31);
+            const uint32_t nw = (a + D * kWaveE + 31) >> 5;
+            if (lane < 20) fw[lane] = 0;
+            wave_sync();
+            if (act && q) {
+              const uint32_t bp = a + D * lane;
+              atomicOr(&fw[bp >> 5], q << (bp & 31));
+              if ((bp & 31) + D > 32) atomicOr(&fw[(bp >> 5) + 1], q >> (32 - (bp & 31)));
+            }
+            wave_sync();
+            if (lane < nw && fw[lane]) atomicOr(&area[(P >> 5) + lane], fw[lane]);
+            wave_sync();
+          }
+          continue;
+        }
         const uint64_t base_bit = (rans ? rbm_bit + 32ull * B.bit[v] : img_bit + 8ull * B.bit[v]) + sm.cur[v];
         for (uint32_t c = 0; c < tvv; c += kWaveE) {
           const bool act = c + lane < tvv;
           const uint32_t s = act ? lb[seg + c + lane] : 0u;
-          const uint32_t cl = B.code[s], len = cl >> 16, code = cl & 0xFFFF;
+          const uint32_t cl = B.code[s], len = (cl >> 16) & 15, code = cl & 0xFFFF;
           const bool bit = act && ((code >> (len - 1 - d)) & 1);
           const uint64_t m1 = __ballot(bit);
           const uint64_t m0 = __ballot(act && !bit);
@@ -766,7 +863,8 @@ __global__ __launch_bounds__(kScanNT) void k_scan2(BlockLay *lay, uint32_t nb, T
 // offsets), nothing written past out_cap.
 __global__ __launch_bounds__(256) void k_stream_head(const BlockLay *lay, const Totals *tot, uint32_t nb,
                                                      uint64_t n, uint32_t bs, uint32_t max_len,
-                                                     uint32_t chunk_log2, uint8_t *out, uint64_t out_cap) {
+                                                     uint32_t chunk_log2, uint32_t version, uint8_t *out,
+                                                     uint64_t out_cap) {
   const uint32_t t = blockIdx.x * 256 + threadIdx.x;
   if (tot->out_bytes > out_cap) return;
   uint64_t *boff = reinterpret_cast<uint64_t *>(out + kHeaderBytes);
@@ -778,7 +876,7 @@ __global__ __launch_bounds__(256) void k_stream_head(const BlockLay *lay, const 
   if (t == 0) {
     uint32_t *h = reinterpret_cast<uint32_t *>(out);
     h[0] = kMagic;
-    h[1] = 1u;                                        // version 1, flags 0
+    h[1] = version;                                   // version (1 or 2), flags 0
     h[2] = static_cast<uint32_t>(n);
     h[3] = static_cast<uint32_t>(n >> 32);
     h[4] = bs;
@@ -868,7 +966,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 bool opts_ok(const pivco_encode_opts *o) {
   return o && o->block_size >= 1 && o->block_size <= (1u << 30) && o->max_len >= 1 &&
          o->max_len <= kMaxLenGpu && o->ans_mode <= 2 && o->rans_chunk_log2 >= 5 &&
-         o->rans_chunk_log2 <= 24;
+         o->rans_chunk_log2 <= 24 && o->tree_shape <= 1 && o->reserved == 0;
 }
 
 struct WsLayout {
@@ -992,7 +1090,7 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
 
   if (nb == 0) {                         // header and the two one-entry tables
     uint8_t h[kHeaderBytes + 16] = {0};
-    const uint32_t w[6] = {kMagic, 1u, 0u, 0u, static_cast<uint32_t>(bs), 0u};
+    const uint32_t w[6] = {kMagic, o->tree_shape ? 2u : 1u, 0u, 0u, static_cast<uint32_t>(bs), 0u};
     std::memcpy(h, w, sizeof(w));
     h[24] = static_cast<uint8_t>(o->max_len);
     h[25] = static_cast<uint8_t>(o->rans_chunk_log2);
@@ -1029,7 +1127,7 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   const uint32_t gl = (nb + kLayoutWaves - 1) / kLayoutWaves;
   hipLaunchKernelGGL(k_layout, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, ws + L.lenm,
                      reinterpret_cast<const uint32_t *>(ws + L.modes), dh, nb, n, static_cast<uint32_t>(bs),
-                     o->ans_mode, o->rans_chunk_log2, deb, dlay, drn, ws + L.hdr);
+                     o->ans_mode, o->rans_chunk_log2, o->tree_shape, deb, dlay, drn, ws + L.hdr);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanNT), 0, s, dlay, nb, dtot);
   uint32_t *dimg = reinterpret_cast<uint32_t *>(ws + L.img);
   uint32_t *drbm = reinterpret_cast<uint32_t *>(ws + L.rbm);
@@ -1056,7 +1154,7 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
 
   // 8. the stream (nothing is written when it would not fit)
   hipLaunchKernelGGL(k_stream_head, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, dlay, dtot, nb, n,
-                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2, out, out_cap);
+                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2, o->tree_shape ? 2u : 1u, out, out_cap);
   const uint64_t max_words = (kHdrStride + bs * o->max_len / 8 + 255 + 4) / 4 + 1;
   const uint32_t segs = static_cast<uint32_t>(div_up(max_words, kAsmSeg));
   if (static_cast<uint64_t>(nb) * segs > 0x7FFFFFFFull) return PIVCO_E_UNSUPPORTED;

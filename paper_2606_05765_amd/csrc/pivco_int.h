@@ -23,7 +23,7 @@ constexpr uint32_t kRansM = 4096;          // 12-bit probabilities
 constexpr uint32_t kRansL = 65536;         // lower state bound, 16-bit words
 constexpr uint32_t kRansLanes = 32;
 constexpr uint32_t kChunkHdr = 4 + 4 * 32; // n_words u32 + 32 lane states
-constexpr uint32_t kParsedBlockBytes = 5648; // per-block record written by the plan kernel
+constexpr uint32_t kParsedBlockBytes = 5984; // per-block record written by the plan kernel
 
 // A block of more than split_min symbols (never fewer than kSplitMin) and at
 // most kMaxTiles tiles is decoded as independent tiles of kTileOut symbols,
@@ -73,8 +73,9 @@ struct JobDev {
   uint64_t scratch_base;   // first scratch word (u32) of this job
   uint32_t n_blocks;
   uint32_t block_size;
-  uint32_t max_len;
-  uint32_t chunk_log2;
+  uint16_t max_len;
+  uint16_t chunk_log2;
+  uint32_t version;        // 1: canonical trees; 2: flat-subtree trees
   int32_t *status;
   uint64_t ans_words;      // scratch words of this job (its stream header's total)
 };

@@ -37,7 +37,7 @@ struct Registered {
   const uint8_t *d_in;
   uint64_t in_len;
   uint64_t n_total, ans_words;
-  uint32_t n_blocks, block_size, max_len, chunk_log2;
+  uint32_t n_blocks, block_size, max_len, chunk_log2, version;
   WorkLists::Need need;           // merge items, tiles and boundary-table entries
   uint64_t chunks;                // bound on its rANS chunks
 };
@@ -203,6 +203,7 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   r.block_size = bs;
   r.max_len = h[24];
   r.chunk_log2 = h[25];
+  r.version = static_cast<uint32_t>(h[4]) | (static_cast<uint32_t>(h[5]) << 8);
   r.need = need;
   r.chunks = chunks;
   *id = static_cast<uint32_t>(sv->reg.size());
@@ -322,8 +323,9 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         d.ans_words = g.ans_words;
         d.n_blocks = g.n_blocks;
         d.block_size = g.block_size;
-        d.max_len = g.max_len;
-        d.chunk_log2 = g.chunk_log2;
+        d.max_len = static_cast<uint16_t>(g.max_len);
+        d.chunk_log2 = static_cast<uint16_t>(g.chunk_log2);
+        d.version = g.version;
         d.status = reinterpret_cast<int32_t *>(s.ws + sv->off_status) + k;
         jobs[k] = d;
         sw = align_up(sw + g.ans_words, 4);

@@ -34,7 +34,8 @@ class Tree(C.Structure):
 
 class EncodeOpts(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("max_len", C.c_uint32), ("ans_mode", C.c_uint32),
-                ("rans_chunk_log2", C.c_uint32), ("tree", C.POINTER(Tree))]
+                ("rans_chunk_log2", C.c_uint32), ("tree", C.POINTER(Tree)),
+                ("tree_shape", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Job(C.Structure):
@@ -160,8 +161,8 @@ def pivco_build_tree(counts, max_len=11):
 # encode
 # ---------------------------------------------------------------------------
 
-def _opts(block_size, max_len, ans_mode, chunk_log2, tree):
-    o = EncodeOpts(block_size, max_len, ans_mode, chunk_log2, None)
+def _opts(block_size, max_len, ans_mode, chunk_log2, tree, flat=False):
+    o = EncodeOpts(block_size, max_len, ans_mode, chunk_log2, None, 1 if flat else 0, 0)
     keep = None
     if tree is not None:
         keep = Tree()
@@ -170,16 +171,17 @@ def _opts(block_size, max_len, ans_mode, chunk_log2, tree):
     return o, keep
 
 
-def pivco_encode_bound(n, block_size, max_len=11, ans_mode=0, chunk_log2=16):
-    o, _ = _opts(block_size, max_len, ans_mode, chunk_log2, None)
+def pivco_encode_bound(n, block_size, max_len=11, ans_mode=0, chunk_log2=16, flat=False):
+    o, _ = _opts(block_size, max_len, ans_mode, chunk_log2, None, flat)
     return int(lib().pivco_encode_bound(n, C.byref(o)))
 
 
-def pivco_encode(data, block_size, max_len=11, ans_mode=0, chunk_log2=16, tree=None):
-    """Encode a uint8 CUDA tensor; returns the stream as a uint8 CUDA tensor."""
+def pivco_encode(data, block_size, max_len=11, ans_mode=0, chunk_log2=16, tree=None, flat=False):
+    """Encode a uint8 CUDA tensor; returns the stream as a uint8 CUDA tensor
+    (v1 with canonical trees, or v2 with flat-subtree trees when flat=True)."""
     data = _dev_u8(data)
     n = data.numel()
-    o, keep = _opts(block_size, max_len, ans_mode, chunk_log2, tree)
+    o, keep = _opts(block_size, max_len, ans_mode, chunk_log2, tree, flat)
     cap = int(lib().pivco_encode_bound(n, C.byref(o)))
     wsb = int(lib().pivco_encode_workspace(n, C.byref(o)))
     if cap == 0:
