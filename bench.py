@@ -104,20 +104,33 @@ def make_workload(name, seed, workers):
 
 
 def element_merges(xs, bss):
-    """Sum over blocks of the symbols passing every internal node (n times
-    the mean code length): the element merges a decode performs.  Trees
-    from the library's own tree builder (the encoder's default)."""
+    """Sum over blocks of the symbols passing every internal node: the
+    element merges a decode performs -- for canonical trees n times the mean
+    code length; for flat-subtree trees (v2) a symbol whose length class puts
+    it in a group of 2^D >= 4 passes D - 1 fewer nodes (Sec. 2.2.3-2.2.4,
+    Table 7's ops/B).  Trees from the library's own tree builder (the
+    encoder's default).  Returns (canonical, flat)."""
     from paper_2606_05765_amd import pivco as P
-    total = 0
+    total = flat = 0
     for x, bs in zip(xs, bss):
         for b0 in range(0, x.size, bs):
             blk = x[b0:b0 + bs]
-            counts = np.bincount(blk, minlength=256).astype(np.uint64)
+            counts = np.bincount(blk, minlength=256).astype(np.int64)
             if np.count_nonzero(counts) < 2:
                 continue
-            lens = P.pivco_build_tree(counts, 11)
-            total += int(np.dot(counts, np.asarray(lens, dtype=np.uint64)))
-    return total
+            lens = np.asarray(P.pivco_build_tree(counts.astype(np.uint64), 11), dtype=np.int64)
+            total += int(np.dot(counts, lens))
+            saved = 0
+            for ln in range(1, 12):
+                syms = np.flatnonzero(lens == ln)
+                pos = 0
+                for d in range(8, -1, -1):
+                    if syms.size >> d & 1:
+                        if d >= 2:
+                            saved += (d - 1) * int(counts[syms[pos:pos + (1 << d)]].sum())
+                        pos += 1 << d
+            flat += int(np.dot(counts, lens)) - saved
+    return total, flat
 
 
 # ---------------------------------------------------------------------------
@@ -238,6 +251,41 @@ def serving_leg(torch, dev, rate_hz, seconds, pool_w, streams, ids, budget, seed
             "max_busy_slots": stats["max_busy_slots"]}
 
 
+def flat_leg(torch, P, d_xs, bss, ans_mode, tune, steps, warmup, n, merges, flat_merges):
+    """The same workload encoded as v2 streams (flat-subtree trees, Sec.
+    2.2.3-2.2.4): batched decode rate, merge-kernel time and HBM fraction,
+    outputs checked against the inputs."""
+    t0 = time.perf_counter()
+    streams = [P.pivco_encode(d, bs, max_len=11, ans_mode=ans_mode, flat=True) for d, bs in zip(d_xs, bss)]
+    torch.cuda.synchronize()
+    enc_s = time.perf_counter() - t0
+    comp = int(sum(s.numel() for s in streams))
+    outs = [torch.empty_like(d) for d in d_xs]
+    if tune is None:
+        tune = P.pivco_autotune(streams, outs)
+    plan = P.BatchPlan(streams, outs, tune=tune)
+    for _ in range(warmup):
+        plan.launch()
+    dt = time_steps(torch, plan, steps)
+    assert (plan.statuses() == 0).all(), f"v2 decode status {plan.statuses()}"
+    for o, d in zip(outs, d_xs):
+        assert torch.equal(o, d), "v2 decoded bytes differ from the input"
+    merge_avg = merge_kernel_ms(torch, plan, steps)
+    variant = P.pivco_merge_variants()[plan.tune.merge_variant]
+    value = n / (dt / steps) / 1e9
+    achieved = (comp + n) / (merge_avg * 1e-3) / 1e9
+    res = {"GBps": round(value, 2), "ms_per_step": round(dt * 1e3 / steps, 4),
+           "merge_ms_avg": round(merge_avg, 4), "merge_roofline_frac": round(achieved / HBM_PEAK_GBPS, 4),
+           "variant": variant, "tune": plan.tune.as_dict(),
+           "compression_ratio": round(n / comp, 4), "encode_GBps": round(n / enc_s / 1e9, 3),
+           "element_merges": {"per_launch": flat_merges, "ops_per_byte": round(flat_merges / n, 4),
+                              "vs_canonical": round(flat_merges / merges, 4),
+                              "G_per_s": round(flat_merges / (merge_avg * 1e-3) / 1e9, 1)}}
+    plan.close()
+    del streams, outs
+    return res
+
+
 def golomb_leg(torch, dev, n=64 << 20, block_size=1 << 16, seed=7, reps=5):
     """PivCo-Golomb (App. G): unary-coded geometric values at the mean code
     lengths the appendix measures (1.25 .. 5 bits), 64 Mi values each in
@@ -311,6 +359,7 @@ def main():
     ap.add_argument("--grid", type=int, default=None, help="fixed merge grid (with --variant)")
     ap.add_argument("--serve-pool", type=int, default=128, help="resident serving requests")
     ap.add_argument("--no-golomb", action="store_true", help="skip the PivCo-Golomb leg")
+    ap.add_argument("--no-flat", action="store_true", help="skip the v2 (flat-subtree) leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -390,7 +439,7 @@ def main():
                   "unit": "GB/s"}
     log(f"merge kernel: {merge_avg:.3f} ms, {achieved:.1f} GB/s algorithmic "
         f"({achieved / HBM_PEAK_GBPS * 100:.1f}%); whole step {step_ach / HBM_PEAK_GBPS * 100:.1f}%")
-    merges = element_merges(xs, bss)
+    merges, flat_merges = element_merges(xs, bss)
 
     plain = grid = topdown = None
     if not args.no_plain:
@@ -436,6 +485,13 @@ def main():
         topdown = round(n / best / 1e9, 2)
         log(f"top-down decode (ablation): {best * 1e3:.2f} ms, {topdown} GB/s")
         del out2, ws
+
+    flat = None
+    if not args.no_flat:
+        log("v2 streams (flat-subtree trees) ...")
+        flat = flat_leg(torch, P, d_xs, bss, w.ans_mode, tune if args.variant is not None else None,
+                        args.steps, args.warmup, n, merges, flat_merges)
+        log("v2:", flat)
 
     if args.copy_probe:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -484,6 +540,7 @@ def main():
         "compression_ratio": round(n / comp, 4),
         "element_merges": {"per_launch": merges, "mean_code_len": round(merges / n, 4),
                            "G_per_s": round(merges / (merge_avg * 1e-3) / 1e9, 1)},
+        "flat_v2": flat,
         "serving": serve,
         "golomb": golomb,
         "cpu_baseline": cpu,

@@ -131,7 +131,8 @@ struct BlockHdr {
   uint8_t gn[18];          // per depth: group nodes (groups of two or more symbols)
   uint8_t nfl[18];         // per level: flat nodes (the level's first nodes)
   uint64_t lvl_total[17];  // bits staged per level (sum of n_v D); set by the merge kernel for streamed blocks
-  uint32_t pad2[2];        // the node tables start at a multiple of 16 bytes
+  uint32_t nflat;          // flat nodes of the block (0: binary nodes only)
+  uint32_t pad2;           // the node tables start at a multiple of 16 bytes
 };
 static_assert(offsetof(BlockHdr, job) == offsetof(BlockExt, job) && sizeof(BlockExt) == 48, "BlockExt prefix");
 
@@ -361,8 +362,10 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
     h.gn[lane] = static_cast<uint8_t>(gn_l);
     h.nfl[lane] = static_cast<uint8_t>(nf_l);
   }
+  const uint32_t nflat = static_cast<uint32_t>(__shfl(static_cast<int>(wave_incl_scan(lane <= 17 ? nf_l : 0u)), kWave - 1, kWave));
   if (lane == 0) {
     h.I = I; h.maxlen = levels; h.kb = kb; h.raw_base = raw_base; h.err = err; h.kraft = kraft;
+    h.nflat = nflat;
   }
   if (err) { wave_sync_lds(); return; }
   // symbols in canonical order
@@ -836,6 +839,10 @@ __device__ __forceinline__ uint32_t flat_tag(const MergeSmem<C> &sm, const NodeT
   return 0x80000000u | (static_cast<uint32_t>(t.fd[v]) << 24) | a;
 }
 
+// Tasks skipped after a level's nft flat tasks so that its binary tasks
+// start a window of their own.
+__device__ __forceinline__ uint32_t flat_pad(uint32_t nft) { return (kWave - nft % kWave) % kWave; }
+
 // Streaming tile: largest multiple of 1024 (at most C::T) whose staged words fit.
 template <class C>
 __device__ uint32_t pick_tile_streaming(const BlockHdr &h, const NodeTab &t) {
@@ -896,7 +903,7 @@ __device__ __forceinline__ uint64_t wave_excl_scan64(uint64_t v, uint64_t &total
 // and the compacted list of the level's nodes with work (with a prefix of
 // their 16-output tasks) come from wave-wide prefix sums.  Cursors advance
 // here.
-template <class C>
+template <class C, bool FLAT>
 __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
   const uint32_t lane = lane_id();
   BlockHdr &h = sm.pb.h;
@@ -936,7 +943,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
     const uint64_t ex = wave_excl_scan64(pk, tot);
     // the level's flat nodes are its first nfl nodes: their tasks are the
     // tasks before lane nfl of the first pass
-    if (v0 == h.lvl[d])
+    if (FLAT && v0 == h.lvl[d])
       ftask = static_cast<uint32_t>(__shfl(ex, static_cast<int>(h.nfl[d]), kWave) >> 32) & 0xFFFF;
     if (valid) {
       const uint32_t ob = out_top + static_cast<uint32_t>(ex & 0xFFFFFFFFu);
@@ -955,10 +962,12 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
       }
       if (isact) {
         const uint32_t ai = act_top + static_cast<uint32_t>(ex >> 48);
-        const uint32_t tp = task_top + static_cast<uint32_t>((ex >> 32) & 0xFFFF);
+        const bool fl = FLAT && t.fd[v];
+        const uint32_t tp = task_top + static_cast<uint32_t>((ex >> 32) & 0xFFFF) +
+                            (FLAT && !fl ? flat_pad(ftask) : 0u);
         NodeRec r;
         r.x0 = x0;
-        r.arank = t.fd[v] ? flat_tag<C>(sm, t, v) : 0u;
+        r.arank = fl ? flat_tag<C>(sm, t, v) : 0u;
         r.ot = sm.obase[v] | (tp << 16);
         r.kids = kids;
         list_node<C>(sm, d, ai, act_base + ai, tp, tasks, r);
@@ -971,7 +980,7 @@ __device__ void count_level_streaming(MergeSmem<C> &sm, uint32_t d) {
     wave_sync_lds();
   }
   if (lane == 0) {
-    sm.ntask[d] = task_top;
+    sm.ntask[d] = task_top + (FLAT ? flat_pad(ftask) : 0u);
     sm.nftask[d] = ftask;
     sm.actbase[d] = act_base;
     sm.act_run = act_base + act_top;
@@ -1042,7 +1051,7 @@ __device__ void count_last(MergeSmem<C> &sm) {
 // node's output offset in its level buffer, its slot in the level's list of
 // nodes with work and the tasks before it; the merge records follow, and
 // the cursors advance.
-template <class C>
+template <class C, bool FLAT>
 __device__ void tile_lists(MergeSmem<C> &sm) {
   const int tid = item_tid();
   const int wave = wave_id();
@@ -1085,10 +1094,12 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
       kids |= code << (16 * bb);
     }
     if (tvv) {
-      const uint32_t tp = static_cast<uint32_t>(rel >> 32) & 0xFFFF;
-      const uint32_t fdv = t.fd[v];
+      const uint32_t fdv = FLAT ? t.fd[v] : 0u;
+      uint32_t tp = static_cast<uint32_t>(rel >> 32) & 0xFFFF;
+      if (FLAT && !fdv && h.nfl[d])         // binary tasks start after the padded flat ones
+        tp += flat_pad(static_cast<uint32_t>((pfx[h.lvl[d] + h.nfl[d]] - pfx[h.lvl[d]]) >> 32) & 0xFFFF);
       NodeRec r;
-      r.x0 = sm.abit[v] + (fdv ? fdv : 1u) * sm.cur[v];     // a flat node keeps D bits per symbol
+      r.x0 = sm.abit[v] + (fdv ? fdv * sm.cur[v] : sm.cur[v]);     // a flat node keeps D bits per symbol
       r.arank = fdv ? flat_tag<C>(sm, t, v) : sm.arank[v];
       r.ot = static_cast<uint32_t>(rel) | (tp << 16);
       r.kids = kids;
@@ -1100,9 +1111,14 @@ __device__ void tile_lists(MergeSmem<C> &sm) {
   }
   if (static_cast<uint32_t>(tid) < h.maxlen) {
     const uint64_t tot = pfx[h.lvl[tid + 1]] - pfx[h.lvl[tid]];
-    const uint64_t ftot = pfx[h.lvl[tid] + h.nfl[tid]] - pfx[h.lvl[tid]];   // the level's flat nodes come first
-    sm.ntask[tid] = static_cast<uint32_t>(tot >> 32) & 0xFFFF;
-    sm.nftask[tid] = static_cast<uint32_t>(ftot >> 32) & 0xFFFF;
+    if (FLAT) {
+      const uint64_t ftot = pfx[h.lvl[tid] + h.nfl[tid]] - pfx[h.lvl[tid]];   // the level's flat nodes come first
+      const uint32_t nft = static_cast<uint32_t>(ftot >> 32) & 0xFFFF;
+      sm.ntask[tid] = (static_cast<uint32_t>(tot >> 32) & 0xFFFF) + flat_pad(nft);
+      sm.nftask[tid] = nft;
+    } else {
+      sm.ntask[tid] = static_cast<uint32_t>(tot >> 32) & 0xFFFF;
+    }
     sm.actbase[tid] = static_cast<uint32_t>(pfx[h.lvl[tid]] >> 48);
   }
   lds_barrier();
@@ -1253,7 +1269,7 @@ __device__ __forceinline__ void merge_flat_window(MergeSmem<C> &sm, int d, uint3
 }
 
 template <class C, bool RESIDENT, int N, bool ROOT>
-__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t *w, uint32_t tlo,
+__device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uint32_t *w,
                                               uint32_t ntask, uint32_t abase, uint8_t *out) {
   const uint32_t lane = lane_id();
   constexpr int G = C::K / 4;                  // groups of 4 outputs
@@ -1268,7 +1284,7 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
     // last node and works on that node's first task (and stores nothing).
     const uint64_t B = sm.smask[d][w[i]];
     const uint32_t slot = sm.wstart[d][w[i]] + static_cast<uint32_t>(__popcll(B & upto));
-    valid[i] = kWave * w[i] + lane < ntask && kWave * w[i] + lane >= tlo;   // tasks below tlo are flat
+    valid[i] = kWave * w[i] + lane < ntask;
     r[i] = sm.rec[abase + slot];
   }
   uint32_t j0[N], bits[N], r1[N];
@@ -1340,36 +1356,39 @@ __device__ __forceinline__ void merge_windows(MergeSmem<C> &sm, int d, const uin
   }
 }
 
-// One level of a tile: first the windows of its flat tasks (a prefix of the
-// level's tasks), then the binary tasks, a wave taking up to C::LOCK of
-// their windows at once; the window holding both kinds is visited by both
-// loops, each lane doing only its own kind.
-template <class C, bool RESIDENT, bool ROOT>
+// One level of a tile: first the windows of its flat tasks, then the binary
+// tasks, a wave taking up to C::LOCK of their windows at once.  The flat
+// tasks are the level's first nft tasks, and its binary tasks start at the
+// next multiple of 64 (flat_pad): no window holds both kinds.
+template <class C, bool RESIDENT, bool ROOT, bool FLAT>
 __device__ __forceinline__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *out) {
   const uint32_t wave = wave_id();
-  const uint32_t ntask = sm.ntask[d], nft = sm.nftask[d], abase = sm.actbase[d];
+  const uint32_t ntask = sm.ntask[d], abase = sm.actbase[d];
   const uint32_t nwin = (ntask + kWave - 1) / kWave;
-  for (uint32_t w = wave; kWave * w < nft; w += C::NW) merge_flat_window<C, RESIDENT, ROOT>(sm, d, w, nft, abase, out);
-  // binary windows from the one holding task nft, dealt to the waves after the flat ones
-  const uint32_t w0 = nft / kWave, nfw = (nft + kWave - 1) / kWave;
-  const uint32_t wv = (wave + C::NW - nfw % C::NW) % C::NW;
-  for (uint32_t w = w0 + wv; w < nwin; w += C::LOCK * C::NW) {
+  uint32_t nfw = 0, wv = wave;
+  if (FLAT) {
+    const uint32_t nft = sm.nftask[d];
+    nfw = (nft + kWave - 1) / kWave;
+    for (uint32_t w = wave; w < nfw; w += C::NW) merge_flat_window<C, RESIDENT, ROOT>(sm, d, w, nft, abase, out);
+    wv = (wave + C::NW - nfw % C::NW) % C::NW;   // binary windows go first to the waves after the flat ones
+  }
+  for (uint32_t w = nfw + wv; w < nwin; w += C::LOCK * C::NW) {
     const uint32_t left = (nwin - w + C::NW - 1) / C::NW;   // windows of this wave from w on
     const uint32_t ww[4] = {w, w + C::NW, w + 2 * C::NW, w + 3 * C::NW};
-    if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1), ROOT>(sm, d, ww, nft, ntask, abase, out);
-    else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1), ROOT>(sm, d, ww, nft, ntask, abase, out);
-    else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1), ROOT>(sm, d, ww, nft, ntask, abase, out);
-    else merge_windows<C, RESIDENT, 1, ROOT>(sm, d, ww, nft, ntask, abase, out);
+    if (C::LOCK >= 4 && left >= 4) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 4 : 1), ROOT>(sm, d, ww, ntask, abase, out);
+    else if (C::LOCK >= 4 && left == 3) merge_windows<C, RESIDENT, (C::LOCK >= 4 ? 3 : 1), ROOT>(sm, d, ww, ntask, abase, out);
+    else if (C::LOCK >= 2 && left >= 2) merge_windows<C, RESIDENT, (C::LOCK >= 2 ? 2 : 1), ROOT>(sm, d, ww, ntask, abase, out);
+    else merge_windows<C, RESIDENT, 1, ROOT>(sm, d, ww, ntask, abase, out);
   }
   lds_barrier();
 }
 
 // All levels of the tile, deepest first (into LDS), the root last (into
 // HBM); one barrier per level.
-template <class C, bool RESIDENT>
+template <class C, bool RESIDENT, bool FLAT>
 __device__ __forceinline__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
-  for (int d = maxd - 1; d >= 1; --d) merge_level<C, RESIDENT, false>(sm, d, out);
-  merge_level<C, RESIDENT, true>(sm, 0, out);
+  for (int d = maxd - 1; d >= 1; --d) merge_level<C, RESIDENT, false, FLAT>(sm, d, out);
+  merge_level<C, RESIDENT, true, FLAT>(sm, 0, out);
 }
 
 // The block's extent and owner from the first 48 bytes of its record.
@@ -1654,6 +1673,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
   }
   const uint32_t T = sm.tile;
   const uint32_t maxd = h.maxlen;        // internal levels are 0 .. maxd-1
+  const bool flat = h.nflat != 0;
   bool bad = false;
 
   publish_next<C>(sm, la);            // visible after the next barrier
@@ -1675,18 +1695,28 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
         }
         lds_barrier();
       }
-      tile_lists<C>(sm);
+      if (flat) tile_lists<C, true>(sm);
+      else tile_lists<C, false>(sm);
     } else {
       for (uint32_t d = 0; d < maxd; ++d) {
         stage_level_streaming<C>(J, sm, d, scratch, scratch_words);
         lds_barrier();
-        if (wave == 0) count_level_streaming<C>(sm, d);
+        if (wave == 0) {
+          if (flat) count_level_streaming<C, true>(sm, d);
+          else count_level_streaming<C, false>(sm, d);
+        }
         lds_barrier();
       }
     }
     if (h.err) { bad = true; break; }
-    if (resident) merge_tile<C, true>(sm, static_cast<int>(maxd), out + t0);
-    else merge_tile<C, false>(sm, static_cast<int>(maxd), out + t0);
+    // blocks without flat nodes run code with no flat paths in it
+    if (resident) {
+      if (flat) merge_tile<C, true, true>(sm, static_cast<int>(maxd), out + t0);
+      else merge_tile<C, true, false>(sm, static_cast<int>(maxd), out + t0);
+    } else {
+      if (flat) merge_tile<C, false, true>(sm, static_cast<int>(maxd), out + t0);
+      else merge_tile<C, false, false>(sm, static_cast<int>(maxd), out + t0);
+    }
     if (!resident) {
       for (uint32_t i = tid; i < I; i += C::NT) sm.tv[i] = 0;
       lds_barrier();
