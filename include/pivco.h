@@ -29,6 +29,12 @@
  * of rANS scratch offsets, then blocks.  Each block holds its 4-bit code
  * lengths (128 bytes, App. D), one kind bit and one count of 1 bits per
  * internal node (breadth-first order), the raw bitmaps, then the rANS bodies.
+ * A v2 stream (version 2) is the same with the flat-subtree tree of Sec.
+ * 2.2.3-2.2.4 in every coded block: the symbols of each code length are cut
+ * into power-of-two groups (largest first) and a group of 2^D >= 4 symbols is
+ * one flat node, whose body holds a D-bit index into its group per passing
+ * symbol (ceil(n_v D / 8) bytes, App. D).  Every decode entry point reads v1
+ * and v2 streams.
  */
 #ifndef PIVCO_H
 #define PIVCO_H
@@ -161,7 +167,8 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
  * node splits the positions that reach it by its bits, stably, into its
  * children's lists (partition), and a leaf writes its symbol at the
  * positions that reach it (scatter).  Same jobs, workspace, statuses and
- * validation as pivco_decode_batch; the decoded bytes are identical. */
+ * validation as pivco_decode_batch; the decoded bytes are identical.  v2
+ * streams (flat-subtree trees) get PIVCO_E_UNSUPPORTED. */
 pivco_status pivco_decode_topdown(const pivco_job *h_jobs, uint32_t count, int32_t *d_status,
                                   void *d_ws, uint64_t ws_bytes, hipStream_t s);
 
