@@ -7,9 +7,9 @@ LIB = os.path.join(HERE, "libpivco_ref.so")
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, f) for f in ("pivco_ref.c", "golomb_ref.c")]
+    srcs = [os.path.join(HERE, f) for f in ("pivco_ref.c", "golomb_ref.c", "fse_ref.c")]
     cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
-           *srcs, "-o", LIB + ".tmp"]
+           *srcs, "-lm", "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -34,6 +34,11 @@
  *   Internal nodes are numbered breadth-first: by depth, then left to right.
  *   Bit 0 = left child, bit 1 = right child (Listing 1).
  *
+ * Stream flags bit 0 (encoder ans_mode 3): entropy-coded nodes use the
+ * selective tANS of bitmap bytes (fse_ref.c) instead of binary rANS; such a
+ * body is marker u8 (table id 1..50 | 0x80 complemented) | 0 u8 | 0 u16 |
+ * body_len u32 | chunks.
+ *
  * Wire format v2 (version u16 = 2) is v1 with the flat-subtree tree of
  * Sec. 2.2.3-2.2.4 in place of the canonical one, derived from the same
  * length table (build_flat_tree).  Its nodes are numbered the same way; a
@@ -574,9 +579,13 @@ static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_
     for (int j = 0; j < 128; j++) out[o + j] = (uint8_t)(len[2 * j] | (len[2 * j + 1] << 4));
     o += 128;
     uint8_t kind[255];
+    uint32_t marker[255];
     for (int i = 0; i < I; i++) {
         tnode *v = &t->nd[t->bfs[i]];
-        kind[i] = v->flat ? 0 : (uint8_t)pivco_ref_select_ans(ans_mode, v->n, v->n_right);
+        marker[i] = 0;
+        if (v->flat) kind[i] = 0;
+        else if (ans_mode == 3) kind[i] = (uint8_t)pivco_ref_fse_select(v->n, v->n_right, (uint32_t)v->depth, &marker[i]);
+        else kind[i] = (uint8_t)pivco_ref_select_ans(ans_mode, v->n, v->n_right);
     }
     uint64_t kb = ((uint64_t)I + 7) / 8;
     if (o + kb + (uint64_t)cw * I > cap) { rc = PVO_E_CAPACITY; goto done; }
@@ -600,11 +609,18 @@ static int encode_block(const uint8_t *in, uint64_t n, uint32_t max_len, uint32_
         tnode *v = &t->nd[t->bfs[i]];
         while (o & 3) { if (o >= cap) { rc = PVO_E_CAPACITY; goto done; } out[o++] = 0; }
         if (o + 8 > cap) { rc = PVO_E_CAPACITY; goto done; }
-        uint32_t p1q = pivco_ref_p1q(v->n, v->n_right);
         uint64_t blen;
-        rc = pivco_ref_rans_encode(bm[i], v->n, p1q, chunk_log2, out + o + 8, cap - o - 8, &blen);
-        if (rc) goto done;
-        put16(out + o, p1q); put16(out + o + 2, 0); put32(out + o + 4, (uint32_t)blen);
+        if (ans_mode == 3) {
+            rc = pivco_ref_fse_encode(bm[i], v->n, marker[i], chunk_log2, out + o + 8, cap - o - 8, &blen);
+            if (rc) goto done;
+            out[o] = (uint8_t)marker[i]; out[o + 1] = 0; put16(out + o + 2, 0);
+        } else {
+            uint32_t p1q = pivco_ref_p1q(v->n, v->n_right);
+            rc = pivco_ref_rans_encode(bm[i], v->n, p1q, chunk_log2, out + o + 8, cap - o - 8, &blen);
+            if (rc) goto done;
+            put16(out + o, p1q); put16(out + o + 2, 0);
+        }
+        put32(out + o + 4, (uint32_t)blen);
         o += 8 + blen;
         *ans_words += (v->n + 31) / 32;
     }
@@ -621,7 +637,7 @@ static int encode_stream(const uint8_t *in, uint64_t n, uint32_t block_size,
                          const uint8_t *tree_len, int flat, uint8_t *out, uint64_t cap,
                          uint64_t *out_len) {
     if ((!in && n) || !out || !out_len || block_size == 0 || max_len < 1 || max_len > 15 ||
-        ans_mode > 2 || chunk_log2 < 5 || chunk_log2 > 24)
+        ans_mode > 3 || chunk_log2 < 5 || chunk_log2 > 24 || (ans_mode == 3 && chunk_log2 < 8))
         return PVO_E_ARG;
     uint64_t nb64 = (n + block_size - 1) / block_size;
     if (nb64 > 0xFFFFFFFFull) return PVO_E_ARG;
@@ -630,7 +646,7 @@ static int encode_stream(const uint8_t *in, uint64_t n, uint32_t block_size,
     if (o > cap) return PVO_E_CAPACITY;
     memset(out, 0, (size_t)o);
     put32(out, 0x31435650u);  /* "PVC1" */
-    put16(out + 4, flat ? 2 : 1); put16(out + 6, 0);
+    put16(out + 4, flat ? 2 : 1); put16(out + 6, ans_mode == 3 ? 1 : 0);
     put64(out + 8, n);
     put32(out + 16, block_size); put32(out + 20, nb);
     out[24] = (uint8_t)max_len; out[25] = (uint8_t)chunk_log2;
@@ -708,13 +724,13 @@ static void free_block(block_t *bk) {
 static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *bk) {
     memset(bk, 0, sizeof(*bk));
     uint32_t version = in_len >= HDR ? get16(in + 4) : 0;
-    if (in_len < HDR || get32(in) != 0x31435650u || (version != 1 && version != 2) ||
-        get16(in + 6) != 0)
+    uint32_t flags = in_len >= HDR ? get16(in + 6) : 0;
+    if (in_len < HDR || get32(in) != 0x31435650u || (version != 1 && version != 2) || flags > 1)
         return PVO_E_CORRUPT;
     bk->version = version;
     uint64_t n_total = get64(in + 8);
     uint32_t bs = get32(in + 16), nb = get32(in + 20), max_len = in[24], cl2 = in[25];
-    if (bs == 0 || max_len < 1 || max_len > 15 || cl2 < 5 || cl2 > 24) return PVO_E_CORRUPT;
+    if (bs == 0 || max_len < 1 || max_len > 15 || cl2 < 5 || cl2 > 24 || (flags && cl2 < 8)) return PVO_E_CORRUPT;
     if ((n_total + bs - 1) / bs != nb || b >= nb) return PVO_E_CORRUPT;
     uint64_t tab = HDR + 16 * ((uint64_t)nb + 1);
     if (tab > in_len) return PVO_E_CORRUPT;
@@ -783,9 +799,16 @@ static int parse_block(const uint8_t *in, uint64_t in_len, uint32_t b, block_t *
         tnode *v = &t->nd[t->bfs[i]];
         while (o & 3) { if (o >= comp || p[o]) { rc = PVO_E_CORRUPT; goto fail; } o++; }
         if (o + 8 > comp || v->n == 0) { rc = PVO_E_CORRUPT; goto fail; }
-        uint32_t p1q = get16(p + o), blen = get32(p + o + 4);
+        uint32_t blen = get32(p + o + 4);
         if (get16(p + o + 2) != 0 || o + 8 + blen > comp) { rc = PVO_E_CORRUPT; goto fail; }
-        if (pivco_ref_rans_decode(p + o + 8, blen, v->n, p1q, cl2, bk->bm[i])) { rc = PVO_E_CORRUPT; goto fail; }
+        if (flags) {
+            if (p[o + 1] != 0 || pivco_ref_fse_decode(p + o + 8, blen, v->n, p[o], cl2, bk->bm[i])) {
+                rc = PVO_E_CORRUPT; goto fail;
+            }
+        } else {
+            uint32_t p1q = get16(p + o);
+            if (pivco_ref_rans_decode(p + o + 8, blen, v->n, p1q, cl2, bk->bm[i])) { rc = PVO_E_CORRUPT; goto fail; }
+        }
         o += 8 + blen;
         aw += (v->n + 31) / 32;
     }
@@ -808,7 +831,7 @@ fail:
 static int check_stream(const uint8_t *in, uint64_t in_len, uint64_t *n_total, uint32_t *nb,
                         uint32_t *bs) {
     if (!in || in_len < HDR || get32(in) != 0x31435650u || (get16(in + 4) != 1 && get16(in + 4) != 2) ||
-        get16(in + 6) != 0)
+        get16(in + 6) > 1)
         return PVO_E_CORRUPT;
     *n_total = get64(in + 8); *bs = get32(in + 16); *nb = get32(in + 20);
     if (*bs == 0 || (*n_total + *bs - 1) / *bs != *nb) return PVO_E_CORRUPT;

@@ -125,6 +125,21 @@ int pivco_ref_classical_decode(const uint8_t *bits, uint64_t nbits,
 int pivco_ref_pivoted_to_classical(const uint8_t *in, uint64_t in_len,
                                    uint8_t *out, uint64_t cap, uint64_t *nbits);
 
+/* Selective tANS of node bitmaps as bytes (Sec. 5.2, App. D, App. F;
+ * fse_ref.c documents the readings): ans_mode 3 of the encoder, stream flags
+ * bit 0.  fse_norm: table t's (1..50) normalized counts (sum 2^11).
+ * fse_cost: its expected bits per bitmap bit at its own skew.  fse_select:
+ * the selection rule; sets *marker = t | 0x80 if coded complemented.
+ * fse_encode/fse_decode: a node body's chunks (without the 8-byte node
+ * header) for a bitmap of nbits bits (ceil(nbits/8) bytes). */
+int pivco_ref_fse_norm(uint32_t t, uint16_t norm[256]);
+double pivco_ref_fse_cost(uint32_t t);
+int pivco_ref_fse_select(uint64_t n_v, uint64_t n_right, uint32_t depth, uint32_t *marker);
+int pivco_ref_fse_encode(const uint8_t *bits, uint64_t nbits, uint32_t marker, uint32_t chunk_log2,
+                         uint8_t *out, uint64_t cap, uint64_t *out_len);
+int pivco_ref_fse_decode(const uint8_t *body, uint64_t body_len, uint64_t nbits, uint32_t marker,
+                         uint32_t chunk_log2, uint8_t *bits);
+
 /* Per-block introspection of a stream: code lengths, internal-node count,
  * per-node (BFS order) depth, n_v, n_right, coding kind and flat depth D (0
  * for binary nodes; may be NULL). Arrays of 255. */

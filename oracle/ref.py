@@ -55,6 +55,12 @@ def lib():
             "pivco_ref_pivoted_to_classical": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
             "pivco_ref_block_info": (C.c_int, [u8p, C.c_uint64, C.c_uint32, u8p, u32p, u32p, u8p,
                                                u64p, u64p, u8p, u8p]),
+            "pivco_ref_fse_norm": (C.c_int, [C.c_uint32, u16p]),
+            "pivco_ref_fse_cost": (C.c_double, [C.c_uint32]),
+            "pivco_ref_fse_select": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint32, u32p]),
+            "pivco_ref_fse_encode": (C.c_int, [u8p, C.c_uint64, C.c_uint32, C.c_uint32, u8p, C.c_uint64,
+                                               u64p]),
+            "pivco_ref_fse_decode": (C.c_int, [u8p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, u8p]),
             "pivco_ref_golomb_bound": (C.c_uint64, [C.c_uint64, C.c_uint32]),
             "pivco_ref_golomb_encode": (C.c_int, [u8p, C.c_uint64, C.c_uint32, u8p, C.c_uint64, u64p]),
             "pivco_ref_golomb_decode": (C.c_int, [u8p, C.c_uint64, u8p, C.c_uint64, u64p]),
@@ -223,7 +229,44 @@ def block_info(stream, block):
             "flat": flat[:k].copy()}
 
 
+def fse_norm(t):
+    """Normalized counts (sum 2^11) of tANS table t (1..50)."""
+    out = np.zeros(256, dtype=np.uint16)
+    _check(lib().pivco_ref_fse_norm(t, out.ctypes.data_as(C.POINTER(C.c_uint16))), "fse_norm")
+    return out
+
+
+def fse_cost(t):
+    return float(lib().pivco_ref_fse_cost(t))
+
+
+def fse_select(n_v, n_right, depth):
+    """(selected, marker) of the selective-tANS rule."""
+    m = C.c_uint32(0)
+    r = lib().pivco_ref_fse_select(n_v, n_right, depth, C.byref(m))
+    return bool(r), m.value
+
+
+def fse_encode(bits_bytes, nbits, marker, chunk_log2=16):
+    b, bp = _u8(bits_bytes)
+    cap = 8 * b.size + 256 * ((nbits >> chunk_log2) + 1) + 64
+    out = np.zeros(cap, dtype=np.uint8)
+    ol = C.c_uint64(0)
+    _check(lib().pivco_ref_fse_encode(bp, nbits, marker, chunk_log2, out.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                      cap, C.byref(ol)), "fse_encode")
+    return out[:ol.value].copy()
+
+
+def fse_decode(body, nbits, marker, chunk_log2=16):
+    b, bp = _u8(body)
+    out = np.zeros((nbits + 7) // 8 + 1, dtype=np.uint8)
+    _check(lib().pivco_ref_fse_decode(bp, b.size, nbits, marker, chunk_log2,
+                                      out.ctypes.data_as(C.POINTER(C.c_uint8))), "fse_decode")
+    return out[:(nbits + 7) // 8]
+
+
 __all__ = ["OracleError", "lib", "lengths", "codes", "p1q", "select_ans", "rans_encode",
+           "fse_norm", "fse_cost", "fse_select", "fse_encode", "fse_decode",
            "rans_decode", "encode_bound", "encode", "stream_info", "decode", "decode_blocks",
            "classical_encode", "classical_decode", "pivoted_to_classical", "block_info",
            "golomb_encode", "golomb_decode", "golomb_decode_merge",

@@ -12,6 +12,8 @@ fast enough for small inputs.
                         ``flat_tree``
 * ``flat_tree``         the regrouped tree from code lengths: each length
                         class split by the binary digits of its size
+* ``fse_table``         the selective-tANS tables of the format (exact
+                        rationals) and a reader of such node bodies
 """
 import heapq
 import itertools
@@ -123,11 +125,70 @@ def flat_tree(lens):
     return nodes, leaf, groups
 
 
+def fse_table(t):
+    """tANS table t (1..50) from the format's readings, written afresh:
+    counts by largest remainder over P(b) = s^k (1-s)^(8-k), s = (t+49)/100,
+    the spread with step 1283, and the decoding entries (symbol, bits read,
+    base of the next state)."""
+    from fractions import Fraction
+    s = Fraction(t + 49, 100)
+    exact = [s ** bin(b).count("1") * (1 - s) ** (8 - bin(b).count("1")) * 2048 for b in range(256)]
+    norm = [max(1, int(e)) for e in exact]
+    frac = [e - int(e) if int(e) >= 1 else Fraction(0) for e in exact]
+    while sum(norm) < 2048:
+        b = max(range(256), key=lambda i: (frac[i], -i))
+        norm[b] += 1
+        frac[b] = Fraction(0)
+    if sum(norm) > 2048:
+        b = max(range(256), key=lambda i: (norm[i], -i))
+        norm[b] -= sum(norm) - 2048
+    spread, pos = [0] * 2048, 0
+    for b in range(256):
+        for _ in range(norm[b]):
+            spread[pos] = b
+            pos = (pos + 1283) % 2048
+    nxt = list(norm)
+    table = []
+    for X in range(2048):
+        b = spread[X]
+        k = nxt[b]
+        nxt[b] += 1
+        nb = 11 - (k.bit_length() - 1)
+        table.append((b, nb, (k << nb) - 2048))
+    return norm, table
+
+
+def fse_body_bits(body, nbits, marker, chunk_log2):
+    """Bitmap bits of a selective-tANS node body (32 cursors per chunk)."""
+    _, table = fse_table(marker & 0x7F)
+    flip = 0xFF if marker & 0x80 else 0
+    nbytes, cb = (nbits + 7) // 8, (1 << chunk_log2) // 8
+    out, o = bytearray(nbytes), 0
+    for c0 in range(0, nbytes, cb):
+        n = min(cb, nbytes - c0)
+        x0 = struct.unpack_from("<32H", body, o)
+        lens = struct.unpack_from("<32H", body, o + 64)
+        so = o + 128
+        for lane in range(32):
+            X, p = x0[lane], 0
+            stream = body[so:so + lens[lane]]
+            for i in range((n - lane + 31) // 32 if n > lane else 0):
+                b, nb, base = table[X]
+                v = sum(((stream[(p + k) >> 3] >> ((p + k) & 7)) & 1) << k for k in range(nb))
+                p += nb
+                X = base + v
+                out[c0 + lane + 32 * i] = b ^ flip
+            assert X == 0 and (p + 7) // 8 == lens[lane]
+            so += lens[lane]
+        o = (so + 3) & ~3
+    return [(out[j >> 3] >> (j & 7)) & 1 for j in range(nbits)]
+
+
 def decode_stream(stream):
     """Decode a v1 or v2 stream (small inputs only)."""
     s = bytes(stream)
     magic, ver, flags, n_total, bs, nb, max_len, cl2 = struct.unpack_from("<IHHQIIBB", s, 0)
-    assert magic == 0x31435650 and ver in (1, 2) and flags == 0
+    assert magic == 0x31435650 and ver in (1, 2) and flags in (0, 1)
     offs = struct.unpack_from(f"<{nb + 1}Q", s, 48)
     out = bytearray()
     for b in range(nb):
@@ -175,7 +236,10 @@ def decode_stream(stream):
                 continue
             q = (q + 3) & ~3
             p1q, _, blen = struct.unpack_from("<HHI", s, q)
-            bitmaps[node] = _rans_bits(s[q + 8:q + 8 + blen], nv[node], p1q, cl2)
+            if flags:                            # selective tANS on bytes
+                bitmaps[node] = fse_body_bits(s[q + 8:q + 8 + blen], nv[node], p1q & 0xFF, cl2)
+            else:
+                bitmaps[node] = _rans_bits(s[q + 8:q + 8 + blen], nv[node], p1q, cl2)
             q += 8 + blen
         cursor = {node: 0 for node in internal}
         for _ in range(n):                       # Listing 1
