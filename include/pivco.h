@@ -8,7 +8,9 @@
  * under control of each node's bitmap (Sec. 3); encoding splits the codes
  * top-down and emits the bitmaps (Sec. 4, Table 11).  Skewed nodes may be
  * entropy-coded instead of stored raw (Sec. 5); here with 32-lane interleaved
- * binary rANS with 12-bit probabilities (method of ref. [4] of the paper).
+ * binary rANS with 12-bit probabilities (method of ref. [4] of the paper), or
+ * with the selective tANS of Sec. 5.2 (50 static byte tables for bitmap
+ * skews of 50..99%, 32 cursors per chunk, App. D's marker).
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are device pointers (HIP device memory, e.g. the
@@ -33,8 +35,15 @@
  * 2.2.3-2.2.4 in every coded block: the symbols of each code length are cut
  * into power-of-two groups (largest first) and a group of 2^D >= 4 symbols is
  * one flat node, whose body holds a D-bit index into its group per passing
- * symbol (ceil(n_v D / 8) bytes, App. D).  Every decode entry point reads v1
- * and v2 streams.
+ * symbol (ceil(n_v D / 8) bytes, App. D).  Stream flags bit 0 (header bytes
+ * 6-7) says that the entropy-coded nodes use the byte tANS tables instead of
+ * rANS: such a body is marker u8 (table t = 1..50 for a majority-bit
+ * fraction of (t + 49)%, | 0x80 when the bitmap is coded complemented) | 0 u8
+ * | 0 u16 | body length u32, then per chunk of 2^chunk_log2 bits (>= 2^8)
+ * 32 u16 cursor states, 32 u16 stream lengths, the 32 cursors' bit streams
+ * (cursor l codes bytes l, l + 32, ... of the chunk) and zero padding to 4
+ * bytes.  Every decode entry point reads v1 and v2 streams, with either
+ * coder.
  */
 #ifndef PIVCO_H
 #define PIVCO_H
@@ -67,8 +76,15 @@ typedef struct {
   uint32_t max_len;          /* code length limit; 11 as in App. D (8..12) */
   uint32_t ans_mode;         /* 0: raw bitmaps only; 1: rANS for nodes whose
                                 one-bit fraction is < 0.1 or > 0.9;
-                                2: rANS for every internal node (testing) */
-  uint32_t rans_chunk_log2;  /* bits per rANS chunk = 2^this; 16 */
+                                2: rANS for every internal node (testing);
+                                3: the selective byte tANS of Sec. 5.2 (a node
+                                of >= 256 bits whose majority-bit fraction f
+                                exceeds 0.625 takes table round(100 f) - 49 if
+                                (depth + h) / (depth + 1) < 0.95, h the
+                                table's expected bits per bit; stream flags
+                                bit 0) */
+  uint32_t rans_chunk_log2;  /* bits per entropy-coded chunk = 2^this; 16
+                                (5..24; 8..24 with ans_mode 3) */
   const pivco_tree *tree;    /* NULL: one optimal tree per block from its
                                 histogram; else this tree for every block */
   uint32_t tree_shape;       /* 0: canonical trees (a v1 stream); 1: the
@@ -106,12 +122,15 @@ uint64_t pivco_encode_bound(uint64_t n, const pivco_encode_opts *o);
 /* Device workspace bytes pivco_encode needs for n input bytes. */
 uint64_t pivco_encode_workspace(uint64_t n, const pivco_encode_opts *o);
 
-/* Encode n bytes at d_in into a v1 stream at d_out.  Synchronous: it waits
- * for the block histograms (the host builds the trees) and for the rANS
- * body sizes, and returns the stream length in *h_out_len.  The stream is
- * byte-identical to the one the format definition implies.  Errors:
- * E_ARG (bad options or a supplied tree that misses a symbol present in the
- * data), E_CAPACITY (out_cap or ws_bytes too small), E_DEVICE. */
+/* Encode n bytes at d_in into a v1 (or, with tree_shape 1, v2) stream at
+ * d_out.  Synchronous: it waits for the block histograms (the host builds
+ * the trees) and for the entropy-coded body sizes, and returns the stream
+ * length in *h_out_len.  The stream is byte-identical to the one the format
+ * definition implies.  Errors: E_ARG (bad options or a supplied tree that
+ * misses a symbol present in the data), E_CAPACITY (out_cap or ws_bytes too
+ * small), E_UNSUPPORTED (ans_mode 3 with 2^24-bit chunks only: a cursor's
+ * stream longer than its 16-bit length field), E_DEVICE.  The tANS tables are
+ * copied to the device on its first use (synchronously). */
 pivco_status pivco_encode(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
                           uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
                           uint64_t ws_bytes, hipStream_t s);
@@ -152,7 +171,9 @@ pivco_status pivco_decode(const void *d_in, uint64_t in_len, void *d_out, uint64
  * (other streams or threads) race, so callers serialise them; the next call
  * may start once this one's work on s has completed or is ordered after it
  * on the same stream.  Otherwise as pivco_decode (synchronous up to the
- * kernel launches, which read the stream header). */
+ * kernel launches, which read the stream header).  A stream with tANS nodes
+ * uses the library's static table arrays, copied to the GPU by the first
+ * call that needs them (a copy, not an allocation). */
 #define PIVCO_NOALLOC_SCRATCH_BYTES (32ull << 20)
 pivco_status pivco_decode_noalloc(const void *d_in, uint64_t in_len, void *d_out, uint64_t out_cap,
                                   int32_t *d_status, hipStream_t s);

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpivco.so")
-SOURCES = ["decode.hip", "encode.hip", "api.cpp", "tree.cpp", "serve.cpp", "noalloc.hip", "golomb.hip"]
+SOURCES = ["decode.hip", "encode.hip", "fse.hip", "api.cpp", "tree.cpp", "serve.cpp", "noalloc.hip", "golomb.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -61,15 +61,16 @@ int device_cus() {
 
 struct StreamHdr {
   uint64_t n_total = 0, ans_words = 0;
-  uint32_t block_size = 0, n_blocks = 0, max_len = 0, chunk_log2 = 0, version = 1;
+  uint32_t block_size = 0, n_blocks = 0, max_len = 0, chunk_log2 = 0, version = 1, flags = 0;
 };
 
 // Parses the 48-byte stream header; returns PIVCO_OK or PIVCO_E_CORRUPT.
 pivco_status parse_stream_header(const uint8_t *h, uint64_t avail, StreamHdr *o) {
   if (avail < kHeaderBytes) return PIVCO_E_CORRUPT;
-  const uint32_t ver = rd16(h + 4);
-  if (rd32(h) != kMagic || (ver != 1 && ver != 2) || rd16(h + 6) != 0) return PIVCO_E_CORRUPT;
+  const uint32_t ver = rd16(h + 4), flags = rd16(h + 6);
+  if (rd32(h) != kMagic || (ver != 1 && ver != 2) || flags > 1) return PIVCO_E_CORRUPT;
   o->version = ver;
+  o->flags = flags;
   o->n_total = rd64(h + 8);
   o->block_size = rd32(h + 16);
   o->n_blocks = rd32(h + 20);
@@ -77,7 +78,7 @@ pivco_status parse_stream_header(const uint8_t *h, uint64_t avail, StreamHdr *o)
   o->chunk_log2 = h[25];
   o->ans_words = rd64(h + 32);
   if (o->block_size == 0 || o->max_len < 1 || o->max_len > 15 || o->chunk_log2 < 5 ||
-      o->chunk_log2 > 24)
+      o->chunk_log2 > 24 || (o->flags && o->chunk_log2 < 8))   // a tANS chunk holds whole 32-byte steps
     return PIVCO_E_CORRUPT;
   if (div_up(o->n_total, o->block_size) != o->n_blocks) return PIVCO_E_CORRUPT;
   return PIVCO_OK;
@@ -90,7 +91,8 @@ struct HostPlan {
   WorkLists w;                 // blocks, rANS blocks, split blocks, merge items
   std::vector<int32_t> status0;
   uint64_t scratch_words = 0;
-  uint64_t chunk_cap = 0;      // rANS chunk list capacity (bound over the jobs)
+  uint64_t chunk_cap = 0;      // entropy-coded chunk list capacity (bound over the jobs)
+  uint32_t coders = 0;         // bit 0: some job has rANS nodes; bit 1: tANS nodes
   // workspace layout (byte offsets)
   uint64_t off_ctr = 0, off_jobs = 0, off_blocks = 0, off_items = 0, off_ritems = 0,
            off_tiled = 0, off_status0 = 0, off_recs = 0, off_tab = 0, off_chunks = 0, off_scratch = 0,
@@ -158,6 +160,7 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
   p.status0.assign(count, PIVCO_OK);
   p.w.clear();
   p.chunk_cap = 0;
+  p.coders = 0;
   uint64_t sw = 0;
   std::vector<StreamHdr> hs(count);
   std::vector<pivco_status> sts(count);
@@ -189,7 +192,9 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
     d.block_size = sh.block_size;
     d.max_len = static_cast<uint16_t>(sh.max_len);
     d.chunk_log2 = static_cast<uint16_t>(sh.chunk_log2);
-    d.version = sh.version;
+    d.version = static_cast<uint16_t>(sh.version);
+    d.flags = static_cast<uint16_t>(sh.flags);
+    if (sh.ans_words) p.coders |= sh.flags ? 2u : 1u;
     d.scratch_base = sw;
     d.ans_words = sh.ans_words;
     sw = align_up(sw + sh.ans_words, 4);
@@ -199,6 +204,7 @@ pivco_status build_plan(const pivco_job *h_jobs, uint32_t count, const std::vect
   }
   p.w.finish();
   if (p.w.items.size() > 0xFFFFFFF0ull || p.w.blocks.size() > 0xFFFFFFF0ull) return PIVCO_E_UNSUPPORTED;
+  if ((p.coders & 2) && !fse_tables()) return PIVCO_E_DEVICE;   // tables on this device, before any launch
   p.scratch_words = sw;
   layout(p);
   return PIVCO_OK;
@@ -273,7 +279,7 @@ pivco_status enqueue_batch(const HostPlan &p, void *d_ws, int32_t *d_status, con
     return PIVCO_E_DEVICE;
   if (!w.ritems.empty() &&
       launch_rans(t.rans_grid, s, d.jobs, d.recs, d.ritems, d.ctr, d.chunks, p.chunk_cap, d.scratch,
-                  -1) != hipSuccess)
+                  -1, p.coders) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
@@ -438,7 +444,7 @@ pivco_status pivco_decode_plain(const pivco_job *h_jobs, uint32_t count, int32_t
   // one merge launch per item, in stream order
   for (size_t r = 0; r < w.ritems.size(); ++r)
     if (launch_rans(1, s, d.jobs, d.recs, d.ritems, d.ctr, d.chunks, p.chunk_cap, d.scratch,
-                    static_cast<int32_t>(r)) != hipSuccess)
+                    static_cast<int32_t>(r), p.coders) != hipSuccess)
       return PIVCO_E_DEVICE;
   if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)
@@ -472,7 +478,7 @@ pivco_status pivco_decode_topdown(const pivco_job *h_jobs, uint32_t count, int32
     return PIVCO_E_DEVICE;
   if (!w.ritems.empty() &&
       launch_rans(t.rans_grid, s, d.jobs, d.recs, d.ritems, d.ctr, d.chunks, p.chunk_cap, d.scratch,
-                  kQueueItems) != hipSuccess)
+                  kQueueItems, p.coders) != hipSuccess)
     return PIVCO_E_DEVICE;
   if (launch_tiles(s, d.jobs, d.tiled, static_cast<uint32_t>(w.tiled.size()), d.recs,
                    d.scratch, p.scratch_words, d.tab) != hipSuccess)

@@ -525,16 +525,21 @@ constexpr int kRansNT = 256;
 constexpr int kRansWin = 2048;        // u16 words per half-wave window in LDS
 constexpr uint32_t kRansSteps = 32;   // steps per window check (one output word per lane)
 
-// Lists the rANS chunks of the block parsed in h/t (one lane): walks the
-// rANS bodies that follow the raw bodies (each: u16 probability, u16 zero,
-// u32 length, then per chunk of 2^chunk_log2 bits a u32 word count, the 32
-// u32 lane states and the words, padded to 4 bytes), checks every size, and
+// Lists the entropy-coded chunks of the block parsed in h/t (one lane):
+// walks the bodies that follow the raw bodies, checks every size, and
 // appends the chunks to the batch's list (a first pass counts them and
-// reserves their slots).  Returns a status.
+// reserves their slots).  A rANS body is u16 probability, u16 zero, u32
+// length, then per chunk of 2^chunk_log2 bits a u32 word count, the 32 u32
+// lane states and the words, padded to 4 bytes.  In a stream with flags bit
+// 0 a body is the tANS marker u8 (table 1..50, 0x80: complemented), u8
+// zero, u16 zero, u32 length, then per chunk the 32 u16 cursor states, the
+// 32 u16 stream lengths, the streams and zero padding to 4 bytes.  Returns
+// a status.
 __device__ int32_t walk_rans(const JobDev &J, BlockHdr &h, const NodeTab &t, Counters *ctr,
                              RansChunk *chunks, uint64_t cap) {
   const uint8_t *bp = J.in + h.blk;
   const uint64_t comp = h.comp, C = 1ull << J.chunk_log2;
+  const bool fse = J.flags & 1;
   for (int pass = 0; pass < 2; ++pass) {
     uint32_t nch = 0;
     uint64_t o = h.raw_end;
@@ -545,18 +550,38 @@ __device__ int32_t walk_rans(const JobDev &J, BlockHdr &h, const NodeTab &t, Cou
         ++o;
       }
       if (o + 8 > comp || t.nv[i] == 0) return PIVCO_E_CORRUPT;
-      const uint32_t p1q = bp[o] | (bp[o + 1] << 8);
+      const uint32_t w0 = bp[o] | (bp[o + 1] << 8);
       const uint32_t pad = bp[o + 2] | (bp[o + 3] << 8);
       const uint32_t blen = *reinterpret_cast<const uint32_t *>(bp + o + 4);
-      if (pad || p1q < 1 || p1q > 4095 || o + 8 + blen > comp) return PIVCO_E_CORRUPT;
+      const uint32_t tt = w0 & 0x7F;
+      if (pad || o + 8 + blen > comp) return PIVCO_E_CORRUPT;
+      if (fse ? ((w0 >> 8) || tt < 1 || tt > kFseTables) : (w0 < 1 || w0 > 4095)) return PIVCO_E_CORRUPT;
+      const uint32_t p1q = fse ? kFseTag | w0 : w0;
       const uint64_t body = o + 8;
       uint64_t co = 0;
       const uint64_t nv = t.nv[i];
       for (uint64_t s = 0; s < nv; s += C) {
-        if (co + kChunkHdr > blen) return PIVCO_E_CORRUPT;
-        const uint32_t nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
-        const uint64_t size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
-        if (nw > C || co + size > blen) return PIVCO_E_CORRUPT;
+        uint32_t nw;
+        uint64_t size;
+        if (fse) {
+          if (co + kFseChunkHdr > blen) return PIVCO_E_CORRUPT;
+          const uint32_t *lens = reinterpret_cast<const uint32_t *>(bp + body + co + 2 * kFseLanes);
+          nw = 0;
+          for (uint32_t q = 0; q < kFseLanes / 2; ++q) {
+            const uint32_t v = lens[q];
+            nw += (v & 0xFFFF) + (v >> 16);
+          }
+          const uint64_t used = kFseChunkHdr + static_cast<uint64_t>(nw);
+          size = (used + 3) & ~3ull;
+          if (co + size > blen) return PIVCO_E_CORRUPT;
+          for (uint64_t u = used; u < size; ++u)
+            if (bp[body + co + u]) return PIVCO_E_CORRUPT;
+        } else {
+          if (co + kChunkHdr > blen) return PIVCO_E_CORRUPT;
+          nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
+          size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
+          if (nw > C || co + size > blen) return PIVCO_E_CORRUPT;
+        }
         if (pass == 1) {
           RansChunk c;
           c.src = h.blk + body + co;
@@ -639,6 +664,7 @@ __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t 
   const uint32_t idx = half ? ib : ia;
   RansChunk c = RansChunk{0, 0, 0, 0, 1, 0};
   if (idx < end) c = chunks[idx];
+  if (c.p1q & kFseTag) c = RansChunk{0, 0, 0, 0, 1, 0};   // a tANS chunk: k_fse's
   const bool has = c.nbits != 0;
   const uint8_t *base = has ? jobs[c.job].in + c.src : nullptr;
   uint32_t x = has ? reinterpret_cast<const uint32_t *>(base)[1 + hl] : kRansL;
@@ -738,6 +764,175 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const Pars
     const uint32_t ia = first + 2 * pair;
     if (ia >= end) break;
     rans_pair(jobs, chunks, ia, ia + 1, end, scratch, win[wave], stage[wave]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel: selective tANS decode of byte-coded node bitmaps into scratch
+// ---------------------------------------------------------------------------
+// In a stream with flags bit 0 the entropy-coded nodes are coded as bytes
+// with one of 50 static tANS tables (Sec. 5.2).  The plan kernel lists their
+// chunks in the same list as rANS chunks (p1q = kFseTag | marker); k_fse
+// decodes them two at a time per wave, lanes 0-31 one chunk's 32 cursors,
+// lanes 32-63 another's.  Cursor l owns bytes l, l + 32, ... of its chunk
+// and reads its own bit stream.  Per step a cursor looks its state up in the
+// chunk's decoding table (in LDS; reloaded only when the half's table
+// changes), takes the entry's bit count from a 64-bit buffer and stages its
+// byte in LDS; every 32 steps the half's 1 KiB of bytes goes out as
+// coalesced words.  The buffer is refilled from a queue of kFseQ words that
+// every lane loads at the start of each group of kFseG steps, so a group
+// waits for memory once.
+constexpr int kFseNT = 256;
+constexpr uint32_t kFseG = 16;   // steps per group: at most 16 * 11 = 176 bits
+constexpr uint32_t kFseQ = 6;    // words queued per group: refills happen with
+                                 // fewer than 11 bits left, so at most 6 a group
+typedef __attribute__((address_space(1))) const uint32_t GlobalCU32;
+
+__device__ void fse_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t ia, uint32_t ib,
+                         uint32_t end, const uint32_t *dec, uint32_t *scratch, uint32_t (*tab)[kFseSize],
+                         uint32_t (*stage)[256], uint32_t &loaded) {
+  const uint32_t lane = lane_id(), half = lane >> 5, hl = lane & 31;
+  const uint32_t idx = half ? ib : ia;
+  RansChunk c = RansChunk{0, 0, 0, 0, 0, 0};
+  if (idx < end) c = chunks[idx];
+  if (!(c.p1q & kFseTag)) c = RansChunk{0, 0, 0, 0, 0, 0};   // a rANS chunk: k_rans's
+  const bool has = c.nbits != 0;
+  const uint32_t tno = has ? c.p1q & 0x7F : 0u;              // 1..50, checked by the plan kernel
+  const uint32_t flip = (c.p1q & 0x80) ? 0xFFu : 0u;
+  // the halves' tables
+  const uint32_t ta = __builtin_amdgcn_readlane(tno, 0), tb = __builtin_amdgcn_readlane(tno, 32);
+  const uint32_t la = __builtin_amdgcn_readlane(loaded, 0), lb = __builtin_amdgcn_readlane(loaded, 32);
+  const bool ra = ta && ta != la, rb = tb && tb != lb;
+  if (ra || rb) {
+    if (half ? rb : ra) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(dec + static_cast<uint64_t>(tno - 1) * kFseSize);
+      uint4 *dst = reinterpret_cast<uint4 *>(tab[half]);
+      for (uint32_t i0 = 0; i0 < kFseSize / 4; i0 += 32 * 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[i0 + 32 * u + hl];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[i0 + 32 * u + hl] = v[u];
+      }
+      loaded = tno;
+    }
+    wave_sync_lds();
+  }
+  const uint32_t *T = tab[half];
+  uint8_t *sb = reinterpret_cast<uint8_t *>(stage[half]);
+  // chunk header: cursor states, then stream lengths; a cursor's stream
+  // starts after the 128-byte header and the streams of the cursors before it
+  const uint8_t *base = has ? jobs[c.job].in + c.src : nullptr;
+  GlobalCU32 *w32 = has ? (GlobalCU32 *)base : nullptr;   // C cast: generic to global
+  const uint32_t hw0 = has ? w32[hl >> 1] : 0u, hw1 = has ? w32[16 + (hl >> 1)] : 0u;
+  const uint32_t X0 = (hl & 1) ? hw0 >> 16 : hw0 & 0xFFFF;
+  const uint32_t len = (hl & 1) ? hw1 >> 16 : hw1 & 0xFFFF;
+  uint32_t incl = wave_incl_scan(len);
+  if (half) incl -= __builtin_amdgcn_readlane(incl, 31);
+  const uint32_t a = kFseChunkHdr + incl - len;              // first byte of the cursor's stream
+  const uint32_t cw = (kFseChunkHdr + c.nw + 3) >> 2;        // the chunk's words
+  const uint32_t cb = (c.nbits + 7) >> 3;                    // bytes it decodes
+  const uint32_t my = cb > hl ? (cb - hl + 31) >> 5 : 0u;    // this cursor's steps
+  const uint32_t K = (cb + 31) >> 5;
+  const uint32_t ka = __builtin_amdgcn_readlane(K, 0), kb = __builtin_amdgcn_readlane(K, 32);
+  const uint32_t kmax = ka > kb ? ka : kb;
+  bool err = has && X0 >= kFseSize;
+  uint32_t X = X0 & (kFseSize - 1);
+  uint32_t wi = a >> 2;
+  uint64_t buf = 0;
+  uint32_t have = 0, p = 0, lastb = 0;
+  if (has) {
+    const uint32_t sh = 8 * (a & 3);
+    buf = (wi < cw ? w32[wi] : 0u) >> sh;
+    have = 32 - sh;
+    ++wi;
+  }
+  const uint32_t lastk = (cb - 1) >> 5, lastl = (cb - 1) & 31;   // the bitmap's last byte
+  uint32_t *dst = scratch + c.dst;
+  const uint32_t ncw = (cb + 3) >> 2;                        // output words of the chunk
+  for (uint32_t k0 = 0; k0 < kmax; k0 += 32) {
+    for (uint32_t g = 0; g < 32 && k0 + g < kmax; g += kFseG) {
+      uint32_t q[kFseQ];
+#pragma unroll
+      for (uint32_t u = 0; u < kFseQ; ++u) q[u] = has && wi + u < cw ? w32[wi + u] : 0u;
+#pragma unroll
+      for (uint32_t j = 0; j < kFseG; ++j) {
+        const uint32_t k = k0 + g + j;
+        const bool act = k < my;
+        if (have < kFseLog) {
+          buf |= static_cast<uint64_t>(q[0]) << have;
+          have += 32;
+          ++wi;
+#pragma unroll
+          for (uint32_t u = 0; u + 1 < kFseQ; ++u) q[u] = q[u + 1];
+          q[kFseQ - 1] = 0;
+        }
+        const uint32_t e = T[X];
+        const uint32_t nb = act ? (e >> 8) & 15 : 0u;
+        const uint32_t v = static_cast<uint32_t>(buf) & ((1u << nb) - 1);
+        buf >>= nb;
+        have -= nb;
+        p += nb;
+        X = act ? (e >> 12) + v : X;
+        const uint32_t byte = act ? (e ^ flip) & 255 : 0u;
+        if (act && k == lastk && hl == lastl) lastb = byte;
+        sb[32 * (g + j) + hl] = static_cast<uint8_t>(byte);
+      }
+    }
+    wave_sync_lds();
+    // the window's words: 32 steps of 32 bytes
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      const uint32_t wj = 32 * u + hl;
+      if (8 * k0 + wj < ncw) dst[8 * k0 + wj] = stage[half][wj];
+    }
+    wave_sync_lds();
+  }
+  if (has) {
+    // every bit of the stream used and no more, its padding bits zero, the
+    // cursor back at state 0; the bitmap's bits past n_v zero
+    if (have < 8) buf |= static_cast<uint64_t>(wi < cw ? w32[wi] : 0u) << have;
+    const uint32_t padb = 8 * len - p;
+    if (X != 0 || (p + 7) >> 3 != len || (static_cast<uint32_t>(buf) & ((1u << (padb & 7)) - 1))) err = true;
+    if (hl == lastl && (c.nbits & 7) && (lastb >> (c.nbits & 7))) err = true;
+  }
+  const uint64_t eb = __ballot(err);
+  const uint32_t eh = half ? static_cast<uint32_t>(eb >> 32) : static_cast<uint32_t>(eb);
+  if (hl == 0 && eh) set_err(jobs[c.job].status, PIVCO_E_CORRUPT);
+}
+
+// Decodes the batch's listed tANS chunks, a pair per wave from a shared
+// counter; or, for single >= 0, only the chunks of block ritems[single] with
+// one workgroup (the per-block launch mode).
+__global__ __launch_bounds__(kFseNT) void k_fse(const JobDev *jobs, const ParsedBlock *recs,
+                                                 const uint2 *ritems, Counters *ctr,
+                                                 const RansChunk *chunks, uint64_t cap,
+                                                 const uint32_t *dec, uint32_t *scratch, int32_t single) {
+  __shared__ uint32_t tab[kFseNT / kWave][2][kFseSize];
+  __shared__ uint32_t stage[kFseNT / kWave][2][256];
+  const uint32_t wave = wave_id();
+  constexpr uint32_t NW = kFseNT / kWave;
+  uint32_t first = 0, end = 0;
+  if (single >= 0) {
+    const BlockHdr &h = recs[ritems[single].x].h;
+    if (!h.err) { first = h.chunk0; end = h.chunk0 + h.nchunk; }
+  } else {
+    const uint32_t n = ctr->rans_chunks;
+    end = n < cap ? n : static_cast<uint32_t>(cap);
+  }
+  uint32_t loaded = 0;
+  for (uint32_t it = 0;; ++it) {
+    uint32_t pair;
+    if (single >= 0) {
+      pair = wave + NW * it;
+    } else {
+      uint32_t p = 0;
+      if (lane_id() == 0) p = atomicAdd(&ctr->fse_next, 1u);
+      pair = __builtin_amdgcn_readfirstlane(p);
+    }
+    const uint32_t ia = first + 2 * pair;
+    if (ia >= end) break;
+    fse_pair(jobs, chunks, ia, ia + 1, end, dec, scratch, tab[wave], stage[wave], loaded);
   }
 }
 
@@ -2255,7 +2450,7 @@ __global__ __launch_bounds__(kWave * kPlanWaves) void k_plan(const JobDev *jobs,
 // not a memset node).
 __global__ void k_init(Counters *ctr, int32_t *status, const int32_t *status0, uint32_t count) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) { ctr->merge_next = 0; ctr->rans_next = 0; ctr->rans_chunks = 0; }
+  if (i == 0) { ctr->merge_next = 0; ctr->rans_next = 0; ctr->rans_chunks = 0; ctr->fse_next = 0; }
   if (i < count) status[i] = status0[i];
 }
 
@@ -2571,11 +2766,23 @@ hipError_t launch_tiles(hipStream_t s, const JobDev *jobs, const TiledBlock *til
 
 hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const void *recs,
                        const uint2 *ritems, Counters *ctr, const RansChunk *chunks,
-                       uint64_t chunk_cap, uint32_t *scratch, int32_t single) {
-  hipLaunchKernelGGL(k_rans, dim3(grid), dim3(kRansNT), 0, s, jobs,
-                     static_cast<const ParsedBlock *>(recs), ritems, ctr, chunks, chunk_cap, scratch,
-                     single);
-  return hipGetLastError();
+                       uint64_t chunk_cap, uint32_t *scratch, int32_t single, uint32_t coders) {
+  if (coders & 1) {
+    hipLaunchKernelGGL(k_rans, dim3(grid), dim3(kRansNT), 0, s, jobs,
+                       static_cast<const ParsedBlock *>(recs), ritems, ctr, chunks, chunk_cap, scratch,
+                       single);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (coders & 2) {
+    const FseTables *ft = fse_tables();
+    if (!ft) return hipErrorNotInitialized;
+    hipLaunchKernelGGL(k_fse, dim3(grid), dim3(kFseNT), 0, s, jobs,
+                       static_cast<const ParsedBlock *>(recs), ritems, ctr, chunks, chunk_cap, ft->dec,
+                       scratch, single);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 int rans_occupancy() {

@@ -119,7 +119,7 @@ struct BlockLay {
 struct RansNode {
   uint32_t rword;         // first word of its bitmap among the block's rANS words
   uint32_t nv;            // bits
-  uint32_t p1q;           // 12-bit probability of a 1 bit
+  uint32_t p1q;           // 12-bit probability of a 1 bit (ans_mode 3: the tANS marker)
   uint32_t ch0;           // its first chunk among the block's chunks
   uint64_t sl0;           // its first slot byte among the block's slots
   uint32_t blen;          // body bytes (all its chunks)
@@ -137,10 +137,12 @@ struct RansJob {
   uint32_t dst;           // byte offset of the chunk in its block (k_sizes)
 };
 
-// Batch totals (k_scan, k_scan2).
+// Batch totals (k_scan, k_scan2); err is set by k_fse_enc when a cursor's
+// stream would not fit its 16-bit length.
 struct Totals {
   uint64_t img_bytes, rbm_words, chunks, slot_bytes, ans_words, out_bytes;
-  uint64_t pad[2];
+  uint32_t err, pad0;
+  uint64_t pad;
 };
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -174,8 +176,31 @@ __device__ __forceinline__ bool select_ans(uint32_t mode, uint32_t nv, uint32_t 
   return mode == 2;
 }
 
+// The selection rule of the byte tANS coder (ans_mode 3, Sec. 5.2): a
+// binary node of at least 256 bits whose majority bit has a fraction above
+// 0.625 (8 maj > 5 n_v) takes table t = round(100 x that fraction) - 49
+// (halves up, at most 50) when the table's expected bits per bitmap bit h_t
+// make (depth + h_t) / (depth + 1) < 0.95; dmax[t] is the number of depths
+// that pass (the test holds exactly for depth < 19 - 20 h_t).  Returns the
+// marker (t, | 0x80 when 1 bits are the minority and the bitmap is coded
+// complemented), or 0.
+__device__ __forceinline__ uint32_t fse_marker(uint32_t nv, uint32_t nr, uint32_t depth,
+                                               const uint8_t *dmax) {
+  if (nv < 256 || nr > nv) return 0;
+  const uint32_t zeros = nv - nr, maj = nr >= zeros ? nr : zeros;
+  if (8ull * maj <= 5ull * nv) return 0;
+  uint64_t pct = (200ull * maj + nv) / (2ull * nv);
+  if (pct > 99) pct = 99;
+  const uint32_t t = static_cast<uint32_t>(pct) - 49;
+  if (depth >= dmax[t]) return 0;
+  return t | (nr < zeros ? 0x80u : 0u);
+}
+
 // Output slot of a chunk of nbits bits: lane states, at most one 16-bit word
-// per bit, padding.
+// per bit, padding.  A tANS chunk of the same bits fits too: 128 header
+// bytes, per cursor at most 11 bits a byte rounded up to bytes, and padding
+// come to at most 161 + 11 nbits / 64 bytes, within this size from 14 bits
+// on; below that, two cursors of one step each take at most 132 bytes.
 __host__ __device__ __forceinline__ uint32_t slot_size(uint32_t nbits) {
   return (kChunkHdr + 2 * nbits + 4 + 15) & ~15u;
 }
@@ -271,8 +296,8 @@ struct LayoutSmem {
 
 __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
     const uint8_t *lenm, const uint32_t *modes, const uint32_t *hist, uint32_t nb, uint64_t n,
-    uint32_t bs, uint32_t ans_mode, uint32_t chunk_log2, uint32_t shape, EncBlock *eb, BlockLay *lay,
-    RansNode *rnodes, uint8_t *hdr) {
+    uint32_t bs, uint32_t ans_mode, uint32_t chunk_log2, uint32_t shape, const uint8_t *fse_dmax,
+    EncBlock *eb, BlockLay *lay, RansNode *rnodes, uint8_t *hdr) {
   __shared__ LayoutSmem smem[kLayoutWaves];
   const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
   const uint32_t b = blockIdx.x * kLayoutWaves + wave;
@@ -410,13 +435,14 @@ __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
   }
   wave_sync();
   // node table: lane owns nodes 4 lane .. 4 lane + 3
-  uint32_t fdk[4] = {0, 0, 0, 0};
+  uint32_t fdk[4] = {0, 0, 0, 0}, dk[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = 4 * lane + k;
     if (i >= I) continue;
     uint32_t d = 0;
     while (sm.lvl[d + 1] <= i) ++d;
+    dk[k] = d;
     const uint32_t r = i - sm.lvl[d];
     uint32_t cc = 0;
     if (r < sm.gn[d]) {                  // group r of depth d (shape 1)
@@ -448,14 +474,15 @@ __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
   }
   // lane owns nodes 4 lane .. 4 lane + 3: kind, sizes and their prefixes
   const uint32_t C = 1u << chunk_log2;
-  uint32_t kd[4], rb[4], aw[4], ch[4], sl[4], nvk[4], nrk[4];
+  uint32_t kd[4], rb[4], aw[4], ch[4], sl[4], nvk[4], nrk[4], mk[4];
   uint32_t lraw = 0, lans = 0, lrn = 0, lch = 0, lsl = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t i = 4 * lane + k;
     nvk[k] = i < I ? sm.nv[i] : 0u;
     nrk[k] = i < I ? sm.nr[i] : 0u;
-    kd[k] = i < I && !fdk[k] && select_ans(ans_mode, nvk[k], nrk[k]) ? 1u : 0u;
+    mk[k] = i < I && !fdk[k] && ans_mode == 3 ? fse_marker(nvk[k], nrk[k], dk[k], fse_dmax) : 0u;
+    kd[k] = i < I && !fdk[k] && (ans_mode == 3 ? mk[k] != 0 : select_ans(ans_mode, nvk[k], nrk[k])) ? 1u : 0u;
     const uint32_t nch = kd[k] ? (nvk[k] + C - 1) / C : 0u;
     const uint32_t rem = nvk[k] - (nch ? (nch - 1) * C : 0u);
     const uint64_t bits = static_cast<uint64_t>(nvk[k]) * (fdk[k] ? fdk[k] : 1u);
@@ -481,7 +508,7 @@ __global__ __launch_bounds__(kWaveE * kLayoutWaves) void k_layout(
       RansNode r;
       r.rword = rword;
       r.nv = nvk[k];
-      r.p1q = p1q_of(nvk[k], nrk[k]);
+      r.p1q = ans_mode == 3 ? mk[k] : p1q_of(nvk[k], nrk[k]);
       r.ch0 = ich - lch + ch[k];
       r.sl0 = 16ull * (isl - lsl + sl[k]);
       r.blen = 0;
@@ -563,6 +590,7 @@ __global__ __launch_bounds__(kScanNT) void k_scan(BlockLay *lay, uint32_t nb, To
     run[4] += L.ans_words;
   }
   if (tid == kScanNT - 1) {
+    tot->err = 0;
     tot->img_bytes = part[0][tid];
     tot->rbm_words = part[1][tid];
     tot->chunks = part[2][tid];
@@ -803,6 +831,96 @@ __global__ __launch_bounds__(256) void k_rans_enc(const RansJob *jobs, const Tot
   }
 }
 
+// Byte tANS coding of the chunk jobs (ans_mode 3, Sec. 5.2), a half-wave
+// per chunk (persistent over pairs of jobs).  Cursor l of a chunk codes its
+// bytes l, l + 32, ... (XOR 0xFF when the marker says complemented) last
+// first, from state 2^11: with n = norm(b), the step emits the low nb bits
+// of the state, nb the smallest count with (state >> nb) < 2n (11 - k or
+// 10 - k for 2^k <= n < 2^(k+1)), and moves to 2^11 + the (state >> nb) -
+// n'th state of b.  A first pass finds the cursor's bit count; its stream
+// starts after the 128-byte header and the streams of the cursors before it,
+// and a second pass writes the bits backwards from the stream's end (the
+// decoder reads step 0's bits first).  The table (norm, first, state) sits
+// in LDS, reloaded when a half's table changes.
+constexpr uint32_t kFseEncNT = 256;
+__global__ __launch_bounds__(kFseEncNT) void k_fse_enc(const RansJob *jobs, Totals *tot,
+                                                       const uint32_t *bmp, const uint16_t *enc,
+                                                       uint8_t *slots, uint32_t *sizes) {
+  __shared__ uint16_t tabs[kFseEncNT / kWaveE][2][kFseEncWords];
+  const uint32_t lane = __lane_id(), half = lane >> 5, hl = lane & 31;
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint64_t njobs = tot->chunks;
+  const uint64_t nwaves = static_cast<uint64_t>(gridDim.x) * (kFseEncNT / kWaveE);
+  uint16_t *E = tabs[wave][half];
+  uint32_t loaded = 0;
+  for (uint64_t pr = blockIdx.x * (kFseEncNT / kWaveE) + wave; 2 * pr < njobs; pr += nwaves) {
+    const uint64_t j = 2 * pr + half;
+    const bool has = j < njobs;
+    RansJob J{};
+    if (has) J = jobs[j];
+    const uint32_t t = has ? J.p1q & 0x7F : 0u;
+    const uint32_t flip = (J.p1q & 0x80) ? 0xFFu : 0u;
+    const uint32_t ta = __builtin_amdgcn_readlane(t, 0), tb = __builtin_amdgcn_readlane(t, 32);
+    const uint32_t la = __builtin_amdgcn_readlane(loaded, 0), lb = __builtin_amdgcn_readlane(loaded, 32);
+    const bool ra = ta && ta != la, rb = tb && tb != lb;
+    if (ra || rb) {
+      if (half ? rb : ra) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(enc + static_cast<uint64_t>(t - 1) * kFseEncWords);
+        uint4 *dst = reinterpret_cast<uint4 *>(E);
+        constexpr uint32_t n16 = kFseEncWords * 2 / 16;
+        for (uint32_t i = hl; i < n16; i += 32) dst[i] = src[i];
+        loaded = t;
+      }
+      wave_sync();
+    }
+    const uint16_t *norm = E, *first = E + 256, *state = E + 512;
+    const uint8_t *bm = reinterpret_cast<const uint8_t *>(bmp + J.bmp_word);
+    const uint32_t cb = (J.nbits + 7) >> 3;
+    const uint32_t steps = has && cb > hl ? (cb - hl + 31) >> 5 : 0u;
+    // pass 1: the cursor's bit count and final state
+    uint32_t x = kFseSize, tbits = 0;
+    for (uint32_t i = steps; i-- > 0;) {
+      const uint32_t b = bm[hl + 32 * i] ^ flip;
+      const uint32_t n = norm[b];
+      const uint32_t k = 31 - __builtin_clz(n);
+      const uint32_t nb = kFseLog - k - (x < (n << (kFseLog - k)) ? 1u : 0u);
+      x = kFseSize + state[first[b] + (x >> nb) - n];
+      tbits += nb;
+    }
+    const uint32_t len = (tbits + 7) >> 3;
+    if (len > 0xFFFF) atomicOr(&tot->err, 1u);
+    uint32_t incl = wave_incl_scan(len);
+    const uint32_t lo = __builtin_amdgcn_readlane(incl, 31), all = __builtin_amdgcn_readlane(incl, 63);
+    if (half) incl -= lo;
+    const uint32_t total = half ? all - lo : lo;     // stream bytes of this half's chunk
+    uint8_t *slot = slots + J.slot;
+    uint8_t *sp = slot + kFseChunkHdr + (incl - len);
+    // pass 2: the same steps, bits written from the stream's end backwards
+    uint32_t acc = 0, accn = 8 * len - tbits, top = len, x2 = kFseSize;
+    for (uint32_t i = steps; i-- > 0;) {
+      const uint32_t b = bm[hl + 32 * i] ^ flip;
+      const uint32_t n = norm[b];
+      const uint32_t k = 31 - __builtin_clz(n);
+      const uint32_t nb = kFseLog - k - (x2 < (n << (kFseLog - k)) ? 1u : 0u);
+      acc = (acc << nb) | (x2 & ((1u << nb) - 1));
+      accn += nb;
+      x2 = kFseSize + state[first[b] + (x2 >> nb) - n];
+      while (accn >= 8) {
+        --top;
+        sp[top] = static_cast<uint8_t>(acc >> (accn - 8));
+        accn -= 8;
+      }
+    }
+    if (has) {
+      reinterpret_cast<uint16_t *>(slot)[hl] = static_cast<uint16_t>(x - kFseSize);
+      reinterpret_cast<uint16_t *>(slot)[kFseLanes + hl] = static_cast<uint16_t>(len);
+      const uint32_t used = kFseChunkHdr + total, size = (used + 3) & ~3u;
+      if (hl < size - used) slot[used + hl] = 0;
+      if (hl == 0) sizes[j] = size;
+    }
+  }
+}
+
 // Block sizes (one thread per block): header, raw bodies, then every rANS
 // node at a multiple of 4 bytes with its 8-byte header and its chunks; the
 // chunks' places in the block go to their jobs, comp_size to the header.
@@ -876,7 +994,7 @@ __global__ __launch_bounds__(256) void k_stream_head(const BlockLay *lay, const 
   if (t == 0) {
     uint32_t *h = reinterpret_cast<uint32_t *>(out);
     h[0] = kMagic;
-    h[1] = version;                                   // version (1 or 2), flags 0
+    h[1] = version;                                   // version (1 or 2) | flags << 16
     h[2] = static_cast<uint32_t>(n);
     h[3] = static_cast<uint32_t>(n >> 32);
     h[4] = bs;
@@ -965,8 +1083,9 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 bool opts_ok(const pivco_encode_opts *o) {
   return o && o->block_size >= 1 && o->block_size <= (1u << 30) && o->max_len >= 1 &&
-         o->max_len <= kMaxLenGpu && o->ans_mode <= 2 && o->rans_chunk_log2 >= 5 &&
-         o->rans_chunk_log2 <= 24 && o->tree_shape <= 1 && o->reserved == 0;
+         o->max_len <= kMaxLenGpu && o->ans_mode <= 3 && o->rans_chunk_log2 >= 5 &&
+         o->rans_chunk_log2 <= 24 && (o->ans_mode != 3 || o->rans_chunk_log2 >= 8) &&
+         o->tree_shape <= 1 && o->reserved == 0;
 }
 
 struct WsLayout {
@@ -1090,7 +1209,8 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
 
   if (nb == 0) {                         // header and the two one-entry tables
     uint8_t h[kHeaderBytes + 16] = {0};
-    const uint32_t w[6] = {kMagic, o->tree_shape ? 2u : 1u, 0u, 0u, static_cast<uint32_t>(bs), 0u};
+    const uint32_t w[6] = {kMagic, (o->tree_shape ? 2u : 1u) | (o->ans_mode == 3 ? 1u << 16 : 0u), 0u, 0u,
+                           static_cast<uint32_t>(bs), 0u};
     std::memcpy(h, w, sizeof(w));
     h[24] = static_cast<uint8_t>(o->max_len);
     h[25] = static_cast<uint8_t>(o->rans_chunk_log2);
@@ -1124,10 +1244,13 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   HIPCHK(hipMemcpyAsync(ws + L.modes, modes.data(), 4ull * nb, hipMemcpyHostToDevice, s));
 
   // 3.-4. layout and offsets
+  const FseTables *ft = nullptr;
+  if (o->ans_mode == 3 && !(ft = fse_tables())) return PIVCO_E_DEVICE;
   const uint32_t gl = (nb + kLayoutWaves - 1) / kLayoutWaves;
   hipLaunchKernelGGL(k_layout, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, ws + L.lenm,
                      reinterpret_cast<const uint32_t *>(ws + L.modes), dh, nb, n, static_cast<uint32_t>(bs),
-                     o->ans_mode, o->rans_chunk_log2, o->tree_shape, deb, dlay, drn, ws + L.hdr);
+                     o->ans_mode, o->rans_chunk_log2, o->tree_shape, ft ? ft->dmax : nullptr, deb, dlay, drn,
+                     ws + L.hdr);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanNT), 0, s, dlay, nb, dtot);
   uint32_t *dimg = reinterpret_cast<uint32_t *>(ws + L.img);
   uint32_t *drbm = reinterpret_cast<uint32_t *>(ws + L.rbm);
@@ -1143,7 +1266,11 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   if (ans) {
     hipLaunchKernelGGL(k_chunks, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, dlay, drn, nb,
                        o->rans_chunk_log2, djobs);
-    hipLaunchKernelGGL(k_rans_enc, dim3(2048), dim3(256), 0, s, djobs, dtot, drbm, ws + L.slots, dsizes);
+    if (ft)
+      hipLaunchKernelGGL(k_fse_enc, dim3(2048), dim3(kFseEncNT), 0, s, djobs, dtot, drbm, ft->enc,
+                         ws + L.slots, dsizes);
+    else
+      hipLaunchKernelGGL(k_rans_enc, dim3(2048), dim3(256), 0, s, djobs, dtot, drbm, ws + L.slots, dsizes);
     HIPCHK(hipGetLastError());
   }
 
@@ -1154,7 +1281,8 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
 
   // 8. the stream (nothing is written when it would not fit)
   hipLaunchKernelGGL(k_stream_head, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, dlay, dtot, nb, n,
-                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2, o->tree_shape ? 2u : 1u, out, out_cap);
+                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2,
+                     (o->tree_shape ? 2u : 1u) | (o->ans_mode == 3 ? 1u << 16 : 0u), out, out_cap);
   const uint64_t max_words = (kHdrStride + bs * o->max_len / 8 + 255 + 4) / 4 + 1;
   const uint32_t segs = static_cast<uint32_t>(div_up(max_words, kAsmSeg));
   if (static_cast<uint64_t>(nb) * segs > 0x7FFFFFFFull) return PIVCO_E_UNSUPPORTED;
@@ -1164,9 +1292,13 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
     hipLaunchKernelGGL(k_assemble_rans, dim3(2048), dim3(256), 0, s, dlay, drn, djobs, dsizes, dtot,
                        ws + L.slots, out, out_cap);
   HIPCHK(hipGetLastError());
-  uint64_t total = 0;
-  HIPCHK(hipMemcpyAsync(&total, &dtot->out_bytes, 8, hipMemcpyDeviceToHost, s));
+  Totals tot{};
+  HIPCHK(hipMemcpyAsync(&tot, dtot, sizeof(Totals), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  // a tANS cursor stream longer than its u16 length field (only with
+  // 2^24-bit chunks of bytes costing more than 8 bits on average)
+  if (tot.err) return PIVCO_E_UNSUPPORTED;
+  const uint64_t total = tot.out_bytes;
   if (total > out_cap) return PIVCO_E_CAPACITY;
   *h_out_len = total;
   return PIVCO_OK;

@@ -75,7 +75,8 @@ struct JobDev {
   uint32_t block_size;
   uint16_t max_len;
   uint16_t chunk_log2;
-  uint32_t version;        // 1: canonical trees; 2: flat-subtree trees
+  uint16_t version;        // 1: canonical trees; 2: flat-subtree trees
+  uint16_t flags;          // bit 0: entropy-coded nodes use the byte tANS tables
   int32_t *status;
   uint64_t ans_words;      // scratch words of this job (its stream header's total)
 };
@@ -85,20 +86,49 @@ static_assert(sizeof(JobDev) == 80, "JobDev layout");
 struct Counters {
   uint32_t merge_next;     // next merge work item
   uint32_t rans_next;      // next pair of rANS chunks to decode
-  uint32_t rans_chunks;    // rANS chunks listed by the plan kernel
-  uint32_t pad[13];
+  uint32_t rans_chunks;    // entropy-coded chunks listed by the plan kernel
+  uint32_t fse_next;       // next pair of chunks for the tANS kernel
+  uint32_t pad[12];
 };
 
-// One rANS chunk of a node's bitmap, listed by the plan kernel: where its
-// 32 lane states and 16-bit words are, where its decoded bits go, how many.
+// One entropy-coded chunk of a node's bitmap, listed by the plan kernel:
+// where its coded data is, where its decoded bits go, how many.  A binary
+// rANS chunk holds 32 lane states and 16-bit words; a tANS chunk (p1q =
+// kFseTag | marker) 32 cursor states, 32 stream lengths and the streams.
 struct RansChunk {
   uint64_t src;            // byte offset of the chunk in the job's stream
   uint64_t dst;            // scratch word of its first decoded word
   uint32_t nbits;          // bits it decodes (<= 2^chunk_log2)
-  uint32_t nw;             // 16-bit renormalisation words it holds
-  uint32_t p1q;            // 12-bit probability of a 1 bit
+  uint32_t nw;             // rANS: 16-bit renormalisation words; tANS: stream bytes
+  uint32_t p1q;            // rANS: 12-bit probability of a 1 bit; tANS: kFseTag | marker
   uint32_t job;
 };
+
+// Selective tANS of bitmap bytes (Sec. 5.2): 50 static tables of 2^11
+// states, table t for bitmaps whose majority bit has fraction (t + 49)%.
+// A node body is marker u8 (t | 0x80 when the bitmap is coded complemented)
+// | 0 u8 | 0 u16 | body_len u32 | chunks; a chunk of 2^chunk_log2 bits is
+// X0 u16[32] | nbytes u16[32] | 32 cursor streams | zero padding to 4 bytes.
+constexpr uint32_t kFseTag = 0x10000u;
+constexpr uint32_t kFseTables = 50;
+constexpr uint32_t kFseLog = 11;
+constexpr uint32_t kFseSize = 1u << kFseLog;
+constexpr uint32_t kFseLanes = 32;
+constexpr uint32_t kFseChunkHdr = 4 * kFseLanes;
+constexpr uint32_t kFseEncWords = 256 + 256 + kFseSize;   // norm | first | state (u16)
+// Device addresses of the tables on one GPU: decoding entries (symbol |
+// bits << 8 | base << 12, per table and state), encoding tables (norm,
+// first state of each byte, states in increasing order, per table), and per
+// table one more than the deepest node the selection rule codes with it.
+struct FseTables {
+  const uint32_t *dec;
+  const uint16_t *enc;
+  const uint8_t *dmax;
+};
+// The current device's tables, built on the host and copied into static
+// device arrays on the first call for the device (synchronous; call it
+// before any stream capture); null on a runtime error.
+const FseTables *fse_tables();
 static_assert(sizeof(RansChunk) == 32, "RansChunk layout");
 
 // Upper bound on the rANS chunks of a job: a rANS node of n_v bits has
@@ -219,9 +249,11 @@ hipError_t launch_merge(uint32_t variant, uint32_t grid, hipStream_t s, const Jo
                         const TiledBlock *tiled, const uint2 *tab, uint32_t n_items,
                         Counters *ctr, const uint32_t *scratch, uint64_t scratch_words,
                         int32_t single);
+// coders: bit 0, some job has rANS nodes; bit 1, some job has tANS nodes
+// (then fse_tables() has been called for the device).
 hipError_t launch_rans(uint32_t grid, hipStream_t s, const JobDev *jobs, const void *recs,
                        const uint2 *ritems, Counters *ctr, const RansChunk *chunks,
-                       uint64_t chunk_cap, uint32_t *scratch, int32_t single);
+                       uint64_t chunk_cap, uint32_t *scratch, int32_t single, uint32_t coders);
 int rans_occupancy();
 // Top-down decode of the same work items (ablation of the merge kernel).
 hipError_t launch_topdown(uint32_t grid, hipStream_t s, const JobDev *jobs, const uint2 *items,

@@ -37,7 +37,7 @@ struct Registered {
   const uint8_t *d_in;
   uint64_t in_len;
   uint64_t n_total, ans_words;
-  uint32_t n_blocks, block_size, max_len, chunk_log2, version;
+  uint32_t n_blocks, block_size, max_len, chunk_log2, version, flags;
   WorkLists::Need need;           // merge items, tiles and boundary-table entries
   uint64_t chunks;                // bound on its rANS chunks
 };
@@ -204,6 +204,8 @@ pivco_status pivco_server_register(pivco_server *sv, const void *d_stream, uint6
   r.max_len = h[24];
   r.chunk_log2 = h[25];
   r.version = static_cast<uint32_t>(h[4]) | (static_cast<uint32_t>(h[5]) << 8);
+  r.flags = static_cast<uint32_t>(h[6]) | (static_cast<uint32_t>(h[7]) << 8);
+  if (r.flags && ans && !fse_tables()) return PIVCO_E_DEVICE;   // tables on this device, before serving
   r.need = need;
   r.chunks = chunks;
   *id = static_cast<uint32_t>(sv->reg.size());
@@ -311,6 +313,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
       WorkLists &w = sv->w;
       w.clear();
       uint64_t sw = 0;
+      uint32_t coders = 0;
       for (uint32_t k = 0; k < batch.size(); ++k) {
         const Registered &g = sv->reg[reqs[batch[k]].id];
         JobDev d{};
@@ -325,7 +328,9 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         d.block_size = g.block_size;
         d.max_len = static_cast<uint16_t>(g.max_len);
         d.chunk_log2 = static_cast<uint16_t>(g.chunk_log2);
-        d.version = g.version;
+        d.version = static_cast<uint16_t>(g.version);
+        d.flags = static_cast<uint16_t>(g.flags);
+        if (g.ans_words) coders |= g.flags ? 2u : 1u;
         d.status = reinterpret_cast<int32_t *>(s.ws + sv->off_status) + k;
         jobs[k] = d;
         sw = align_up(sw + g.ans_words, 4);
@@ -368,7 +373,7 @@ pivco_status pivco_server_run(pivco_server *sv, const pivco_request *reqs, uint3
         return PIVCO_E_DEVICE;
       if (nr && launch_rans(std::max<uint32_t>(1, std::min<uint32_t>(rgrid_full, static_cast<uint32_t>((chunks + 7) / 8))),
                             s.stream, dj, recs, reinterpret_cast<const uint2 *>(s.ws + o_ritems), ctr,
-                            d_chunks, chunks, scr, -1) != hipSuccess)
+                            d_chunks, chunks, scr, -1, coders) != hipSuccess)
         return PIVCO_E_DEVICE;
       if (launch_tiles(s.stream, dj, d_tiled, nt, recs, scr, sw, d_tab) != hipSuccess)
         return PIVCO_E_DEVICE;
