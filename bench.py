@@ -286,6 +286,37 @@ def flat_leg(torch, P, d_xs, bss, ans_mode, tune, steps, warmup, n, merges, flat
     return res
 
 
+def fse_leg(torch, P, d_xs, bss, tune, steps, warmup, n, comp_rans, gbps_rans):
+    """The same workload with the selective byte tANS of Sec. 5.2 as the
+    entropy coder (encoder ans_mode 3) instead of binary rANS: compression,
+    encode rate and batched decode rate, outputs checked against the inputs."""
+    t0 = time.perf_counter()
+    streams = [P.pivco_encode(d, bs, max_len=11, ans_mode=3) for d, bs in zip(d_xs, bss)]
+    torch.cuda.synchronize()
+    enc_s = time.perf_counter() - t0
+    comp = int(sum(s.numel() for s in streams))
+    ans_words = int(sum(P.pivco_stream_info(s)["ans_words"] for s in streams))
+    outs = [torch.empty_like(d) for d in d_xs]
+    if tune is None:
+        tune = P.pivco_autotune(streams, outs)
+    plan = P.BatchPlan(streams, outs, tune=tune)
+    for _ in range(warmup):
+        plan.launch()
+    dt = time_steps(torch, plan, steps)
+    assert (plan.statuses() == 0).all(), f"tANS decode status {plan.statuses()}"
+    for o, d in zip(outs, d_xs):
+        assert torch.equal(o, d), "tANS decoded bytes differ from the input"
+    value = n / (dt / steps) / 1e9
+    res = {"GBps": round(value, 2), "ms_per_step": round(dt * 1e3 / steps, 4),
+           "compression_ratio": round(n / comp, 4), "encode_GBps": round(n / enc_s / 1e9, 3),
+           "entropy_coded_bitmap_bytes": 4 * ans_words,
+           "vs_rans": {"size": round(comp / comp_rans, 4), "decode_rate": round(value / gbps_rans, 4)},
+           "tune": plan.tune.as_dict()}
+    plan.close()
+    del streams, outs
+    return res
+
+
 def golomb_leg(torch, dev, n=64 << 20, block_size=1 << 16, seed=7, reps=5):
     """PivCo-Golomb (App. G): unary-coded geometric values at the mean code
     lengths the appendix measures (1.25 .. 5 bits), 64 Mi values each in
@@ -360,6 +391,7 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=128, help="resident serving requests")
     ap.add_argument("--no-golomb", action="store_true", help="skip the PivCo-Golomb leg")
     ap.add_argument("--no-flat", action="store_true", help="skip the v2 (flat-subtree) leg")
+    ap.add_argument("--no-fse", action="store_true", help="skip the selective-tANS leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -493,6 +525,13 @@ def main():
                         args.steps, args.warmup, n, merges, flat_merges)
         log("v2:", flat)
 
+    fse = None
+    if not args.no_fse:
+        log("selective tANS streams (ans_mode 3) ...")
+        fse = fse_leg(torch, P, d_xs, bss, tune if args.variant is not None else None,
+                      args.steps, args.warmup, n, comp, value)
+        log("tANS:", fse)
+
     if args.copy_probe:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -541,6 +580,7 @@ def main():
         "element_merges": {"per_launch": merges, "mean_code_len": round(merges / n, 4),
                            "G_per_s": round(merges / (merge_avg * 1e-3) / 1e9, 1)},
         "flat_v2": flat,
+        "fse_tans": fse,
         "serving": serve,
         "golomb": golomb,
         "cpu_baseline": cpu,
