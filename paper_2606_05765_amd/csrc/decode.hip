@@ -26,6 +26,8 @@
 // per chunk, renormalisation words addressed with ballot + mbcnt.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "pivco_int.h"
 
 namespace pivco {
@@ -521,6 +523,9 @@ __device__ void parse_block_wave(const JobDev &J, uint32_t b, BlockHdr &h, NodeT
 // 16-bit words in lane order (the cursor + their rank in the half-wave's
 // ballot) from a window of the chunk's words staged in LDS; the half-wave's
 // 32 decoded bits are its part of the ballot of the bits (bit i = lane i).
+// A step is a chain of dependent operations (state, ballot, rank, LDS word);
+// the step is branch-free and keeps the cursors in registers, so that the
+// chain holds no scalar round trip.
 constexpr int kRansNT = 256;
 constexpr int kRansWin = 2048;        // u16 words per half-wave window in LDS
 constexpr uint32_t kRansSteps = 32;   // steps per window check (one output word per lane)
@@ -614,28 +619,34 @@ __device__ int32_t walk_rans(const JobDev &J, BlockHdr &h, const NodeTab &t, Cou
   return PIVCO_OK;
 }
 
-// Decodes chunks ia (lanes 0-31) and ib (lanes 32-63) of the list; an index
-// at or past `end`, or an empty chunk, leaves its half idle.  The step is
-// branch-free except for the window refill: an inactive lane keeps its
-// state, the window word is read at a clamped index and used only by lanes
-// that renormalise, and lane j of a half collects the half's decoded word of
-// every step k = j (mod 32) and stores it with the other lanes every 32
-// steps (one coalesced 128-byte store).
 typedef __attribute__((address_space(1))) const uint16_t GlobalCU16;
 
+// v_writelane_b32: lane `lane` of r takes the wave-uniform value v (the lane
+// select goes through M0: two SGPR operands would exceed the constant bus).
+__device__ __forceinline__ void write_lane(uint32_t &r, uint32_t v, uint32_t lane) {
+  asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(r) : "s"(v), "{m0}"(lane));
+}
+// The same with a lane known at compile time (an inline constant).
+template <uint32_t L>
+__device__ __forceinline__ void write_lane_i(uint32_t &r, uint32_t v) {
+  static_assert(L < 64, "a lane of the wave");
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(r) : "s"(v), "i"(L));
+}
+
 // One decode step of both half-waves (lane hl of half h: bit 32 k + hl of
-// its chunk).  FULL: every lane of both halves is active.  The cursors pa,
-// pb (words consumed per half) and the window starts wsa, wsb are
-// wave-uniform.  A lane whose state fell below 2^16 takes the word at its
-// half's cursor + its rank among the half's such lanes; the window index is
-// masked, so a corrupt chunk that runs past its words reads stale window
-// words and fails the final cursor check.  The step's ballot of decoded
-// bits (half 0 low, half 1 high) goes to stage[j].
+// its chunk); returns the ballot of the decoded bits (half 0 low, half 1
+// high).  FULL: every lane of both halves is active.  co is the lane's
+// half's cursor relative to its window (words consumed - window start).  A
+// lane whose state fell below 2^16 takes the window word at co + its rank
+// among the half's such lanes (mbcnt over the half's word of the ballot;
+// mbcnt_hi counts nothing for lanes 0-31), and co advances by the half's
+// count.  Every lane reads a word, so no branch surrounds the
+// renormalisation; the window index is masked, so a corrupt chunk that runs
+// past its words reads stale window words and fails the final cursor check.
 template <bool FULL>
-__device__ __forceinline__ void rans_step(uint32_t &x, uint64_t *stage, uint32_t &pa, uint32_t &pb,
-                                          uint32_t wsa, uint32_t wsb, uint32_t j, uint32_t k,
-                                          uint32_t hl, uint32_t half, uint32_t nbits, uint32_t f0,
-                                          uint32_t f1, const uint16_t *w) {
+__device__ __forceinline__ uint64_t rans_step(uint32_t &x, uint32_t &co, uint32_t k, uint32_t hl,
+                                              uint32_t half, uint32_t nbits, uint32_t f0, uint32_t f1,
+                                              const uint16_t *w) {
   const bool act = FULL || 32 * k + hl < nbits;
   const uint32_t slot = x & (kRansM - 1);
   const bool bit = slot >= f0;
@@ -643,23 +654,37 @@ __device__ __forceinline__ void rans_step(uint32_t &x, uint64_t *stage, uint32_t
   x = act ? xn : x;
   const bool need = act && x < kRansL;
   const uint64_t m = __ballot(need);
-  if (m) {
-    const uint32_t mlo = static_cast<uint32_t>(m), mhi = static_cast<uint32_t>(m >> 32);
-    const uint32_t clo = __popc(mlo);
-    // lanes of the upper half count the lower half's bits too: subtract them
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
-    const uint32_t adj = half ? pb - wsb - clo : pa - wsa;
-    const uint32_t wv = w[(rank + adj) & (kRansWin - 1)];
-    x = need ? ((x << 16) | wv) : x;
-    pa += clo;
-    pb += __popc(mhi);
-  }
-  const uint64_t bm = __ballot(act && bit);
-  if (hl == 0 && half == 0) stage[j] = bm;
+  const uint32_t mlo = static_cast<uint32_t>(m), mhi = static_cast<uint32_t>(m >> 32);
+  // both halves' forms in every lane, then a select (no divergent branch)
+  uint32_t rlo = __builtin_amdgcn_mbcnt_lo(mlo, co), rhi = __builtin_amdgcn_mbcnt_hi(mhi, co);
+  uint32_t clo = __popc(mlo) + co, chi = __popc(mhi) + co;
+  asm volatile("" : "+v"(rlo), "+v"(rhi), "+v"(clo), "+v"(chi));
+  uint32_t wv = w[(half ? rhi : rlo) & (kRansWin - 1)];
+  asm volatile("" : "+v"(wv));
+  x = need ? ((x << 16) | wv) : x;
+  co = half ? chi : clo;
+  return __ballot(act && bit);
 }
 
+// 32 full steps, unrolled, the ballot of step J into lanes J and 32 + J of stg.
+template <size_t... J>
+__device__ __forceinline__ void rans_full_group(std::index_sequence<J...>, uint32_t &x, uint32_t &stg,
+                                                uint32_t &co, uint32_t hl, uint32_t half, uint32_t f0,
+                                                uint32_t f1, const uint16_t *w) {
+  ((void)([&] {
+     const uint64_t bm = rans_step<true>(x, co, 0, hl, half, 0, f0, f1, w);
+     write_lane_i<J>(stg, static_cast<uint32_t>(bm));
+     write_lane_i<32 + J>(stg, static_cast<uint32_t>(bm >> 32));
+   }()), ...);
+}
+
+// Decodes chunks ia (lanes 0-31) and ib (lanes 32-63) of the list; an index
+// at or past `end`, or an empty chunk, leaves its half idle.  Every 32 steps
+// lane j of a half holds the half's decoded word of step j (the step's
+// ballot went into lane j, resp. 32 + j, with v_writelane) and the 32 words
+// go out as one coalesced store.
 __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t ia, uint32_t ib,
-                          uint32_t end, uint32_t *scratch, uint16_t (*win)[kRansWin], uint64_t *stage) {
+                          uint32_t end, uint32_t *scratch, uint16_t (*win)[kRansWin]) {
   const uint32_t lane = lane_id(), half = lane >> 5, hl = lane & 31;
   const uint32_t idx = half ? ib : ia;
   RansChunk c = RansChunk{0, 0, 0, 0, 1, 0};
@@ -678,17 +703,19 @@ __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t 
   const uint32_t kmax = ka > kb ? ka : kb;
   const uint32_t nba = __builtin_amdgcn_readlane(c.nbits, 0), nbb = __builtin_amdgcn_readlane(c.nbits, 32);
   const uint32_t nwa = __builtin_amdgcn_readlane(c.nw, 0), nwb = __builtin_amdgcn_readlane(c.nw, 32);
-  uint32_t pa = 0, pb = 0, wsa = 0, wsb = 0, wea = 0, web = 0;
+  uint32_t wsa = 0, wsb = 0, wea = 0, web = 0, co = 0;
   uint32_t *dst = scratch + c.dst;
   constexpr uint32_t kAhead = kRansSteps * 32;   // most words a half takes in kRansSteps steps
   static_assert(kAhead <= static_cast<uint32_t>(kRansWin), "a group's words fit the window");
   for (uint32_t k0 = 0; k0 < kmax; k0 += kRansSteps) {
-    // slide a half's window to its cursor when fewer than kAhead of its
-    // words are staged ahead of it (and the chunk has more)
+    // the halves' cursors; slide a half's window to its cursor when fewer
+    // than kAhead of its words are staged ahead of it (and the chunk has more)
+    const uint32_t pa = wsa + __builtin_amdgcn_readlane(co, 0), pb = wsb + __builtin_amdgcn_readlane(co, 32);
     const bool ra = pa + kAhead > wea && wea < nwa, rb = pb + kAhead > web && web < nwb;
     if (ra || rb) {
       if (ra) { wsa = pa < nwa ? pa : nwa; wea = nwa - wsa > kRansWin ? wsa + kRansWin : nwa; }
       if (rb) { wsb = pb < nwb ? pb : nwb; web = nwb - wsb > kRansWin ? wsb + kRansWin : nwb; }
+      co = half ? pb - wsb : pa - wsa;
       if (half ? rb : ra) {
         const uint32_t ws = half ? wsb : wsa, nwin = (half ? web : wea) - ws;
         for (uint32_t i0 = 0; i0 < nwin; i0 += 32 * 8) {
@@ -709,22 +736,24 @@ __device__ void rans_pair(const JobDev *jobs, const RansChunk *chunks, uint32_t 
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    uint32_t stg = 0;
     const uint32_t full_bits = 32 * (k0 + kRansSteps);
     if (full_bits <= nba && full_bits <= nbb) {
-#pragma unroll
-      for (uint32_t j = 0; j < kRansSteps; ++j)
-        rans_step<true>(x, stage, pa, pb, wsa, wsb, j, k0 + j, hl, half, c.nbits, f0, f1, w);
+      rans_full_group(std::make_index_sequence<kRansSteps>(), x, stg, co, hl, half, f0, f1, w);
     } else {
       const uint32_t steps = kmax - k0 < kRansSteps ? kmax - k0 : kRansSteps;
-      for (uint32_t j = 0; j < steps; ++j)
-        rans_step<false>(x, stage, pa, pb, wsa, wsb, j, k0 + j, hl, half, c.nbits, f0, f1, w);
+      for (uint32_t j = 0; j < steps; ++j) {
+        const uint64_t bm = rans_step<false>(x, co, k0 + j, hl, half, c.nbits, f0, f1, w);
+        write_lane(stg, static_cast<uint32_t>(bm), j);
+        write_lane(stg, static_cast<uint32_t>(bm >> 32), 32 + j);
+      }
     }
-    // lane hl of half h: the half's bits of step k0 + hl (entries past the
-    // group's steps are never read: k0 + hl < K <= k0 + steps)
-    if (k0 + hl < K) dst[k0 + hl] = reinterpret_cast<const uint32_t *>(stage)[2 * hl + half];
+    // lane hl of half h: the half's bits of step k0 + hl (lanes past the
+    // group's steps hold nothing and store nothing: k0 + hl < K <= k0 + steps)
+    if (k0 + hl < K) dst[k0 + hl] = stg;
   }
   if (has) {
-    if ((half ? pb : pa) != c.nw || x != kRansL) err = true;
+    if ((half ? wsb : wsa) + co != c.nw || x != kRansL) err = true;
     const uint32_t used = kChunkHdr + 2 * c.nw, size = (used + 3) & ~3u;
     if (hl < size - used && base[used + hl] != 0) err = true;
   }
@@ -741,7 +770,6 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const Pars
                                                    const RansChunk *chunks, uint64_t cap,
                                                    uint32_t *scratch, int32_t single) {
   __shared__ uint16_t win[kRansNT / kWave][2][kRansWin];
-  __shared__ uint64_t stage[kRansNT / kWave][kRansSteps];
   const uint32_t wave = wave_id();
   constexpr uint32_t NW = kRansNT / kWave;
   uint32_t first = 0, end = 0;
@@ -763,7 +791,7 @@ __global__ __launch_bounds__(kRansNT) void k_rans(const JobDev *jobs, const Pars
     }
     const uint32_t ia = first + 2 * pair;
     if (ia >= end) break;
-    rans_pair(jobs, chunks, ia, ia + 1, end, scratch, win[wave], stage[wave]);
+    rans_pair(jobs, chunks, ia, ia + 1, end, scratch, win[wave]);
   }
 }
 
