@@ -123,17 +123,35 @@ uint64_t pivco_encode_bound(uint64_t n, const pivco_encode_opts *o);
 uint64_t pivco_encode_workspace(uint64_t n, const pivco_encode_opts *o);
 
 /* Encode n bytes at d_in into a v1 (or, with tree_shape 1, v2) stream at
- * d_out.  Synchronous: it waits for the block histograms (the host builds
- * the trees) and for the entropy-coded body sizes, and returns the stream
- * length in *h_out_len.  The stream is byte-identical to the one the format
- * definition implies.  Errors: E_ARG (bad options or a supplied tree that
- * misses a symbol present in the data), E_CAPACITY (out_cap or ws_bytes too
- * small), E_UNSUPPORTED (ans_mode 3 with 2^24-bit chunks only: a cursor's
- * stream longer than its 16-bit length field), E_DEVICE.  The tANS tables are
- * copied to the device on its first use (synchronously). */
+ * d_out: histograms (Sec. 4: end-to-end encode is dominated by them),
+ * length-limited optimal code lengths per block (package-merge on the
+ * device, with the tie rules every encoder of the format follows: items by
+ * weight, a single before a package on equal weight, symbols by id; the
+ * multiset of lengths handed out ascending to the symbols by (count desc, id
+ * asc)) or the supplied tree, the top-down split of Table 11, entropy coding
+ * of the selected nodes, assembly.  The stream is byte-identical to the one
+ * the format definition implies.  Synchronous: returns the stream length in
+ * *h_out_len.  Errors: E_ARG (bad options or a supplied tree that misses a
+ * symbol present in the data), E_CAPACITY (out_cap or ws_bytes too small;
+ * nothing is written to d_out), E_UNSUPPORTED (ans_mode 3 with 2^24-bit
+ * chunks only: a cursor's stream longer than its 16-bit length field),
+ * E_DEVICE.  The tANS tables are copied to the device on their first use
+ * (synchronously). */
 pivco_status pivco_encode(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
                           uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
                           uint64_t ws_bytes, hipStream_t s);
+
+/* The same encode, asynchronous on s (nothing waits on the host, so it can
+ * be captured in a HIP graph once the tANS tables are on the device): the
+ * stream length goes to *d_out_len (a device uint64; the length the stream
+ * needs also when it exceeds out_cap) and the call's status to *d_status (a
+ * device int32: PIVCO_OK, E_ARG for a supplied tree that misses a present
+ * symbol, E_CAPACITY when the stream exceeds out_cap -- then nothing is
+ * written to d_out -- or E_UNSUPPORTED as above).  Argument errors are
+ * returned at once.  Workspace and bound as for pivco_encode. */
+pivco_status pivco_encode_async(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                                uint64_t *d_out_len, int32_t *d_status, const pivco_encode_opts *o,
+                                void *d_ws, uint64_t ws_bytes, hipStream_t s);
 
 /* ---------------------------------------------------------------------- */
 /* Decode (Sec. 3, bottom-up merge)                                       */

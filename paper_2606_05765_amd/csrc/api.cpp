@@ -21,6 +21,9 @@ pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, u
 pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
                            uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
                            uint64_t ws_bytes, hipStream_t s);
+pivco_status encode_stream_async(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                                 uint64_t *d_out_len, int32_t *d_status, const pivco_encode_opts *o,
+                                 void *d_ws, uint64_t ws_bytes, hipStream_t s);
 uint64_t encode_bound(uint64_t n, const pivco_encode_opts *o);
 uint64_t encode_workspace(uint64_t n, const pivco_encode_opts *o);
 }  // namespace pivco
@@ -639,6 +642,12 @@ pivco_status pivco_encode(const void *d_in, uint64_t n, void *d_out, uint64_t ou
                           uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
                           uint64_t ws_bytes, hipStream_t s) {
   return encode_stream(d_in, n, d_out, out_cap, h_out_len, o, d_ws, ws_bytes, s);
+}
+
+pivco_status pivco_encode_async(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                                uint64_t *d_out_len, int32_t *d_status, const pivco_encode_opts *o,
+                                void *d_ws, uint64_t ws_bytes, hipStream_t s) {
+  return encode_stream_async(d_in, n, d_out, out_cap, d_out_len, d_status, o, d_ws, ws_bytes, s);
 }
 
 }  // extern "C"

@@ -9,8 +9,9 @@
 //                    slice of it (end-to-end encode time is dominated by this
 //                    count, Sec. 4); k_slice_prefix turns the slice counts
 //                    into per-slice prefixes;
-//   2. host          optimal length-limited lengths per block (package-merge,
-//                    threads over blocks): the one step on the host;
+//   2. k_tree        optimal length-limited lengths per block (package-merge,
+//                    one wave per block, the host's tie rules), or the
+//                    supplied tree;
 //   3. k_layout      per block, from its lengths and histogram: canonical
 //                    codes, breadth-first node table, n_v and n_right, the
 //                    rANS selection rule, body sizes and offsets, and the
@@ -23,29 +24,28 @@
 //                    raw image, rANS nodes into word-aligned scratch -- and
 //                    scatters the symbols to the children's segments in LDS
 //                    with ballot + mbcnt ranks (stable);
-//   6. k_chunks      the rANS chunk jobs; k_rans_enc codes them (32-lane
-//                    interleaved binary rANS, one wave per chunk, steps in
-//                    reverse order);
+//   6. k_chunks      the entropy-coded chunk jobs; k_rans_enc codes them
+//                    (32-lane interleaved binary rANS, one wave per chunk,
+//                    steps in reverse order), or k_fse_enc (byte tANS);
 //   7. k_sizes       block sizes from the rANS body sizes; k_scan2 the block
 //                    offsets and the stream size;
 //   8. k_assemble    stream header, offset tables, block headers and raw
 //                    images (aligned 4-byte words); k_assemble_rans the rANS
 //                    bodies.
-// The host waits twice: for the histograms (the trees are built on the host)
-// and for the stream size.
+//   9. k_finish      the stream length and the call's status into device
+//                    memory.
+// Nothing waits on the host: pivco_encode_async leaves the length and status
+// in device memory; pivco_encode reads them back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cstring>
-#include <thread>
 #include <vector>
 
 #include "pivco_int.h"
 
 namespace pivco {
 
-pivco_status lengths_from_counts(const uint64_t counts[256], uint32_t max_len, uint8_t len[256]);
 bool tree_is_complete(const uint8_t len[256], uint32_t max_len);
 
 namespace {
@@ -58,6 +58,9 @@ constexpr uint32_t kHdrStride = 1216;   // block header bytes: 12 + 128 + 32 + 4
 constexpr uint32_t kLayoutWaves = 4;
 constexpr uint32_t kAsmSeg = 16384;     // output words per assembling workgroup
 constexpr uint32_t kScanNT = 1024;
+// Error word of one encode (in its status area); the first error wins.
+constexpr uint32_t kErrArg = 1;          // a block's tree: PIVCO_E_ARG
+constexpr uint32_t kErrUnsupported = 2;  // a tANS cursor stream past its 16-bit length: PIVCO_E_UNSUPPORTED
 
 // Per-block description for the split kernel, written by k_layout.
 struct EncBlock {
@@ -137,12 +140,10 @@ struct RansJob {
   uint32_t dst;           // byte offset of the chunk in its block (k_sizes)
 };
 
-// Batch totals (k_scan, k_scan2); err is set by k_fse_enc when a cursor's
-// stream would not fit its 16-bit length.
+// Batch totals (k_scan, k_scan2).
 struct Totals {
   uint64_t img_bytes, rbm_words, chunks, slot_bytes, ans_words, out_bytes;
-  uint32_t err, pad0;
-  uint64_t pad;
+  uint64_t pad[2];
 };
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -272,6 +273,196 @@ __global__ __launch_bounds__(256) void k_slice_prefix(uint32_t *slh, uint32_t sp
     const uint32_t c = row[256ull * k];
     row[256ull * k] = run;
     run += c;
+  }
+}
+
+// Code lengths of every block on the device (one wave per block), the same
+// package-merge and determinism rules as the host's lengths_from_counts
+// (items by weight; on equal weight a single before a package, symbols by
+// id, packages in creation order; the multiset of lengths handed out again
+// ascending to the symbols by (count desc, id asc)), in parallel form:
+//   * the present symbols are ranked by (count, id) by counting over all 256
+//     keys (a broadcast LDS read each), which also gives each symbol's run of
+//     equal counts;
+//   * row L holds the first min(m, 2m - 2) singles; row r - 1 merges the m
+//     singles with the packages (sums of consecutive pairs) of row r: single
+//     i lands at i + #(packages lighter than it), package j at j + #(singles
+//     no heavier), both by binary search, and positions past 2m - 2 are
+//     dropped.  Each row keeps the positions of its singles;
+//   * buying the first k = 2m - 2 items of row 1 buys the singles placed
+//     below k and 2 (k - singles) items of the next row, and so on; a
+//     symbol's length is the number of rows in which it was bought.
+// A block with one symbol becomes a constant block; a supplied tree is
+// copied (a present symbol without a code is an argument error).  A block
+// in error gets the constant mode (nothing to split) and sets *err.
+constexpr uint32_t kTreeRows = kMaxLenGpu + 1;
+struct TreeSmem {
+  uint64_t key[256];          // (count << 8 | symbol); ~0 for an absent symbol
+  uint64_t w[256];            // counts in (count, id) order
+  uint64_t row[2][512];       // item weights of two rows
+  uint64_t pk[256];           // packages of the row below
+  uint16_t spos[kTreeRows][256];   // row r: position of single i (0xFFFF: not in the row)
+  uint32_t rlen[kTreeRows];
+};
+
+__global__ __launch_bounds__(kWaveE) void k_tree(const uint32_t *hist, uint32_t nb, uint32_t L,
+                                                 pivco_tree tree, uint32_t use_tree, uint8_t *lenm,
+                                                 uint32_t *modes, uint32_t *err) {
+  __shared__ TreeSmem sm;
+  const uint32_t b = blockIdx.x, lane = __lane_id();
+  if (b >= nb) return;
+  uint32_t c[4];
+  bool pres[4];
+  uint32_t nsym = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    c[e] = hist[256ull * b + 4 * lane + e];
+    pres[e] = c[e] != 0;
+  }
+  uint64_t bal[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    bal[e] = __ballot(pres[e]);
+    nsym += static_cast<uint32_t>(__popcll(bal[e]));
+  }
+  const uint32_t m = nsym;
+  uint8_t *lb = lenm + 256ull * b;
+  if (use_tree) {
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint8_t l = tree.code_len[4 * lane + e];
+      bad |= pres[e] && l == 0;
+      lb[4 * lane + e] = l;
+    }
+    const bool any = __ballot(bad) != 0;
+    if (lane == 0) {
+      modes[b] = any ? 1u : 0u;
+      if (any) atomicCAS(err, 0u, kErrArg);
+    }
+    return;
+  }
+  if (m == 1 || m == 0 || (m > (1u << L))) {   // constant block, or no code of this length exists
+    uint32_t sym = 256;                   // the smallest present symbol (the same in every lane)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (bal[e]) {
+        const uint32_t cand = 4 * static_cast<uint32_t>(__ffsll(static_cast<long long>(bal[e])) - 1) + e;
+        sym = cand < sym ? cand : sym;
+      }
+    sym &= 255;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) lb[4 * lane + e] = 0;
+    if (lane == 0) {
+      modes[b] = 1u | (sym << 8);
+      if (m != 1) atomicCAS(err, 0u, kErrArg);
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t sy = 4 * lane + e;
+    sm.key[sy] = pres[e] ? (static_cast<uint64_t>(c[e]) << 8) | sy : ~0ull;
+  }
+  wave_sync();
+  // rank by (count, id), and the run of equal counts: [lt, le)
+  uint32_t rank[4] = {0, 0, 0, 0}, lt[4] = {0, 0, 0, 0}, le[4] = {0, 0, 0, 0};
+  for (uint32_t t = 0; t < 256; ++t) {
+    const uint64_t kt = sm.key[t];
+    const bool pt = kt != ~0ull;
+    const uint64_t ct = kt >> 8;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint64_t ke = (static_cast<uint64_t>(c[e]) << 8) | (4 * lane + e);
+      rank[e] += pt && kt < ke ? 1u : 0u;
+      lt[e] += pt && ct < c[e] ? 1u : 0u;
+      le[e] += pt && ct <= c[e] ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (pres[e]) sm.w[rank[e]] = c[e];
+  const uint32_t cap = 2 * m - 2, top = m < cap ? m : cap;
+  for (uint32_t i = lane; i < 256; i += kWaveE) sm.spos[L][i] = i < top ? static_cast<uint16_t>(i) : 0xFFFFu;
+  if (lane == 0) sm.rlen[L] = top;
+  wave_sync();
+  for (uint32_t i = lane; i < top; i += kWaveE) sm.row[L & 1][i] = sm.w[i];
+  wave_sync();
+  uint32_t rl = top;
+  for (uint32_t r = L; r > 1; --r) {
+    const uint64_t *cur = sm.row[r & 1];
+    uint64_t *nxt = sm.row[(r - 1) & 1];
+    const uint32_t np = rl / 2;
+    for (uint32_t j = lane; j < np; j += kWaveE) sm.pk[j] = cur[2 * j] + cur[2 * j + 1];
+    wave_sync();
+    const uint32_t total = m + np < cap ? m + np : cap;
+    for (uint32_t i = lane; i < m; i += kWaveE) {      // singles: packages strictly lighter come first
+      const uint64_t x = sm.w[i];
+      uint32_t lo = 0, hi = np;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sm.pk[mid] < x) lo = mid + 1; else hi = mid;
+      }
+      const uint32_t pos = i + lo;
+      if (pos < total) nxt[pos] = x;
+      sm.spos[r - 1][i] = pos < total ? static_cast<uint16_t>(pos) : 0xFFFFu;
+    }
+    for (uint32_t j = lane; j < np; j += kWaveE) {     // packages: singles no heavier come first
+      const uint64_t y = sm.pk[j];
+      uint32_t lo = 0, hi = m;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sm.w[mid] <= y) lo = mid + 1; else hi = mid;
+      }
+      const uint32_t pos = j + lo;
+      if (pos < total) nxt[pos] = y;
+    }
+    if (lane == 0) sm.rlen[r - 1] = total;
+    rl = total;
+    wave_sync();
+  }
+  // bought items, row by row
+  uint32_t depth[4] = {0, 0, 0, 0};
+  bool bad = false;
+  uint32_t k = cap;
+  for (uint32_t r = 1; r <= L && k; ++r) {
+    if (k > sm.rlen[r]) { bad = true; break; }
+    uint32_t sg = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t i = 4 * lane + e;
+      sg += static_cast<uint32_t>(__popcll(__ballot(i < m && sm.spos[r][i] < k)));
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) depth[e] += 4 * lane + e < sg ? 1u : 0u;
+    k = 2 * (k - sg);
+  }
+  // lengths: the ascending multiset to the symbols by (count desc, id asc)
+  uint32_t cum[kTreeRows + 1];
+  cum[0] = 0;
+  for (uint32_t l = 1; l <= L; ++l) {
+    uint32_t nl = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) nl += static_cast<uint32_t>(__popcll(__ballot(4 * lane + e < m && depth[e] == l)));
+    cum[l] = cum[l - 1] + nl;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (4 * lane + e < m && (depth[e] < 1 || depth[e] > L)) bad = true;
+  bad = __ballot(bad) != 0 || cum[L] != m;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t len = 0;
+    if (pres[e]) {
+      const uint32_t pd = (m - le[e]) + (rank[e] - lt[e]);
+      for (uint32_t l = 1; l <= L; ++l)
+        if (len == 0 && cum[l] > pd) len = l;
+    }
+    lb[4 * lane + e] = bad ? 0 : static_cast<uint8_t>(len);
+  }
+  if (lane == 0) {
+    modes[b] = bad ? 1u : 0u;
+    if (bad) atomicCAS(err, 0u, kErrArg);
   }
 }
 
@@ -590,7 +781,6 @@ __global__ __launch_bounds__(kScanNT) void k_scan(BlockLay *lay, uint32_t nb, To
     run[4] += L.ans_words;
   }
   if (tid == kScanNT - 1) {
-    tot->err = 0;
     tot->img_bytes = part[0][tid];
     tot->rbm_words = part[1][tid];
     tot->chunks = part[2][tid];
@@ -843,9 +1033,9 @@ __global__ __launch_bounds__(256) void k_rans_enc(const RansJob *jobs, const Tot
 // decoder reads step 0's bits first).  The table (norm, first, state) sits
 // in LDS, reloaded when a half's table changes.
 constexpr uint32_t kFseEncNT = 256;
-__global__ __launch_bounds__(kFseEncNT) void k_fse_enc(const RansJob *jobs, Totals *tot,
+__global__ __launch_bounds__(kFseEncNT) void k_fse_enc(const RansJob *jobs, const Totals *tot,
                                                        const uint32_t *bmp, const uint16_t *enc,
-                                                       uint8_t *slots, uint32_t *sizes) {
+                                                       uint8_t *slots, uint32_t *sizes, uint32_t *err) {
   __shared__ uint16_t tabs[kFseEncNT / kWaveE][2][kFseEncWords];
   const uint32_t lane = __lane_id(), half = lane >> 5, hl = lane & 31;
   const uint32_t wave = threadIdx.x >> 6;
@@ -888,7 +1078,7 @@ __global__ __launch_bounds__(kFseEncNT) void k_fse_enc(const RansJob *jobs, Tota
       tbits += nb;
     }
     const uint32_t len = (tbits + 7) >> 3;
-    if (len > 0xFFFF) atomicOr(&tot->err, 1u);
+    if (len > 0xFFFF) atomicCAS(err, 0u, kErrUnsupported);
     uint32_t incl = wave_incl_scan(len);
     const uint32_t lo = __builtin_amdgcn_readlane(incl, 31), all = __builtin_amdgcn_readlane(incl, 63);
     if (half) incl -= lo;
@@ -1076,6 +1266,35 @@ __global__ __launch_bounds__(256) void k_assemble_rans(const BlockLay *lay, cons
   }
 }
 
+// The call's result on the device: the stream length (also when it exceeds
+// out_cap, in which case nothing was written) and a status.
+__global__ void k_finish(const Totals *tot, const uint32_t *err, uint64_t out_cap, uint64_t *d_len,
+                         int32_t *d_status) {
+  if (threadIdx.x != 0) return;
+  const uint64_t n = tot->out_bytes;
+  const uint32_t e = *err;
+  *d_len = n;
+  *d_status = e == kErrArg ? PIVCO_E_ARG : e ? PIVCO_E_UNSUPPORTED : n > out_cap ? PIVCO_E_CAPACITY : PIVCO_OK;
+}
+
+// The stream of an empty input: header and the two one-entry tables.
+struct EmptyStream {
+  uint32_t w[16];
+};
+__global__ void k_empty(EmptyStream h, uint8_t *out, uint64_t out_cap, uint64_t *d_len, int32_t *d_status) {
+  const uint32_t t = threadIdx.x;
+  const bool fits = out_cap >= sizeof(h.w);
+  if (t < 16 && fits) reinterpret_cast<uint32_t *>(out)[t] = h.w[t];
+  if (t == 0) {
+    *d_len = sizeof(h.w);
+    *d_status = fits ? PIVCO_OK : PIVCO_E_CAPACITY;
+  }
+}
+
+__global__ void k_zero_words(uint32_t *p, uint32_t n) {
+  if (threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -1089,7 +1308,7 @@ bool opts_ok(const pivco_encode_opts *o) {
 }
 
 struct WsLayout {
-  uint64_t hist, slh, lenm, modes, eb, lay, rnodes, hdr, img, rbm, jobs, sizes, slots, tot, total;
+  uint64_t hist, slh, lenm, modes, eb, lay, rnodes, hdr, img, rbm, jobs, sizes, slots, tot, stat, total;
 };
 
 // Sizes from n and the options alone (the data is not known yet): every
@@ -1116,54 +1335,12 @@ WsLayout ws_layout(uint64_t n, const pivco_encode_opts *o) {
   L.sizes = x; x = align_up(x + chunks * 4, 256);
   L.slots = x; x = align_up(x + (o->ans_mode ? 2 * bits + chunks * 160 : 0) + 64, 256);
   L.tot = x; x = align_up(x + sizeof(Totals), 256);
+  L.stat = x; x = align_up(x + 64, 256);     // error word, then the synchronous call's length and status
   L.total = x;
   return L;
 }
 
 #define HIPCHK(x) do { if ((x) != hipSuccess) return PIVCO_E_DEVICE; } while (0)
-
-// Code lengths (or constant-block mode) of every block from its histogram:
-// package-merge per block, on up to 16 host threads.
-pivco_status build_trees(const std::vector<uint32_t> &hist, uint32_t nb, const pivco_encode_opts *o,
-                         std::vector<uint8_t> &lenm, std::vector<uint32_t> &modes) {
-  lenm.assign(static_cast<size_t>(nb) * 256, 0);
-  modes.assign(nb, 0);
-  std::atomic<int> err{PIVCO_OK};
-  auto work = [&](uint32_t b0, uint32_t b1) {
-    for (uint32_t b = b0; b < b1 && err.load(std::memory_order_relaxed) == PIVCO_OK; ++b) {
-      uint64_t counts[256];
-      int m = 0, last = 0;
-      for (int k = 0; k < 256; ++k) {
-        counts[k] = hist[static_cast<size_t>(b) * 256 + k];
-        if (counts[k]) { ++m; last = k; }
-      }
-      uint8_t *len = &lenm[static_cast<size_t>(b) * 256];
-      if (!o->tree && m == 1) {
-        modes[b] = 1u | (static_cast<uint32_t>(last) << 8);
-        continue;
-      }
-      if (o->tree) {
-        std::memcpy(len, o->tree->code_len, 256);
-        for (int k = 0; k < 256; ++k)
-          if (counts[k] && !len[k]) { err = PIVCO_E_ARG; return; }
-      } else {
-        const pivco_status st = lengths_from_counts(counts, o->max_len, len);
-        if (st) { err = st; return; }
-      }
-    }
-  };
-  const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const uint32_t nt = std::min<uint32_t>(hw, std::max<uint32_t>(1, nb / 64));
-  if (nt <= 1) {
-    work(0, nb);
-  } else {
-    std::vector<std::thread> th;
-    const uint32_t per = (nb + nt - 1) / nt;
-    for (uint32_t t = 0; t < nt; ++t) th.emplace_back(work, t * per, std::min(nb, (t + 1) * per));
-    for (auto &t : th) t.join();
-  }
-  return static_cast<pivco_status>(err.load());
-}
 
 }  // namespace
 
@@ -1183,10 +1360,14 @@ uint64_t encode_workspace(uint64_t n, const pivco_encode_opts *o) {
   return ws_layout(n, o).total;
 }
 
-pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
-                           uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
-                           uint64_t ws_bytes, hipStream_t s) {
-  if (!opts_ok(o) || !h_out_len || (n && !d_in) || !d_out) return PIVCO_E_ARG;
+namespace {
+
+// Enqueues a whole encode on s: no host wait.  The stream length and the
+// call's status go to d_len and d_status on the device.
+pivco_status encode_enqueue(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap, uint64_t *d_len,
+                            int32_t *d_status, const pivco_encode_opts *o, void *d_ws, uint64_t ws_bytes,
+                            hipStream_t s) {
+  if (!opts_ok(o) || (n && !d_in) || !d_out || !d_len || !d_status) return PIVCO_E_ARG;
   if ((reinterpret_cast<uintptr_t>(d_in) & 15) || (reinterpret_cast<uintptr_t>(d_out) & 15))
     return PIVCO_E_ARG;
   if (o->tree && !tree_is_complete(o->tree->code_len, o->max_len)) return PIVCO_E_ARG;
@@ -1195,62 +1376,58 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   const uint64_t spb64 = div_up(bs, kHistSlice);
   if (nb64 > 0xFFFFFFFFull || nb64 * spb64 > 0x7FFFFFFFull) return PIVCO_E_ARG;
   const uint32_t nb = static_cast<uint32_t>(nb64), spb = static_cast<uint32_t>(spb64);
+  const uint32_t flags = o->ans_mode == 3 ? 1u : 0u;
+  const uint32_t version = o->tree_shape ? 2u : 1u;
+  uint8_t *out = static_cast<uint8_t *>(d_out);
+  if (nb == 0) {                         // header and the two one-entry tables
+    EmptyStream h{};
+    h.w[0] = kMagic;
+    h.w[1] = version | (flags << 16);
+    h.w[4] = static_cast<uint32_t>(bs);
+    h.w[6] = (o->max_len & 255) | ((o->rans_chunk_log2 & 255) << 8);
+    h.w[12] = static_cast<uint32_t>(sizeof(h.w));     // block_off[0] = the stream size
+    hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, h, out, out_cap, d_len, d_status);
+    HIPCHK(hipGetLastError());
+    return PIVCO_OK;
+  }
   const WsLayout L = ws_layout(n, o);
   if (ws_bytes < L.total || !d_ws) return PIVCO_E_CAPACITY;
+  const FseTables *ft = nullptr;
+  if (o->ans_mode == 3 && !(ft = fse_tables())) return PIVCO_E_DEVICE;   // copied once per device
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   const uint8_t *in = static_cast<const uint8_t *>(d_in);
-  uint8_t *out = static_cast<uint8_t *>(d_out);
   Totals *dtot = reinterpret_cast<Totals *>(ws + L.tot);
   BlockLay *dlay = reinterpret_cast<BlockLay *>(ws + L.lay);
   EncBlock *deb = reinterpret_cast<EncBlock *>(ws + L.eb);
   RansNode *drn = reinterpret_cast<RansNode *>(ws + L.rnodes);
   RansJob *djobs = reinterpret_cast<RansJob *>(ws + L.jobs);
   uint32_t *dsizes = reinterpret_cast<uint32_t *>(ws + L.sizes);
-
-  if (nb == 0) {                         // header and the two one-entry tables
-    uint8_t h[kHeaderBytes + 16] = {0};
-    const uint32_t w[6] = {kMagic, (o->tree_shape ? 2u : 1u) | (o->ans_mode == 3 ? 1u << 16 : 0u), 0u, 0u,
-                           static_cast<uint32_t>(bs), 0u};
-    std::memcpy(h, w, sizeof(w));
-    h[24] = static_cast<uint8_t>(o->max_len);
-    h[25] = static_cast<uint8_t>(o->rans_chunk_log2);
-    const uint64_t end = sizeof(h);
-    std::memcpy(h + kHeaderBytes, &end, 8);
-    if (out_cap < sizeof(h)) return PIVCO_E_CAPACITY;
-    HIPCHK(hipMemcpyAsync(out, h, sizeof(h), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    *h_out_len = sizeof(h);
-    return PIVCO_OK;
-  }
+  uint32_t *derr = reinterpret_cast<uint32_t *>(ws + L.stat);
+  uint8_t *dlenm = ws + L.lenm;
+  uint32_t *dmodes = reinterpret_cast<uint32_t *>(ws + L.modes);
 
   // 1. histograms of the blocks and of their slices
-  std::vector<uint32_t> hist(static_cast<size_t>(nb) * 256, 0);
   uint32_t *dh = reinterpret_cast<uint32_t *>(ws + L.hist);
   uint32_t *dslh = reinterpret_cast<uint32_t *>(ws + L.slh);
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, derr, 1u);
   hipLaunchKernelGGL(k_fill_zero, dim3(std::min<uint64_t>(4096, div_up(nb64 * 256, 256))), dim3(256), 0, s,
                      dh, nb64 * 256);
   hipLaunchKernelGGL(k_hist, dim3(nb * spb), dim3(256), 0, s, in, n, static_cast<uint32_t>(bs), spb, dh, dslh);
   HIPCHK(hipGetLastError());
   if (spb > 1) hipLaunchKernelGGL(k_slice_prefix, dim3(nb), dim3(256), 0, s, dslh, spb);
-  HIPCHK(hipMemcpyAsync(hist.data(), dh, hist.size() * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
 
-  // 2. code lengths (host)
-  std::vector<uint8_t> lenm;
-  std::vector<uint32_t> modes;
-  const pivco_status st = build_trees(hist, nb, o, lenm, modes);
-  if (st) return st;
-  HIPCHK(hipMemcpyAsync(ws + L.lenm, lenm.data(), lenm.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(ws + L.modes, modes.data(), 4ull * nb, hipMemcpyHostToDevice, s));
+  // 2. code lengths (package-merge per block, or the supplied tree)
+  pivco_tree tree{};
+  if (o->tree) tree = *o->tree;
+  hipLaunchKernelGGL(k_tree, dim3(nb), dim3(kWaveE), 0, s, dh, nb, o->max_len, tree, o->tree ? 1u : 0u,
+                     dlenm, dmodes, derr);
+  HIPCHK(hipGetLastError());
 
   // 3.-4. layout and offsets
-  const FseTables *ft = nullptr;
-  if (o->ans_mode == 3 && !(ft = fse_tables())) return PIVCO_E_DEVICE;
   const uint32_t gl = (nb + kLayoutWaves - 1) / kLayoutWaves;
-  hipLaunchKernelGGL(k_layout, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, ws + L.lenm,
-                     reinterpret_cast<const uint32_t *>(ws + L.modes), dh, nb, n, static_cast<uint32_t>(bs),
-                     o->ans_mode, o->rans_chunk_log2, o->tree_shape, ft ? ft->dmax : nullptr, deb, dlay, drn,
-                     ws + L.hdr);
+  hipLaunchKernelGGL(k_layout, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, dlenm, dmodes, dh, nb, n,
+                     static_cast<uint32_t>(bs), o->ans_mode, o->rans_chunk_log2, o->tree_shape,
+                     ft ? ft->dmax : nullptr, deb, dlay, drn, ws + L.hdr);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanNT), 0, s, dlay, nb, dtot);
   uint32_t *dimg = reinterpret_cast<uint32_t *>(ws + L.img);
   uint32_t *drbm = reinterpret_cast<uint32_t *>(ws + L.rbm);
@@ -1261,14 +1438,14 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   hipLaunchKernelGGL(k_split, dim3(nb * spb), dim3(kSplitNT), 0, s, in, deb, dlay, nb, spb, dslh, dimg, drbm);
   HIPCHK(hipGetLastError());
 
-  // 6. rANS chunks
+  // 6. entropy-coded chunks
   const bool ans = o->ans_mode != 0;
   if (ans) {
     hipLaunchKernelGGL(k_chunks, dim3(gl), dim3(kWaveE * kLayoutWaves), 0, s, dlay, drn, nb,
                        o->rans_chunk_log2, djobs);
     if (ft)
       hipLaunchKernelGGL(k_fse_enc, dim3(2048), dim3(kFseEncNT), 0, s, djobs, dtot, drbm, ft->enc,
-                         ws + L.slots, dsizes);
+                         ws + L.slots, dsizes, derr);
     else
       hipLaunchKernelGGL(k_rans_enc, dim3(2048), dim3(256), 0, s, djobs, dtot, drbm, ws + L.slots, dsizes);
     HIPCHK(hipGetLastError());
@@ -1281,8 +1458,8 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
 
   // 8. the stream (nothing is written when it would not fit)
   hipLaunchKernelGGL(k_stream_head, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, dlay, dtot, nb, n,
-                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2,
-                     (o->tree_shape ? 2u : 1u) | (o->ans_mode == 3 ? 1u << 16 : 0u), out, out_cap);
+                     static_cast<uint32_t>(bs), o->max_len, o->rans_chunk_log2, version | (flags << 16), out,
+                     out_cap);
   const uint64_t max_words = (kHdrStride + bs * o->max_len / 8 + 255 + 4) / 4 + 1;
   const uint32_t segs = static_cast<uint32_t>(div_up(max_words, kAsmSeg));
   if (static_cast<uint64_t>(nb) * segs > 0x7FFFFFFFull) return PIVCO_E_UNSUPPORTED;
@@ -1291,16 +1468,39 @@ pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t o
   if (ans)
     hipLaunchKernelGGL(k_assemble_rans, dim3(2048), dim3(256), 0, s, dlay, drn, djobs, dsizes, dtot,
                        ws + L.slots, out, out_cap);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, dtot, derr, out_cap, d_len, d_status);
   HIPCHK(hipGetLastError());
-  Totals tot{};
-  HIPCHK(hipMemcpyAsync(&tot, dtot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+  return PIVCO_OK;
+}
+
+}  // namespace
+
+pivco_status encode_stream_async(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                                 uint64_t *d_out_len, int32_t *d_status, const pivco_encode_opts *o,
+                                 void *d_ws, uint64_t ws_bytes, hipStream_t s) {
+  return encode_enqueue(d_in, n, d_out, out_cap, d_out_len, d_status, o, d_ws, ws_bytes, s);
+}
+
+pivco_status encode_stream(const void *d_in, uint64_t n, void *d_out, uint64_t out_cap,
+                           uint64_t *h_out_len, const pivco_encode_opts *o, void *d_ws,
+                           uint64_t ws_bytes, hipStream_t s) {
+  if (!opts_ok(o) || !h_out_len || !d_ws) return PIVCO_E_ARG;
+  const WsLayout L = ws_layout(n, o);
+  if (ws_bytes < L.total) return PIVCO_E_CAPACITY;
+  // the result words sit in the workspace's status area
+  uint8_t *res = static_cast<uint8_t *>(d_ws) + L.stat + 16;
+  uint64_t *d_len = reinterpret_cast<uint64_t *>(res);
+  int32_t *d_st = reinterpret_cast<int32_t *>(res + 8);
+  const pivco_status st = encode_enqueue(d_in, n, d_out, out_cap, d_len, d_st, o, d_ws, ws_bytes, s);
+  if (st) return st;
+  struct {
+    uint64_t len;
+    int32_t status, pad;
+  } r{};
+  HIPCHK(hipMemcpyAsync(&r, res, 16, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  // a tANS cursor stream longer than its u16 length field (only with
-  // 2^24-bit chunks of bytes costing more than 8 bits on average)
-  if (tot.err) return PIVCO_E_UNSUPPORTED;
-  const uint64_t total = tot.out_bytes;
-  if (total > out_cap) return PIVCO_E_CAPACITY;
-  *h_out_len = total;
+  if (r.status) return static_cast<pivco_status>(r.status);
+  *h_out_len = r.len;
   return PIVCO_OK;
 }
 

@@ -93,6 +93,7 @@ def lib():
             "pivco_encode_bound": (u64, [u64, C.POINTER(EncodeOpts)]),
             "pivco_encode_workspace": (u64, [u64, C.POINTER(EncodeOpts)]),
             "pivco_encode": (i32, [vp, u64, vp, u64, u64p, C.POINTER(EncodeOpts), vp, u64, vp]),
+            "pivco_encode_async": (i32, [vp, u64, vp, u64, vp, vp, C.POINTER(EncodeOpts), vp, u64, vp]),
             "pivco_stream_info": (i32, [vp, u64, u64p, u32p, u32p, u64p]),
             "pivco_decode_workspace": (u64, [C.POINTER(Job), u32, vp]),
             "pivco_decode_batch": (i32, [C.POINTER(Job), u32, vp, vp, u64, vp]),
@@ -194,6 +195,32 @@ def pivco_encode(data, block_size, max_len=11, ans_mode=0, chunk_log2=16, tree=N
                               _stream()), "pivco_encode")
     del keep
     return out[:olen.value].clone()
+
+
+def pivco_encode_async(data, out, out_len, status, ws, block_size, max_len=11, ans_mode=0, chunk_log2=16,
+                       tree=None, flat=False):
+    """Enqueue an encode on the current stream without waiting: the stream
+    goes to out (a uint8 CUDA tensor of at least pivco_encode_bound bytes),
+    its length to out_len (a one-element int64 CUDA tensor) and the status to
+    status (a one-element int32 CUDA tensor); ws is a uint8 CUDA tensor of at
+    least pivco_encode_workspace bytes."""
+    data = _dev_u8(data)
+    out = _dev_u8(out)
+    ws = _dev_u8(ws)
+    if not (out_len.is_cuda and out_len.dtype == torch.int64 and status.is_cuda and status.dtype == torch.int32):
+        raise TypeError("out_len: an int64 CUDA tensor, status: an int32 CUDA tensor")
+    n = data.numel()
+    o, keep = _opts(block_size, max_len, ans_mode, chunk_log2, tree, flat)
+    _check(lib().pivco_encode_async(C.c_void_p(data.data_ptr() if n else 0), n, C.c_void_p(out.data_ptr()),
+                                    out.numel(), C.c_void_p(out_len.data_ptr()), C.c_void_p(status.data_ptr()),
+                                    C.byref(o), C.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+           "pivco_encode_async")
+    del keep
+
+
+def pivco_encode_workspace(n, block_size, max_len=11, ans_mode=0, chunk_log2=16, flat=False):
+    o, _ = _opts(block_size, max_len, ans_mode, chunk_log2, None, flat)
+    return int(lib().pivco_encode_workspace(n, C.byref(o)))
 
 
 # ---------------------------------------------------------------------------
