@@ -221,6 +221,14 @@ __device__ __forceinline__ uint32_t item_tid() {
   return t;
 }
 
+// A wave-uniform 64-bit value in scalar registers: the load that produced it
+// is waited for here, once, not at its first use inside a loop.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // The wave's index in the workgroup, as a scalar (wave-uniform) value.
 __device__ __forceinline__ uint32_t wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1658,13 +1666,18 @@ __device__ void load_block(const JobDev &J, const ParsedBlock *rec, const BlockE
   if (block_resident<C>(ext)) {
     const uint64_t g0 = ext.blk & ~15ull;
     const uint64_t span = ((ext.end + 15) & ~15ull) - g0;
-    const uint64_t in_dw = J.in_len >> 2;
-    const uint64_t in16 = J.in_len >> 4;
-    const uint32_t *gin = reinterpret_cast<const uint32_t *>(J.in);
+    // the job's stream pointer and length in registers: read from the job
+    // table inside the loop, each read would wait for every direct-to-LDS
+    // load issued before it (a global load's s_waitcnt vmcnt counts them)
+    const uint8_t *const jin = J.in;
+    const uint64_t jlen = J.in_len;
+    const uint64_t in_dw = jlen >> 2;
+    const uint64_t in16 = jlen >> 4;
+    const uint32_t *gin = reinterpret_cast<const uint32_t *>(jin);
     const uint32_t n16 = static_cast<uint32_t>(span >> 4);
     for (uint32_t base = kWave * wave; base < n16; base += kWave * C::NW) {
       if (base + kWave <= n16 && (g0 >> 4) + base + kWave <= in16) {
-        __builtin_amdgcn_global_load_lds(J.in + g0 + 16ull * (base + lane), &sm.body[4 * base], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(jin + g0 + 16ull * (base + lane), &sm.body[4 * base], 16, 0, 0);
       } else {
         const uint32_t i = base + lane;
         if (i < n16) {
@@ -2019,16 +2032,37 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
     return;
   }
   // copy: one wave per node, 64 chunks per step, direct to LDS where the
-  // source chunk lies inside its buffer, guarded byte loads otherwise
-  for (uint32_t v = wave; v < I; v += C::NW) {
-    const uint32_t cnt = sm.ones[v];
+  // source chunk lies inside its buffer, guarded byte loads otherwise.  Every
+  // value the copy needs is read from LDS (and the job table) before the
+  // first load is issued: a direct-to-LDS load writes LDS, so an LDS or
+  // global read issued after it waits for every such load in flight (one
+  // memory round trip per node).  Lane j of the wave holds node wave + NW j
+  // (a wave has at most 256 / NW <= 64 nodes).
+  static_assert(256 / C::NW <= kWave, "a wave's nodes fit its lanes");
+  const uint8_t *const jin = reinterpret_cast<const uint8_t *>(uniform64(reinterpret_cast<uint64_t>(J.in)));
+  const uint64_t jlen = uniform64(J.in_len);
+  const uint32_t vl = static_cast<uint32_t>(wave) + C::NW * lane;   // the lane's node
+  uint32_t cnt_l = 0, off_l = 0, kind_l = 0;
+  uint64_t s16_l = 0;
+  if (vl < I) {
+    cnt_l = sm.ones[vl];
+    off_l = sm.stg[vl];
+    kind_l = t.kind[vl];
+    const uint64_t g = (kind_l ? 32ull * (h.ans_word0 + t.boff[vl]) : 8ull * (h.blk + t.boff[vl])) +
+                       static_cast<uint64_t>(t.fd[vl] ? t.fd[vl] : 1u) * sm.cur[vl];
+    s16_l = (g >> 3) & ~15ull;
+  }
+  const uint32_t nmine = (I > static_cast<uint32_t>(wave)) ? (I - static_cast<uint32_t>(wave) + C::NW - 1) / C::NW : 0u;
+  for (uint32_t j = 0; j < nmine; ++j) {
+    const uint32_t cnt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(cnt_l), static_cast<int>(j)));
     if (!cnt) continue;
-    const uint32_t off = sm.stg[v];
-    const uint64_t g = (t.kind[v] ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v])) +
-                       static_cast<uint64_t>(t.fd[v] ? t.fd[v] : 1u) * sm.cur[v];
-    const uint64_t s16 = (g >> 3) & ~15ull;
-    const uint8_t *src = t.kind[v] ? reinterpret_cast<const uint8_t *>(scratch) : J.in;
-    const uint64_t lim = t.kind[v] ? 4ull * scratch_words : J.in_len;
+    const uint32_t off = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(off_l), static_cast<int>(j)));
+    const bool kind = __builtin_amdgcn_readlane(static_cast<int>(kind_l), static_cast<int>(j)) != 0;
+    const uint64_t s16 = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(
+                              static_cast<int>(s16_l >> 32), static_cast<int>(j)))) << 32) |
+                         static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(s16_l), static_cast<int>(j)));
+    const uint8_t *src = kind ? reinterpret_cast<const uint8_t *>(scratch) : jin;
+    const uint64_t lim = kind ? 4ull * scratch_words : jlen;
     for (uint32_t c0 = 0; c0 < cnt; c0 += kWave) {
       const uint32_t c = c0 + lane;
       const uint64_t q = s16 + 16ull * c;

@@ -47,15 +47,16 @@ def _plan_decode(streams, outs, reps=2):
     plan.close()
 
 
-def _single_stream(w, sample_blocks=24):
+def _single_stream(w, sample_blocks=24, ans_mode=None):
     x = w.jobs[0]
-    _say("workload", w.name, x.size, "bytes, block", w.block_size)
+    mode = w.ans_mode if ans_mode is None else ans_mode
+    _say("workload", w.name, x.size, "bytes, block", w.block_size, "ans_mode", mode)
     d_x = torch.from_numpy(x).cuda()
-    st = P.pivco_encode(d_x, w.block_size, ans_mode=w.ans_mode)
+    st = P.pivco_encode(d_x, w.block_size, ans_mode=mode)
     torch.cuda.synchronize()
     g = st.cpu().numpy()
     _say("gpu stream", g.size, "bytes; oracle encode ...")
-    want = O.encode(x, w.block_size, ans_mode=w.ans_mode)
+    want = O.encode(x, w.block_size, ans_mode=mode)
     assert g.size == want.size and np.array_equal(g, want), \
         f"stream sizes {g.size}/{want.size}, first difference at byte {_first_diff(g, want)}"
     _say("stream identical; batched decode ...")
@@ -87,6 +88,12 @@ def test_zipf256m_full():
 @pytest.mark.timeout(300)
 def test_skew256m_full():
     _single_stream(W.skew256m(seed=1))
+
+
+@pytest.mark.timeout(300)
+def test_skew256m_full_selective_tans():
+    # the same workload with the selective tANS of Sec. 5.2 (ans_mode 3)
+    _single_stream(W.skew256m(seed=1), ans_mode=3)
 
 
 @pytest.mark.timeout(400)
