@@ -1993,6 +1993,9 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
     sm.cur[v] = a;
     sm.tv[v] = b > a ? b - a : 0u;
   }
+  // the job's stream pointer and length, read with the record
+  const uint8_t *const jin = reinterpret_cast<const uint8_t *>(uniform64(reinterpret_cast<uint64_t>(J.in)));
+  const uint64_t jlen = uniform64(J.in_len);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   BlockHdr &h = sm.pb.h;
@@ -2031,59 +2034,65 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
     lds_barrier();
     return;
   }
-  // copy: one wave per node, 64 chunks per step, direct to LDS where the
-  // source chunk lies inside its buffer, guarded byte loads otherwise.  Every
-  // value the copy needs is read from LDS (and the job table) before the
-  // first load is issued: a direct-to-LDS load writes LDS, so an LDS or
-  // global read issued after it waits for every such load in flight (one
-  // memory round trip per node).  Lane j of the wave holds node wave + NW j
-  // (a wave has at most 256 / NW <= 64 nodes).
-  static_assert(256 / C::NW <= kWave, "a wave's nodes fit its lanes");
-  const uint8_t *const jin = reinterpret_cast<const uint8_t *>(uniform64(reinterpret_cast<uint64_t>(J.in)));
-  const uint64_t jlen = uniform64(J.in_len);
-  const uint32_t vl = static_cast<uint32_t>(wave) + C::NW * lane;   // the lane's node
-  uint32_t cnt_l = 0, off_l = 0, kind_l = 0;
-  uint64_t s16_l = 0;
-  if (vl < I) {
-    cnt_l = sm.ones[vl];
-    off_l = sm.stg[vl];
-    kind_l = t.kind[vl];
-    const uint64_t g = (kind_l ? 32ull * (h.ans_word0 + t.boff[vl]) : 8ull * (h.blk + t.boff[vl])) +
-                       static_cast<uint64_t>(t.fd[vl] ? t.fd[vl] : 1u) * sm.cur[vl];
-    s16_l = (g >> 3) & ~15ull;
-  }
-  const uint32_t nmine = (I > static_cast<uint32_t>(wave)) ? (I - static_cast<uint32_t>(wave) + C::NW - 1) / C::NW : 0u;
-  for (uint32_t j = 0; j < nmine; ++j) {
-    const uint32_t cnt = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(cnt_l), static_cast<int>(j)));
-    if (!cnt) continue;
-    const uint32_t off = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(off_l), static_cast<int>(j)));
-    const bool kind = __builtin_amdgcn_readlane(static_cast<int>(kind_l), static_cast<int>(j)) != 0;
-    const uint64_t s16 = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(
-                              static_cast<int>(s16_l >> 32), static_cast<int>(j)))) << 32) |
-                         static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(s16_l), static_cast<int>(j)));
-    const uint8_t *src = kind ? reinterpret_cast<const uint8_t *>(scratch) : jin;
-    const uint64_t lim = kind ? 4ull * scratch_words : jlen;
-    for (uint32_t c0 = 0; c0 < cnt; c0 += kWave) {
-      const uint32_t c = c0 + lane;
-      const uint64_t q = s16 + 16ull * c;
-      if (c < cnt && q + 16 <= lim) {
-        __builtin_amdgcn_global_load_lds(src + q, &sm.body[4 * (off + c0)], 16, 0, 0);
-      } else if (c < cnt) {
-        uint32_t w[4];
+  // copy: the staged chunks in order, C::NT per step.  Staged chunk s (of
+  // node v, stg[v] <= s < stg[v] + ones[v]) goes to LDS slot s, so a wave's
+  // 64 lanes fill 64 consecutive slots with one direct-to-LDS load, each lane
+  // gathering from its own node's range; chunks not wholly inside their
+  // buffer take guarded byte loads afterwards.  Every source address is
+  // computed (LDS reads) before the first load is issued: a direct-to-LDS
+  // load writes LDS, so an LDS or global read issued after it waits for
+  // every such load in flight.
+  constexpr uint32_t KS = (C::BODY / 16 + C::NT - 1) / C::NT;
+  for (uint32_t i = 4 * total + tid; i < 4 * total + 16; i += C::NT) sm.body[i] = 0u;   // not a load target
+  uint64_t qa[KS];          // source byte offset of the lane's chunk at each step
+  uint32_t inb = 0, scr = 0;  // bit k: step k's chunk lies inside its buffer / comes from scratch
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          uint32_t x = 0;
-          for (int by = 0; by < 4; ++by) {
-            const uint64_t a = q + 4 * e + by;
-            if (a < lim) x |= static_cast<uint32_t>(src[a]) << (8 * by);
-          }
-          w[e] = x;
-        }
-        *reinterpret_cast<uint4 *>(&sm.body[4 * (off + c)]) = make_uint4(w[0], w[1], w[2], w[3]);
+  for (uint32_t k = 0; k < KS; ++k) {
+    const uint32_t sc = k * C::NT + static_cast<uint32_t>(tid);
+    qa[k] = 0;
+    if (sc < total) {
+      uint32_t lo = 0, hi = I;                  // the last node whose chunks start at or before sc
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sm.stg[mid] <= sc) lo = mid; else hi = mid;
       }
+      const uint32_t v = lo;
+      const bool kind = t.kind[v] != 0;
+      const uint64_t g = (kind ? 32ull * (h.ans_word0 + t.boff[v]) : 8ull * (h.blk + t.boff[v])) +
+                         static_cast<uint64_t>(t.fd[v] ? t.fd[v] : 1u) * sm.cur[v];
+      const uint64_t q = ((g >> 3) & ~15ull) + 16ull * (sc - sm.stg[v]);
+      qa[k] = q;
+      if (q + 16 <= (kind ? 4ull * scratch_words : jlen)) inb |= 1u << k;
+      if (kind) scr |= 1u << k;
     }
   }
-  for (uint32_t i = 4 * total + tid; i < 4 * total + 16; i += C::NT) sm.body[i] = 0u;
+  const uint8_t *const sbase = reinterpret_cast<const uint8_t *>(scratch);
+#pragma unroll
+  for (uint32_t k = 0; k < KS; ++k) {
+    const uint32_t b = k * C::NT + kWave * static_cast<uint32_t>(wave);   // the wave's first slot
+    if (b < total && ((inb >> k) & 1))
+      __builtin_amdgcn_global_load_lds(((scr >> k) & 1 ? sbase : jin) + qa[k], &sm.body[4 * b], 16, 0, 0);
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < KS; ++k) {
+    const uint32_t sc = k * C::NT + static_cast<uint32_t>(tid);
+    if (sc < total && !((inb >> k) & 1)) {
+      const bool kind = (scr >> k) & 1;
+      const uint8_t *src = kind ? sbase : jin;
+      const uint64_t lim = kind ? 4ull * scratch_words : jlen;
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t x = 0;
+        for (int by = 0; by < 4; ++by) {
+          const uint64_t a = qa[k] + 4 * e + by;
+          if (a < lim) x |= static_cast<uint32_t>(src[a]) << (8 * by);
+        }
+        w[e] = x;
+      }
+      *reinterpret_cast<uint4 *>(&sm.body[4 * sc]) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   // LDS bit address of each share's first bit (abit shares its words with
