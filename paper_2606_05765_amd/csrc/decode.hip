@@ -1972,7 +1972,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
 // A tile of a split block: the block's record and the tile's two boundary
 // rows (each node's position at the tile's start and end), then every node's
 // share of the tile -- the covering 16-byte chunks of its bitmap, from the
-// stream or from the rANS scratch -- copied into LDS node after node.  Ends
+// stream or from the rANS scratch -- gathered into LDS, node after node.  Ends
 // with a barrier; sm.cur and sm.tv hold the shares, sm.abit the LDS bit
 // address of each share's first bit, sm.stage_top the staged words.
 template <class C>
@@ -2260,26 +2260,35 @@ struct TilesSmem {
   int32_t err;
 };
 
-// The region's 1 bits before bit x (b0 <= x <= b1): the directory entry of
-// x's piece (of the last piece when x is the region's end on a piece
-// boundary) and the piece's bits before x.
+// The region's 1 bits before bit x (b0 <= x <= b1), from the directory
+// entry of x's piece (of the last piece when x is the region's end on a
+// piece boundary): the entry plus the piece's bits before x, or, when x lies
+// in the second half of a piece that is not the region's last, the next
+// entry minus the piece's bits from x on.  Only the chunks that hold those
+// bits are loaded (at most SPR / 2 + 1), B at a time.
 template <uint32_t SPR>                            // chunks per piece: G = 128 * SPR
 __device__ __forceinline__ uint32_t region_prefix(const TilesSmem &sm, const TileRegion &r, uint64_t x) {
   constexpr uint32_t LG = 31 - __builtin_clz(SPR) + 7, B = SPR < 8 ? SPR : 8;
   if (r.np == 0) return 0u;
   uint32_t j = static_cast<uint32_t>((x >> LG) - (r.b0 >> LG));
   j = j < r.np ? j : r.np - 1;
-  const uint64_t sb = ((r.b0 >> LG) + j) << LG, lo = sb > r.b0 ? sb : r.b0;
-  uint32_t n = sm.dir[r.d0 + j];
-  for (uint32_t c0 = 0; c0 < SPR; c0 += B) {       // the piece's bits before x, B chunks in flight
+  const uint64_t sb = ((r.b0 >> LG) + j) << LG, pe = sb + (1ull << LG);
+  const bool back = j + 1 < r.np && x - sb > (1ull << (LG - 1));
+  // bits [lo, hi) counted; chunks from byte q0 on
+  const uint64_t lo = back ? x : (sb > r.b0 ? sb : r.b0), hi = back ? pe : x;
+  const uint64_t q0 = back ? (x >> 7) << 4 : sb >> 3;
+  const uint32_t nck = hi > lo ? static_cast<uint32_t>((hi - 8 * q0 + 127) >> 7) : 0u;
+  uint32_t n = 0;
+  for (uint32_t c0 = 0; c0 < nck; c0 += B) {
     Chunk ch[B];
 #pragma unroll
-    for (uint32_t c = 0; c < B; ++c) ch[c] = chunk_load(r.p, r.nb, (sb >> 3) + 16ull * (c0 + c));
+    for (uint32_t c = 0; c < B; ++c)       // past the last chunk: the last one again (counted once)
+      ch[c] = chunk_load(r.p, r.nb, q0 + 16ull * (c0 + c < nck ? c0 + c : nck - 1));
 #pragma unroll
-    for (uint32_t c = 0; c < B; ++c)               // chunks at or after x count nothing
-      n += chunk_count(ch[c], (sb >> 3) + 16ull * (c0 + c), lo, x);
+    for (uint32_t c = 0; c < B; ++c)
+      if (c0 + c < nck) n += chunk_count(ch[c], q0 + 16ull * (c0 + c), lo, hi);
   }
-  return n;
+  return back ? sm.dir[r.d0 + j + 1] - n : sm.dir[r.d0 + j] + n;
 }
 
 // The level loop of k_tiles (POS_LDS: positions in sm.pos, else in the table).
