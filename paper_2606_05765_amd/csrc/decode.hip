@@ -98,6 +98,13 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
   return (static_cast<uint64_t>(wave_incl_scan(hi)) << 32) | wave_incl_scan(lo);
 }
 
+// tot[0] + ... + tot[n-1] for a wave-uniform n <= 64 (all lanes active):
+// lane i reads tot[i], then one wave-wide sum, instead of n dependent reads.
+__device__ __forceinline__ uint32_t sum_first(const uint32_t *tot, uint32_t n) {
+  const uint32_t x = __lane_id() < n ? tot[__lane_id()] : 0u;
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wave_incl_scan(x)), kWave - 1));
+}
+
 // ---------------------------------------------------------------------------
 // Block header state shared by the rANS and merge kernels
 // ---------------------------------------------------------------------------
@@ -1792,9 +1799,10 @@ __device__ void fill_constant(uint8_t *out, uint32_t n, uint32_t c) {
 // Rank directory over the first body_dw words of sm.body: per 256-bit
 // superblock the 1 bits before it, per 64-bit word the 1 bits of its
 // superblock before it; then every node's rank at its first bit (sm.abit).
-// Ends with a barrier.
+// Ends with a barrier only when `last` is set: otherwise the caller's next
+// barrier orders the ranks before their readers.
 template <class C>
-__device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) {
+__device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I, bool last) {
   const uint32_t tid = item_tid();
   const uint32_t wave = wave_id();
   const uint32_t lane = lane_id();
@@ -1807,10 +1815,7 @@ __device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) 
     const uint4 c = *reinterpret_cast<const uint4 *>(&sm.body[8 * k + 4]);
     const uint32_t w0 = __popc(a.x) + __popc(a.y), w1 = __popc(a.z) + __popc(a.w);
     const uint32_t w2 = __popc(c.x) + __popc(c.y), w3 = __popc(c.z) + __popc(c.w);
-    sm.rel[4 * k] = 0;
-    sm.rel[4 * k + 1] = static_cast<uint8_t>(w0);
-    sm.rel[4 * k + 2] = static_cast<uint8_t>(w0 + w1);
-    sm.rel[4 * k + 3] = static_cast<uint8_t>(w0 + w1 + w2);
+    *reinterpret_cast<uint32_t *>(&sm.rel[4 * k]) = (w0 << 8) | ((w0 + w1) << 16) | ((w0 + w1 + w2) << 24);
     const uint32_t cnt = w0 + w1 + w2 + w3;
     sm.sup[k] = cnt;
     loc += cnt;
@@ -1818,8 +1823,7 @@ __device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) 
   const uint32_t inc = wave_incl_scan(loc);
   if (lane == kWave - 1) sm.scan_tot[wave] = inc;
   lds_barrier();
-  uint32_t run = inc - loc;
-  for (uint32_t w = 0; w < wave; ++w) run += sm.scan_tot[w];
+  uint32_t run = inc - loc + sum_first(sm.scan_tot, wave);
   for (uint32_t k = s0; k < s0 + per && k < nsb; ++k) {
     const uint32_t c = sm.sup[k];
     sm.sup[k] = run;
@@ -1831,7 +1835,7 @@ __device__ void build_directory(MergeSmem<C> &sm, uint32_t body_dw, uint32_t I) 
     sm.r0[i] = r;
     sm.arank[i] = r;
   }
-  lds_barrier();
+  if (last) lds_barrier();
 }
 
 // Decodes the block whose record (and, when resident, body) load_block put
@@ -1877,7 +1881,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
       t.nv[i] = sm.tv[i];
     }
     if (tid == 0) sm.tile = C::T;
-    build_directory<C>(sm, 4 * sm.stage_top, I);
+    build_directory<C>(sm, 4 * sm.stage_top, I, n == 0);   // the tile loop's first barrier follows
   } else {
     if (resident) {
       const uint32_t lb = static_cast<uint32_t>(h.blk - g0);
@@ -1904,7 +1908,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
       if (!resident) sm.obase[0] = 0;      // shares the union with the resident arrays
     }
     // build_directory's barriers order the writes above before their readers
-    if (resident) build_directory<C>(sm, static_cast<uint32_t>(span >> 2) + h.ans_words, I);
+    if (resident) build_directory<C>(sm, static_cast<uint32_t>(span >> 2) + h.ans_words, I, n == 0);
     else lds_barrier();
   }
   const uint32_t T = sm.tile;
@@ -2016,16 +2020,14 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
   const uint32_t inc = tid < 256 ? wave_incl_scan(nch) : 0u;
   if (tid < 256 && lane == kWave - 1) sm.scan_tot[wave] = inc;
   lds_barrier();
+  const uint32_t before = tid < 256 ? sum_first(sm.scan_tot, static_cast<uint32_t>(wave)) : 0u;
   if (static_cast<uint32_t>(tid) < I) {
-    uint32_t off = inc - nch;
-    for (int w = 0; w < wave; ++w) off += sm.scan_tot[w];
-    sm.stg[tid] = off;                  // first staged chunk of the node
+    sm.stg[tid] = inc - nch + before;   // first staged chunk of the node
     sm.ones[tid] = nch;                 // its chunks
   }
-  if (tid == 0) {
-    uint32_t tot = 0;
-    for (int w = 0; w < 4; ++w) tot += sm.scan_tot[w];
-    sm.stage_top = tot;
+  if (wave == 0) {
+    const uint32_t tot = sum_first(sm.scan_tot, 4);
+    if (tid == 0) sm.stage_top = tot;
   }
   lds_barrier();
   const uint32_t total = sm.stage_top;
@@ -2444,8 +2446,7 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
     __shared__ uint32_t tot[kTilesNT / kWave];
     if (lane == kWave - 1) tot[wave] = incl;
     __syncthreads();
-    uint32_t run = incl - loc;
-    for (uint32_t w = 0; w < wave; ++w) run += tot[w];
+    uint32_t run = incl - loc + sum_first(tot, wave);
     __syncthreads();
     for (uint32_t f = f0; f < f1; ++f) {
       const uint32_t c = sm.dir[f];
