@@ -1917,6 +1917,10 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
   bool bad = false;
 
   publish_next<C>(sm, la);            // visible after the next barrier
+  // a split block's tile is one pass whose shares are known: the task lists'
+  // first barrier orders the rank directory's last writes before their
+  // readers, and the root's share already is troot
+  const bool one_tile = tiled && C::T >= static_cast<int>(kTileOut);
   for (uint32_t t0 = 0; t0 < n; t0 += T) {
     const uint32_t troot = n - t0 < T ? n - t0 : T;
     if (tid == 0) {
@@ -1924,7 +1928,7 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
       sm.act_run = 0;
       sm.tv[0] = troot;
     }
-    lds_barrier();
+    if (!one_tile) lds_barrier();
     if (resident) {
       if (!tiled || C::T < kTileOut) {
         if (t0 + troot < n) {
@@ -1976,9 +1980,10 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
 // A tile of a split block: the block's record and the tile's two boundary
 // rows (each node's position at the tile's start and end), then every node's
 // share of the tile -- the covering 16-byte chunks of its bitmap, from the
-// stream or from the rANS scratch -- gathered into LDS, node after node.  Ends
-// with a barrier; sm.cur and sm.tv hold the shares, sm.abit the LDS bit
-// address of each share's first bit, sm.stage_top the staged words.
+// stream or from the rANS scratch -- gathered into LDS, node after node.
+// After its last barrier sm.cur and sm.tv hold the shares and sm.stage_top
+// the staged words; sm.abit (the LDS bit address of each share's first bit)
+// is written by thread v for node v after that barrier.
 template <class C>
 __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *tab, uint32_t k,
                           const uint32_t *scratch, uint64_t scratch_words, MergeSmem<C> &sm) {
@@ -2098,10 +2103,10 @@ __device__ void load_tile(const JobDev &J, const ParsedBlock *rec, const uint2 *
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   // LDS bit address of each share's first bit (abit shares its words with
-  // tone, not with stg or ones)
+  // tone, not with stg or ones); read after the rank directory's first
+  // barrier
   if (static_cast<uint32_t>(tid) < I)
     sm.abit[tid] = sm.tv[tid] ? 128u * sm.stg[tid] + static_cast<uint32_t>(gb - 8 * a16) : 0u;
-  lds_barrier();
 }
 
 // Persistent merge: a workgroup takes items from the queue (largest first) --
