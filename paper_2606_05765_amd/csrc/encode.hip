@@ -5,7 +5,7 @@
 // through it, emits one bit per symbol (its bitmap) and partitions the
 // symbols between its children (the enc_partition primitives of Table 11).
 // The driver:
-//   1. k_hist        symbol histogram of every block and of every 64Ki-symbol
+//   1. k_hist        symbol histogram of every block and of every 4Ki-symbol
 //                    slice of it (end-to-end encode time is dominated by this
 //                    count, Sec. 4); k_slice_prefix turns the slice counts
 //                    into per-slice prefixes;
@@ -51,7 +51,7 @@ bool tree_is_complete(const uint8_t len[256], uint32_t max_len);
 namespace {
 
 constexpr int kWaveE = 64;
-constexpr uint32_t kHistSlice = 1u << 16;
+constexpr uint32_t kHistSlice = 1u << 12;   // one split tile: a 4 MiB block is 1024 workgroups
 constexpr int kSplitNT = 256;
 constexpr uint32_t kSplitT = 4096;      // input symbols per tile
 constexpr uint32_t kHdrStride = 1216;   // block header bytes: 12 + 128 + 32 + 4 * 255 <= this
