@@ -228,7 +228,8 @@ __global__ void k_zero_areas(uint32_t *img, uint32_t *rbm, const Totals *tot) {
 
 // Histogram of every block, one workgroup per slice of kHistSlice symbols:
 // the slice's counts go to its own row of slh (the split kernel's slices
-// start at the same boundaries) and are added to the block's row of hist.
+// start at the same boundaries); a block of one slice also writes them to
+// its row of hist (k_slice_prefix writes the totals of larger blocks).
 __global__ __launch_bounds__(256) void k_hist(const uint8_t *in, uint64_t n, uint32_t bs,
                                               uint32_t spb, uint32_t *hist, uint32_t *slh) {
   __shared__ uint32_t h[4][256];
@@ -260,20 +261,32 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t *in, uint64_t n, uin
   __syncthreads();
   const uint32_t v = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
   slh[static_cast<uint64_t>(blockIdx.x) * 256 + tid] = v;
-  if (v) atomicAdd(&hist[b * 256 + tid], v);
+  if (spb == 1) hist[b * 256 + tid] = v;
 }
 
 // Per block, the slice histograms become exclusive prefixes: row k holds the
-// count of each symbol in the block's slices before slice k (one thread per
-// symbol, one workgroup per block).
-__global__ __launch_bounds__(256) void k_slice_prefix(uint32_t *slh, uint32_t spb) {
+// count of each symbol in the block's slices before slice k, and the block's
+// row of hist the totals (one thread per symbol, one workgroup per block;
+// 16 rows read before any is rewritten).
+__global__ __launch_bounds__(256) void k_slice_prefix(uint32_t *slh, uint32_t spb, uint32_t *hist) {
   uint32_t *row = slh + static_cast<uint64_t>(blockIdx.x) * spb * 256 + threadIdx.x;
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < spb; ++k) {
+  uint32_t run = 0, k = 0;
+  for (; k + 16 <= spb; k += 16) {
+    uint32_t c[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) c[j] = row[256ull * (k + j)];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      row[256ull * (k + j)] = run;
+      run += c[j];
+    }
+  }
+  for (; k < spb; ++k) {
     const uint32_t c = row[256ull * k];
     row[256ull * k] = run;
     run += c;
   }
+  hist[static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x] = run;
 }
 
 // Code lengths of every block on the device (one wave per block), the same
@@ -1414,7 +1427,7 @@ pivco_status encode_enqueue(const void *d_in, uint64_t n, void *d_out, uint64_t 
                      dh, nb64 * 256);
   hipLaunchKernelGGL(k_hist, dim3(nb * spb), dim3(256), 0, s, in, n, static_cast<uint32_t>(bs), spb, dh, dslh);
   HIPCHK(hipGetLastError());
-  if (spb > 1) hipLaunchKernelGGL(k_slice_prefix, dim3(nb), dim3(256), 0, s, dslh, spb);
+  if (spb > 1) hipLaunchKernelGGL(k_slice_prefix, dim3(nb), dim3(256), 0, s, dslh, spb, dh);
 
   // 2. code lengths (package-merge per block, or the supplied tree)
   pivco_tree tree{};
