@@ -1444,8 +1444,10 @@ __device__ __forceinline__ void store_task(MergeSmem<C> &sm, int d, uint32_t ot,
       const uint32_t j = j0 + CB * c;
       uint8_t *dst = out + j;
       if (j + CB <= tvv && !(reinterpret_cast<uintptr_t>(dst) & (CB - 1))) {
-        if (CB == 16) *(GlobalU4 *)(dst) = U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};   // C cast: generic to global
-        else *(GlobalU2 *)(dst) = U32x2{o[0], o[1]};
+        // decoded bytes are written once and not read back here: non-temporal
+        if (CB == 16) __builtin_nontemporal_store(U32x4{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]},
+                                                  (GlobalU4 *)(dst));   // C cast: generic to global
+        else __builtin_nontemporal_store(U32x2{o[0], o[1]}, (GlobalU2 *)(dst));
       } else if (j < tvv) {
         const uint32_t kk2 = tvv - j < CB ? tvv - j : CB;
         GlobalU8 *gd = (GlobalU8 *)(dst);   // C cast: generic to global address space
@@ -1622,9 +1624,22 @@ __device__ __forceinline__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *ou
 }
 
 // All levels of the tile, deepest first (into LDS), the root last (into
-// HBM); one barrier per level.
+// HBM); one barrier per level.  For a tile of a whole block (touch) the
+// last wave, which has the fewest windows in the deep levels, first reads
+// one word of every 4 KiB page of the tile's output, so that the root
+// level's stores find their address translations cached: without it they
+// stalled on translation misses, and a 64Ki-symbol block's root levels
+// took about a third of its merge cycles when the blocks' outputs lay in
+// one large buffer.  (A split block's tiles are taken by many workgroups at
+// once and showed no such stall; read earlier, the translations were gone
+// again by the root level.)
 template <class C, bool RESIDENT, bool FLAT>
-__device__ __forceinline__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out) {
+__device__ __forceinline__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out, bool touch) {
+  if (touch && wave_id() == C::NW - 1) {
+    const uint32_t a = lane_id() * 4096u, troot = sm.tv[0];
+    const uint32_t v = a + 4 <= troot ? *reinterpret_cast<const uint32_t *>(out + a) : 0u;
+    if (v == 0x9E3779B9u) sm.warm_sink = v;   // keeps the read; the value is irrelevant
+  }
   for (int d = maxd - 1; d >= 1; --d) merge_level<C, RESIDENT, false, FLAT>(sm, d, out);
   merge_level<C, RESIDENT, true, FLAT>(sm, 0, out);
 }
@@ -1955,11 +1970,11 @@ __device__ void decode_block(const JobDev &J, const BlockExt &ext, uint32_t k,
     if (h.err) { bad = true; break; }
     // blocks without flat nodes run code with no flat paths in it
     if (resident) {
-      if (flat) merge_tile<C, true, true>(sm, static_cast<int>(maxd), out + t0);
-      else merge_tile<C, true, false>(sm, static_cast<int>(maxd), out + t0);
+      if (flat) merge_tile<C, true, true>(sm, static_cast<int>(maxd), out + t0, !tiled);
+      else merge_tile<C, true, false>(sm, static_cast<int>(maxd), out + t0, !tiled);
     } else {
-      if (flat) merge_tile<C, false, true>(sm, static_cast<int>(maxd), out + t0);
-      else merge_tile<C, false, false>(sm, static_cast<int>(maxd), out + t0);
+      if (flat) merge_tile<C, false, true>(sm, static_cast<int>(maxd), out + t0, !tiled);
+      else merge_tile<C, false, false>(sm, static_cast<int>(maxd), out + t0, !tiled);
     }
     if (!resident) {
       for (uint32_t i = tid; i < I; i += C::NT) sm.tv[i] = 0;
