@@ -2247,9 +2247,12 @@ __device__ __forceinline__ uint32_t chunk_count(const Chunk &c, uint64_t q, uint
 // G-bit boundaries of its buffer (G = 512 .. 8192: the smallest whose
 // directory fits), the 1 bits of each piece are counted by spr = G/128
 // consecutive lanes (one 16-byte chunk each: the region is streamed with
-// coalesced loads, four steps in flight) and exclusive-scanned.  Then P(x),
-// the region's 1 bits before bit x, is a directory entry plus one popcount
-// of less than G bits (at most spr chunk loads, eight in flight), and node
+// coalesced loads, four steps in flight) and exclusive-scanned in two levels
+// (per superblock of kTilesSB pieces a 32-bit count of the region's 1 bits
+// before it, per piece a 16-bit count of the superblock's before it; the
+// second region starts a superblock of its own).  Then P(x), the region's 1
+// bits before bit x, is a directory entry plus or minus one popcount of at
+// most half a piece (region_prefix), and node
 // v's rank at position s is P(start_v + s) - P(start_v).  Top-down by level,
 // every (node, boundary) pair of the level is one thread: node v's position
 // at boundary k (symbols of the block before k * kTileOut that pass it)
@@ -2262,7 +2265,8 @@ __device__ __forceinline__ uint32_t chunk_count(const Chunk &c, uint64_t q, uint
 // never read outside their bitmaps.  A flat node (v2 streams) has leaves
 // only: its positions are all a tile needs (D bits per position).
 constexpr int kTilesNT = 1024;
-constexpr uint32_t kTilesDir = 16384;     // directory entries (LDS)
+constexpr uint32_t kTilesDir = 32768;     // directory pieces (LDS)
+constexpr uint32_t kTilesSB = 8;          // pieces per directory superblock
 constexpr uint32_t kTilesPos = 16384;     // positions kept in LDS
 constexpr int kTilesG = 5;                // piece sizes 512 << e, e < kTilesG
 
@@ -2276,7 +2280,8 @@ struct TileRegion {
 
 struct TilesSmem {
   ParsedBlock pb;
-  uint32_t dir[kTilesDir + 1];
+  uint16_t rel[kTilesDir];                // 1 bits of the superblock before the piece
+  uint32_t sup[kTilesDir / kTilesSB + 1]; // 1 bits of the region before the superblock
   uint32_t pos[kTilesPos];                // [v * (K + 1) + k] when (K + 1) * I fits
   uint32_t pstart[256];                   // P(start of node v's bitmap)
   int32_t err;
@@ -2310,7 +2315,9 @@ __device__ __forceinline__ uint32_t region_prefix(const TilesSmem &sm, const Til
     for (uint32_t c = 0; c < B; ++c)
       if (c0 + c < nck) n += chunk_count(ch[c], q0 + 16ull * (c0 + c), lo, hi);
   }
-  return back ? sm.dir[r.d0 + j + 1] - n : sm.dir[r.d0 + j] + n;
+  const uint32_t e = r.d0 + j + (back ? 1 : 0);
+  const uint32_t base = sm.sup[e / kTilesSB] + sm.rel[e];
+  return back ? base - n : base + n;
 }
 
 // The level loop of k_tiles (POS_LDS: positions in sm.pos, else in the table).
@@ -2402,23 +2409,26 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
   reg[1].nb = 4ull * scratch_words;
   reg[1].b0 = 32ull * h.ans_word0;
   reg[1].b1 = 32ull * (h.ans_word0 + h.ans_words);
-  // the smallest piece size whose directory fits
-  uint32_t lg = 0, S = 0;
+  // the smallest piece size whose directory fits (the second region's
+  // pieces start at a superblock boundary)
+  uint32_t lg = 0, S = 0, np[2] = {0, 0};
   for (;; ++lg) {
-    S = 0;
     for (int i = 0; i < 2; ++i)
-      if (reg[i].b1 > reg[i].b0) S += static_cast<uint32_t>(((reg[i].b1 - 1) >> (9 + lg)) - (reg[i].b0 >> (9 + lg)) + 1);
+      np[i] = reg[i].b1 > reg[i].b0
+                  ? static_cast<uint32_t>(((reg[i].b1 - 1) >> (9 + lg)) - (reg[i].b0 >> (9 + lg)) + 1)
+                  : 0u;
+    S = (np[0] + kTilesSB - 1) / kTilesSB * kTilesSB + np[1];
     if (S <= kTilesDir || lg + 1 == kTilesG) break;
   }
-  if (S > kTilesDir) {                             // more than 8192 * 16Ki bitmap bits
+  if (S > kTilesDir) {                             // more than 8192 * 32Ki bitmap bits
     if (tid == 0) set_err(J.status, PIVCO_E_UNSUPPORTED);
     return;
   }
   const uint32_t LG = 9 + lg, spr = 4u << lg;      // G = 1 << LG bits = spr chunks
   reg[0].d0 = 0;
-  reg[0].np = reg[0].b1 > reg[0].b0 ? static_cast<uint32_t>(((reg[0].b1 - 1) >> LG) - (reg[0].b0 >> LG) + 1) : 0u;
-  reg[1].d0 = reg[0].np;
-  reg[1].np = S - reg[0].np;
+  reg[0].np = np[0];
+  reg[1].d0 = S - np[1];
+  reg[1].np = np[1];
   const bool pos_lds = (K + 1) * I <= kTilesPos;
   for (uint32_t k = tid; k <= K; k += kTilesNT) {
     const uint64_t s = static_cast<uint64_t>(k) * kTileOut;
@@ -2431,7 +2441,7 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
   // add up one piece
   {
     constexpr uint32_t U = 4, STEP = kWave * U;
-    const uint32_t CT = S * spr, c1 = reg[0].np * spr;
+    const uint32_t CT = S * spr, c0e = reg[0].np * spr, c1 = reg[1].d0 * spr;
     for (uint32_t base = wave * STEP; base < CT; base += NW * STEP) {
       Chunk x[U];
       uint64_t q[U], lo[U], hi[U];
@@ -2440,10 +2450,11 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
         const uint32_t c = base + u * kWave + lane;
         const bool second = c >= c1;
         const TileRegion &r = reg[second ? 1 : 0];
-        const uint32_t cr = second ? c - c1 : c;
+        const uint32_t cr = second ? c - c1 : (c < c0e ? c : 0u);
         q[u] = ((r.b0 >> LG) << (LG - 3)) + 16ull * cr;
         lo[u] = r.b0;
-        hi[u] = c < CT ? r.b1 : r.b0;              // past the last piece: no bits
+        // between the regions and past the last piece: no bits
+        hi[u] = c < CT && (second || c < c0e) ? r.b1 : r.b0;
         x[u] = chunk_load(second ? reg[1].p : reg[0].p, second ? reg[1].nb : reg[0].nb, q[u]);
       }
 #pragma unroll
@@ -2451,33 +2462,42 @@ __global__ __launch_bounds__(kTilesNT) void k_tiles(const JobDev *jobs, const Ti
         uint32_t m = chunk_count(x[u], q[u], lo[u], hi[u]);
         for (uint32_t sh = spr >> 1; sh >= 1; sh >>= 1) m += __shfl_xor(m, static_cast<int>(sh), static_cast<int>(spr));
         const uint32_t c = base + u * kWave + lane;
-        if (c % spr == 0 && c < CT) sm.dir[c / spr] = m;
+        if (c % spr == 0 && c < CT) sm.rel[c / spr] = static_cast<uint16_t>(m);   // at most 8192
       }
     }
   }
   __syncthreads();
-  // exclusive scan of the directory per region (contiguous runs per thread)
+  // exclusive scan of the directory (whole superblocks per thread): per
+  // superblock the 1 bits before it, per piece those of its superblock
+  // before it (at most 7 * 8192: 16 bits)
   {
-    const uint32_t per = (S + kTilesNT - 1) / kTilesNT;
-    const uint32_t f0 = tid * per, f1 = f0 + per < S ? f0 + per : S;
+    const uint32_t nsb = (S + kTilesSB - 1) / kTilesSB;
+    const uint32_t per = (nsb + kTilesNT - 1) / kTilesNT;
+    const uint32_t s0 = tid * per, s1 = s0 + per < nsb ? s0 + per : nsb;
     uint32_t loc = 0;
-    for (uint32_t f = f0; f < f1; ++f) loc += sm.dir[f];
+    for (uint32_t f = s0 * kTilesSB; f < s1 * kTilesSB && f < S; ++f) loc += sm.rel[f];
     const uint32_t incl = wave_incl_scan(loc);
     __shared__ uint32_t tot[kTilesNT / kWave];
     if (lane == kWave - 1) tot[wave] = incl;
     __syncthreads();
     uint32_t run = incl - loc + sum_first(tot, wave);
     __syncthreads();
-    for (uint32_t f = f0; f < f1; ++f) {
-      const uint32_t c = sm.dir[f];
-      sm.dir[f] = run;
-      run += c;
+    for (uint32_t sb = s0; sb < s1; ++sb) {
+      sm.sup[sb] = run;
+      uint32_t acc = 0;
+      for (uint32_t f = sb * kTilesSB; f < (sb + 1) * kTilesSB && f < S; ++f) {
+        const uint32_t c = sm.rel[f];
+        sm.rel[f] = static_cast<uint16_t>(acc);
+        acc += c;
+      }
+      run += acc;
     }
     __syncthreads();
-    // the second region's prefix starts from its own first piece
-    const uint32_t base1 = reg[1].np ? sm.dir[reg[1].d0] : 0u;
+    // the second region's prefix starts from its own first piece (the first
+    // of a superblock)
+    const uint32_t base1 = reg[1].np ? sm.sup[reg[1].d0 / kTilesSB] : 0u;
     __syncthreads();
-    for (uint32_t f = reg[1].d0 + tid; f < S; f += kTilesNT) sm.dir[f] -= base1;
+    for (uint32_t sb = reg[1].d0 / kTilesSB + tid; sb < nsb; sb += kTilesNT) sm.sup[sb] -= base1;
   }
   __syncthreads();
   switch (lg) {
