@@ -1627,12 +1627,11 @@ __device__ __forceinline__ void merge_level(MergeSmem<C> &sm, int d, uint8_t *ou
 // HBM); one barrier per level.  For a tile of a whole block (touch) the
 // last wave, which has the fewest windows in the deep levels, first reads
 // one word of every 4 KiB page of the tile's output, so that the root
-// level's stores find their address translations cached: without it they
-// stalled on translation misses, and a 64Ki-symbol block's root levels
-// took about a third of its merge cycles when the blocks' outputs lay in
-// one large buffer.  (A split block's tiles are taken by many workgroups at
-// once and showed no such stall; read earlier, the translations were gone
-// again by the root level.)
+// level's stores find their address translations cached (64Ki-symbol blocks
+// decoding into one large buffer: 0.4% of the step).  Reading them for a
+// split block's tiles too cost more than it saved, and reading them earlier
+// (with the item's loads, or during the first tile's rank chain) either
+// stalled the workgroup on the misses or came too early to help.
 template <class C, bool RESIDENT, bool FLAT>
 __device__ __forceinline__ void merge_tile(MergeSmem<C> &sm, int maxd, uint8_t *out, bool touch) {
   if (touch && wave_id() == C::NW - 1) {
