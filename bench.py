@@ -392,6 +392,9 @@ def main():
     ap.add_argument("--no-golomb", action="store_true", help="skip the PivCo-Golomb leg")
     ap.add_argument("--no-flat", action="store_true", help="skip the v2 (flat-subtree) leg")
     ap.add_argument("--no-fse", action="store_true", help="skip the selective-tANS leg")
+    ap.add_argument("--rans-chunk-log2", type=int, default=16,
+                    help="bits per rANS chunk (log2) of the main leg's streams (the chain a chunk's "
+                         "decode runs is 2^k / 32 steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -420,7 +423,8 @@ def main():
 
     # encode on the GPU (reported as an extra; synchronous per stream)
     t0 = time.perf_counter()
-    streams = [P.pivco_encode(d, bs, max_len=11, ans_mode=w.ans_mode) for d, bs in zip(d_xs, bss)]
+    streams = [P.pivco_encode(d, bs, max_len=11, ans_mode=w.ans_mode, chunk_log2=args.rans_chunk_log2)
+               for d, bs in zip(d_xs, bss)]
     torch.cuda.synchronize()
     enc_s = time.perf_counter() - t0
     comp = int(sum(s.numel() for s in streams))
@@ -463,7 +467,7 @@ def main():
     achieved = algo_bytes / (merge_avg * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": measured_traffic(args.workload, variant),
+                "traffic": measured_traffic(args.workload, variant) if args.rans_chunk_log2 == 16 else None,
                 "kernel": f"k_merge<{variant}>", "merge_ms_avg": round(merge_avg, 4),
                 "algorithmic_bytes_per_launch": algo_bytes}
     step_ach = algo_bytes / (ms_per_step * 1e-3) / 1e9
@@ -568,6 +572,7 @@ def main():
                    "decode": "batched: one HIP-graph replay per step, persistent merge kernel "
                              "over a longest-first work queue",
                    "variant": variant,
+                   "rans_chunk_bits": 1 << args.rans_chunk_log2,
                    "tune": plan.tune.as_dict() if plan.tune is not None else None},
         "roofline": roofline,
         "whole_step_roofline": whole_step,
