@@ -546,9 +546,10 @@ constexpr int kRansWin = 2048;        // u16 words per half-wave window in LDS
 constexpr uint32_t kRansSteps = 32;   // steps per window check (one output word per lane)
 
 // Lists the entropy-coded chunks of the block parsed in h/t (one lane):
-// walks the bodies that follow the raw bodies, checks every size, and
-// appends the chunks to the batch's list (a first pass counts them and
-// reserves their slots).  A rANS body is u16 probability, u16 zero, u32
+// reserves the block's slots in the batch's list (their number follows
+// from the node sizes), then walks the bodies that follow the raw bodies
+// once, checking every size and filling the slots (on a corrupt body the
+// rest become empty chunks).  A rANS body is u16 probability, u16 zero, u32
 // length, then per chunk of 2^chunk_log2 bits a u32 word count, the 32 u32
 // lane states and the words, padded to 4 bytes.  In a stream with flags bit
 // 0 a body is the tANS marker u8 (table 1..50, 0x80: complemented), u8
@@ -560,77 +561,82 @@ __device__ int32_t walk_rans(const JobDev &J, BlockHdr &h, const NodeTab &t, Cou
   const uint8_t *bp = J.in + h.blk;
   const uint64_t comp = h.comp, C = 1ull << J.chunk_log2;
   const bool fse = J.flags & 1;
-  for (int pass = 0; pass < 2; ++pass) {
-    uint32_t nch = 0;
-    uint64_t o = h.raw_end;
-    for (uint32_t i = 0; i < h.I; ++i) {
-      if (!t.kind[i]) continue;
-      while (o & 3) {
-        if (o >= comp || bp[o]) return PIVCO_E_CORRUPT;
-        ++o;
-      }
-      if (o + 8 > comp || t.nv[i] == 0) return PIVCO_E_CORRUPT;
-      const uint32_t w0 = bp[o] | (bp[o + 1] << 8);
-      const uint32_t pad = bp[o + 2] | (bp[o + 3] << 8);
-      const uint32_t blen = *reinterpret_cast<const uint32_t *>(bp + o + 4);
-      const uint32_t tt = w0 & 0x7F;
-      if (pad || o + 8 + blen > comp) return PIVCO_E_CORRUPT;
-      if (fse ? ((w0 >> 8) || tt < 1 || tt > kFseTables) : (w0 < 1 || w0 > 4095)) return PIVCO_E_CORRUPT;
-      const uint32_t p1q = fse ? kFseTag | w0 : w0;
-      const uint64_t body = o + 8;
-      uint64_t co = 0;
-      const uint64_t nv = t.nv[i];
-      for (uint64_t s = 0; s < nv; s += C) {
-        uint32_t nw;
-        uint64_t size;
-        if (fse) {
-          if (co + kFseChunkHdr > blen) return PIVCO_E_CORRUPT;
-          const uint32_t *lens = reinterpret_cast<const uint32_t *>(bp + body + co + 2 * kFseLanes);
-          nw = 0;
-          for (uint32_t q = 0; q < kFseLanes / 2; ++q) {
-            const uint32_t v = lens[q];
-            nw += (v & 0xFFFF) + (v >> 16);
-          }
-          const uint64_t used = kFseChunkHdr + static_cast<uint64_t>(nw);
-          size = (used + 3) & ~3ull;
-          if (co + size > blen) return PIVCO_E_CORRUPT;
-          for (uint64_t u = used; u < size; ++u)
-            if (bp[body + co + u]) return PIVCO_E_CORRUPT;
-        } else {
-          if (co + kChunkHdr > blen) return PIVCO_E_CORRUPT;
-          nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
-          size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
-          if (nw > C || co + size > blen) return PIVCO_E_CORRUPT;
-        }
-        if (pass == 1) {
-          RansChunk c;
-          c.src = h.blk + body + co;
-          c.dst = h.ans_word0 + t.boff[i] + s / 32;
-          c.nbits = static_cast<uint32_t>(nv - s < C ? nv - s : C);
-          c.nw = nw;
-          c.p1q = p1q;
-          c.job = h.job;
-          chunks[h.chunk0 + nch] = c;
-        }
-        ++nch;
-        co += size;
-      }
-      if (co != blen) return PIVCO_E_CORRUPT;
-      o = body + blen;
-    }
-    if (o != comp) return PIVCO_E_CORRUPT;
-    if (pass == 0) {
-      const uint32_t base = atomicAdd(&ctr->rans_chunks, nch);
-      if (static_cast<uint64_t>(base) + nch > cap) {
-        // slots reserved past the list's capacity stay unused (k_rans reads
-        // at most cap); the ones below it become empty chunks
-        for (uint64_t f = base; f < cap; ++f) chunks[f] = RansChunk{0, 0, 0, 0, 1, h.job};
-        return PIVCO_E_UNSUPPORTED;
-      }
-      h.chunk0 = base;
-      h.nchunk = nch;
-    }
+  // a node of n_v bits has ceil(n_v / C) chunks: the block's slots are
+  // reserved before the walk, which then reads each chunk header once
+  uint64_t want = 0;
+  for (uint32_t i = 0; i < h.I; ++i)
+    if (t.kind[i]) want += (static_cast<uint64_t>(t.nv[i]) + C - 1) / C;
+  const uint32_t nch = want > 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(want);
+  const uint32_t base = atomicAdd(&ctr->rans_chunks, nch);
+  if (static_cast<uint64_t>(base) + nch > cap) {
+    // slots reserved past the list's capacity stay unused (k_rans reads
+    // at most cap); the ones below it become empty chunks
+    for (uint64_t f = base; f < cap; ++f) chunks[f] = RansChunk{0, 0, 0, 0, 1, h.job};
+    return PIVCO_E_UNSUPPORTED;
   }
+  h.chunk0 = base;
+  h.nchunk = nch;
+  uint32_t k = 0;                        // slots written
+  // on a corrupt body the slots not yet written become empty chunks
+  auto fail = [&]() {
+    for (uint32_t f = k; f < nch; ++f) chunks[base + f] = RansChunk{0, 0, 0, 0, 1, h.job};
+    return static_cast<int32_t>(PIVCO_E_CORRUPT);
+  };
+  uint64_t o = h.raw_end;
+  for (uint32_t i = 0; i < h.I; ++i) {
+    if (!t.kind[i]) continue;
+    while (o & 3) {
+      if (o >= comp || bp[o]) return fail();
+      ++o;
+    }
+    if (o + 8 > comp || t.nv[i] == 0) return fail();
+    const uint32_t w0 = bp[o] | (bp[o + 1] << 8);
+    const uint32_t pad = bp[o + 2] | (bp[o + 3] << 8);
+    const uint32_t blen = *reinterpret_cast<const uint32_t *>(bp + o + 4);
+    const uint32_t tt = w0 & 0x7F;
+    if (pad || o + 8 + blen > comp) return fail();
+    if (fse ? ((w0 >> 8) || tt < 1 || tt > kFseTables) : (w0 < 1 || w0 > 4095)) return fail();
+    const uint32_t p1q = fse ? kFseTag | w0 : w0;
+    const uint64_t body = o + 8;
+    uint64_t co = 0;
+    const uint64_t nv = t.nv[i];
+    for (uint64_t s = 0; s < nv; s += C) {
+      uint32_t nw;
+      uint64_t size;
+      if (fse) {
+        if (co + kFseChunkHdr > blen) return fail();
+        const uint32_t *lens = reinterpret_cast<const uint32_t *>(bp + body + co + 2 * kFseLanes);
+        nw = 0;
+        for (uint32_t q = 0; q < kFseLanes / 2; ++q) {
+          const uint32_t v = lens[q];
+          nw += (v & 0xFFFF) + (v >> 16);
+        }
+        const uint64_t used = kFseChunkHdr + static_cast<uint64_t>(nw);
+        size = (used + 3) & ~3ull;
+        if (co + size > blen) return fail();
+        for (uint64_t u = used; u < size; ++u)
+          if (bp[body + co + u]) return fail();
+      } else {
+        if (co + kChunkHdr > blen) return fail();
+        nw = *reinterpret_cast<const uint32_t *>(bp + body + co);
+        size = (kChunkHdr + 2ull * nw + 3) & ~3ull;
+        if (nw > C || co + size > blen) return fail();
+      }
+      RansChunk c;
+      c.src = h.blk + body + co;
+      c.dst = h.ans_word0 + t.boff[i] + s / 32;
+      c.nbits = static_cast<uint32_t>(nv - s < C ? nv - s : C);
+      c.nw = nw;
+      c.p1q = p1q;
+      c.job = h.job;
+      chunks[base + k] = c;
+      ++k;
+      co += size;
+    }
+    if (co != blen) return fail();
+    o = body + blen;
+  }
+  if (o != comp) return fail();
   return PIVCO_OK;
 }
 
