@@ -193,3 +193,36 @@ def test_corrupt_split_blocks_flagged_and_isolated():
             if not ok:
                 assert s != 0, (mode, name)
 
+
+
+def test_corrupt_entropy_coded_bodies_match_oracle():
+    """Single-bit flips in the second half of forced-rANS streams (whole
+    blocks: where the entropy-coded bodies lie), each decoded in one batch
+    with the intact stream: the plan kernel reserves a block's chunk slots
+    before it walks the bodies, and a body found corrupt must leave empty
+    chunks behind.  Every flipped stream gets the oracle's verdict: rejected,
+    or decoded to exactly the oracle's bytes; the intact one decodes."""
+    rng = np.random.default_rng(33)
+    import workloads as W
+    x = W.draw(rng, W.geometric_p(0.85), 200_000)
+    good = O.encode(x, 1 << 15, ans_mode=2)
+    muts = []
+    for _ in range(60):
+        b = good.copy()
+        pos = int(rng.integers(good.size // 2, good.size))
+        b[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        muts.append((f"flip_{pos}", b))
+    streams = [dev(good)] + [dev(m) for _, m in muts]
+    outs = [torch.empty(x.size, dtype=torch.uint8, device="cuda") for _ in streams]
+    got, status = P.pivco_decode_batch(streams, outs)
+    torch.cuda.synchronize()
+    assert status[0] == 0 and np.array_equal(got[0].cpu().numpy(), x)
+    for (name, m), s, o in zip(muts, status[1:], got[1:]):
+        try:
+            want = O.decode(m, n=x.size)
+        except O.OracleError:
+            want = None
+        if want is None:
+            assert s != 0, name
+        else:
+            assert s == 0 and np.array_equal(o.cpu().numpy(), want), name
